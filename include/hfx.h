@@ -1,0 +1,152 @@
+/*
+ * hfx.h -- plane-wave Gamma-point Hartree-Fock exact exchange on MI355X (gfx950).
+ *
+ * The operations follow the exact-exchange definitions of the Methods
+ * section ("MTACE Method for H-AIMD Simulation") of Kar, Mandal, Thakkur,
+ * Meyer, Nair, "Speeding-up Hybrid Functional based Ab Initio Molecular
+ * Dynamics using Multiple Time-stepping and Resonance Free Thermostat":
+ *
+ *   Eq. (vx)   V_X psi_i = - sum_j v_ij(r) psi_j,          i = 1..N_orb
+ *   Eq. (vij)  v_ij(r)   = <psi_j | 1/r12 | psi_i>  (Coulomb potential of the
+ *                          pair density psi_i psi_j)
+ *   Eq. (HFX)  exact-exchange energy (prefactor convention below)
+ *   M_kl = <psi_k | V_X | psi_l>, the matrix whose Cholesky factor builds the
+ *          ACE operator (same subsection).
+ *
+ * Conventions (the paper leaves them open; these are this library's):
+ *   - Orbitals are real (Gamma point), float64, layout [orb][z][y][x] with x
+ *     fastest, on a cubic n x n x n grid in an orthorhombic box L[0..2]
+ *     (bohr).  dV = Lx Ly Lz / n^3 and <f|g> = dV sum f g.
+ *   - Periodic Coulomb kernel v(G): HFX_KERNEL_TRUNCATED uses
+ *     4 pi / G^2 (1 - cos(G Rc)), v(0) = 2 pi Rc^2, Rc = (3 Omega / 4 pi)^(1/3);
+ *     HFX_KERNEL_ERFC uses 4 pi / G^2 (1 - exp(-G^2 / 4 w^2)), v(0) = pi / w^2
+ *     with w = hfx_system.param (bohr^-1).
+ *   - K psi_i = V_X psi_i; E_x = 1/2 sum_i <psi_i | K psi_i> = -1/2 sum_ij e_ij
+ *     with e_ij = <psi_i psi_j | v_ij> >= 0, i.e. half of the paper's
+ *     closed-shell sum in Eq. (HFX).  No hybrid mixing fraction is applied.
+ *     dE_x / dpsi_i(r) = 2 dV (K psi_i)(r).
+ *   - The functional is evaluated for the orbitals as given; they need not be
+ *     orthonormal.
+ *
+ * Memory: every pointer argument is a DEVICE pointer unless its name ends in
+ * _host.  The caller allocates and owns every buffer, including the
+ * workspace; a plan owns only its own small device tables (kernel values,
+ * twiddles, tile descriptors).  Systems of a batched plan are concatenated
+ * in plan order in psi, kpsi, ex and m.
+ *
+ * Streams: work is enqueued asynchronously on `stream` (a hipStream_t, NULL
+ * for the default stream); no call synchronises the device except
+ * hfx_plan_create and hfx_plan_destroy.
+ *
+ * Errors: status codes only.  Arguments are validated before any HIP call;
+ * HIP failures map to HFX_EDEVICE.  hfx_last_error() returns a thread-local
+ * description of the most recent failure.
+ */
+#ifndef HFX_H
+#define HFX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HFX_OK = 0,
+  HFX_EINVAL = 1,       /* invalid argument (null pointer, size, shape)      */
+  HFX_EUNSUPPORTED = 2, /* valid but not supported (grid size, non-cubic)    */
+  HFX_ENOMEM = 3,       /* workspace too small, or device allocation failed */
+  HFX_EDEVICE = 4       /* a HIP runtime call failed                        */
+} hfx_status;
+
+typedef enum { HFX_KERNEL_TRUNCATED = 0, HFX_KERNEL_ERFC = 1 } hfx_kernel;
+typedef enum { HFX_FP32 = 0, HFX_FP64 = 1 } hfx_precision;
+typedef enum { HFX_ORTHO_LOWDIN = 0 } hfx_ortho_method;
+
+/* One periodic system. */
+typedef struct {
+  int n[3];      /* grid points along x, y, z; must be equal (cubic grid)   */
+  double L[3];   /* box lengths along x, y, z, bohr; each > 0               */
+  int n_orb;     /* number of occupied real orbitals, >= 1                   */
+  int kernel;    /* hfx_kernel                                              */
+  double param;  /* erfc screening w (bohr^-1) > 0; ignored for truncated   */
+} hfx_system;
+
+typedef struct hfx_plan_t* hfx_plan;
+
+/*
+ * Create a plan for n_sys systems at the given precision (hfx_precision).
+ * Supported grids: n in {24, 64, 72, 80, 96, 108, 120, 128}.  `options` is a
+ * nullable "key=value;key=value" string: tiles=<k> caps the orbital tiles per
+ * batch; maxws=<bytes> caps the workspace.  The environment variable
+ * HFX_MAX_WORKSPACE_BYTES also caps the workspace.  Uploads the plan's tables
+ * (synchronous).  Errors: HFX_EINVAL for null out/sys, n_sys < 1, n <= 0,
+ * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0;
+ * HFX_EUNSUPPORTED for a non-cubic or unsupported grid size; HFX_EDEVICE or
+ * HFX_ENOMEM when device set-up fails.  *out is NULL on failure.
+ */
+hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int precision,
+                           const char* options);
+
+/* Release the plan and its device tables (synchronises the device). */
+hfx_status hfx_plan_destroy(hfx_plan plan);
+
+/* Workspace bytes that every compute call of this plan needs. */
+hfx_status hfx_workspace_size(hfx_plan plan, size_t* bytes_host);
+
+/*
+ * E_x for each system (Eq. HFX with the 1/2 convention above), without
+ * forming K psi.  psi: float64 orbitals; ex: n_sys float64 results.
+ */
+hfx_status hfx_exchange_energy(hfx_plan plan, const double* psi, double* ex, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/*
+ * K psi = V_X psi (Eq. vx) for every orbital, and optionally E_x.
+ * kpsi: [n_orb][n^3] per system, float32 for an HFX_FP32 plan and float64
+ * for an HFX_FP64 plan (overwritten).  ex: nullable, n_sys float64.
+ */
+hfx_status hfx_apply_exchange(hfx_plan plan, const double* psi, void* kpsi, double* ex,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Exchange matrix M = dV Psi^T (K Psi), M_kl = <psi_k | K psi_l>, as float64
+ * row-major n_orb x n_orb blocks per system.  kpsi is the output of
+ * hfx_apply_exchange for the same plan and psi (precision of the plan).
+ * FP32 plans: psi is split into float32 hi + lo parts, both multiplied with
+ * the float32 K psi on FP32 MFMA, float64 accumulation across k-blocks.
+ * FP64 plans: float64 MFMA.
+ */
+hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, const void* kpsi, double* m,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Gradient of E_x: grad = 2 dV * gscale[s] * (K psi) for every system s, as
+ * float64 [n_orb][n^3] (overwritten).  The pair potentials are recomputed
+ * (nothing is kept from an earlier energy call).  gscale: nullable device
+ * array of n_sys float64 factors (the incoming adjoint of E_x); NULL means 1.
+ */
+hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double* gscale,
+                                 double* grad, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * In-place Loewdin orthonormalisation of psi in float64:
+ * Psi <- Psi S^(-1/2), S = dV Psi^T Psi (the occupied Kohn-Sham orbitals on
+ * which V_X acts are orthonormal).  S^(-1/2) comes from a coupled
+ * Newton-Schulz iteration run to float64 convergence.  method must be
+ * HFX_ORTHO_LOWDIN.
+ */
+hfx_status hfx_orthonormalize(hfx_plan plan, double* psi, int method, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* hfx_status_string(hfx_status s);
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char* hfx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HFX_H */

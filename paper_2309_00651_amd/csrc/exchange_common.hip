@@ -1,0 +1,96 @@
+// Elementwise helpers of the exchange pipeline: float64 -> float32 staging
+// of the orbitals, zero fill (a kernel rather than a memset, so the calls stay
+// graph-capture friendly), and the fixed-order float64 energy reduction.
+#include <hip/hip_runtime.h>
+
+#include "hfx_internal.hpp"
+
+namespace hfx {
+
+__global__ void __launch_bounds__(256) k_cast_f64_f32(const double* __restrict__ in,
+                                                      float* __restrict__ out, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x * 2;
+  for (size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; i < n; i += stride) {
+    if (i + 1 < n) {
+      const double2 v = *reinterpret_cast<const double2*>(in + i);
+      *reinterpret_cast<float2*>(out + i) = make_float2((float)v.x, (float)v.y);
+    } else {
+      out[i] = (float)in[i];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_zero(uint4* __restrict__ p, size_t n16,
+                                              unsigned char* __restrict__ tail, size_t ntail) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (blockIdx.x == 0)
+    for (size_t i = threadIdx.x; i < ntail; i += blockDim.x) tail[i] = 0;
+}
+
+// out[0] = scale * sum(partials), summed in a fixed order by one workgroup.
+__global__ void __launch_bounds__(256) k_energy_reduce(const double* __restrict__ partials,
+                                                       long long n, double scale,
+                                                       double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 256) s += partials[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = scale * red[0];
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_scale_to_f64(const S* __restrict__ src,
+                                                      double* __restrict__ dst, size_t n,
+                                                      double scale,
+                                                      const double* __restrict__ gscale) {
+  const double f = gscale ? scale * gscale[0] : scale;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = f * (double)src[i];
+}
+
+static int grid_for(size_t work) {
+  const size_t b = (work + 255) / 256;
+  return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+void launch_cast_f64_f32(const double* in, float* out, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cast_f64_f32, dim3(grid_for((n + 1) / 2)), dim3(256), 0, s, in, out, n);
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  // buffers come from the caller; only the 16-byte body is vectorised
+  const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
+  if (addr % 16 != 0) {
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, static_cast<uint4*>(nullptr), (size_t)0,
+                       static_cast<unsigned char*>(p), bytes);
+    return;
+  }
+  const size_t n16 = bytes / 16;
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(n16)), dim3(256), 0, s, static_cast<uint4*>(p), n16,
+                     static_cast<unsigned char*>(p) + n16 * 16, bytes - n16 * 16);
+}
+
+void launch_scale_to_f64(const void* src, int src_is_f64, double* dst, size_t n, double scale,
+                         const double* gscale, hipStream_t s) {
+  if (src_is_f64)
+    hipLaunchKernelGGL(k_scale_to_f64<double>, dim3(grid_for(n)), dim3(256), 0, s,
+                       static_cast<const double*>(src), dst, n, scale, gscale);
+  else
+    hipLaunchKernelGGL(k_scale_to_f64<float>, dim3(grid_for(n)), dim3(256), 0, s,
+                       static_cast<const float*>(src), dst, n, scale, gscale);
+}
+
+void launch_energy_reduce(const double* partials, long long n, double scale, double* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, s, partials, n, scale, out);
+}
+
+}  // namespace hfx

@@ -1,0 +1,37 @@
+// float64 exchange pipelines.  Planes of up to 96^2 points fit in LDS in
+// float64; larger grids split the plane pass into x rows and y columns.
+#include "exchange_kernels.hpp"
+
+namespace hfx {
+namespace {
+using P24 = FusedPipeline<double, 24, 16, 64, 8, Sched<4, 6>, Sched<6, 4>, 144, Sched<4, 6>,
+                          Sched<6, 4>, Sched<4, 6>, Sched<6, 4>>;
+using P64 = FusedPipeline<double, 64, 16, 128, 8, Sched<8, 8>, Sched<8, 8>, 256, Sched<8, 8>,
+                          Sched<8, 8>, Sched<8, 8>, Sched<8, 8>>;
+using P72 = FusedPipeline<double, 72, 16, 144, 8, Sched<8, 9>, Sched<9, 8>, 216, Sched<8, 9>,
+                          Sched<9, 8>, Sched<8, 9>, Sched<9, 8>>;
+using P80 = FusedPipeline<double, 80, 16, 160, 8, Sched<8, 10>, Sched<10, 8>, 320, Sched<8, 10>,
+                          Sched<10, 8>, Sched<8, 10>, Sched<10, 8>>;
+using P96 = FusedPipeline<double, 96, 16, 192, 8, Sched<8, 12>, Sched<12, 8>, 384, Sched<8, 12>,
+                          Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
+// SplitPipeline<T, N, W, pencil threads, tile, z fwd, z inv, rows per wg,
+//               row threads, x fwd, x inv, y fwd, y inv>
+using P108 = SplitPipeline<double, 108, 16, 192, 8, Sched<12, 9>, Sched<9, 12>, 16, 192,
+                           Sched<12, 9>, Sched<9, 12>, Sched<12, 9>, Sched<9, 12>>;
+using P120 = SplitPipeline<double, 120, 16, 240, 8, Sched<8, 15>, Sched<15, 8>, 16, 240,
+                           Sched<8, 15>, Sched<15, 8>, Sched<8, 15>, Sched<15, 8>>;
+using P128 = SplitPipeline<double, 128, 16, 256, 8, Sched<8, 16>, Sched<16, 8>, 16, 256,
+                           Sched<8, 16>, Sched<16, 8>, Sched<8, 16>, Sched<16, 8>>;
+}  // namespace
+
+const Variant* variants_f64(int* count) {
+  static const Variant v[] = {
+      P24::describe("f64-n24"),   P64::describe("f64-n64"),   P72::describe("f64-n72"),
+      P80::describe("f64-n80"),   P96::describe("f64-n96"),   P108::describe("f64-n108"),
+      P120::describe("f64-n120"), P128::describe("f64-n128"),
+  };
+  *count = (int)(sizeof(v) / sizeof(v[0]));
+  return v;
+}
+
+}  // namespace hfx

@@ -1,0 +1,561 @@
+// Exchange pipeline kernels (templated on precision, grid size and schedules).
+//
+// One "pair grid" packs two real pair densities as one complex grid,
+// c = psi_a psi_b + i psi_a psi_b'.  Because v(G) is real and even, the
+// real and imaginary parts of IFFT(v FFT(c)) are the two pair potentials
+// v_ab and v_ab' of Eq. (vij) (Methods, MTACE subsection).
+//
+// Three passes per batch of tiles, all over workspace grids [slot][z][y][x]:
+//   pair_fwd : a brick of W x-columns at fixed y, all z: forms the products
+//              from psi (read once per tile), forward FFT along z, stores.
+//   plane    : one kz plane of one grid: forward FFT along x and y in LDS,
+//              multiply by v(G)/N_r, inverse along y and x, stores.
+//              (float64 grids whose plane exceeds LDS use rows_fwd,
+//              cols_conv and rows_inv instead.)
+//   inv_acc  : the brick again: inverse FFT along z, then per point the pair
+//              energies rho_ab v_ab (float64 sums) and
+//              K psi_a -= v_ab psi_b, K psi_b -= v_ab psi_a   (Eq. vx).
+// Workgroups of one launch touch disjoint K psi rows (tiles of a batch share
+// no orbital, bricks of a tile share no point), so accumulation is plain
+// read-modify-write with a fixed order: results are bitwise reproducible.
+#pragma once
+
+#include "fft.hpp"
+#include "hfx_internal.hpp"
+
+namespace hfx {
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
+// XCD walks a contiguous range of logical indices (shared L2 for neighbours).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = b & 7, idx = b >> 3;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// Deterministic workgroup sum of one double per thread (fixed tree order).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  constexpr int P2 = NT <= 64 ? 64 : NT <= 128 ? 128 : NT <= 256 ? 256 : NT <= 512 ? 512 : 1024;
+  red[tid] = v;
+  for (int t = tid + NT; t < P2; t += NT) red[t] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int s = P2 / 2; s > 0; s >>= 1) {
+    for (int t = tid; t < s; t += NT) red[t] += red[t + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+template <int NT>
+constexpr int pow2_at_least() {
+  return NT <= 64 ? 64 : NT <= 128 ? 128 : NT <= 256 ? 256 : NT <= 512 ? 512 : 1024;
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1: pair product + forward z FFT on bricks.
+template <typename T, int N, int W, int NT, int TT, class SZF>
+__global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
+  using G = Geom<T, N, W, NT, true, W, 1>;
+  using F = FirstStage<G, SZF>;
+  using L = LastStage<G, SZF>;
+  using E = FFT<G, false, SZF>;
+  constexpr int NXB = (N + W - 1) / W;
+  constexpr int BR = N * NXB;
+  constexpr long long NR = (long long)N * N * N;
+  __shared__ cpx<T> lds[N * W];
+  const int tid = threadIdx.x;
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int t = lg / BR, br = lg - t * BR;
+  const int y = br / NXB, x0 = (br - y * NXB) * W;
+  const TileDesc td = a.tiles[t];
+  const T* __restrict__ psi = static_cast<const T*>(a.psi);
+  const cpx<T>* __restrict__ tw = static_cast<const cpx<T>*>(a.tw_zf);
+  cpx<T>* __restrict__ grids = static_cast<cpx<T>*>(a.grids);
+
+  // element offsets (within one N^3 grid) of this thread's stage-0 inputs
+  int off[F::VALS];
+  bool ok[F::VALS];
+#pragma unroll
+  for (int i = 0; i < F::PER; ++i) {
+    int m = 0, j = 0;
+    F::mj(tid, i, m, j);
+    const bool v = F::valid(tid, i) && (x0 + m) < N;
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SZF>::first; ++r) {
+      const int z = F::in_pos(j, r);
+      off[i * SchedInfo<SZF>::first + r] = (z * N + y) * N + x0 + m;
+      ok[i * SchedInfo<SZF>::first + r] = v;
+    }
+  }
+  int offL[L::VALS];
+  bool okL[L::VALS];
+#pragma unroll
+  for (int i = 0; i < L::PER; ++i) {
+    int m = 0, j = 0;
+    L::mj(tid, i, m, j);
+    const bool v = L::valid(tid, i) && (x0 + m) < N;
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SZF>::last; ++r) {
+      const int z = L::in_pos(j, r);
+      offL[i * SchedInfo<SZF>::last + r] = (z * N + y) * N + x0 + m;
+      okL[i * SchedInfo<SZF>::last + r] = v;
+    }
+  }
+
+  T pj[TT][F::VALS];
+#pragma unroll
+  for (int b = 0; b < TT; ++b) {
+    const bool bv = b < td.nJ;
+    const T* p = psi + (long long)(td.j0 + (bv ? b : 0)) * NR;
+#pragma unroll
+    for (int e = 0; e < F::VALS; ++e) pj[b][e] = (bv && ok[e]) ? p[off[e]] : T(0);
+  }
+
+  for (int ia = 0; ia < td.nI; ++ia) {
+    const T* pa_ptr = psi + (long long)(td.i0 + ia) * NR;
+    T pa[F::VALS];
+#pragma unroll
+    for (int e = 0; e < F::VALS; ++e) pa[e] = ok[e] ? pa_ptr[off[e]] : T(0);
+    static_for<0, TT / 2>([&](auto bp) {
+      constexpr int b0 = 2 * decltype(bp)::value, b1 = b0 + 1;
+      if (b0 >= td.nJ) return;
+      if (td.diag && b1 < ia) return;
+      cpx<T> v[F::VALS];
+#pragma unroll
+      for (int e = 0; e < F::VALS; ++e) v[e] = {pa[e] * pj[b0][e], pa[e] * pj[b1][e]};
+      cpx<T> out[L::VALS];
+      E::reg2reg(v, lds, tw, tid, out);
+      cpx<T>* g = grids + (long long)(td.slot0 + ia * (TT / 2) + decltype(bp)::value) * NR;
+#pragma unroll
+      for (int e = 0; e < L::VALS; ++e)
+        if (okL[e]) g[offL[e]] = out[e];
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 3: inverse z FFT + pair energies + K psi accumulation on bricks.
+template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC>
+__global__ void __launch_bounds__(NT) k_inv_acc(PassArgs a) {
+  using G = Geom<T, N, W, NT, true, W, 1>;
+  using F = FirstStage<G, SZI>;
+  using L = LastStage<G, SZI>;
+  using E = FFT<G, true, SZI>;
+  constexpr int NXB = (N + W - 1) / W;
+  constexpr int BR = N * NXB;
+  constexpr long long NR = (long long)N * N * N;
+  __shared__ cpx<T> lds[N * W];
+  __shared__ double red[pow2_at_least<NT>()];
+  const int tid = threadIdx.x;
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int t = lg / BR, br = lg - t * BR;
+  const int y = br / NXB, x0 = (br - y * NXB) * W;
+  const TileDesc td = a.tiles[t];
+  const T* __restrict__ psi = static_cast<const T*>(a.psi);
+  T* __restrict__ kpsi = static_cast<T*>(a.kpsi);
+  const cpx<T>* __restrict__ tw = static_cast<const cpx<T>*>(a.tw_zi);
+  const cpx<T>* __restrict__ grids = static_cast<const cpx<T>*>(a.grids);
+
+  int off[F::VALS];
+  bool ok[F::VALS];
+#pragma unroll
+  for (int i = 0; i < F::PER; ++i) {
+    int m = 0, j = 0;
+    F::mj(tid, i, m, j);
+    const bool v = F::valid(tid, i) && (x0 + m) < N;
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SZI>::first; ++r) {
+      off[i * SchedInfo<SZI>::first + r] = (F::in_pos(j, r) * N + y) * N + x0 + m;
+      ok[i * SchedInfo<SZI>::first + r] = v;
+    }
+  }
+  int offL[L::VALS];
+  bool okL[L::VALS];
+#pragma unroll
+  for (int i = 0; i < L::PER; ++i) {
+    int m = 0, j = 0;
+    L::mj(tid, i, m, j);
+    const bool v = L::valid(tid, i) && (x0 + m) < N;
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SZI>::last; ++r) {
+      offL[i * SchedInfo<SZI>::last + r] = (L::in_pos(j, r) * N + y) * N + x0 + m;
+      okL[i * SchedInfo<SZI>::last + r] = v;
+    }
+  }
+
+  T accJ[ACC ? TT : 1][L::VALS];
+#pragma unroll
+  for (int b = 0; b < (ACC ? TT : 1); ++b)
+#pragma unroll
+    for (int e = 0; e < L::VALS; ++e) accJ[b][e] = T(0);
+  double eacc = 0.0;
+
+  for (int ia = 0; ia < td.nI; ++ia) {
+    const int oa = td.i0 + ia;
+    const T* pa_ptr = psi + (long long)oa * NR;
+    T pa[L::VALS], acca[L::VALS];
+#pragma unroll
+    for (int e = 0; e < L::VALS; ++e) {
+      pa[e] = okL[e] ? pa_ptr[offL[e]] : T(0);
+      acca[e] = T(0);
+    }
+    static_for<0, TT / 2>([&](auto bp) {
+      constexpr int b0 = 2 * decltype(bp)::value;
+      if (b0 >= td.nJ) return;
+      if (td.diag && b0 + 1 < ia) return;
+      const cpx<T>* g = grids + (long long)(td.slot0 + ia * (TT / 2) + decltype(bp)::value) * NR;
+      cpx<T> v[F::VALS];
+#pragma unroll
+      for (int e = 0; e < F::VALS; ++e) v[e] = ok[e] ? g[off[e]] : cpx<T>{T(0), T(0)};
+      cpx<T> out[L::VALS];
+      E::reg2reg(v, lds, tw, tid, out);
+      static_for<0, 2>([&](auto half) {
+        constexpr int b = b0 + decltype(half)::value;
+        if (b >= td.nJ) return;
+        // weight of e_ab in sum_{i,j} e_ij: 2 for a != b, 1 for a == b
+        const int w = td.diag ? (b > ia ? 2 : (b == ia ? 1 : 0)) : 2;
+        if (w == 0) return;
+        const T* pb_ptr = psi + (long long)(td.j0 + b) * NR;
+        const double wd = (double)w;
+#pragma unroll
+        for (int e = 0; e < L::VALS; ++e) {
+          if (!okL[e]) continue;
+          const T vv = decltype(half)::value ? out[e].im : out[e].re;
+          const T pb = pb_ptr[offL[e]];
+          const T rho = pa[e] * pb;
+          eacc += wd * (double)rho * (double)vv;
+          if constexpr (ACC) {
+            accJ[b][e] -= vv * pa[e];
+            if (w == 2) acca[e] -= vv * pb;
+          }
+        }
+      });
+    });
+    if constexpr (ACC) {
+      T* ka = kpsi + (long long)oa * NR;
+#pragma unroll
+      for (int e = 0; e < L::VALS; ++e)
+        if (okL[e]) ka[offL[e]] += acca[e];
+    }
+  }
+  if constexpr (ACC) {
+#pragma unroll
+    for (int b = 0; b < TT; ++b) {
+      if (b >= td.nJ) break;
+      T* kb = kpsi + (long long)(td.j0 + b) * NR;
+#pragma unroll
+      for (int e = 0; e < L::VALS; ++e)
+        if (okL[e]) kb[offL[e]] += accJ[b][e];
+    }
+  }
+  const double s = block_sum<NT>(eacc, red);
+  if (tid == 0) a.partials[a.part_base + lg] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2: fused plane convolution for one kz plane of one pair grid.
+template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI>
+__global__ void __launch_bounds__(NT) k_plane_conv(PassArgs a) {
+  constexpr int P = N + 1;
+  using GX = Geom<T, N, N, NT, false, 1, P>;  // rows: sequence m = y, element n = x
+  using GY = Geom<T, N, N, NT, true, P, 1>;   // columns: sequence m = x, element n = y
+  using EXF = FFT<GX, false, SXF>;
+  using EXI = FFT<GX, true, SXI>;
+  using EYF = FFT<GY, false, SYF>;
+  using EYI = FFT<GY, true, SYI>;
+  using FX = FirstStage<GX, SXF>;
+  using LXF = LastStage<GX, SXF>;
+  using LY = LastStage<GY, SYF>;
+  using FYI = FirstStage<GY, SYI>;
+  using LYI = LastStage<GY, SYI>;
+  using LXI = LastStage<GX, SXI>;
+  static_assert(SchedInfo<SYI>::first == SchedInfo<SYF>::last, "fused y schedules");
+  static_assert(FYI::VALS == LY::VALS, "fused y register maps");
+  constexpr long long NR = (long long)N * N * N;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* plane = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int kz = lg / a.n_active, ai = lg - kz * a.n_active;
+  const int slot = a.active[ai];
+  cpx<T>* __restrict__ base = static_cast<cpx<T>*>(a.grids) + (long long)slot * NR + (long long)kz * N * N;
+  const T* __restrict__ vt = static_cast<const T*>(a.vtab) + (long long)kz * N * N;
+
+  // x forward: stage-0 inputs straight from HBM (rows, x contiguous)
+  cpx<T> v[FX::VALS];
+#pragma unroll
+  for (int i = 0; i < FX::PER; ++i) {
+    if (!FX::valid(tid, i)) continue;
+    int m, j;
+    FX::mj(tid, i, m, j);
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SXF>::first; ++r)
+      v[i * SchedInfo<SXF>::first + r] = base[m * N + FX::in_pos(j, r)];
+  }
+  {
+    cpx<T> o[LXF::VALS];
+    EXF::reg2reg(v, plane, static_cast<const cpx<T>*>(a.tw_xf), tid, o);
+    EXF::store_last(o, plane, tid);
+  }
+  __syncthreads();
+  // y forward, multiply by v(G)/N_r, y inverse (hand-over in registers)
+  cpx<T> oy[LY::VALS];
+  EYF::lds2reg(plane, static_cast<const cpx<T>*>(a.tw_yf), tid, oy);
+#pragma unroll
+  for (int i = 0; i < LY::PER; ++i) {
+    if (!LY::valid(tid, i)) continue;
+    int m, j;
+    LY::mj(tid, i, m, j);
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SYF>::last; ++r) {
+      const T f = vt[LY::in_pos(j, r) * N + m];
+      oy[i * SchedInfo<SYF>::last + r] = cscale(oy[i * SchedInfo<SYF>::last + r], f);
+    }
+  }
+  {
+    cpx<T> o[LYI::VALS];
+    EYI::reg2reg(oy, plane, static_cast<const cpx<T>*>(a.tw_yi), tid, o);
+    EYI::store_last(o, plane, tid);
+  }
+  __syncthreads();
+  // x inverse, results straight to HBM
+  cpx<T> ox[LXI::VALS];
+  EXI::lds2reg(plane, static_cast<const cpx<T>*>(a.tw_xi), tid, ox);
+#pragma unroll
+  for (int i = 0; i < LXI::PER; ++i) {
+    if (!LXI::valid(tid, i)) continue;
+    int m, j;
+    LXI::mj(tid, i, m, j);
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SXI>::last; ++r)
+      base[m * N + LXI::in_pos(j, r)] = ox[i * SchedInfo<SXI>::last + r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split plane pass for grids whose plane does not fit in LDS:
+// (a) FFT along x of RW consecutive rows, (b) y columns with the multiply.
+template <typename T, int N, int RW, int NT, class SX, bool INV>
+__global__ void __launch_bounds__(NT) k_rows(PassArgs a) {
+  constexpr int P = N + 1;
+  using G = Geom<T, N, RW, NT, false, 1, P>;
+  using E = FFT<G, INV, SX>;
+  using F = FirstStage<G, SX>;
+  using L = LastStage<G, SX>;
+  constexpr long long NR = (long long)N * N * N;
+  constexpr int RB = (N * N + RW - 1) / RW;  // row blocks per grid
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int ai = lg / RB, rb = lg - ai * RB;
+  const int slot = a.active[ai];
+  cpx<T>* __restrict__ base = static_cast<cpx<T>*>(a.grids) + (long long)slot * NR;
+  const long long row0 = (long long)rb * RW;
+  const cpx<T>* tw = static_cast<const cpx<T>*>(INV ? a.tw_xi : a.tw_xf);
+  cpx<T> v[F::VALS];
+#pragma unroll
+  for (int i = 0; i < F::PER; ++i) {
+    if (!F::valid(tid, i)) continue;
+    int m, j;
+    F::mj(tid, i, m, j);
+    const bool rv = row0 + m < (long long)N * N;
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SX>::first; ++r)
+      v[i * SchedInfo<SX>::first + r] =
+          rv ? base[(row0 + m) * N + F::in_pos(j, r)] : cpx<T>{T(0), T(0)};
+  }
+  cpx<T> o[L::VALS];
+  E::reg2reg(v, lds, tw, tid, o);
+#pragma unroll
+  for (int i = 0; i < L::PER; ++i) {
+    if (!L::valid(tid, i)) continue;
+    int m, j;
+    L::mj(tid, i, m, j);
+    if (row0 + m >= (long long)N * N) continue;
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SX>::last; ++r)
+      base[(row0 + m) * N + L::in_pos(j, r)] = o[i * SchedInfo<SX>::last + r];
+  }
+}
+
+template <typename T, int N, int W, int NT, class SYF, class SYI>
+__global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
+  using G = Geom<T, N, W, NT, true, W, 1>;
+  using EF = FFT<G, false, SYF>;
+  using EI = FFT<G, true, SYI>;
+  using F = FirstStage<G, SYF>;
+  using LF = LastStage<G, SYF>;
+  using FI = FirstStage<G, SYI>;
+  using LI = LastStage<G, SYI>;
+  static_assert(SchedInfo<SYI>::first == SchedInfo<SYF>::last, "fused y schedules");
+  static_assert(FI::VALS == LF::VALS, "fused y register maps");
+  constexpr int NXB = (N + W - 1) / W;
+  constexpr long long NR = (long long)N * N * N;
+  __shared__ cpx<T> lds[N * W];
+  const int tid = threadIdx.x;
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int per_grid = N * NXB;
+  const int ai = lg / per_grid, rem = lg - ai * per_grid;
+  const int z = rem / NXB, x0 = (rem - z * NXB) * W;
+  const int slot = a.active[ai];
+  cpx<T>* __restrict__ base = static_cast<cpx<T>*>(a.grids) + (long long)slot * NR + (long long)z * N * N;
+  const T* __restrict__ vt = static_cast<const T*>(a.vtab) + (long long)z * N * N;
+  cpx<T> v[F::VALS];
+#pragma unroll
+  for (int i = 0; i < F::PER; ++i) {
+    int m = 0, j = 0;
+    F::mj(tid, i, m, j);
+    const bool ok = F::valid(tid, i) && x0 + m < N;
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SYF>::first; ++r)
+      v[i * SchedInfo<SYF>::first + r] =
+          ok ? base[F::in_pos(j, r) * N + x0 + m] : cpx<T>{T(0), T(0)};
+  }
+  cpx<T> o[LF::VALS];
+  EF::reg2reg(v, lds, static_cast<const cpx<T>*>(a.tw_yf), tid, o);
+#pragma unroll
+  for (int i = 0; i < LF::PER; ++i) {
+    int m = 0, j = 0;
+    LF::mj(tid, i, m, j);
+    const bool ok = LF::valid(tid, i) && x0 + m < N;
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SYF>::last; ++r) {
+      const T f = ok ? vt[LF::in_pos(j, r) * N + x0 + m] : T(0);
+      o[i * SchedInfo<SYF>::last + r] = cscale(o[i * SchedInfo<SYF>::last + r], f);
+    }
+  }
+  cpx<T> b[LI::VALS];
+  EI::reg2reg(o, lds, static_cast<const cpx<T>*>(a.tw_yi), tid, b);
+#pragma unroll
+  for (int i = 0; i < LI::PER; ++i) {
+    int m = 0, j = 0;
+    LI::mj(tid, i, m, j);
+    if (!(LI::valid(tid, i) && x0 + m < N)) continue;
+#pragma unroll
+    for (int r = 0; r < SchedInfo<SYI>::last; ++r)
+      base[LI::in_pos(j, r) * N + x0 + m] = b[i * SchedInfo<SYI>::last + r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Registry glue: one compiled pipeline configuration.
+template <int... R>
+constexpr void fill_radices(int* dst, int& n, Sched<R...>) {
+  const int r[] = {R...};
+  n = (int)sizeof...(R);
+  for (int i = 0; i < n; ++i) dst[i] = r[i];
+}
+
+template <typename T, int N, int W, int NTP, int TT, class SZF, class SZI, int NTQ, class SXF,
+          class SXI, class SYF, class SYI>
+struct FusedPipeline {
+  static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
+  static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTP, TT, SZF>), dim3(nb), dim3(NTP), 0, s, a);
+  }
+  static void plane(const PassArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI>), dim3(nb), dim3(NTQ), lds, s,
+                       a);
+  }
+  static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTP, TT, SZI, true>), dim3(nb), dim3(NTP), 0, s, a);
+  }
+  static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTP, TT, SZI, false>), dim3(nb), dim3(NTP), 0, s, a);
+  }
+  static hipError_t prepare() {
+    return hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  static Variant describe(const char* name) {
+    Variant v{};
+    v.name = name;
+    v.n = N;
+    v.prec = sizeof(T) == 8 ? 1 : 0;
+    v.brick = W;
+    v.tile = TT;
+    v.nt_pencil = NTP;
+    v.nt_plane = NTQ;
+    v.plane_mode = 0;
+    v.rows_per_wg = 0;
+    fill_radices(v.zf, v.nzf, SZF{});
+    fill_radices(v.zi, v.nzi, SZI{});
+    fill_radices(v.xf, v.nxf, SXF{});
+    fill_radices(v.xi, v.nxi, SXI{});
+    fill_radices(v.yf, v.nyf, SYF{});
+    fill_radices(v.yi, v.nyi, SYI{});
+    v.plane_lds = lds;
+    v.pair_fwd = &pair_fwd;
+    v.plane = &plane;
+    v.inv_acc = &inv_acc;
+    v.inv_energy = &inv_energy;
+    v.prepare = &prepare;
+    return v;
+  }
+};
+
+template <typename T, int N, int W, int NTP, int TT, class SZF, class SZI, int RW, int NTQ,
+          class SXF, class SXI, class SYF, class SYI>
+struct SplitPipeline {
+  static constexpr size_t lds = (size_t)RW * (N + 1) * sizeof(cpx<T>);
+  static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTP, TT, SZF>), dim3(nb), dim3(NTP), 0, s, a);
+  }
+  static void rows_fwd(const PassArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXF, false>), dim3(nb), dim3(NTQ), lds, s, a);
+  }
+  static void rows_inv(const PassArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXI, true>), dim3(nb), dim3(NTQ), lds, s, a);
+  }
+  static void cols_conv(const PassArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_cols_conv<T, N, W, NTP, SYF, SYI>), dim3(nb), dim3(NTP), 0, s, a);
+  }
+  static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTP, TT, SZI, true>), dim3(nb), dim3(NTP), 0, s, a);
+  }
+  static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTP, TT, SZI, false>), dim3(nb), dim3(NTP), 0, s, a);
+  }
+  static hipError_t prepare() {
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_rows<T, N, RW, NTQ, SXF, false>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rows<T, N, RW, NTQ, SXI, true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  static Variant describe(const char* name) {
+    Variant v{};
+    v.name = name;
+    v.n = N;
+    v.prec = sizeof(T) == 8 ? 1 : 0;
+    v.brick = W;
+    v.tile = TT;
+    v.nt_pencil = NTP;
+    v.nt_plane = NTQ;
+    v.plane_mode = 1;
+    v.rows_per_wg = RW;
+    fill_radices(v.zf, v.nzf, SZF{});
+    fill_radices(v.zi, v.nzi, SZI{});
+    fill_radices(v.xf, v.nxf, SXF{});
+    fill_radices(v.xi, v.nxi, SXI{});
+    fill_radices(v.yf, v.nyf, SYF{});
+    fill_radices(v.yi, v.nyi, SYI{});
+    v.plane_lds = lds;
+    v.pair_fwd = &pair_fwd;
+    v.rows_fwd = &rows_fwd;
+    v.cols_conv = &cols_conv;
+    v.rows_inv = &rows_inv;
+    v.inv_acc = &inv_acc;
+    v.inv_energy = &inv_energy;
+    v.prepare = &prepare;
+    return v;
+  }
+};
+
+}  // namespace hfx

@@ -1,0 +1,413 @@
+// Mixed-radix Stockham FFT engine for CDNA4 workgroups.
+//
+// A workgroup of NT threads transforms M independent complex sequences of
+// length N at once.  Each stage of radix R runs M*N/R butterflies: a thread
+// gathers the R legs of its butterflies into registers, applies the stage
+// twiddles, runs an unrolled radix-R codelet and scatters the results.
+// Between stages the data pass through LDS (all threads read, barrier,
+// compute, write, barrier); the first stage may take its inputs straight
+// from registers (loaded from HBM by the caller) and the last stage leaves its
+// outputs in registers, so a kernel can fuse a pointwise producer before the
+// transform and a consumer after it.
+//
+// Stage s (radix R, span Ns = product of the earlier radices), butterfly j:
+//   inputs  x[j + r N/R]                                   r = 0..R-1
+//   twiddle W_{Ns R}^{r (j mod Ns)}   (W_n = exp(-2 pi i / n), conjugated
+//                                      for the inverse transform)
+//   outputs y[(j div Ns) Ns R + (j mod Ns) + r Ns]
+// After the last stage the outputs are in natural order, and butterfly j of
+// the last stage holds X[j + r N/R_last].
+//
+// Butterflies are numbered q = tid + i*NT (i < PER) and mapped to
+// (sequence m, butterfly j) either m-fastest (MFAST: neighbouring threads own
+// neighbouring sequences, used for pencils whose sequences are adjacent in
+// memory) or j-fastest (neighbouring threads walk along one sequence, used
+// for contiguous rows).  LDS element (m, n) lives at m*TS + n*ES.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "trig.hpp"
+
+#define HFX_HD __host__ __device__ __forceinline__
+
+namespace hfx {
+
+template <typename T>
+struct cpx {
+  T re, im;
+};
+
+template <typename T>
+HFX_HD cpx<T> operator+(cpx<T> a, cpx<T> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename T>
+HFX_HD cpx<T> operator-(cpx<T> a, cpx<T> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+template <typename T>
+HFX_HD cpx<T> cscale(cpx<T> a, T s) {
+  return {a.re * s, a.im * s};
+}
+// a * (-i)
+template <typename T>
+HFX_HD cpx<T> mul_mi(cpx<T> a) {
+  return {a.im, -a.re};
+}
+// a * (+i)
+template <typename T>
+HFX_HD cpx<T> mul_pi(cpx<T> a) {
+  return {-a.im, a.re};
+}
+// a * w, or a * conj(w) when CONJ
+template <bool CONJ, typename T>
+HFX_HD cpx<T> cmul(cpx<T> a, cpx<T> w) {
+  if constexpr (CONJ) {
+    return {a.re * w.re + a.im * w.im, a.im * w.re - a.re * w.im};
+  } else {
+    return {a.re * w.re - a.im * w.im, a.re * w.im + a.im * w.re};
+  }
+}
+
+template <int B, int E, class F>
+HFX_HD void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a * W_N^K with W_N = exp(-2 pi i / N) (forward) or exp(+2 pi i / N) (INV);
+// trivial and eighth-turn rotations are special-cased at compile time.
+template <int N, int K, bool INV, typename T>
+HFX_HD cpx<T> rot(cpx<T> a) {
+  constexpr int k = ((K % N) + N) % N;
+  if constexpr (k == 0) {
+    return a;
+  } else if constexpr (2 * k == N) {
+    return {-a.re, -a.im};
+  } else if constexpr (4 * k == N) {
+    return INV ? mul_pi(a) : mul_mi(a);
+  } else if constexpr (4 * k == 3 * N) {
+    return INV ? mul_mi(a) : mul_pi(a);
+  } else if constexpr ((8 * k) % N == 0) {
+    // odd multiple of pi/4: both parts of W have magnitude sqrt(1/2)
+    constexpr SinCos sc = sincos_2pi(k, N);
+    constexpr T h = T(0.70710678118654752440084436210484903928);
+    constexpr int sgc = sc.c > 0 ? 1 : -1;
+    constexpr int sgs = (INV ? 1 : -1) * (sc.s > 0 ? 1 : -1);  // sign of Im W
+    const T x = (sgc > 0 ? a.re : -a.re) - (sgs > 0 ? a.im : -a.im);
+    const T y = (sgs > 0 ? a.re : -a.re) + (sgc > 0 ? a.im : -a.im);
+    return {h * x, h * y};
+  } else {
+    constexpr SinCos sc = sincos_2pi(k, N);
+    constexpr T c = T(sc.c);
+    constexpr T s = INV ? T(sc.s) : T(-sc.s);
+    return {a.re * c - a.im * s, a.re * s + a.im * c};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Radix-R codelets: v[k] <- sum_n v[n] W_R^{nk}, in registers.
+template <int R, bool INV, typename T>
+struct DFT;
+
+template <bool INV, typename T>
+struct DFT<1, INV, T> {
+  HFX_HD static void run(cpx<T>*) {}
+};
+
+template <bool INV, typename T>
+struct DFT<2, INV, T> {
+  HFX_HD static void run(cpx<T>* v) {
+    const cpx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  }
+};
+
+template <bool INV, typename T>
+struct DFT<3, INV, T> {
+  HFX_HD static void run(cpx<T>* v) {
+    constexpr T s3 = T(0.86602540378443864676372317075293618);  // sin(2pi/3)
+    const cpx<T> t = v[1] + v[2];
+    const cpx<T> d = cscale(v[1] - v[2], s3);
+    const cpx<T> m = {v[0].re - T(0.5) * t.re, v[0].im - T(0.5) * t.im};
+    v[0] = v[0] + t;
+    const cpx<T> id = mul_pi(d);  // i * s3 * (v1 - v2)
+    if constexpr (INV) {
+      v[1] = m + id;
+      v[2] = m - id;
+    } else {
+      v[1] = m - id;
+      v[2] = m + id;
+    }
+  }
+};
+
+template <bool INV, typename T>
+struct DFT<4, INV, T> {
+  HFX_HD static void run(cpx<T>* v) {
+    const cpx<T> a0 = v[0] + v[2], a1 = v[0] - v[2];
+    const cpx<T> b0 = v[1] + v[3], b1 = v[1] - v[3];
+    const cpx<T> ib1 = mul_pi(b1);
+    v[0] = a0 + b0;
+    v[2] = a0 - b0;
+    if constexpr (INV) {
+      v[1] = a1 + ib1;
+      v[3] = a1 - ib1;
+    } else {
+      v[1] = a1 - ib1;
+      v[3] = a1 + ib1;
+    }
+  }
+};
+
+template <bool INV, typename T>
+struct DFT<5, INV, T> {
+  HFX_HD static void run(cpx<T>* v) {
+    constexpr T c1 = T(0.30901699437494742410229341718281906);   // cos(2pi/5)
+    constexpr T c2 = T(-0.80901699437494742410229341718281906);  // cos(4pi/5)
+    constexpr T s1 = T(0.95105651629515357211643933337938214);   // sin(2pi/5)
+    constexpr T s2 = T(0.58778525229247312916870595463907277);   // sin(4pi/5)
+    const cpx<T> a1 = v[1] + v[4], b1 = v[1] - v[4];
+    const cpx<T> a2 = v[2] + v[3], b2 = v[2] - v[3];
+    const cpx<T> x0 = v[0];
+    const cpx<T> p1 = {x0.re + c1 * a1.re + c2 * a2.re, x0.im + c1 * a1.im + c2 * a2.im};
+    const cpx<T> p2 = {x0.re + c2 * a1.re + c1 * a2.re, x0.im + c2 * a1.im + c1 * a2.im};
+    const cpx<T> q1 = {s1 * b1.re + s2 * b2.re, s1 * b1.im + s2 * b2.im};
+    const cpx<T> q2 = {s2 * b1.re - s1 * b2.re, s2 * b1.im - s1 * b2.im};
+    const cpx<T> iq1 = mul_pi(q1), iq2 = mul_pi(q2);
+    v[0] = x0 + a1 + a2;
+    if constexpr (INV) {
+      v[1] = p1 + iq1;
+      v[4] = p1 - iq1;
+      v[2] = p2 + iq2;
+      v[3] = p2 - iq2;
+    } else {
+      v[1] = p1 - iq1;
+      v[4] = p1 + iq1;
+      v[2] = p2 - iq2;
+      v[3] = p2 + iq2;
+    }
+  }
+};
+
+// Composite radix P*Q: inputs n = Q n1 + n2, outputs k = k1 + P k2.
+//   step 1: DFT_P over n1 for each n2, times W_{PQ}^{n2 k1}
+//   step 2: DFT_Q over n2 for each k1
+template <int P, int Q, bool INV, typename T>
+struct DFTPQ {
+  HFX_HD static void run(cpx<T>* v) {
+    cpx<T> t[P * Q];
+    static_for<0, Q>([&](auto n2) {
+      cpx<T> a[P];
+      static_for<0, P>([&](auto n1) { a[n1] = v[Q * n1 + n2]; });
+      DFT<P, INV, T>::run(a);
+      static_for<0, P>([&](auto k1) {
+        t[n2 * P + k1] = rot<P * Q, decltype(n2)::value * decltype(k1)::value, INV>(a[k1]);
+      });
+    });
+    static_for<0, P>([&](auto k1) {
+      cpx<T> b[Q];
+      static_for<0, Q>([&](auto n2) { b[n2] = t[n2 * P + k1]; });
+      DFT<Q, INV, T>::run(b);
+      static_for<0, Q>([&](auto k2) { v[k1 + P * k2] = b[k2]; });
+    });
+  }
+};
+
+template <bool INV, typename T> struct DFT<6, INV, T> : DFTPQ<3, 2, INV, T> {};
+template <bool INV, typename T> struct DFT<8, INV, T> : DFTPQ<2, 4, INV, T> {};
+template <bool INV, typename T> struct DFT<9, INV, T> : DFTPQ<3, 3, INV, T> {};
+template <bool INV, typename T> struct DFT<10, INV, T> : DFTPQ<2, 5, INV, T> {};
+template <bool INV, typename T> struct DFT<12, INV, T> : DFTPQ<3, 4, INV, T> {};
+template <bool INV, typename T> struct DFT<15, INV, T> : DFTPQ<3, 5, INV, T> {};
+template <bool INV, typename T> struct DFT<16, INV, T> : DFTPQ<4, 4, INV, T> {};
+
+// ---------------------------------------------------------------------------
+// Geometry of one batched transform inside a workgroup.
+template <typename T_, int N_, int M_, int NT_, bool MFAST_, int ES_, int TS_>
+struct Geom {
+  using T = T_;
+  static constexpr int N = N_;     // transform length
+  static constexpr int M = M_;     // number of sequences
+  static constexpr int NT = NT_;   // threads in the workgroup
+  static constexpr bool MFAST = MFAST_;
+  static constexpr int ES = ES_;   // LDS stride between elements of a sequence
+  static constexpr int TS = TS_;   // LDS stride between sequences
+};
+
+template <class G, int R, int NS>
+struct Stage {
+  using T = typename G::T;
+  static_assert(G::N % R == 0, "radix must divide the length");
+  static constexpr int NBF = G::N / R;        // butterflies per sequence
+  static constexpr int NB = G::M * NBF;       // butterflies per stage
+  static constexpr int PER = (NB + G::NT - 1) / G::NT;
+  static constexpr bool EXACT = (NB % G::NT) == 0;
+  static constexpr int VALS = PER * R;        // complex registers per thread
+
+  HFX_HD static bool valid(int tid, int i) {
+    return EXACT || (tid + i * G::NT) < NB;
+  }
+  HFX_HD static void mj(int tid, int i, int& m, int& j) {
+    const int q = tid + i * G::NT;
+    if constexpr (G::MFAST) {
+      m = q % G::M;
+      j = q / G::M;
+    } else {
+      j = q % NBF;
+      m = q / NBF;
+    }
+  }
+  // position inside the sequence of input leg r of butterfly j
+  HFX_HD static int in_pos(int j, int r) { return j + r * NBF; }
+  // position of output leg r of butterfly j
+  HFX_HD static int out_pos(int j, int r) {
+    return (j / NS) * NS * R + (j % NS) + r * NS;
+  }
+
+  // twiddles + codelet on registers v[PER*R]; tw holds W_{NS R}^{r k}
+  // at tw[k*(R-1) + r-1] (forward sign), conjugated here for INV.
+  template <bool INV>
+  HFX_HD static void compute(cpx<T>* v, int tid, const cpx<T>* __restrict__ tw) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (!valid(tid, i)) continue;
+      if constexpr (NS > 1) {
+        int m, j;
+        mj(tid, i, m, j);
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          v[i * R + r] = cmul<INV>(v[i * R + r], tw[k * (R - 1) + r - 1]);
+        }
+      }
+      DFT<R, INV, T>::run(v + i * R);
+    }
+  }
+
+  HFX_HD static void read(cpx<T>* v, const cpx<T>* lds, int tid) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (!valid(tid, i)) continue;
+      int m, j;
+      mj(tid, i, m, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i * R + r] = lds[m * G::TS + in_pos(j, r) * G::ES];
+    }
+  }
+
+  HFX_HD static void write(const cpx<T>* v, cpx<T>* lds, int tid) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (!valid(tid, i)) continue;
+      int m, j;
+      mj(tid, i, m, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[m * G::TS + out_pos(j, r) * G::ES] = v[i * R + r];
+    }
+  }
+};
+
+template <int... Rs>
+struct Sched {};
+
+template <class S>
+struct SchedInfo;
+template <int R0, int... Rs>
+struct SchedInfo<Sched<R0, Rs...>> {
+  static constexpr int first = R0;
+  static constexpr int count = 1 + sizeof...(Rs);
+  static constexpr int radices[count] = {R0, Rs...};
+  static constexpr int last = radices[count - 1];
+  static constexpr int product = (R0 * ... * Rs);
+  // span of the last stage
+  static constexpr int last_span = product / last;
+  // number of twiddle entries (stages with span > 1)
+  static constexpr int tw_count() {
+    int n = 0, ns = 1;
+    for (int s = 0; s < count; ++s) {
+      if (ns > 1) n += ns * (radices[s] - 1);
+      ns *= radices[s];
+    }
+    return n;
+  }
+};
+
+template <class G, class S>
+using FirstStage = Stage<G, SchedInfo<S>::first, 1>;
+template <class G, class S>
+using LastStage = Stage<G, SchedInfo<S>::last, SchedInfo<S>::last_span>;
+
+// Stages 1..end: read from LDS, compute, write to LDS (or keep the final
+// stage in registers `out`).  A barrier follows the final read, so the
+// caller may write LDS again as soon as this returns.
+template <class G, bool INV, int NS, int TWOFF, int R, int... Rest>
+__device__ __forceinline__ void fft_tail(cpx<typename G::T>* lds,
+                                         const cpx<typename G::T>* __restrict__ tw, int tid,
+                                         cpx<typename G::T>* out) {
+  using St = Stage<G, R, NS>;
+  cpx<typename G::T> v[St::VALS];
+  St::read(v, lds, tid);
+  __syncthreads();
+  St::template compute<INV>(v, tid, tw + TWOFF);
+  if constexpr (sizeof...(Rest) > 0) {
+    St::write(v, lds, tid);
+    __syncthreads();
+    fft_tail<G, INV, NS * R, TWOFF + NS * (R - 1), Rest...>(lds, tw, tid, out);
+  } else {
+#pragma unroll
+    for (int e = 0; e < St::VALS; ++e) out[e] = v[e];
+  }
+}
+
+template <class G, bool INV, class S>
+struct FFT;
+
+template <class G, bool INV, int R0, int... Rest>
+struct FFT<G, INV, Sched<R0, Rest...>> {
+  using T = typename G::T;
+  using S = Sched<R0, Rest...>;
+  using First = Stage<G, R0, 1>;
+  using Last = LastStage<G, S>;
+
+  // Stage-0 inputs in registers `v` (First::VALS values, element map of
+  // First), outputs in registers `out` (Last::VALS, element map of Last).
+  // LDS must hold M*N elements with the geometry's strides.
+  __device__ __forceinline__ static void reg2reg(cpx<T>* v, cpx<T>* lds,
+                                                 const cpx<T>* __restrict__ tw, int tid,
+                                                 cpx<T>* out) {
+    First::template compute<INV>(v, tid, tw);
+    if constexpr (sizeof...(Rest) == 0) {
+#pragma unroll
+      for (int e = 0; e < First::VALS; ++e) out[e] = v[e];
+    } else {
+      First::write(v, lds, tid);
+      __syncthreads();
+      fft_tail<G, INV, R0, 0, Rest...>(lds, tw, tid, out);
+    }
+  }
+
+  // Stage-0 inputs from LDS (the caller has synchronised), outputs in registers.
+  __device__ __forceinline__ static void lds2reg(cpx<T>* lds, const cpx<T>* __restrict__ tw,
+                                                 int tid, cpx<T>* out) {
+    cpx<T> v[First::VALS];
+    First::read(v, lds, tid);
+    __syncthreads();
+    reg2reg(v, lds, tw, tid, out);
+  }
+
+  // Final outputs from registers to LDS in natural order (no barrier).
+  __device__ __forceinline__ static void store_last(const cpx<T>* out, cpx<T>* lds, int tid) {
+    Last::write(out, lds, tid);
+  }
+};
+
+}  // namespace hfx

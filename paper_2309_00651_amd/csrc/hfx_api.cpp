@@ -1,0 +1,581 @@
+// C ABI of the exact-exchange library: plan construction, argument
+// validation, workspace layout and the launch sequence of each entry point.
+//
+// Pair work is scheduled in orbital tiles of T x T pairs (T = variant tile).
+// Blocks of T orbitals meet in round-robin rounds (circle method), so the
+// tiles of one round share no orbital; a batch is a slice of one round, and
+// its three pipeline passes run back to back on the caller's stream.  This
+// makes K psi accumulation race-free and its order fixed (the pair loop of
+// Eq. (vx) split over tiles, in the spirit of the paper's task groups, which
+// also divide the pair list and sum the partial operators).
+#include "../../include/hfx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hfx_internal.hpp"
+#include "twiddle.hpp"
+
+using namespace hfx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hfx_status fail(hfx_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(e_ == hipErrorOutOfMemory ? HFX_ENOMEM : HFX_EDEVICE,            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+struct Batch {
+  int tile_off, n_tiles;
+  int active_off, n_active;
+  long long part_base;
+};
+
+struct SystemPlan {
+  hfx_system sys;
+  const Variant* var = nullptr;
+  int n = 0;
+  long long nr = 0;
+  double dv = 0.0;
+  int tiles_per_batch = 1;
+  int slots_per_batch = 0;
+  std::vector<TileDesc> tiles;
+  std::vector<int> active;
+  std::vector<Batch> batches;
+  long long n_partials = 0;
+  // device tables (owned)
+  void* vtab = nullptr;
+  void* tw[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  TileDesc* d_tiles = nullptr;
+  int* d_active = nullptr;
+  // offsets inside the caller's workspace
+  size_t off_psi32 = 0, off_grids = 0, off_partials = 0, off_gemm = 0, off_ortho = 0;
+  size_t off_grad = 0;  // float32 K psi staging of the gradient (float32 plans)
+  size_t ws_end = 0;
+  // offsets inside concatenated user buffers
+  long long psi_off = 0, m_off = 0;
+  int gemm_chunks = 1;
+};
+
+}  // namespace
+
+struct hfx_plan_t {
+  int prec = 0;
+  std::vector<SystemPlan> sys;
+  size_t ws_bytes = 0;
+  int device = 0;
+};
+
+namespace {
+
+const Variant* find_variant(int n, int prec) {
+  int count = 0;
+  const Variant* v = prec == HFX_FP64 ? variants_f64(&count) : variants_f32(&count);
+  for (int i = 0; i < count; ++i)
+    if (v[i].n == n) return &v[i];
+  return nullptr;
+}
+
+long long parse_option(const char* opts, const char* key, long long def) {
+  if (!opts) return def;
+  const std::string s(opts), k = std::string(key) + "=";
+  size_t p = 0;
+  while (p < s.size()) {
+    size_t e = s.find(';', p);
+    if (e == std::string::npos) e = s.size();
+    const std::string item = s.substr(p, e - p);
+    if (item.compare(0, k.size(), k) == 0) return std::atoll(item.c_str() + k.size());
+    p = e + 1;
+  }
+  return def;
+}
+
+// Round-robin (circle method) schedule of orbital blocks: each round lists
+// block pairs (I, J), I <= J, in which no block appears twice.
+std::vector<std::vector<std::pair<int, int>>> tile_rounds(int nb) {
+  std::vector<std::vector<std::pair<int, int>>> rounds;
+  if (nb == 1) {
+    rounds.push_back({{0, 0}});
+    return rounds;
+  }
+  const bool odd = nb % 2 == 1;
+  const int n = odd ? nb + 1 : nb;  // team nb is the dummy when odd
+  std::vector<int> pos(n);
+  for (int i = 0; i < n; ++i) pos[i] = i;
+  for (int r = 0; r < n - 1; ++r) {
+    std::vector<std::pair<int, int>> round;
+    for (int i = 0; i < n / 2; ++i) {
+      int a = pos[i], b = pos[n - 1 - i];
+      if (odd && (a == nb || b == nb)) {
+        const int c = a == nb ? b : a;
+        round.push_back({c, c});  // diagonal tile of the block left without partner
+      } else {
+        round.push_back({std::min(a, b), std::max(a, b)});
+      }
+    }
+    rounds.push_back(round);
+    // rotate all but the first position
+    const int last = pos[n - 1];
+    for (int i = n - 1; i > 1; --i) pos[i] = pos[i - 1];
+    pos[1] = last;
+  }
+  if (!odd) {
+    std::vector<std::pair<int, int>> diag;
+    for (int b = 0; b < nb; ++b) diag.push_back({b, b});
+    rounds.push_back(diag);
+  }
+  return rounds;
+}
+
+int bricks_per_tile(const Variant* v) {
+  return v->n * ((v->n + v->brick - 1) / v->brick);
+}
+
+void build_schedule(SystemPlan& sp, long long tiles_cap) {
+  const Variant* v = sp.var;
+  const int T = v->tile;
+  const int nb = (sp.sys.n_orb + T - 1) / T;
+  const auto rounds = tile_rounds(nb);
+  const int br = bricks_per_tile(v);
+  int tpb = std::max(1, (4096 + br - 1) / br);
+  if (tiles_cap > 0) tpb = (int)std::min<long long>(tpb, tiles_cap);
+  size_t max_round = 0;
+  for (auto& r : rounds) max_round = std::max(max_round, r.size());
+  tpb = std::min<int>(tpb, (int)max_round);
+  sp.tiles_per_batch = tpb;
+  sp.slots_per_batch = tpb * T * (T / 2);
+  sp.tiles.clear();
+  sp.active.clear();
+  sp.batches.clear();
+  long long part = 0;
+  for (auto& round : rounds) {
+    for (size_t s = 0; s < round.size(); s += tpb) {
+      Batch b{};
+      b.tile_off = (int)sp.tiles.size();
+      b.active_off = (int)sp.active.size();
+      b.part_base = part;
+      const size_t e = std::min(round.size(), s + tpb);
+      for (size_t k = s; k < e; ++k) {
+        TileDesc td{};
+        const int bi = round[k].first, bj = round[k].second;
+        td.i0 = bi * T;
+        td.nI = std::min(T, sp.sys.n_orb - td.i0);
+        td.j0 = bj * T;
+        td.nJ = std::min(T, sp.sys.n_orb - td.j0);
+        td.diag = bi == bj ? 1 : 0;
+        td.slot0 = (int)(k - s) * T * (T / 2);
+        for (int ia = 0; ia < td.nI; ++ia)
+          for (int bp = 0; bp < T / 2; ++bp) {
+            const int b0 = 2 * bp;
+            if (b0 >= td.nJ) continue;
+            if (td.diag && b0 + 1 < ia) continue;
+            sp.active.push_back(td.slot0 + ia * (T / 2) + bp);
+          }
+        sp.tiles.push_back(td);
+      }
+      b.n_tiles = (int)sp.tiles.size() - b.tile_off;
+      b.n_active = (int)sp.active.size() - b.active_off;
+      part += (long long)b.n_tiles * br;
+      sp.batches.push_back(b);
+    }
+  }
+  sp.n_partials = part;
+}
+
+template <typename T>
+std::vector<T> kernel_table(const hfx_system& s, int n) {
+  const double pi = 3.14159265358979323846;
+  const double om = s.L[0] * s.L[1] * s.L[2];
+  const double nr = (double)n * n * n;
+  const double rc = std::cbrt(3.0 * om / (4.0 * pi));
+  std::vector<T> out((size_t)n * n * n);
+  auto freq = [n](int k) { return k < (n + 1) / 2 ? k : k - n; };
+  for (int z = 0; z < n; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        const double gx = 2 * pi * freq(x) / s.L[0];
+        const double gy = 2 * pi * freq(y) / s.L[1];
+        const double gz = 2 * pi * freq(z) / s.L[2];
+        const double g2 = gx * gx + gy * gy + gz * gz;
+        double v;
+        if (s.kernel == HFX_KERNEL_TRUNCATED) {
+          if (g2 == 0.0) {
+            v = 2 * pi * rc * rc;
+          } else {
+            const double sh = std::sin(0.5 * std::sqrt(g2) * rc);
+            v = 8 * pi * sh * sh / g2;
+          }
+        } else {
+          const double w = s.param;
+          v = g2 == 0.0 ? pi / (w * w) : -4 * pi * std::expm1(-g2 / (4 * w * w)) / g2;
+        }
+        out[((size_t)z * n + y) * n + x] = T(v / nr);
+      }
+  return out;
+}
+
+template <typename T>
+hfx_status upload(const std::vector<T>& h, void** d) {
+  HIP_TRY(hipMalloc(d, std::max<size_t>(h.size(), 1) * sizeof(T)));
+  if (!h.empty()) HIP_TRY(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return HFX_OK;
+}
+
+hfx_status upload_twiddles(const int* r, int nr_, int prec, void** d) {
+  const std::vector<double> t = twiddle_table(r, nr_);
+  if (prec == HFX_FP64) return upload(t, d);
+  std::vector<float> f(t.begin(), t.end());
+  return upload(f, d);
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+hfx_status validate_system(const hfx_system& s, int idx) {
+  const std::string at = " (system " + std::to_string(idx) + ")";
+  for (int k = 0; k < 3; ++k) {
+    if (s.n[k] <= 0) return fail(HFX_EINVAL, "grid size must be positive" + at);
+    if (!(s.L[k] > 0.0) || !std::isfinite(s.L[k]))
+      return fail(HFX_EINVAL, "box length must be positive and finite" + at);
+  }
+  if (s.n_orb < 1) return fail(HFX_EINVAL, "n_orb must be >= 1" + at);
+  if (s.kernel != HFX_KERNEL_TRUNCATED && s.kernel != HFX_KERNEL_ERFC)
+    return fail(HFX_EINVAL, "unknown kernel" + at);
+  if (s.kernel == HFX_KERNEL_ERFC && !(s.param > 0.0 && std::isfinite(s.param)))
+    return fail(HFX_EINVAL, "erfc kernel needs w > 0" + at);
+  if (s.n[0] != s.n[1] || s.n[1] != s.n[2])
+    return fail(HFX_EUNSUPPORTED, "only cubic grids n x n x n are supported" + at);
+  return HFX_OK;
+}
+
+void free_system(SystemPlan& sp) {
+  if (sp.vtab) (void)hipFree(sp.vtab);
+  for (auto& p : sp.tw)
+    if (p) (void)hipFree(p);
+  if (sp.d_tiles) (void)hipFree(sp.d_tiles);
+  if (sp.d_active) (void)hipFree(sp.d_active);
+  sp.vtab = nullptr;
+  for (auto& p : sp.tw) p = nullptr;
+  sp.d_tiles = nullptr;
+  sp.d_active = nullptr;
+}
+
+hfx_status check_call(hfx_plan plan, const void* psi, void* ws, size_t ws_bytes) {
+  if (!plan) return fail(HFX_EINVAL, "null plan");
+  if (!psi) return fail(HFX_EINVAL, "null psi");
+  if (!ws && plan->ws_bytes > 0) return fail(HFX_EINVAL, "null workspace");
+  if (ws_bytes < plan->ws_bytes)
+    return fail(HFX_ENOMEM, "workspace too small: need " + std::to_string(plan->ws_bytes) +
+                                " bytes, got " + std::to_string(ws_bytes));
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(HFX_EINVAL, "workspace must be 256-byte aligned");
+  return HFX_OK;
+}
+
+// Runs the pair pipeline of one system.  acc: accumulate K psi into kpsi.
+hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* kpsi, double* ex,
+                        char* ws, hipStream_t st, bool acc) {
+  const Variant* v = sp.var;
+  const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
+  const void* psi_w = psi;
+  if (plan->prec == HFX_FP32) {
+    float* p32 = reinterpret_cast<float*>(ws + sp.off_psi32);
+    launch_cast_f64_f32(psi, p32, (size_t)sp.sys.n_orb * sp.nr, st);
+    psi_w = p32;
+  }
+  if (acc) launch_zero(kpsi, (size_t)sp.sys.n_orb * sp.nr * elem, st);
+  double* partials = reinterpret_cast<double*>(ws + sp.off_partials);
+  PassArgs a{};
+  a.psi = psi_w;
+  a.kpsi = kpsi;
+  a.grids = ws + sp.off_grids;
+  a.vtab = sp.vtab;
+  a.tw_zf = sp.tw[0];
+  a.tw_zi = sp.tw[1];
+  a.tw_xf = sp.tw[2];
+  a.tw_xi = sp.tw[3];
+  a.tw_yf = sp.tw[4];
+  a.tw_yi = sp.tw[5];
+  a.partials = partials;
+  a.n_orb = sp.sys.n_orb;
+  const int br = bricks_per_tile(v);
+  const int n = v->n;
+  const int nxb = (n + v->brick - 1) / v->brick;
+  for (const Batch& b : sp.batches) {
+    a.tiles = sp.d_tiles + b.tile_off;
+    a.active = sp.d_active + b.active_off;
+    a.n_tiles = b.n_tiles;
+    a.n_active = b.n_active;
+    a.part_base = b.part_base;
+    v->pair_fwd(a, b.n_tiles * br, st);
+    if (v->plane_mode == 0) {
+      v->plane(a, b.n_active * n, st);
+    } else {
+      const int rb = (n * n + v->rows_per_wg - 1) / v->rows_per_wg;
+      v->rows_fwd(a, b.n_active * rb, st);
+      v->cols_conv(a, b.n_active * n * nxb, st);
+      v->rows_inv(a, b.n_active * rb, st);
+    }
+    if (acc)
+      v->inv_acc(a, b.n_tiles * br, st);
+    else
+      v->inv_energy(a, b.n_tiles * br, st);
+  }
+  if (ex) launch_energy_reduce(partials, sp.n_partials, -0.5 * sp.dv, ex, st);
+  HIP_TRY(hipGetLastError());
+  return HFX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hfx_status_string(hfx_status s) {
+  switch (s) {
+    case HFX_OK: return "HFX_OK";
+    case HFX_EINVAL: return "HFX_EINVAL: invalid argument";
+    case HFX_EUNSUPPORTED: return "HFX_EUNSUPPORTED: unsupported configuration";
+    case HFX_ENOMEM: return "HFX_ENOMEM: insufficient memory";
+    case HFX_EDEVICE: return "HFX_EDEVICE: HIP runtime error";
+  }
+  return "unknown hfx_status";
+}
+
+const char* hfx_last_error(void) { return g_last_error.c_str(); }
+
+hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int precision,
+                           const char* options) {
+  g_last_error.clear();
+  if (!out) return fail(HFX_EINVAL, "null output plan pointer");
+  *out = nullptr;
+  if (!sys) return fail(HFX_EINVAL, "null system array");
+  if (n_sys < 1) return fail(HFX_EINVAL, "n_sys must be >= 1");
+  if (precision != HFX_FP32 && precision != HFX_FP64)
+    return fail(HFX_EINVAL, "precision must be HFX_FP32 or HFX_FP64");
+  for (int i = 0; i < n_sys; ++i) {
+    hfx_status s = validate_system(sys[i], i);
+    if (s != HFX_OK) return s;
+    if (!find_variant(sys[i].n[0], precision))
+      return fail(HFX_EUNSUPPORTED, "grid size " + std::to_string(sys[i].n[0]) +
+                                        " is not supported (system " + std::to_string(i) +
+                                        ")");
+  }
+  const long long tiles_cap = parse_option(options, "tiles", 0);
+  long long ws_cap = parse_option(options, "maxws", 0);
+  if (const char* env = std::getenv("HFX_MAX_WORKSPACE_BYTES")) {
+    const long long e = std::atoll(env);
+    if (e > 0) ws_cap = ws_cap > 0 ? std::min(ws_cap, e) : e;
+  }
+
+  hfx_plan p = new hfx_plan_t();
+  p->prec = precision;
+  p->sys.resize(n_sys);
+  size_t off = 0;
+  long long psi_off = 0, m_off = 0;
+  const size_t elem = precision == HFX_FP64 ? 8 : 4;
+  for (int i = 0; i < n_sys; ++i) {
+    SystemPlan& sp = p->sys[i];
+    sp.sys = sys[i];
+    sp.var = find_variant(sys[i].n[0], precision);
+    sp.n = sys[i].n[0];
+    sp.nr = (long long)sp.n * sp.n * sp.n;
+    sp.dv = sys[i].L[0] * sys[i].L[1] * sys[i].L[2] / (double)sp.nr;
+    build_schedule(sp, tiles_cap);
+    sp.psi_off = psi_off;
+    sp.m_off = m_off;
+    psi_off += (long long)sys[i].n_orb * sp.nr;
+    m_off += (long long)sys[i].n_orb * sys[i].n_orb;
+    sp.gemm_chunks = gemm_chunks(sys[i].n_orb, sp.nr);
+    // workspace layout of this system
+    sp.off_psi32 = off;
+    if (precision == HFX_FP32) off = align_up(off + (size_t)sys[i].n_orb * sp.nr * 4);
+    sp.off_grids = off;
+    off = align_up(off + (size_t)sp.slots_per_batch * sp.nr * 2 * elem);
+    sp.off_partials = off;
+    off = align_up(off + (size_t)sp.n_partials * 8);
+    sp.off_gemm = off;
+    const int tiles = (sys[i].n_orb + 63) / 64;
+    off = align_up(off + (size_t)tiles * tiles * sp.gemm_chunks * 64 * 64 * 8);
+    sp.off_grad = off;
+    if (precision == HFX_FP32) off = align_up(off + (size_t)sys[i].n_orb * sp.nr * 4);
+    sp.off_ortho = off;
+    off = align_up(off + (size_t)6 * sys[i].n_orb * sys[i].n_orb * 8 + 64);
+    off = align_up(off + (size_t)sys[i].n_orb * std::min<long long>(sp.nr, 32768) * 8);
+    sp.ws_end = off;
+  }
+  p->ws_bytes = off;
+  if (ws_cap > 0 && (long long)p->ws_bytes > ws_cap) {
+    const size_t need = p->ws_bytes;
+    delete p;
+    return fail(HFX_ENOMEM, "workspace of " + std::to_string(need) +
+                                " bytes exceeds the configured cap " + std::to_string(ws_cap));
+  }
+
+  auto cleanup = [&](hfx_status s) {
+    for (auto& sp : p->sys) free_system(sp);
+    delete p;
+    return s;
+  };
+  if (hipGetDevice(&p->device) != hipSuccess)
+    return cleanup(fail(HFX_EDEVICE, "no HIP device available"));
+  for (auto& sp : p->sys) {
+    hfx_status s;
+    if (sp.var->prepare) {
+      hipError_t e = sp.var->prepare();
+      if (e != hipSuccess)
+        return cleanup(fail(HFX_EDEVICE, std::string("kernel set-up: ") + hipGetErrorString(e)));
+    }
+    if (precision == HFX_FP64)
+      s = upload(kernel_table<double>(sp.sys, sp.n), &sp.vtab);
+    else
+      s = upload(kernel_table<float>(sp.sys, sp.n), &sp.vtab);
+    if (s != HFX_OK) return cleanup(s);
+    const Variant* v = sp.var;
+    const int* rs[6] = {v->zf, v->zi, v->xf, v->xi, v->yf, v->yi};
+    const int cs[6] = {v->nzf, v->nzi, v->nxf, v->nxi, v->nyf, v->nyi};
+    for (int k = 0; k < 6; ++k) {
+      s = upload_twiddles(rs[k], cs[k], precision, &sp.tw[k]);
+      if (s != HFX_OK) return cleanup(s);
+    }
+    void* d = nullptr;
+    s = upload(sp.tiles, &d);
+    if (s != HFX_OK) return cleanup(s);
+    sp.d_tiles = static_cast<TileDesc*>(d);
+    s = upload(sp.active, &d);
+    if (s != HFX_OK) return cleanup(s);
+    sp.d_active = static_cast<int*>(d);
+  }
+  *out = p;
+  return HFX_OK;
+}
+
+hfx_status hfx_plan_destroy(hfx_plan plan) {
+  if (!plan) return fail(HFX_EINVAL, "null plan");
+  const hipError_t e = hipDeviceSynchronize();
+  for (auto& sp : plan->sys) free_system(sp);
+  delete plan;
+  if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("pending device error: ") + hipGetErrorString(e));
+  return HFX_OK;
+}
+
+hfx_status hfx_workspace_size(hfx_plan plan, size_t* bytes) {
+  if (!plan) return fail(HFX_EINVAL, "null plan");
+  if (!bytes) return fail(HFX_EINVAL, "null output pointer");
+  *bytes = plan->ws_bytes;
+  return HFX_OK;
+}
+
+hfx_status hfx_exchange_energy(hfx_plan plan, const double* psi, double* ex, void* ws,
+                               size_t ws_bytes, void* stream) {
+  hfx_status s = check_call(plan, psi, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (!ex) return fail(HFX_EINVAL, "null ex");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (size_t i = 0; i < plan->sys.size(); ++i) {
+    SystemPlan& sp = plan->sys[i];
+    s = run_exchange(plan, sp, psi + sp.psi_off, nullptr, ex + i, static_cast<char*>(ws), st,
+                     false);
+    if (s != HFX_OK) return s;
+  }
+  return HFX_OK;
+}
+
+hfx_status hfx_apply_exchange(hfx_plan plan, const double* psi, void* kpsi, double* ex,
+                              void* ws, size_t ws_bytes, void* stream) {
+  hfx_status s = check_call(plan, psi, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (!kpsi) return fail(HFX_EINVAL, "null kpsi");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
+  for (size_t i = 0; i < plan->sys.size(); ++i) {
+    SystemPlan& sp = plan->sys[i];
+    void* kp = static_cast<char*>(kpsi) + (size_t)sp.psi_off * elem;
+    s = run_exchange(plan, sp, psi + sp.psi_off, kp, ex ? ex + i : nullptr,
+                     static_cast<char*>(ws), st, true);
+    if (s != HFX_OK) return s;
+  }
+  return HFX_OK;
+}
+
+hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double* gscale,
+                                 double* grad, void* ws, size_t ws_bytes, void* stream) {
+  hfx_status s = check_call(plan, psi, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (!grad) return fail(HFX_EINVAL, "null grad");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (size_t i = 0; i < plan->sys.size(); ++i) {
+    SystemPlan& sp = plan->sys[i];
+    double* g = grad + sp.psi_off;
+    void* kp = plan->prec == HFX_FP64 ? static_cast<void*>(g)
+                                      : static_cast<void*>(static_cast<char*>(ws) + sp.off_grad);
+    s = run_exchange(plan, sp, psi + sp.psi_off, kp, nullptr, static_cast<char*>(ws), st, true);
+    if (s != HFX_OK) return s;
+    launch_scale_to_f64(kp, plan->prec == HFX_FP64, g, (size_t)sp.sys.n_orb * sp.nr,
+                        2.0 * sp.dv, gscale ? gscale + i : nullptr, st);
+  }
+  HIP_TRY(hipGetLastError());
+  return HFX_OK;
+}
+
+hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, const void* kpsi, double* m,
+                               void* ws, size_t ws_bytes, void* stream) {
+  hfx_status s = check_call(plan, psi, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (!kpsi) return fail(HFX_EINVAL, "null kpsi");
+  if (!m) return fail(HFX_EINVAL, "null m");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
+  for (auto& sp : plan->sys) {
+    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + sp.off_gemm);
+    const char* kp = static_cast<const char*>(kpsi) + (size_t)sp.psi_off * elem;
+    if (plan->prec == HFX_FP32)
+      launch_xtx_split(psi + sp.psi_off, reinterpret_cast<const float*>(kp), sp.sys.n_orb, sp.nr,
+                       sp.dv, part, sp.gemm_chunks, m + sp.m_off, st);
+    else
+      launch_xtx_f64(psi + sp.psi_off, reinterpret_cast<const double*>(kp), sp.sys.n_orb, sp.nr,
+                     sp.dv, part, sp.gemm_chunks, m + sp.m_off, st);
+  }
+  HIP_TRY(hipGetLastError());
+  return HFX_OK;
+}
+
+hfx_status hfx_orthonormalize(hfx_plan plan, double* psi, int method, void* ws, size_t ws_bytes,
+                              void* stream) {
+  hfx_status s = check_call(plan, psi, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (method != HFX_ORTHO_LOWDIN) return fail(HFX_EUNSUPPORTED, "only Loewdin is implemented");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (auto& sp : plan->sys) {
+    const int n = sp.sys.n_orb;
+    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + sp.off_gemm);
+    double* work = reinterpret_cast<double*>(static_cast<char*>(ws) + sp.off_ortho);
+    double* smat = work;  // n x n overlap, replaced by S^(-1/2)
+    double* ns_work = work + (size_t)n * n;  // 5 n^2 doubles + flags
+    double* tmp = reinterpret_cast<double*>(
+        static_cast<char*>(ws) + align_up(sp.off_ortho + (size_t)6 * n * n * 8 + 64));
+    double* p = psi + sp.psi_off;
+    launch_xtx_f64(p, p, n, sp.nr, sp.dv, part, sp.gemm_chunks, smat, st);
+    HIP_TRY(launch_inverse_sqrt(smat, n, ns_work, 60, st));
+    launch_apply_left(smat, p, n, sp.nr, tmp, st);
+  }
+  HIP_TRY(hipGetLastError());
+  return HFX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal interface between the host-side plan (hfx_api.cpp) and the
+// templated HIP kernels (exchange_*.hip, gemm.hip).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace hfx {
+
+// One orbital tile: pairs (a, b) with a in [i0, i0+nI) and b in [j0, j0+nJ).
+// Off-diagonal tiles (diag == 0, disjoint blocks) take every (a, b); diagonal
+// tiles (the same block twice) take a <= b.  Packed pair-grid slot of
+// (a - i0, b - j0) is slot0 + (a - i0) * (tile / 2) + (b - j0) / 2: the two
+// pairs (a, 2p) and (a, 2p+1) share one complex grid (real and imaginary part).
+struct TileDesc {
+  int i0, nI, j0, nJ, diag, slot0;
+};
+
+// Arguments of one exchange pass over one batch of tiles of one system.
+struct PassArgs {
+  const void* psi;        // [n_orb][N^3] orbitals in the working precision
+  void* kpsi;             // [n_orb][N^3] K psi accumulators (working precision)
+  void* grids;            // [slots][N^3] complex pair grids
+  const TileDesc* tiles;  // tiles of this batch
+  const int* active;      // grid slots that carry at least one pair
+  const void* vtab;       // v(G) / N_r, [kz][ky][kx]
+  const void* tw_zf;      // twiddle tables (see twiddle.hpp) per axis/direction
+  const void* tw_zi;
+  const void* tw_xf;
+  const void* tw_xi;
+  const void* tw_yf;
+  const void* tw_yi;
+  double* partials;       // per-workgroup energy partial sums
+  long long part_base;    // first partial of this launch
+  int n_orb;
+  int n_tiles;
+  int n_active;
+};
+
+typedef void (*launch_fn)(const PassArgs&, int nblocks, hipStream_t);
+
+// One compiled configuration of the exchange pipeline for a grid size and
+// precision: radix schedules, launch shapes and the launchers.
+struct Variant {
+  const char* name;
+  int n;           // grid points per axis
+  int prec;        // 0 float32, 1 float64
+  int brick;       // pencil width W (x values per workgroup)
+  int tile;        // orbital tile T
+  int nt_pencil;   // threads per pencil workgroup
+  int nt_plane;    // threads per plane workgroup (or per row/column workgroup)
+  int plane_mode;  // 0: fused xy plane in LDS; 1: x rows + y columns passes
+  int rows_per_wg; // plane_mode 1: rows per row-FFT workgroup
+  int zf[4], nzf, zi[4], nzi;  // z radix schedules (forward, inverse)
+  int xf[4], nxf, xi[4], nxi;  // x
+  int yf[4], nyf, yi[4], nyi;  // y
+  size_t plane_lds;            // dynamic LDS bytes of the plane/row kernels
+  launch_fn pair_fwd;          // pair product + forward z FFT
+  launch_fn plane;             // plane_mode 0: x/y forward, * v, y/x inverse
+  launch_fn rows_fwd;          // plane_mode 1: forward x FFT on rows
+  launch_fn cols_conv;         // plane_mode 1: y forward, * v, y inverse
+  launch_fn rows_inv;          // plane_mode 1: inverse x FFT on rows
+  launch_fn inv_acc;           // inverse z FFT + energy + K psi accumulation
+  launch_fn inv_energy;        // inverse z FFT + energy only
+  hipError_t (*prepare)();     // raise dynamic-LDS limits of the kernels
+};
+
+const Variant* variants_f32(int* count);
+const Variant* variants_f64(int* count);
+
+// Elementwise helpers (exchange_common.hip)
+void launch_cast_f64_f32(const double* in, float* out, size_t n, hipStream_t s);
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+// grad[i] = scale * gscale[0 or nothing] * src[i] (src float32 or float64, in place allowed
+// for float64)
+void launch_scale_to_f64(const void* src, int src_is_f64, double* dst, size_t n, double scale,
+                         const double* gscale, hipStream_t s);
+void launch_energy_reduce(const double* partials, long long n, double scale, double* out,
+                          hipStream_t s);
+
+// Dense products (gemm.hip)
+// C[k][l] = alpha * sum_r A[k][r] B[l][r], A float64 split into hi + lo
+// float32 parts, B float32, float32 MFMA with float64 accumulation across
+// k-blocks; partials then reduced in a fixed order.
+void launch_xtx_split(const double* a, const float* b, int n_orb, long long nr, double alpha,
+                      double* partial, int n_chunks, double* c, hipStream_t s);
+// C = alpha * A B^T with A, B float64 [n][nr] (float64 MFMA)
+void launch_xtx_f64(const double* a, const double* b, int n_orb, long long nr, double alpha,
+                    double* partial, int n_chunks, double* c, hipStream_t s);
+int gemm_chunks(int n_orb, long long nr);
+
+// Orthonormalisation helpers (ortho.hip)
+hipError_t launch_inverse_sqrt(double* s, int n, double* work, int max_iter, hipStream_t st);
+void launch_apply_left(const double* m, double* psi, int n, long long nr, double* tmp,
+                       hipStream_t st);
+
+}  // namespace hfx

@@ -1,0 +1,200 @@
+// Host emulation of the workgroup FFT engine: every Stage read / compute /
+// write of the device code runs here on the CPU, thread by thread, phase by
+// phase, and the result is compared with a naive O(N^2) DFT in float64.
+// It also checks the fused "forward, pointwise multiply, inverse" hand-off in
+// registers that the plane and pencil kernels use.
+//
+// Build: hipcc -std=c++17 -O1 tests/native/fft_engine_check.hip -o <exe>
+// (host code only; no GPU is needed to run it).  Exit status 0 on success.
+#include <array>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <random>
+#include <vector>
+
+#include "../../paper_2309_00651_amd/csrc/fft.hpp"
+#include "../../paper_2309_00651_amd/csrc/twiddle.hpp"
+
+using namespace hfx;
+
+template <typename T>
+std::vector<cpx<T>> make_tw(const std::vector<int>& radices) {
+  std::vector<double> t = twiddle_table(radices.data(), (int)radices.size());
+  std::vector<cpx<T>> out(t.size() / 2);
+  for (size_t i = 0; i < out.size(); ++i) out[i] = {T(t[2 * i]), T(t[2 * i + 1])};
+  return out;
+}
+
+// emulated stages 1..end (mirror of fft_tail)
+template <class G, bool INV, int NS, int TWOFF, int R, int... Rest>
+void host_tail(std::vector<cpx<typename G::T>>& lds, const cpx<typename G::T>* tw,
+               std::vector<std::vector<cpx<typename G::T>>>& out) {
+  using T = typename G::T;
+  using St = Stage<G, R, NS>;
+  std::vector<std::vector<cpx<T>>> v(G::NT, std::vector<cpx<T>>(St::VALS));
+  for (int t = 0; t < G::NT; ++t) St::read(v[t].data(), lds.data(), t);
+  for (int t = 0; t < G::NT; ++t) St::template compute<INV>(v[t].data(), t, tw + TWOFF);
+  if constexpr (sizeof...(Rest) > 0) {
+    for (int t = 0; t < G::NT; ++t) St::write(v[t].data(), lds.data(), t);
+    host_tail<G, INV, NS * R, TWOFF + NS * (R - 1), Rest...>(lds, tw, out);
+  } else {
+    out = v;
+  }
+}
+
+template <class G, bool INV, class S>
+struct HostFFT;
+template <class G, bool INV, int R0, int... Rest>
+struct HostFFT<G, INV, Sched<R0, Rest...>> {
+  using T = typename G::T;
+  static void reg2reg(std::vector<std::vector<cpx<T>>>& v, std::vector<cpx<T>>& lds,
+                      const cpx<T>* tw, std::vector<std::vector<cpx<T>>>& out) {
+    using F = Stage<G, R0, 1>;
+    for (int t = 0; t < G::NT; ++t) F::template compute<INV>(v[t].data(), t, tw);
+    if constexpr (sizeof...(Rest) == 0) {
+      out = v;
+    } else {
+      for (int t = 0; t < G::NT; ++t) F::write(v[t].data(), lds.data(), t);
+      host_tail<G, INV, R0, 0, Rest...>(lds, tw, out);
+    }
+  }
+};
+
+template <class S>
+std::vector<int> radices_of() {
+  std::vector<int> r;
+  for (int i = 0; i < SchedInfo<S>::count; ++i) r.push_back(SchedInfo<S>::radices[i]);
+  return r;
+}
+
+static int g_fail = 0;
+
+// Forward transform of M random sequences, then (optionally) a pointwise
+// multiply by a real even-free table and the inverse with schedule SI, all
+// handed over in registers; compare with naive DFTs in float64.
+template <typename T, int N, int M, int NT, bool MFAST, class SF, class SI>
+void check(const char* name, double tol) {
+  constexpr int ES = MFAST ? M : 1;
+  constexpr int TS = MFAST ? 1 : N + 1;  // padded rows when j-fastest
+  using G = Geom<T, N, M, NT, MFAST, ES, TS>;
+  using F = FirstStage<G, SF>;
+  using L = LastStage<G, SF>;
+  using FI = FirstStage<G, SI>;
+  using LI = LastStage<G, SI>;
+  static_assert(SchedInfo<SF>::product == N && SchedInfo<SI>::product == N, "schedule");
+  std::mt19937_64 rng(1234 + N * 7 + M);
+  std::normal_distribution<double> nd;
+  std::vector<std::complex<double>> x(M * N), mult(M * N);
+  for (auto& z : x) z = {nd(rng), nd(rng)};
+  for (auto& z : mult) z = {0.5 + std::fabs(nd(rng)), 0.0};
+  const int lds_size = M * TS > N * ES ? (M * TS + N * ES) : (N * ES + M * TS);
+  std::vector<cpx<T>> lds(lds_size + 64);
+  auto twf = make_tw<T>(radices_of<SF>());
+  auto twi = make_tw<T>(radices_of<SI>());
+  // stage-0 inputs
+  std::vector<std::vector<cpx<T>>> v(NT, std::vector<cpx<T>>(F::VALS));
+  for (int t = 0; t < NT; ++t)
+    for (int i = 0; i < F::PER; ++i) {
+      if (!F::valid(t, i)) continue;
+      int m, j;
+      F::mj(t, i, m, j);
+      for (int r = 0; r < SchedInfo<SF>::first; ++r) {
+        auto z = x[m * N + F::in_pos(j, r)];
+        v[t][i * SchedInfo<SF>::first + r] = {T(z.real()), T(z.imag())};
+      }
+    }
+  std::vector<std::vector<cpx<T>>> out;
+  HostFFT<G, false, SF>::reg2reg(v, lds, twf.data(), out);
+  // naive forward DFT
+  std::vector<std::complex<double>> X(M * N);
+  const double pi = 3.14159265358979323846;
+  for (int m = 0; m < M; ++m)
+    for (int k = 0; k < N; ++k) {
+      std::complex<double> s = 0;
+      for (int n = 0; n < N; ++n) s += x[m * N + n] * std::polar(1.0, -2 * pi * double(n) * k / N);
+      X[m * N + k] = s;
+    }
+  double err = 0, scale = 0;
+  for (int t = 0; t < NT; ++t)
+    for (int i = 0; i < L::PER; ++i) {
+      if (!L::valid(t, i)) continue;
+      int m, j;
+      L::mj(t, i, m, j);
+      for (int r = 0; r < SchedInfo<SF>::last; ++r) {
+        const int k = j + r * (N / SchedInfo<SF>::last);
+        auto got = out[t][i * SchedInfo<SF>::last + r];
+        err = std::fmax(err, std::abs(std::complex<double>(got.re, got.im) - X[m * N + k]));
+        scale = std::fmax(scale, std::abs(X[m * N + k]));
+      }
+    }
+  // fused multiply then inverse: requires identical element maps
+  static_assert(SchedInfo<SI>::first == SchedInfo<SF>::last, "fusion radix");
+  static_assert(FI::VALS == L::VALS, "fusion register count");
+  for (int t = 0; t < NT; ++t)
+    for (int i = 0; i < L::PER; ++i) {
+      if (!L::valid(t, i)) continue;
+      int m, j;
+      L::mj(t, i, m, j);
+      for (int r = 0; r < SchedInfo<SF>::last; ++r) {
+        const int k = j + r * (N / SchedInfo<SF>::last);
+        auto& o = out[t][i * SchedInfo<SF>::last + r];
+        const T f = T(mult[m * N + k].real());
+        o = {o.re * f, o.im * f};
+      }
+    }
+  std::vector<std::vector<cpx<T>>> back;
+  HostFFT<G, true, SI>::reg2reg(out, lds, twi.data(), back);
+  double err2 = 0, scale2 = 0;
+  std::vector<std::complex<double>> Y(M * N);
+  for (int m = 0; m < M; ++m)
+    for (int n = 0; n < N; ++n) {
+      std::complex<double> s = 0;
+      for (int k = 0; k < N; ++k)
+        s += X[m * N + k] * mult[m * N + k] * std::polar(1.0, 2 * pi * double(n) * k / N);
+      Y[m * N + n] = s;
+    }
+  for (int t = 0; t < NT; ++t)
+    for (int i = 0; i < LI::PER; ++i) {
+      if (!LI::valid(t, i)) continue;
+      int m, j;
+      LI::mj(t, i, m, j);
+      for (int r = 0; r < SchedInfo<SI>::last; ++r) {
+        const int n = j + r * (N / SchedInfo<SI>::last);
+        auto got = back[t][i * SchedInfo<SI>::last + r];
+        err2 = std::fmax(err2, std::abs(std::complex<double>(got.re, got.im) - Y[m * N + n]));
+        scale2 = std::fmax(scale2, std::abs(Y[m * N + n]));
+      }
+    }
+  const double rel = err / scale, rel2 = err2 / scale2;
+  const bool ok = rel <= tol && rel2 <= tol;
+  if (!ok) g_fail++;
+  std::printf("%-34s fwd rel %.2e  conv rel %.2e  %s\n", name, rel, rel2, ok ? "ok" : "FAIL");
+}
+
+int main() {
+  // float64: rounding-level agreement
+  check<double, 24, 16, 64, true, Sched<4, 6>, Sched<6, 4>>("f64 N24 pencil (4,6)", 1e-13);
+  check<double, 64, 16, 64, true, Sched<8, 8>, Sched<8, 8>>("f64 N64 pencil (8,8)", 1e-13);
+  check<double, 72, 16, 64, true, Sched<8, 9>, Sched<9, 8>>("f64 N72 pencil (8,9)", 1e-13);
+  check<double, 80, 16, 64, true, Sched<4, 4, 5>, Sched<5, 4, 4>>("f64 N80 pencil (4,4,5)", 1e-13);
+  check<double, 96, 16, 64, true, Sched<8, 12>, Sched<12, 8>>("f64 N96 pencil (8,12)", 1e-13);
+  check<double, 96, 8, 64, true, Sched<6, 4, 4>, Sched<4, 4, 6>>("f64 N96 pencil (6,4,4)", 1e-13);
+  check<double, 108, 16, 64, true, Sched<12, 9>, Sched<9, 12>>("f64 N108 pencil (12,9)", 1e-13);
+  check<double, 120, 16, 64, true, Sched<2, 6, 10>, Sched<10, 6, 2>>("f64 N120 pencil (2,6,10)", 1e-13);
+  check<double, 120, 8, 64, true, Sched<8, 15>, Sched<15, 8>>("f64 N120 pencil (8,15)", 1e-13);
+  check<double, 128, 16, 64, true, Sched<8, 16>, Sched<16, 8>>("f64 N128 pencil (8,16)", 1e-13);
+  check<double, 96, 96, 384, false, Sched<8, 12>, Sched<12, 8>>("f64 N96 rows (8,12)", 1e-13);
+  check<double, 128, 128, 512, false, Sched<8, 16>, Sched<16, 8>>("f64 N128 rows (8,16)", 1e-13);
+  check<double, 120, 120, 256, false, Sched<10, 12>, Sched<12, 10>>("f64 N120 rows (10,12)", 1e-13);
+  check<double, 16, 4, 64, false, Sched<16>, Sched<16>>("f64 N16 rows single stage", 1e-13);
+  check<double, 30, 4, 64, false, Sched<2, 3, 5>, Sched<5, 3, 2>>("f64 N30 rows (2,3,5)", 1e-13);
+  check<double, 90, 4, 64, true, Sched<10, 9>, Sched<9, 10>>("f64 N90 pencil (10,9)", 1e-13);
+  check<double, 60, 4, 64, true, Sched<15, 4>, Sched<4, 15>>("f64 N60 pencil (15,4)", 1e-13);
+  // float32: a few units of rounding
+  check<float, 96, 16, 64, true, Sched<8, 12>, Sched<12, 8>>("f32 N96 pencil (8,12)", 1e-6);
+  check<float, 128, 128, 512, false, Sched<8, 16>, Sched<16, 8>>("f32 N128 rows (8,16)", 1e-6);
+  check<float, 120, 16, 64, true, Sched<2, 6, 10>, Sched<10, 6, 2>>("f32 N120 pencil (2,6,10)", 1e-6);
+  std::printf("%s\n", g_fail ? "FAILED" : "ALL OK");
+  return g_fail ? 1 : 0;
+}

@@ -1,0 +1,216 @@
+"""Parity of the HIP path (through the C ABI) with the float64 CPU oracle.
+
+Bars: float32 plans |dE_x|/|E_x| <= 1e-7 and max|dK psi| <= 1e-5 (atomic
+units); float64 plans |dE_x|/|E_x| <= 1e-12 and max|dK psi| <= 1e-10 max|K psi|.
+Exchange matrix: |dM_kl| <= ||psi_k|| ||dK psi_l|| <= sqrt(Omega) max|dK psi|
+(Cauchy-Schwarz in the grid inner product) with the K psi bar above, plus
+E_x = tr(M)/2 to the energy bar.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import generate
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2309_00651_amd import hfx  # noqa: E402
+
+TOL = {hfx.FP32: dict(e=1e-7, k_abs=1e-5, k_rel=None),
+       hfx.FP64: dict(e=1e-12, k_abs=None, k_rel=1e-10)}
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def make_inputs(n, L, n_orb, family, seed):
+    shape, box = (n, n, n), (L, L, L)
+    if family == "pw":
+        return generate.random_pw(shape, box, n_orb, 5.0, seed)
+    return generate.gaussians(shape, box, n_orb, 20.0 if n >= 64 else 5.0, seed)[0]
+
+
+def oracle_run(psi, L, kernel, param):
+    box = (L, L, L)
+    vg = oracle.coulomb_kernel(psi.shape[1:], box, kernel, param)
+    return oracle.exchange(psi, box, vg)
+
+
+def gpu_run(psi, L, kernel, param, prec, options=None):
+    dev = _dev()
+    n, n_orb = psi.shape[-1], psi.shape[0]
+    plan = hfx.Plan(hfx.SystemSpec(n, (L, L, L), n_orb, kernel, param), prec, options, dev)
+    pt = torch.from_numpy(np.ascontiguousarray(psi)).to(dev)
+    kpsi, ex = plan.apply_exchange(pt)
+    m = plan.exchange_matrix(pt, kpsi)
+    e_only = plan.exchange_energy(pt)
+    torch.cuda.synchronize()
+    return dict(plan=plan, psi=pt, kpsi=kpsi.double().cpu().numpy(), ex=float(ex[0]),
+                e_only=float(e_only[0]), m=m.view(n_orb, n_orb).cpu().numpy())
+
+
+def check(ref, got, prec, L, psi):
+    t = TOL[prec]
+    rel = abs(got["ex"] - ref["ex"]) / abs(ref["ex"])
+    dk = np.max(np.abs(got["kpsi"] - ref["kpsi"]))
+    kmax = np.max(np.abs(ref["kpsi"]))
+    print(f"  rel dE {rel:.2e}  max dK {dk:.2e} (max K {kmax:.2e})", flush=True)
+    assert rel <= t["e"], rel
+    if t["k_abs"] is not None:
+        assert dk <= t["k_abs"], dk
+    else:
+        assert dk <= t["k_rel"] * kmax, dk
+    # energy-only entry point gives the same energy
+    assert abs(got["e_only"] - got["ex"]) <= 1e-13 * abs(got["ex"])
+    # exchange matrix
+    dv = L ** 3 / psi[0].size
+    m_ref = oracle.exchange_matrix(psi, ref["kpsi"], dv)
+    dm = np.max(np.abs(got["m"] - m_ref))
+    kbar = t["k_abs"] if t["k_abs"] is not None else t["k_rel"] * kmax
+    norms = np.sqrt(dv * np.sum(psi.reshape(len(psi), -1) ** 2, axis=1))
+    assert dm <= norms.max() * math.sqrt(L ** 3) * kbar + 1e-12, dm
+    assert abs(0.5 * np.trace(got["m"]) - got["ex"]) <= 2 * t["e"] * abs(got["ex"])
+
+
+# every compiled grid size, both precisions, both kernels
+VARIANTS = [(24, 10.0, 5, "pw", hfx.TRUNCATED, 0.0), (64, 12.0, 3, "g", hfx.ERFC, 0.106),
+            (72, 17.6, 3, "g", hfx.ERFC, 0.106), (80, 19.6, 3, "g", hfx.TRUNCATED, 0.0),
+            (96, 23.5, 3, "g", hfx.ERFC, 0.106), (108, 26.4, 2, "g", hfx.TRUNCATED, 0.0),
+            (120, 29.4, 2, "g", hfx.ERFC, 0.106), (128, 29.6, 2, "g", hfx.TRUNCATED, 0.0)]
+
+
+@pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("n,L,n_orb,fam,kernel,param", VARIANTS,
+                         ids=[f"n{v[0]}" for v in VARIANTS])
+def test_grid_variants(n, L, n_orb, fam, kernel, param, prec):
+    psi = make_inputs(n, L, n_orb, fam, seed=1000 + n)
+    print(f"case n={n} n_orb={n_orb} prec={prec}", flush=True)
+    ref = oracle_run(psi, L, kernel, param)
+    got = gpu_run(psi, L, kernel, param, prec)
+    check(ref, got, prec, L, psi)
+
+
+# tile coverage: single orbital, ragged blocks, odd and even block counts
+@pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("n_orb", [1, 2, 7, 9, 16, 17, 21])
+def test_tiles_and_ragged_tails(n_orb, prec):
+    psi = make_inputs(24, 10.0, n_orb, "pw", seed=77 + n_orb)
+    print(f"case n=24 n_orb={n_orb} prec={prec}", flush=True)
+    ref = oracle_run(psi, 10.0, hfx.TRUNCATED, 0.0)
+    got = gpu_run(psi, 10.0, hfx.TRUNCATED, 0.0, prec)
+    check(ref, got, prec, 10.0, psi)
+
+
+def test_several_tiles_per_batch_and_batches():
+    """n=64 with 20 orbitals: 3 blocks, 3 rounds; tiles=1 forces one tile per batch."""
+    psi = make_inputs(64, 12.0, 20, "g", seed=5)
+    ref = oracle_run(psi, 12.0, hfx.ERFC, 0.106)
+    a = gpu_run(psi, 12.0, hfx.ERFC, 0.106, hfx.FP32)
+    b = gpu_run(psi, 12.0, hfx.ERFC, 0.106, hfx.FP32, options="tiles=1")
+    check(ref, a, hfx.FP32, 12.0, psi)
+    check(ref, b, hfx.FP32, 12.0, psi)
+
+
+def test_bitwise_repeatable():
+    psi = make_inputs(64, 12.0, 12, "g", seed=6)
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec(64, (12.0,) * 3, 12, hfx.ERFC, 0.106), hfx.FP32, device=dev)
+    pt = torch.from_numpy(psi).to(dev)
+    k1, e1 = plan.apply_exchange(pt)
+    k1 = k1.clone()
+    e1 = e1.clone()
+    k2, e2 = plan.apply_exchange(pt)
+    torch.cuda.synchronize()
+    assert torch.equal(k1, k2) and torch.equal(e1, e2)
+
+
+def test_tiny_workload_orthonormalised():
+    """Workload 1 end to end: raw orbitals -> Loewdin on each side -> exchange."""
+    from workloads import configs
+    s = configs.TINY24
+    psi = s.orbitals()
+    dv = 1000.0 / 24 ** 3
+    psi_o, _ = oracle.lowdin(psi, dv)
+    ref = oracle_run(psi_o, s.L, s.kernel, s.param)
+    dev = _dev()
+    for prec in (hfx.FP32, hfx.FP64):
+        plan = hfx.Plan(hfx.SystemSpec(s.n, s.box, s.n_orb, s.kernel, s.param), prec, device=dev)
+        pt = torch.from_numpy(psi).to(dev)
+        plan.orthonormalize(pt)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(pt.cpu().numpy() - psi_o)) <= 1e-12
+        kpsi, ex = plan.apply_exchange(pt)
+        m = plan.exchange_matrix(pt, kpsi)
+        torch.cuda.synchronize()
+        got = dict(kpsi=kpsi.double().cpu().numpy(), ex=float(ex[0]),
+                   e_only=float(plan.exchange_energy(pt)[0]),
+                   m=m.view(s.n_orb, s.n_orb).cpu().numpy())
+        check(ref, got, prec, s.L, psi_o)
+
+
+def test_orthonormalize_matches_oracle_lowdin():
+    psi = make_inputs(24, 10.0, 13, "pw", seed=3)
+    rng = np.random.default_rng(4)
+    psi = psi + 0.3 * rng.standard_normal(psi.shape) * 0.05
+    dv = 1000.0 / 24 ** 3
+    ref, lam = oracle.lowdin(psi, dv)
+    assert lam > 1e-3
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec(24, (10.0,) * 3, 13), hfx.FP64, device=dev)
+    pt = torch.from_numpy(psi).to(dev)
+    plan.orthonormalize(pt)
+    torch.cuda.synchronize()
+    got = pt.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+    s = oracle.overlap(got, dv)
+    assert np.max(np.abs(s - np.eye(13))) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
+def test_gradient_entry_point(prec):
+    psi = make_inputs(24, 10.0, 6, "pw", seed=8)
+    ref = oracle_run(psi, 10.0, hfx.ERFC, 0.3)
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec(24, (10.0,) * 3, 6, hfx.ERFC, 0.3), prec, device=dev)
+    pt = torch.from_numpy(psi).to(dev)
+    gs = torch.tensor([0.75], dtype=torch.float64, device=dev)
+    g = plan.exchange_gradient(pt, gscale=gs)
+    torch.cuda.synchronize()
+    dv = 1000.0 / 24 ** 3
+    want = 2 * dv * 0.75 * ref["kpsi"]
+    tol = 2 * dv * 0.75 * (1e-5 if prec == hfx.FP32 else 1e-10 * np.max(np.abs(ref["kpsi"])))
+    assert np.max(np.abs(g.cpu().numpy() - want)) <= tol
+
+
+def test_autograd_function_matches_oracle_gradient():
+    psi = make_inputs(24, 10.0, 5, "pw", seed=9)
+    ref = oracle_run(psi, 10.0, hfx.TRUNCATED, 0.0)
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec(24, (10.0,) * 3, 5), hfx.FP32, device=dev)
+    pt = torch.from_numpy(psi).to(dev).requires_grad_(True)
+    e = hfx.ExchangeEnergy.apply(pt, plan)
+    (2.0 * e.sum()).backward()
+    torch.cuda.synchronize()
+    dv = 1000.0 / 24 ** 3
+    assert abs(float(e[0]) - ref["ex"]) <= 1e-7 * abs(ref["ex"])
+    assert np.max(np.abs(pt.grad.cpu().numpy() - 2 * 2 * dv * ref["kpsi"])) <= 4 * dv * 1e-5
+
+
+def test_workspace_too_small_is_rejected():
+    import ctypes
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec(24, (10.0,) * 3, 3), hfx.FP32, device=dev)
+    pt = torch.zeros((3, 24, 24, 24), dtype=torch.float64, device=dev)
+    ex = torch.zeros(1, dtype=torch.float64, device=dev)
+    ws = plan.workspace()
+    lib = hfx.load_library()
+    st = lib.hfx_exchange_energy(plan._h, ctypes.c_void_p(pt.data_ptr()),
+                                 ctypes.c_void_p(ex.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                 plan.ws_bytes - 1, ctypes.c_void_p(0))
+    assert st == 3 and "workspace too small" in lib.hfx_last_error().decode()
