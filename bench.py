@@ -1,0 +1,213 @@
+#!/usr/bin/env python
+"""Benchmark: pair-exchange evaluations per second on one MI355X.
+
+Workload (default ``water96``): cubic box L = 23.5 bohr, 96^3 grid, 256
+localised Gaussian orbitals band-limited to 20 Ha, erfc-screened kernel
+w = 0.106 bohr^-1 -- a synthetic stand-in for the paper's 64-water-like
+condensed-phase boxes.  One step is one SCF step's exchange work on the GPU:
+Loewdin orthonormalisation (float64), K psi for all 32,896 orbital pairs with
+E_x (float32 FFT path), and the exchange matrix M = dV Psi^T (K Psi).
+
+Prints one JSON line.  ``value`` = pairs / second of the whole step.  The
+``roofline`` object is measured live with HIP events around every launch of
+the dominant pass during the timed steps; ``cpu_baseline`` times the float64
+CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-exchange evals/s and K-psi time per SCF step, FP32 vs FP64 at fixed dE_x"
+HBM_PEAK_GBS = 8000.0
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def traffic_from_profiles(kernel_pass, workload):
+    """HBM bytes per launch measured by rocprofv3 counters, if recorded."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_pass}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(system, psi, seconds_target=15.0):
+    """Time the float64 oracle on a subset of orbitals of the same workload."""
+    import numpy as np
+
+    import oracle
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    vg = oracle.coulomb_kernel(system.shape, system.box, system.kernel, system.param)
+    # probe: one pair to size the sample
+    t0 = time.perf_counter()
+    oracle.pair_energy(psi[0], psi[1], vg, 1.0)
+    t_pair = max(time.perf_counter() - t0, 1e-4)
+    pairs_target = seconds_target * cores / t_pair
+    k = int(max(4, min(system.n_orb, (math.sqrt(8 * pairs_target + 1) - 1) / 2)))
+    sub = np.ascontiguousarray(psi[:k])
+    t0 = time.perf_counter()
+    oracle.exchange(sub, system.box, vg, workers=cores)
+    dt = time.perf_counter() - t0
+    pairs = k * (k + 1) // 2
+    return {"value": pairs / dt, "unit": "pair-exchange evals/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{k} of {system.n_orb} orbitals ({pairs} pairs) of the {system.name} "
+                      f"workload, float64, scipy FFT, {cores} worker processes, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="water96")
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2309_00651_amd import hfx
+    from workloads import configs
+
+    system = configs.ALL[args.workload]
+    log(f"generating {system.name}: n={system.n} n_orb={system.n_orb}")
+    psi = system.orbitals()
+    dev = torch.device("cuda:0")
+    spec = hfx.SystemSpec(system.n, system.box, system.n_orb, system.kernel, system.param)
+    psi0 = torch.from_numpy(psi).to(dev)
+    n_pairs = system.n_pairs
+
+    def run(prec, steps, warmup, profile):
+        plan = hfx.Plan(spec, prec, device=dev)
+        p = psi0.clone()
+        kpsi = torch.empty(p.shape, dtype=plan.kpsi_dtype, device=dev)
+        ex = torch.empty(1, dtype=torch.float64, device=dev)
+        m = torch.empty(system.n_orb ** 2, dtype=torch.float64, device=dev)
+        plan.workspace()
+
+        def step():
+            plan.orthonormalize(p)
+            plan.apply_exchange(p, kpsi=kpsi, ex=ex)
+            plan.exchange_matrix(p, kpsi, m=m)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        if profile:
+            plan.profile(True)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        start.record()
+        for _ in range(steps):
+            step()
+        stop.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev_ms = start.elapsed_time(stop)
+        prof = plan.profile_read() if profile else None
+        plan.profile(False)
+        out = dict(ms=ev_ms / steps, wall_ms=1e3 * wall / steps, prof=prof, ex=float(ex[0]),
+                   m=m, kpsi=kpsi)
+        return out, plan
+
+    log(f"fp32: {args.warmup} warm-up + {args.steps} timed steps")
+    r32, plan32 = run(hfx.FP32, args.steps, args.warmup, True)
+    ms = r32["ms"]
+    prof = r32["prof"]
+    # dominant pass by summed time
+    dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    dname, d = dom
+    if dname == "contract":
+        achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / MFMA_FP32_PEAK_TFLOPS, "traffic": None}
+    else:
+        achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        tr = traffic_from_profiles(dname, system.name)
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": tr}
+    roof["kernel"] = dname
+    roof["launches"] = d["launches"]
+    roof["avg_launch_ms"] = d["ms"] / max(d["launches"], 1)
+    passes = {k: {"ms_per_step": v["ms"] / args.steps,
+                  "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None,
+                  "TFLOPs": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else None}
+              for k, v in prof.items()}
+    pair_ms = sum(prof[k]["ms"] for k in ("pair_fwd", "plane", "inv_acc", "rows_fwd",
+                                          "cols_conv", "rows_inv") if k in prof) / args.steps
+    hbm_pair_bytes = sum(prof[k]["bytes"] for k in ("pair_fwd", "plane", "inv_acc", "rows_fwd",
+                                                    "cols_conv", "rows_inv") if k in prof)
+    exch_frac = hbm_pair_bytes / args.steps / (pair_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    log(f"fp32 {ms:.2f} ms/step, dominant pass {dname} {achieved:.1f}")
+
+    extra = {"kpsi_ms_per_step_fp32": pair_ms, "pair_pipeline_hbm_frac": exch_frac,
+             "passes": passes, "ex_fp32": r32["ex"]}
+    if not args.no_fp64:
+        log(f"fp64: 1 warm-up + {args.fp64_steps} timed steps")
+        r64, _ = run(hfx.FP64, args.fp64_steps, 1, False)
+        extra.update({"ms_per_step_fp64": r64["ms"], "ex_fp64": r64["ex"],
+                      "fp32_speedup_vs_fp64": r64["ms"] / ms,
+                      "rel_dEx_fp32_vs_fp64": abs(r32["ex"] - r64["ex"]) / abs(r64["ex"])})
+        del r64
+    golden = os.path.join(ROOT, "tests", "golden", f"{system.name}_oracle.json")
+    if os.path.exists(golden):
+        with open(golden) as f:
+            g = json.load(f)
+        extra["rel_dEx_fp32_vs_oracle"] = abs(r32["ex"] - g["ex"]) / abs(g["ex"])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(system, psi)
+
+    line = {
+        "metric": METRIC,
+        "value": n_pairs / (ms * 1e-3),
+        "unit": "pair-exchange evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{system.name}: L={system.L} bohr, {system.n}^3 grid, "
+                               f"{system.n_orb} localised Gaussian orbitals ({system.ecut:g} Ha), "
+                               f"erfc w={system.param}; step = orthonormalise + K psi (all "
+                               f"{n_pairs} pairs) + E_x + exchange matrix",
+                   "n": system.n, "n_orb": system.n_orb, "pairs": n_pairs,
+                   "precision": "fp32 FFT/kernel, fp64 orthonormalisation and sums"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -139,6 +139,36 @@ hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double*
 hfx_status hfx_orthonormalize(hfx_plan plan, double* psi, int method, void* ws,
                               size_t ws_bytes, void* stream);
 
+/*
+ * Per-pass timing (tracing aid).  While enabled, every kernel launch of the
+ * plan is bracketed by a pair of HIP events recorded on the caller's stream,
+ * and the pass's algorithmic HBM bytes (each operand read or written once;
+ * workspace grids count as HBM traffic) and flops are tallied.
+ * hfx_profile_read waits for the recorded events, writes per-pass totals into
+ * host arrays of length n (index = hfx_pass; NULL arrays are skipped) and
+ * clears the record.  Events add a few microseconds per launch.
+ */
+typedef enum {
+  HFX_PASS_STAGE = 0,      /* float64 -> float32 orbital copy               */
+  HFX_PASS_ZERO,           /* K psi zero fill                                */
+  HFX_PASS_PAIR_FWD,       /* pair product + forward z FFT                   */
+  HFX_PASS_PLANE,          /* xy FFT, * v(G), inverse xy FFT (fused plane)   */
+  HFX_PASS_ROWS_FWD,       /* split plane: forward x FFT                     */
+  HFX_PASS_COLS_CONV,      /* split plane: y FFT, * v(G), inverse y FFT      */
+  HFX_PASS_ROWS_INV,       /* split plane: inverse x FFT                     */
+  HFX_PASS_INV_ACC,        /* inverse z FFT + energy + K psi accumulation    */
+  HFX_PASS_INV_ENERGY,     /* inverse z FFT + energy                         */
+  HFX_PASS_ENERGY_REDUCE,  /* fixed-order energy sum                         */
+  HFX_PASS_CONTRACT,       /* Psi^T (K Psi) or Psi^T Psi on MFMA + reduction */
+  HFX_PASS_ORTHO,          /* Newton-Schulz S^(-1/2) and Psi <- S^(-1/2) Psi */
+  HFX_PASS_SCALE,          /* gradient scaling                               */
+  HFX_PASS_COUNT
+} hfx_pass;
+
+hfx_status hfx_profile_enable(hfx_plan plan, int enable);
+hfx_status hfx_profile_read(hfx_plan plan, double* ms_host, double* bytes_host,
+                            double* flops_host, long long* launches_host, int n);
+
 /* Static description of a status code. */
 const char* hfx_status_string(hfx_status s);
 

@@ -31,7 +31,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // MFMA 16x16x4 operand layout (one 64-wide wavefront, lane l):
 //   A operand: A[l % 16][l / 16]   (16 x 4)
 //   B operand: B[l / 16][l % 16]   (4 x 16)
-//   result:    4 values, D[4 (l / 16) + i][l % 16], i = 0..3
+//   result, 4 values i = 0..3:  f32: D[4 (l / 16) + i][l % 16]
+//                               f64: D[(l / 16) + 4 i][l % 16]
+// (both checked on gfx950 against a host product).
 template <bool SPLIT>
 __global__ void __launch_bounds__(256) k_xtx(const double* __restrict__ a,
                                              const void* __restrict__ bv, int n, long long nr,
@@ -142,7 +144,7 @@ __global__ void __launch_bounds__(256) k_xtx(const double* __restrict__ a,
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int rr = wr + p * 16 + 4 * lk + i;
+        const int rr = wr + p * 16 + (SPLIT ? 4 * lk + i : lk + 4 * i);
         const int cc = wc + q * 16 + lr;
         out[rr * TM + cc] = SPLIT ? accd[p][q][i] : acc64[p][q][i];
       }

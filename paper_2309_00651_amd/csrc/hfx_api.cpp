@@ -76,11 +76,20 @@ struct SystemPlan {
 
 }  // namespace
 
+struct ProfRec {
+  int pass;
+  hipEvent_t start, stop;
+  double bytes, flops;
+};
+
 struct hfx_plan_t {
   int prec = 0;
   std::vector<SystemPlan> sys;
   size_t ws_bytes = 0;
   int device = 0;
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
 };
 
 namespace {
@@ -276,6 +285,37 @@ void free_system(SystemPlan& sp) {
   sp.d_active = nullptr;
 }
 
+// Event bracket around one launch when profiling is on.
+struct Bracket {
+  hfx_plan plan;
+  int pass;
+  hipStream_t st;
+  hipEvent_t start = nullptr;
+  Bracket(hfx_plan p, int ps, hipStream_t s) : plan(p), pass(ps), st(s) {
+    if (!plan->prof) return;
+    start = take_event(plan);
+    if (start) (void)hipEventRecord(start, st);
+  }
+  void done(double bytes, double flops) {
+    if (!plan->prof || !start) return;
+    hipEvent_t stop = take_event(plan);
+    if (!stop) return;
+    (void)hipEventRecord(stop, st);
+    plan->recs.push_back({pass, start, stop, bytes, flops});
+    start = nullptr;
+  }
+  static hipEvent_t take_event(hfx_plan p) {
+    hipEvent_t e = nullptr;
+    if (!p->pool.empty()) {
+      e = p->pool.back();
+      p->pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+};
+
 hfx_status check_call(hfx_plan plan, const void* psi, void* ws, size_t ws_bytes) {
   if (!plan) return fail(HFX_EINVAL, "null plan");
   if (!psi) return fail(HFX_EINVAL, "null psi");
@@ -294,12 +334,19 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   const Variant* v = sp.var;
   const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
   const void* psi_w = psi;
+  const double orb_pts = (double)sp.sys.n_orb * (double)sp.nr;
   if (plan->prec == HFX_FP32) {
     float* p32 = reinterpret_cast<float*>(ws + sp.off_psi32);
+    Bracket br(plan, HFX_PASS_STAGE, st);
     launch_cast_f64_f32(psi, p32, (size_t)sp.sys.n_orb * sp.nr, st);
+    br.done(orb_pts * 12.0, 0.0);
     psi_w = p32;
   }
-  if (acc) launch_zero(kpsi, (size_t)sp.sys.n_orb * sp.nr * elem, st);
+  if (acc) {
+    Bracket br(plan, HFX_PASS_ZERO, st);
+    launch_zero(kpsi, (size_t)sp.sys.n_orb * sp.nr * elem, st);
+    br.done(orb_pts * elem, 0.0);
+  }
   double* partials = reinterpret_cast<double*>(ws + sp.off_partials);
   PassArgs a{};
   a.psi = psi_w;
@@ -317,27 +364,63 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   const int br = bricks_per_tile(v);
   const int n = v->n;
   const int nxb = (n + v->brick - 1) / v->brick;
+  const double nr = (double)sp.nr, ce = 2.0 * elem;  // complex element bytes
+  // FFT flops per complex grid and axis pass: 5 N_r log2(N) (radix-2 count)
+  const double fft_axis = 5.0 * nr * std::log2((double)n);
   for (const Batch& b : sp.batches) {
     a.tiles = sp.d_tiles + b.tile_off;
     a.active = sp.d_active + b.active_off;
     a.n_tiles = b.n_tiles;
     a.n_active = b.n_active;
     a.part_base = b.part_base;
-    v->pair_fwd(a, b.n_tiles * br, st);
+    double orbs = 0.0;  // orbital rows a batch reads (each tile's blocks once)
+    for (int t = 0; t < b.n_tiles; ++t) {
+      const TileDesc& td = sp.tiles[b.tile_off + t];
+      orbs += td.diag ? td.nJ : td.nI + td.nJ;
+    }
+    const double grids = (double)b.n_active;
+    {
+      Bracket bk(plan, HFX_PASS_PAIR_FWD, st);
+      v->pair_fwd(a, b.n_tiles * br, st);
+      bk.done(orbs * nr * elem + grids * nr * ce, grids * fft_axis);
+    }
     if (v->plane_mode == 0) {
+      Bracket bk(plan, HFX_PASS_PLANE, st);
       v->plane(a, b.n_active * n, st);
+      bk.done(grids * nr * ce * 2.0, grids * fft_axis * 4.0);
     } else {
       const int rb = (n * n + v->rows_per_wg - 1) / v->rows_per_wg;
-      v->rows_fwd(a, b.n_active * rb, st);
-      v->cols_conv(a, b.n_active * n * nxb, st);
-      v->rows_inv(a, b.n_active * rb, st);
+      {
+        Bracket bk(plan, HFX_PASS_ROWS_FWD, st);
+        v->rows_fwd(a, b.n_active * rb, st);
+        bk.done(grids * nr * ce * 2.0, grids * fft_axis);
+      }
+      {
+        Bracket bk(plan, HFX_PASS_COLS_CONV, st);
+        v->cols_conv(a, b.n_active * n * nxb, st);
+        bk.done(grids * nr * ce * 2.0, grids * fft_axis * 2.0);
+      }
+      {
+        Bracket bk(plan, HFX_PASS_ROWS_INV, st);
+        v->rows_inv(a, b.n_active * rb, st);
+        bk.done(grids * nr * ce * 2.0, grids * fft_axis);
+      }
     }
-    if (acc)
+    if (acc) {
+      Bracket bk(plan, HFX_PASS_INV_ACC, st);
       v->inv_acc(a, b.n_tiles * br, st);
-    else
+      bk.done(grids * nr * ce + orbs * nr * elem * 3.0, grids * fft_axis);
+    } else {
+      Bracket bk(plan, HFX_PASS_INV_ENERGY, st);
       v->inv_energy(a, b.n_tiles * br, st);
+      bk.done(grids * nr * ce + orbs * nr * elem, grids * fft_axis);
+    }
   }
-  if (ex) launch_energy_reduce(partials, sp.n_partials, -0.5 * sp.dv, ex, st);
+  if (ex) {
+    Bracket bk(plan, HFX_PASS_ENERGY_REDUCE, st);
+    launch_energy_reduce(partials, sp.n_partials, -0.5 * sp.dv, ex, st);
+    bk.done((double)sp.n_partials * 8.0, 0.0);
+  }
   HIP_TRY(hipGetLastError());
   return HFX_OK;
 }
@@ -465,9 +548,50 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   return HFX_OK;
 }
 
+hfx_status hfx_profile_enable(hfx_plan plan, int enable) {
+  if (!plan) return fail(HFX_EINVAL, "null plan");
+  plan->prof = enable != 0;
+  return HFX_OK;
+}
+
+hfx_status hfx_profile_read(hfx_plan plan, double* ms, double* bytes, double* flops,
+                            long long* launches, int n) {
+  if (!plan) return fail(HFX_EINVAL, "null plan");
+  if (n < 0) return fail(HFX_EINVAL, "negative array length");
+  for (int k = 0; k < n; ++k) {
+    if (ms) ms[k] = 0.0;
+    if (bytes) bytes[k] = 0.0;
+    if (flops) flops[k] = 0.0;
+    if (launches) launches[k] = 0;
+  }
+  hipError_t err = hipSuccess;
+  for (auto& r : plan->recs) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(r.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.stop);
+    if (e != hipSuccess) err = e;
+    if (r.pass < n) {
+      if (ms) ms[r.pass] += t;
+      if (bytes) bytes[r.pass] += r.bytes;
+      if (flops) flops[r.pass] += r.flops;
+      if (launches) launches[r.pass] += 1;
+    }
+    plan->pool.push_back(r.start);
+    plan->pool.push_back(r.stop);
+  }
+  plan->recs.clear();
+  if (err != hipSuccess) return fail(HFX_EDEVICE, std::string("event timing: ") + hipGetErrorString(err));
+  return HFX_OK;
+}
+
 hfx_status hfx_plan_destroy(hfx_plan plan) {
   if (!plan) return fail(HFX_EINVAL, "null plan");
   const hipError_t e = hipDeviceSynchronize();
+  for (auto& r : plan->recs) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  for (auto& ev : plan->pool) (void)hipEventDestroy(ev);
   for (auto& sp : plan->sys) free_system(sp);
   delete plan;
   if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("pending device error: ") + hipGetErrorString(e));
@@ -526,8 +650,10 @@ hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double*
                                       : static_cast<void*>(static_cast<char*>(ws) + sp.off_grad);
     s = run_exchange(plan, sp, psi + sp.psi_off, kp, nullptr, static_cast<char*>(ws), st, true);
     if (s != HFX_OK) return s;
+    Bracket bk(plan, HFX_PASS_SCALE, st);
     launch_scale_to_f64(kp, plan->prec == HFX_FP64, g, (size_t)sp.sys.n_orb * sp.nr,
                         2.0 * sp.dv, gscale ? gscale + i : nullptr, st);
+    bk.done((double)sp.sys.n_orb * sp.nr * (plan->prec == HFX_FP64 ? 16.0 : 12.0), 0.0);
   }
   HIP_TRY(hipGetLastError());
   return HFX_OK;
@@ -544,12 +670,16 @@ hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, const void* kps
   for (auto& sp : plan->sys) {
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + sp.off_gemm);
     const char* kp = static_cast<const char*>(kpsi) + (size_t)sp.psi_off * elem;
+    const double nn = (double)sp.sys.n_orb, npts = (double)sp.nr;
+    Bracket bk(plan, HFX_PASS_CONTRACT, st);
     if (plan->prec == HFX_FP32)
       launch_xtx_split(psi + sp.psi_off, reinterpret_cast<const float*>(kp), sp.sys.n_orb, sp.nr,
                        sp.dv, part, sp.gemm_chunks, m + sp.m_off, st);
     else
       launch_xtx_f64(psi + sp.psi_off, reinterpret_cast<const double*>(kp), sp.sys.n_orb, sp.nr,
                      sp.dv, part, sp.gemm_chunks, m + sp.m_off, st);
+    // split precision: two float32 products per term
+    bk.done(nn * npts * (8.0 + elem), 2.0 * nn * nn * npts * (plan->prec == HFX_FP32 ? 2.0 : 1.0));
   }
   HIP_TRY(hipGetLastError());
   return HFX_OK;
@@ -570,9 +700,16 @@ hfx_status hfx_orthonormalize(hfx_plan plan, double* psi, int method, void* ws, 
     double* tmp = reinterpret_cast<double*>(
         static_cast<char*>(ws) + align_up(sp.off_ortho + (size_t)6 * n * n * 8 + 64));
     double* p = psi + sp.psi_off;
-    launch_xtx_f64(p, p, n, sp.nr, sp.dv, part, sp.gemm_chunks, smat, st);
+    const double nn = n, npts = (double)sp.nr;
+    {
+      Bracket bk(plan, HFX_PASS_CONTRACT, st);
+      launch_xtx_f64(p, p, n, sp.nr, sp.dv, part, sp.gemm_chunks, smat, st);
+      bk.done(nn * npts * 8.0, 2.0 * nn * nn * npts);
+    }
+    Bracket bk(plan, HFX_PASS_ORTHO, st);
     HIP_TRY(launch_inverse_sqrt(smat, n, ns_work, 60, st));
     launch_apply_left(smat, p, n, sp.nr, tmp, st);
+    bk.done(nn * npts * 16.0, 2.0 * nn * nn * npts);
   }
   HIP_TRY(hipGetLastError());
   return HFX_OK;

@@ -24,7 +24,8 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 }  // namespace
 
 // C[M][N] = alpha * A[M][K] B[K][N] (row-major, leading dims lda, ldb, ldc),
-// skipped entirely when *flag != 0.  4 wavefronts x (2 x 2) MFMA f64 16x16x4.
+// skipped entirely when *flag != 0.  4 wavefronts x (2 x 2) MFMA f64 16x16x4
+// (lane l: A[l%16][l/16], B[l/16][l%16], result i = D[l/16 + 4i][l%16]).
 __global__ void __launch_bounds__(256) k_gemm_nn_f64(const double* __restrict__ a, int lda,
                                                      const double* __restrict__ b, long long ldb,
                                                      double* __restrict__ c, long long ldc, int M,
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(256) k_gemm_nn_f64(const double* __restrict__ 
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = row0 + wr + p * 16 + 4 * lk + i;
+        const int r = row0 + wr + p * 16 + lk + 4 * i;
         const long long cc = col0 + wc + q * 16 + lr;
         if (r < M && cc < N) c[(long long)r * ldc + cc] = alpha * acc[p][q][i];
       }

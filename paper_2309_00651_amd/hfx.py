@@ -26,6 +26,8 @@ ERFC = 1
 FP32 = 0
 FP64 = 1
 ORTHO_LOWDIN = 0
+PASSES = ("stage", "zero", "pair_fwd", "plane", "rows_fwd", "cols_conv", "rows_inv", "inv_acc",
+          "inv_energy", "energy_reduce", "contract", "ortho", "scale")
 
 _STATUS = {0: "HFX_OK", 1: "HFX_EINVAL", 2: "HFX_EUNSUPPORTED", 3: "HFX_ENOMEM",
            4: "HFX_EDEVICE"}
@@ -64,13 +66,17 @@ def load_library(path=None):
     lib.hfx_exchange_matrix.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.hfx_orthonormalize.argtypes = [vp, vp, i, vp, sz, vp]
     lib.hfx_exchange_gradient.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.hfx_profile_enable.argtypes = [vp, i]
+    lib.hfx_profile_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
+                                     ctypes.POINTER(ctypes.c_longlong), i]
     lib.hfx_status_string.argtypes = [i]
     lib.hfx_status_string.restype = ctypes.c_char_p
     lib.hfx_last_error.argtypes = []
     lib.hfx_last_error.restype = ctypes.c_char_p
     for name in ("hfx_plan_create", "hfx_plan_destroy", "hfx_workspace_size",
                  "hfx_exchange_energy", "hfx_apply_exchange", "hfx_exchange_matrix",
-                 "hfx_orthonormalize", "hfx_exchange_gradient"):
+                 "hfx_orthonormalize", "hfx_exchange_gradient", "hfx_profile_enable",
+                 "hfx_profile_read"):
         getattr(lib, name).restype = i
     if path is None:
         _lib = lib
@@ -222,6 +228,18 @@ class Plan:
         _check(_lib.hfx_orthonormalize(self._h, _ptr(psi), int(method), _ptr(ws), self.ws_bytes,
                                        _stream()))
         return psi
+
+    def profile(self, enable=True):
+        _check(_lib.hfx_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{pass: dict(ms, bytes, flops, launches)} since the last read (waits for events)."""
+        n = len(PASSES)
+        ms, by, fl = (ctypes.c_double * n)(), (ctypes.c_double * n)(), (ctypes.c_double * n)()
+        la = (ctypes.c_longlong * n)()
+        _check(_lib.hfx_profile_read(self._h, ms, by, fl, la, n))
+        return {PASSES[k]: dict(ms=ms[k], bytes=by[k], flops=fl[k], launches=la[k])
+                for k in range(n) if la[k]}
 
     def split(self, flat):
         """Views of a concatenated per-system buffer (orbital-shaped)."""

@@ -1,0 +1,68 @@
+"""Write full-size oracle reference values for a named workload.
+
+Calls only the float64 CPU oracle (``oracle/``) and the seeded input
+generators (``workloads/``).  Output ``tests/golden/<name>_oracle.json``:
+
+  ex        E_x of the Loewdin-orthonormalised orbitals
+  m_diag    <psi_i | K psi_i> = -sum_j e_ij for every orbital i
+  samples   K psi values of a few orbitals at seeded grid points
+            (orbital index, flat point index, value)
+
+Usage: python tests/golden/make_golden.py water96 [--workers 8]
+The workload definitions live in workloads/configs.py; each record stores the
+generator parameters it was made from.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from workloads import configs  # noqa: E402
+
+SAMPLE_ORBITALS = (0, 1)
+SAMPLE_POINTS = 256
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("name")
+    ap.add_argument("--workers", type=int, default=os.cpu_count() or 1)
+    a = ap.parse_args()
+    s = configs.ALL[a.name]
+    t0 = time.time()
+    psi = s.orbitals()
+    dv = oracle.volume(s.box) / psi[0].size
+    psi_o, lam_min = oracle.lowdin(psi, dv)
+    del psi
+    vg = oracle.coulomb_kernel(s.shape, s.box, s.kernel, s.param)
+    print(f"{s.name}: orthonormalised (min eig S {lam_min:.3e}), running {s.n_pairs} pairs "
+          f"on {a.workers} workers", flush=True)
+    res = oracle.exchange(psi_o, s.box, vg, want_kpsi=False, workers=a.workers)
+    m_diag = -res["e"].sum(axis=1)
+    print(f"E_x = {res['ex']:.15f}  ({time.time() - t0:.0f} s)", flush=True)
+    rng = np.random.default_rng(12345)
+    pts = rng.choice(psi_o[0].size, size=SAMPLE_POINTS, replace=False)
+    rows = oracle.apply_exchange_rows(psi_o, s.box, vg, list(SAMPLE_ORBITALS))
+    samples = [[int(o), int(p), float(rows[k].reshape(-1)[p])]
+               for k, o in enumerate(SAMPLE_ORBITALS) for p in pts]
+    rec = {"name": s.name, "n": s.n, "L": s.L, "n_orb": s.n_orb, "kernel": s.kernel,
+           "param": s.param, "family": s.family, "ecut": s.ecut, "seed": s.seed,
+           "orthonormalisation": "Loewdin (oracle eigh)", "min_eig_overlap": lam_min,
+           "ex": res["ex"], "m_diag": [float(x) for x in m_diag], "samples": samples,
+           "seconds": time.time() - t0, "workers": a.workers}
+    out = os.path.join(HERE, f"{s.name}_oracle.json")
+    with open(out, "w") as f:
+        json.dump(rec, f)
+    print(f"wrote {out} ({time.time() - t0:.0f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()
