@@ -56,15 +56,22 @@ constexpr int pow2_at_least() {
 
 // ---------------------------------------------------------------------------
 // Pass 1: pair product + forward z FFT on bricks.
+// Thread tid forms the products at brick points p = tid + k NT (k < PT,
+// contiguous x for coalesced psi reads) and writes them to LDS in natural
+// order; the transform starts from there and its last stage stores straight
+// to HBM.  psi of the tile's J block stays in registers for the whole tile.
 template <typename T, int N, int W, int NT, int TT, class SZF>
 __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   using G = Geom<T, N, W, NT, true, W, 1>;
-  using F = FirstStage<G, SZF>;
   using L = LastStage<G, SZF>;
   using E = FFT<G, false, SZF>;
+  constexpr int RL = SchedInfo<SZF>::last;
   constexpr int NXB = (N + W - 1) / W;
   constexpr int BR = N * NXB;
+  constexpr int P = N * W;
+  constexpr int PT = (P + NT - 1) / NT;
   constexpr long long NR = (long long)N * N * N;
+  constexpr int ZSL = (N / RL) * N * N;  // offset between legs of a last-stage butterfly
   __shared__ cpx<T> lds[N * W];
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
@@ -72,81 +79,84 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   const int y = br / NXB, x0 = (br - y * NXB) * W;
   const TileDesc td = a.tiles[t];
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
-  const cpx<T>* __restrict__ tw = static_cast<const cpx<T>*>(a.tw_zf);
+  const TwEntry<T>* __restrict__ tw = static_cast<const TwEntry<T>*>(a.tw_zf);
   cpx<T>* __restrict__ grids = static_cast<cpx<T>*>(a.grids);
 
-  // element offsets (within one N^3 grid) of this thread's stage-0 inputs
-  int off[F::VALS];
-  bool ok[F::VALS];
+  int offA[PT];
+  bool vA[PT];
 #pragma unroll
-  for (int i = 0; i < F::PER; ++i) {
-    int m = 0, j = 0;
-    F::mj(tid, i, m, j);
-    const bool v = F::valid(tid, i) && (x0 + m) < N;
-#pragma unroll
-    for (int r = 0; r < SchedInfo<SZF>::first; ++r) {
-      const int z = F::in_pos(j, r);
-      off[i * SchedInfo<SZF>::first + r] = (z * N + y) * N + x0 + m;
-      ok[i * SchedInfo<SZF>::first + r] = v;
-    }
+  for (int k = 0; k < PT; ++k) {
+    const int p = tid + k * NT;
+    const int z = p / W, m = p - (p / W) * W;
+    vA[k] = p < P && (x0 + m) < N;
+    offA[k] = vA[k] ? (z * N + y) * N + x0 + m : 0;
   }
-  int offL[L::VALS];
-  bool okL[L::VALS];
+  int offL[L::PER];
+  bool vL[L::PER];
 #pragma unroll
   for (int i = 0; i < L::PER; ++i) {
     int m = 0, j = 0;
     L::mj(tid, i, m, j);
-    const bool v = L::valid(tid, i) && (x0 + m) < N;
-#pragma unroll
-    for (int r = 0; r < SchedInfo<SZF>::last; ++r) {
-      const int z = L::in_pos(j, r);
-      offL[i * SchedInfo<SZF>::last + r] = (z * N + y) * N + x0 + m;
-      okL[i * SchedInfo<SZF>::last + r] = v;
-    }
+    vL[i] = L::valid(tid, i) && (x0 + m) < N;
+    offL[i] = vL[i] ? (j * N + y) * N + x0 + m : 0;
   }
 
-  T pj[TT][F::VALS];
+  T pj[TT][PT];
 #pragma unroll
   for (int b = 0; b < TT; ++b) {
     const bool bv = b < td.nJ;
     const T* p = psi + (long long)(td.j0 + (bv ? b : 0)) * NR;
 #pragma unroll
-    for (int e = 0; e < F::VALS; ++e) pj[b][e] = (bv && ok[e]) ? p[off[e]] : T(0);
+    for (int k = 0; k < PT; ++k) pj[b][k] = (bv && vA[k]) ? p[offA[k]] : T(0);
   }
 
   for (int ia = 0; ia < td.nI; ++ia) {
     const T* pa_ptr = psi + (long long)(td.i0 + ia) * NR;
-    T pa[F::VALS];
+    T pa[PT];
 #pragma unroll
-    for (int e = 0; e < F::VALS; ++e) pa[e] = ok[e] ? pa_ptr[off[e]] : T(0);
+    for (int k = 0; k < PT; ++k) pa[k] = vA[k] ? pa_ptr[offA[k]] : T(0);
     static_for<0, TT / 2>([&](auto bp) {
       constexpr int b0 = 2 * decltype(bp)::value, b1 = b0 + 1;
       if (b0 >= td.nJ) return;
       if (td.diag && b1 < ia) return;
-      cpx<T> v[F::VALS];
 #pragma unroll
-      for (int e = 0; e < F::VALS; ++e) v[e] = {pa[e] * pj[b0][e], pa[e] * pj[b1][e]};
+      for (int k = 0; k < PT; ++k)
+        if (tid + k * NT < P) lds[tid + k * NT] = {pa[k] * pj[b0][k], pa[k] * pj[b1][k]};
+      __syncthreads();
       cpx<T> out[L::VALS];
-      E::reg2reg(v, lds, tw, tid, out);
+      E::lds2reg(lds, tw, tid, out);
       cpx<T>* g = grids + (long long)(td.slot0 + ia * (TT / 2) + decltype(bp)::value) * NR;
 #pragma unroll
-      for (int e = 0; e < L::VALS; ++e)
-        if (okL[e]) g[offL[e]] = out[e];
+      for (int i = 0; i < L::PER; ++i)
+        if (vL[i])
+#pragma unroll
+          for (int r = 0; r < RL; ++r) g[offL[i] + r * ZSL] = out[i * RL + r];
     });
   }
 }
 
 // ---------------------------------------------------------------------------
 // Pass 3: inverse z FFT + pair energies + K psi accumulation on bricks.
+// The inverse transform leaves the potentials of one grid in LDS in natural
+// order; the accumulation then uses its own point map: thread tid owns brick
+// points p = tid + k NT (k < PT), i.e. contiguous x for coalesced K psi
+// traffic.  psi of the tile's J block and the J-side accumulators stay in
+// registers for the whole tile; the pair energy of a thread's points is
+// summed in the working precision per pair and added to a float64
+// accumulator once per pair.
 template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC>
 __global__ void __launch_bounds__(NT) k_inv_acc(PassArgs a) {
   using G = Geom<T, N, W, NT, true, W, 1>;
   using F = FirstStage<G, SZI>;
   using L = LastStage<G, SZI>;
   using E = FFT<G, true, SZI>;
+  constexpr int RF = SchedInfo<SZI>::first;
   constexpr int NXB = (N + W - 1) / W;
   constexpr int BR = N * NXB;
+  constexpr int P = N * W;                 // brick points
+  constexpr int PT = (P + NT - 1) / NT;    // accumulation points per thread
   constexpr long long NR = (long long)N * N * N;
+  constexpr int ZSF = (N / RF) * N * N;    // offset between legs of a first-stage butterfly
   __shared__ cpx<T> lds[N * W];
   __shared__ double red[pow2_at_least<NT>()];
   const int tid = threadIdx.x;
@@ -156,51 +166,51 @@ __global__ void __launch_bounds__(NT) k_inv_acc(PassArgs a) {
   const TileDesc td = a.tiles[t];
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
   T* __restrict__ kpsi = static_cast<T*>(a.kpsi);
-  const cpx<T>* __restrict__ tw = static_cast<const cpx<T>*>(a.tw_zi);
+  const TwEntry<T>* __restrict__ tw = static_cast<const TwEntry<T>*>(a.tw_zi);
   const cpx<T>* __restrict__ grids = static_cast<const cpx<T>*>(a.grids);
 
-  int off[F::VALS];
-  bool ok[F::VALS];
+  int offF[F::PER];
+  bool vF[F::PER];
 #pragma unroll
   for (int i = 0; i < F::PER; ++i) {
     int m = 0, j = 0;
     F::mj(tid, i, m, j);
-    const bool v = F::valid(tid, i) && (x0 + m) < N;
-#pragma unroll
-    for (int r = 0; r < SchedInfo<SZI>::first; ++r) {
-      off[i * SchedInfo<SZI>::first + r] = (F::in_pos(j, r) * N + y) * N + x0 + m;
-      ok[i * SchedInfo<SZI>::first + r] = v;
-    }
+    vF[i] = F::valid(tid, i) && (x0 + m) < N;
+    offF[i] = vF[i] ? (j * N + y) * N + x0 + m : 0;
   }
-  int offL[L::VALS];
-  bool okL[L::VALS];
+  int offA[PT];
+  bool vA[PT];
 #pragma unroll
-  for (int i = 0; i < L::PER; ++i) {
-    int m = 0, j = 0;
-    L::mj(tid, i, m, j);
-    const bool v = L::valid(tid, i) && (x0 + m) < N;
-#pragma unroll
-    for (int r = 0; r < SchedInfo<SZI>::last; ++r) {
-      offL[i * SchedInfo<SZI>::last + r] = (L::in_pos(j, r) * N + y) * N + x0 + m;
-      okL[i * SchedInfo<SZI>::last + r] = v;
-    }
+  for (int k = 0; k < PT; ++k) {
+    const int p = tid + k * NT;
+    const int z = p / W, m = p - (p / W) * W;
+    vA[k] = p < P && (x0 + m) < N;
+    offA[k] = vA[k] ? (z * N + y) * N + x0 + m : 0;
   }
 
-  T accJ[ACC ? TT : 1][L::VALS];
+  T pj[TT][PT];
+  T accJ[ACC ? TT : 1][PT];
+#pragma unroll
+  for (int b = 0; b < TT; ++b) {
+    const bool bv = b < td.nJ;
+    const T* pb = psi + (long long)(td.j0 + (bv ? b : 0)) * NR;
+#pragma unroll
+    for (int k = 0; k < PT; ++k) pj[b][k] = (bv && vA[k]) ? pb[offA[k]] : T(0);
+  }
 #pragma unroll
   for (int b = 0; b < (ACC ? TT : 1); ++b)
 #pragma unroll
-    for (int e = 0; e < L::VALS; ++e) accJ[b][e] = T(0);
+    for (int k = 0; k < PT; ++k) accJ[b][k] = T(0);
   double eacc = 0.0;
 
   for (int ia = 0; ia < td.nI; ++ia) {
     const int oa = td.i0 + ia;
     const T* pa_ptr = psi + (long long)oa * NR;
-    T pa[L::VALS], acca[L::VALS];
+    T pa[PT], acca[PT];
 #pragma unroll
-    for (int e = 0; e < L::VALS; ++e) {
-      pa[e] = okL[e] ? pa_ptr[offL[e]] : T(0);
-      acca[e] = T(0);
+    for (int k = 0; k < PT; ++k) {
+      pa[k] = vA[k] ? pa_ptr[offA[k]] : T(0);
+      acca[k] = T(0);
     }
     static_for<0, TT / 2>([&](auto bp) {
       constexpr int b0 = 2 * decltype(bp)::value;
@@ -209,36 +219,46 @@ __global__ void __launch_bounds__(NT) k_inv_acc(PassArgs a) {
       const cpx<T>* g = grids + (long long)(td.slot0 + ia * (TT / 2) + decltype(bp)::value) * NR;
       cpx<T> v[F::VALS];
 #pragma unroll
-      for (int e = 0; e < F::VALS; ++e) v[e] = ok[e] ? g[off[e]] : cpx<T>{T(0), T(0)};
-      cpx<T> out[L::VALS];
-      E::reg2reg(v, lds, tw, tid, out);
+      for (int i = 0; i < F::PER; ++i)
+#pragma unroll
+        for (int r = 0; r < RF; ++r)
+          v[i * RF + r] = vF[i] ? g[offF[i] + r * ZSF] : cpx<T>{T(0), T(0)};
+      {
+        cpx<T> out[L::VALS];
+        E::reg2reg(v, lds, tw, tid, out);
+        E::store_last(out, lds, tid);
+      }
+      __syncthreads();
+      cpx<T> pot[PT];
+#pragma unroll
+      for (int k = 0; k < PT; ++k)
+        pot[k] = (tid + k * NT < P) ? lds[tid + k * NT] : cpx<T>{T(0), T(0)};
+      __syncthreads();  // LDS is rewritten by the next transform
       static_for<0, 2>([&](auto half) {
         constexpr int b = b0 + decltype(half)::value;
         if (b >= td.nJ) return;
         // weight of e_ab in sum_{i,j} e_ij: 2 for a != b, 1 for a == b
         const int w = td.diag ? (b > ia ? 2 : (b == ia ? 1 : 0)) : 2;
         if (w == 0) return;
-        const T* pb_ptr = psi + (long long)(td.j0 + b) * NR;
-        const double wd = (double)w;
+        T es = T(0);
 #pragma unroll
-        for (int e = 0; e < L::VALS; ++e) {
-          if (!okL[e]) continue;
-          const T vv = decltype(half)::value ? out[e].im : out[e].re;
-          const T pb = pb_ptr[offL[e]];
-          const T rho = pa[e] * pb;
-          eacc += wd * (double)rho * (double)vv;
+        for (int k = 0; k < PT; ++k) {
+          const T vv = decltype(half)::value ? pot[k].im : pot[k].re;
+          const T vb = vv * pj[b][k];  // v_ab psi_b
+          es += vb * pa[k];            // rho_ab v_ab
           if constexpr (ACC) {
-            accJ[b][e] -= vv * pa[e];
-            if (w == 2) acca[e] -= vv * pb;
+            accJ[b][k] -= vv * pa[k];
+            if (w == 2) acca[k] -= vb;
           }
         }
+        eacc += (double)w * (double)es;
       });
     });
     if constexpr (ACC) {
       T* ka = kpsi + (long long)oa * NR;
 #pragma unroll
-      for (int e = 0; e < L::VALS; ++e)
-        if (okL[e]) ka[offL[e]] += acca[e];
+      for (int k = 0; k < PT; ++k)
+        if (vA[k]) ka[offA[k]] += acca[k];
     }
   }
   if constexpr (ACC) {
@@ -247,8 +267,8 @@ __global__ void __launch_bounds__(NT) k_inv_acc(PassArgs a) {
       if (b >= td.nJ) break;
       T* kb = kpsi + (long long)(td.j0 + b) * NR;
 #pragma unroll
-      for (int e = 0; e < L::VALS; ++e)
-        if (okL[e]) kb[offL[e]] += accJ[b][e];
+      for (int k = 0; k < PT; ++k)
+        if (vA[k]) kb[offA[k]] += accJ[b][k];
     }
   }
   const double s = block_sum<NT>(eacc, red);
@@ -297,13 +317,13 @@ __global__ void __launch_bounds__(NT) k_plane_conv(PassArgs a) {
   }
   {
     cpx<T> o[LXF::VALS];
-    EXF::reg2reg(v, plane, static_cast<const cpx<T>*>(a.tw_xf), tid, o);
+    EXF::reg2reg(v, plane, static_cast<const TwEntry<T>*>(a.tw_xf), tid, o);
     EXF::store_last(o, plane, tid);
   }
   __syncthreads();
   // y forward, multiply by v(G)/N_r, y inverse (hand-over in registers)
   cpx<T> oy[LY::VALS];
-  EYF::lds2reg(plane, static_cast<const cpx<T>*>(a.tw_yf), tid, oy);
+  EYF::lds2reg(plane, static_cast<const TwEntry<T>*>(a.tw_yf), tid, oy);
 #pragma unroll
   for (int i = 0; i < LY::PER; ++i) {
     if (!LY::valid(tid, i)) continue;
@@ -317,13 +337,13 @@ __global__ void __launch_bounds__(NT) k_plane_conv(PassArgs a) {
   }
   {
     cpx<T> o[LYI::VALS];
-    EYI::reg2reg(oy, plane, static_cast<const cpx<T>*>(a.tw_yi), tid, o);
+    EYI::reg2reg(oy, plane, static_cast<const TwEntry<T>*>(a.tw_yi), tid, o);
     EYI::store_last(o, plane, tid);
   }
   __syncthreads();
   // x inverse, results straight to HBM
   cpx<T> ox[LXI::VALS];
-  EXI::lds2reg(plane, static_cast<const cpx<T>*>(a.tw_xi), tid, ox);
+  EXI::lds2reg(plane, static_cast<const TwEntry<T>*>(a.tw_xi), tid, ox);
 #pragma unroll
   for (int i = 0; i < LXI::PER; ++i) {
     if (!LXI::valid(tid, i)) continue;
@@ -355,7 +375,7 @@ __global__ void __launch_bounds__(NT) k_rows(PassArgs a) {
   const int slot = a.active[ai];
   cpx<T>* __restrict__ base = static_cast<cpx<T>*>(a.grids) + (long long)slot * NR;
   const long long row0 = (long long)rb * RW;
-  const cpx<T>* tw = static_cast<const cpx<T>*>(INV ? a.tw_xi : a.tw_xf);
+  const TwEntry<T>* tw = static_cast<const TwEntry<T>*>(INV ? a.tw_xi : a.tw_xf);
   cpx<T> v[F::VALS];
 #pragma unroll
   for (int i = 0; i < F::PER; ++i) {
@@ -416,7 +436,7 @@ __global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
           ok ? base[F::in_pos(j, r) * N + x0 + m] : cpx<T>{T(0), T(0)};
   }
   cpx<T> o[LF::VALS];
-  EF::reg2reg(v, lds, static_cast<const cpx<T>*>(a.tw_yf), tid, o);
+  EF::reg2reg(v, lds, static_cast<const TwEntry<T>*>(a.tw_yf), tid, o);
 #pragma unroll
   for (int i = 0; i < LF::PER; ++i) {
     int m = 0, j = 0;
@@ -429,7 +449,7 @@ __global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
     }
   }
   cpx<T> b[LI::VALS];
-  EI::reg2reg(o, lds, static_cast<const cpx<T>*>(a.tw_yi), tid, b);
+  EI::reg2reg(o, lds, static_cast<const TwEntry<T>*>(a.tw_yi), tid, b);
 #pragma unroll
   for (int i = 0; i < LI::PER; ++i) {
     int m = 0, j = 0;
@@ -443,6 +463,15 @@ __global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
 
 // ---------------------------------------------------------------------------
 // Registry glue: one compiled pipeline configuration.
+
+// Brick points per thread of the pair_fwd / inv_acc passes: 4 in float32,
+// 2 in float64 (keeps the tile's psi and accumulators in registers at >= 3-4
+// wavefronts per SIMD), and 4 for float64 bricks too large for 768 threads
+// (more threads per workgroup would cap the registers at 128 and spill).
+template <typename T, int N, int W>
+constexpr int pts_per_thread() {
+  return sizeof(T) == 4 ? 4 : (N * W / 2 > 768 ? 4 : 2);
+}
 template <int... R>
 constexpr void fill_radices(int* dst, int& n, Sched<R...>) {
   const int r[] = {R...};
@@ -451,21 +480,21 @@ constexpr void fill_radices(int* dst, int& n, Sched<R...>) {
 }
 
 template <typename T, int N, int W, int NTP, int TT, class SZF, class SZI, int NTQ, class SXF,
-          class SXI, class SYF, class SYI>
+          class SXI, class SYF, class SYI, int NTA = (N * W + pts_per_thread<T, N, W>() - 1) / pts_per_thread<T, N, W>()>
 struct FusedPipeline {
   static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
   static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTP, TT, SZF>), dim3(nb), dim3(NTP), 0, s, a);
+    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTA, TT, SZF>), dim3(nb), dim3(NTA), 0, s, a);
   }
   static void plane(const PassArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI>), dim3(nb), dim3(NTQ), lds, s,
                        a);
   }
   static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTP, TT, SZI, true>), dim3(nb), dim3(NTP), 0, s, a);
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTA, TT, SZI, true>), dim3(nb), dim3(NTA), 0, s, a);
   }
   static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTP, TT, SZI, false>), dim3(nb), dim3(NTP), 0, s, a);
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTA, TT, SZI, false>), dim3(nb), dim3(NTA), 0, s, a);
   }
   static hipError_t prepare() {
     return hipFuncSetAttribute(
@@ -500,11 +529,12 @@ struct FusedPipeline {
 };
 
 template <typename T, int N, int W, int NTP, int TT, class SZF, class SZI, int RW, int NTQ,
-          class SXF, class SXI, class SYF, class SYI>
+          class SXF, class SXI, class SYF, class SYI,
+          int NTA = (N * W + pts_per_thread<T, N, W>() - 1) / pts_per_thread<T, N, W>()>
 struct SplitPipeline {
   static constexpr size_t lds = (size_t)RW * (N + 1) * sizeof(cpx<T>);
   static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTP, TT, SZF>), dim3(nb), dim3(NTP), 0, s, a);
+    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTA, TT, SZF>), dim3(nb), dim3(NTA), 0, s, a);
   }
   static void rows_fwd(const PassArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXF, false>), dim3(nb), dim3(NTQ), lds, s, a);
@@ -516,10 +546,10 @@ struct SplitPipeline {
     hipLaunchKernelGGL((k_cols_conv<T, N, W, NTP, SYF, SYI>), dim3(nb), dim3(NTP), 0, s, a);
   }
   static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTP, TT, SZI, true>), dim3(nb), dim3(NTP), 0, s, a);
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTA, TT, SZI, true>), dim3(nb), dim3(NTA), 0, s, a);
   }
   static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTP, TT, SZI, false>), dim3(nb), dim3(NTP), 0, s, a);
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTA, TT, SZI, false>), dim3(nb), dim3(NTA), 0, s, a);
   }
   static hipError_t prepare() {
     hipError_t e = hipFuncSetAttribute(

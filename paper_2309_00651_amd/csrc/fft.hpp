@@ -73,6 +73,54 @@ HFX_HD cpx<T> cmul(cpx<T> a, cpx<T> w) {
   }
 }
 
+// x * c for a compile-time constant c.  In float32 the constant is carried as
+// hi + lo (hi = fl32(c), lo = fl32(c - hi)) and the product is formed as
+// fma(x, hi, x * lo): plain rounding of constants such as sqrt(1/2) or
+// sin(2 pi / 3) is one-sided and would bias the gain of every transform by
+// ~1e-8 per codelet, which accumulates over the six passes of a convolution.
+template <typename T>
+HFX_HD T mulk(T x, double c) {
+  if constexpr (sizeof(T) == 8) {
+    return x * c;
+  } else {
+    const float hi = (float)c;
+    const float lo = (float)(c - (double)hi);
+    return __builtin_fmaf(x, hi, x * lo);
+  }
+}
+
+// Stage twiddle table entry.  float64: the value itself.  float32: hi + lo
+// split of the float64 value, applied with a compensated product for the same
+// reason as mulk (no one-sided gain error from rounding the table).
+template <typename T>
+struct TwEntry {
+  cpx<T> w;
+};
+template <>
+struct TwEntry<float> {
+  cpx<float> hi, lo;
+};
+
+template <bool CONJ, typename T>
+HFX_HD cpx<T> twmul(cpx<T> a, const TwEntry<T>& t) {
+  return cmul<CONJ>(a, t.w);
+}
+template <bool CONJ>
+HFX_HD cpx<float> twmul(cpx<float> a, const TwEntry<float>& t) {
+  const cpx<float> h = t.hi, l = t.lo;
+  if constexpr (CONJ) {
+    const float re_l = a.re * l.re + a.im * l.im;
+    const float im_l = a.im * l.re - a.re * l.im;
+    return {__builtin_fmaf(a.re, h.re, __builtin_fmaf(a.im, h.im, re_l)),
+            __builtin_fmaf(a.im, h.re, __builtin_fmaf(-a.re, h.im, im_l))};
+  } else {
+    const float re_l = a.re * l.re - a.im * l.im;
+    const float im_l = a.re * l.im + a.im * l.re;
+    return {__builtin_fmaf(a.re, h.re, __builtin_fmaf(-a.im, h.im, re_l)),
+            __builtin_fmaf(a.re, h.im, __builtin_fmaf(a.im, h.re, im_l))};
+  }
+}
+
 template <int B, int E, class F>
 HFX_HD void static_for(F&& f) {
   if constexpr (B < E) {
@@ -98,17 +146,17 @@ HFX_HD cpx<T> rot(cpx<T> a) {
   } else if constexpr ((8 * k) % N == 0) {
     // odd multiple of pi/4: both parts of W have magnitude sqrt(1/2)
     constexpr SinCos sc = sincos_2pi(k, N);
-    constexpr T h = T(0.70710678118654752440084436210484903928);
+    constexpr double h = 0.70710678118654752440084436210484903928;
     constexpr int sgc = sc.c > 0 ? 1 : -1;
     constexpr int sgs = (INV ? 1 : -1) * (sc.s > 0 ? 1 : -1);  // sign of Im W
     const T x = (sgc > 0 ? a.re : -a.re) - (sgs > 0 ? a.im : -a.im);
     const T y = (sgs > 0 ? a.re : -a.re) + (sgc > 0 ? a.im : -a.im);
-    return {h * x, h * y};
+    return {mulk(x, h), mulk(y, h)};
   } else {
     constexpr SinCos sc = sincos_2pi(k, N);
-    constexpr T c = T(sc.c);
-    constexpr T s = INV ? T(sc.s) : T(-sc.s);
-    return {a.re * c - a.im * s, a.re * s + a.im * c};
+    constexpr double c = sc.c;
+    constexpr double s = INV ? sc.s : -sc.s;
+    return {mulk(a.re, c) - mulk(a.im, s), mulk(a.re, s) + mulk(a.im, c)};
   }
 }
 
@@ -134,9 +182,10 @@ struct DFT<2, INV, T> {
 template <bool INV, typename T>
 struct DFT<3, INV, T> {
   HFX_HD static void run(cpx<T>* v) {
-    constexpr T s3 = T(0.86602540378443864676372317075293618);  // sin(2pi/3)
+    constexpr double s3 = 0.86602540378443864676372317075293618;  // sin(2pi/3)
     const cpx<T> t = v[1] + v[2];
-    const cpx<T> d = cscale(v[1] - v[2], s3);
+    const cpx<T> d0 = v[1] - v[2];
+    const cpx<T> d = {mulk(d0.re, s3), mulk(d0.im, s3)};
     const cpx<T> m = {v[0].re - T(0.5) * t.re, v[0].im - T(0.5) * t.im};
     v[0] = v[0] + t;
     const cpx<T> id = mul_pi(d);  // i * s3 * (v1 - v2)
@@ -171,17 +220,19 @@ struct DFT<4, INV, T> {
 template <bool INV, typename T>
 struct DFT<5, INV, T> {
   HFX_HD static void run(cpx<T>* v) {
-    constexpr T c1 = T(0.30901699437494742410229341718281906);   // cos(2pi/5)
-    constexpr T c2 = T(-0.80901699437494742410229341718281906);  // cos(4pi/5)
-    constexpr T s1 = T(0.95105651629515357211643933337938214);   // sin(2pi/5)
-    constexpr T s2 = T(0.58778525229247312916870595463907277);   // sin(4pi/5)
+    constexpr double c1 = 0.30901699437494742410229341718281906;   // cos(2pi/5)
+    constexpr double c2 = -0.80901699437494742410229341718281906;  // cos(4pi/5)
+    constexpr double s1 = 0.95105651629515357211643933337938214;   // sin(2pi/5)
+    constexpr double s2 = 0.58778525229247312916870595463907277;   // sin(4pi/5)
     const cpx<T> a1 = v[1] + v[4], b1 = v[1] - v[4];
     const cpx<T> a2 = v[2] + v[3], b2 = v[2] - v[3];
     const cpx<T> x0 = v[0];
-    const cpx<T> p1 = {x0.re + c1 * a1.re + c2 * a2.re, x0.im + c1 * a1.im + c2 * a2.im};
-    const cpx<T> p2 = {x0.re + c2 * a1.re + c1 * a2.re, x0.im + c2 * a1.im + c1 * a2.im};
-    const cpx<T> q1 = {s1 * b1.re + s2 * b2.re, s1 * b1.im + s2 * b2.im};
-    const cpx<T> q2 = {s2 * b1.re - s1 * b2.re, s2 * b1.im - s1 * b2.im};
+    const cpx<T> p1 = {x0.re + mulk(a1.re, c1) + mulk(a2.re, c2),
+                       x0.im + mulk(a1.im, c1) + mulk(a2.im, c2)};
+    const cpx<T> p2 = {x0.re + mulk(a1.re, c2) + mulk(a2.re, c1),
+                       x0.im + mulk(a1.im, c2) + mulk(a2.im, c1)};
+    const cpx<T> q1 = {mulk(b1.re, s1) + mulk(b2.re, s2), mulk(b1.im, s1) + mulk(b2.im, s2)};
+    const cpx<T> q2 = {mulk(b1.re, s2) - mulk(b2.re, s1), mulk(b1.im, s2) - mulk(b2.im, s1)};
     const cpx<T> iq1 = mul_pi(q1), iq2 = mul_pi(q2);
     v[0] = x0 + a1 + a2;
     if constexpr (INV) {
@@ -276,7 +327,7 @@ struct Stage {
   // twiddles + codelet on registers v[PER*R]; tw holds W_{NS R}^{r k}
   // at tw[k*(R-1) + r-1] (forward sign), conjugated here for INV.
   template <bool INV>
-  HFX_HD static void compute(cpx<T>* v, int tid, const cpx<T>* __restrict__ tw) {
+  HFX_HD static void compute(cpx<T>* v, int tid, const TwEntry<T>* __restrict__ tw) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       if (!valid(tid, i)) continue;
@@ -286,7 +337,7 @@ struct Stage {
         const int k = j % NS;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          v[i * R + r] = cmul<INV>(v[i * R + r], tw[k * (R - 1) + r - 1]);
+          v[i * R + r] = twmul<INV>(v[i * R + r], tw[k * (R - 1) + r - 1]);
         }
       }
       DFT<R, INV, T>::run(v + i * R);
@@ -351,7 +402,7 @@ using LastStage = Stage<G, SchedInfo<S>::last, SchedInfo<S>::last_span>;
 // caller may write LDS again as soon as this returns.
 template <class G, bool INV, int NS, int TWOFF, int R, int... Rest>
 __device__ __forceinline__ void fft_tail(cpx<typename G::T>* lds,
-                                         const cpx<typename G::T>* __restrict__ tw, int tid,
+                                         const TwEntry<typename G::T>* __restrict__ tw, int tid,
                                          cpx<typename G::T>* out) {
   using St = Stage<G, R, NS>;
   cpx<typename G::T> v[St::VALS];
@@ -382,7 +433,7 @@ struct FFT<G, INV, Sched<R0, Rest...>> {
   // First), outputs in registers `out` (Last::VALS, element map of Last).
   // LDS must hold M*N elements with the geometry's strides.
   __device__ __forceinline__ static void reg2reg(cpx<T>* v, cpx<T>* lds,
-                                                 const cpx<T>* __restrict__ tw, int tid,
+                                                 const TwEntry<T>* __restrict__ tw, int tid,
                                                  cpx<T>* out) {
     First::template compute<INV>(v, tid, tw);
     if constexpr (sizeof...(Rest) == 0) {
@@ -396,7 +447,7 @@ struct FFT<G, INV, Sched<R0, Rest...>> {
   }
 
   // Stage-0 inputs from LDS (the caller has synchronised), outputs in registers.
-  __device__ __forceinline__ static void lds2reg(cpx<T>* lds, const cpx<T>* __restrict__ tw,
+  __device__ __forceinline__ static void lds2reg(cpx<T>* lds, const TwEntry<T>* __restrict__ tw,
                                                  int tid, cpx<T>* out) {
     cpx<T> v[First::VALS];
     First::read(v, lds, tid);

@@ -247,10 +247,20 @@ hfx_status upload(const std::vector<T>& h, void** d) {
   return HFX_OK;
 }
 
+// float64 tables hold (re, im); float32 tables hold (hi.re, hi.im, lo.re, lo.im)
+// with hi = fl32(w) and lo = fl32(w - hi) (see TwEntry in fft.hpp).
 hfx_status upload_twiddles(const int* r, int nr_, int prec, void** d) {
   const std::vector<double> t = twiddle_table(r, nr_);
   if (prec == HFX_FP64) return upload(t, d);
-  std::vector<float> f(t.begin(), t.end());
+  std::vector<float> f;
+  f.reserve(t.size() * 2);
+  for (size_t i = 0; i < t.size(); i += 2) {
+    const float hr = (float)t[i], hi = (float)t[i + 1];
+    f.push_back(hr);
+    f.push_back(hi);
+    f.push_back((float)(t[i] - (double)hr));
+    f.push_back((float)(t[i + 1] - (double)hi));
+  }
   return upload(f, d);
 }
 

@@ -1,0 +1,61 @@
+"""Full-size parity on the benchmark workloads, in the launch configuration
+bench.py times, against stored oracle values (tests/golden/*_oracle.json,
+written by tests/golden/make_golden.py, which calls only the oracle).
+
+Checked: E_x (float32 plan: |dE_x|/|E_x| <= 1e-7; float64 plan: <= 1e-12),
+<psi_i|K psi_i> for every orbital (diagonal of the exchange matrix, float32:
+relative 1e-6, i.e. ten times the energy bar per orbital), and K psi at
+seeded sample points (float32: max abs 1e-5; float64: 1e-10 relative to the
+largest sampled value).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2309_00651_amd import hfx  # noqa: E402
+from workloads import configs  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+NAMES = [n for n in ("grad72", "water96", "large128")
+         if os.path.exists(os.path.join(GOLDEN, f"{n}_oracle.json"))]
+
+
+@pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("name", NAMES)
+def test_fullsize_against_oracle(name, prec):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    with open(os.path.join(GOLDEN, f"{name}_oracle.json")) as f:
+        g = json.load(f)
+    s = configs.ALL[name]
+    assert (g["n"], g["n_orb"], g["seed"], g["kernel"]) == (s.n, s.n_orb, s.seed, s.kernel)
+    print(f"case {name} prec={prec}", flush=True)
+    dev = torch.device("cuda:0")
+    psi = torch.from_numpy(s.orbitals()).to(dev)
+    plan = hfx.Plan(hfx.SystemSpec(s.n, s.box, s.n_orb, s.kernel, s.param), prec, device=dev)
+    plan.orthonormalize(psi)
+    kpsi, ex = plan.apply_exchange(psi)
+    m = plan.exchange_matrix(psi, kpsi)
+    torch.cuda.synchronize()
+    rel = abs(float(ex[0]) - g["ex"]) / abs(g["ex"])
+    mdiag = m.view(s.n_orb, s.n_orb).diagonal().cpu().numpy()
+    ref_d = np.array(g["m_diag"])
+    dd = np.max(np.abs(mdiag - ref_d) / np.abs(ref_d))
+    flat = kpsi.view(s.n_orb, -1)
+    got = np.array([float(flat[o, p]) for o, p, _ in g["samples"]])
+    want = np.array([v for _, _, v in g["samples"]])
+    dk = np.max(np.abs(got - want))
+    print(f"  rel dE {rel:.2e}  max rel dM_ii {dd:.2e}  max dK(samples) {dk:.2e}", flush=True)
+    if prec == hfx.FP32:
+        assert rel <= 1e-7
+        assert dd <= 1e-6
+        assert dk <= 1e-5
+    else:
+        assert rel <= 1e-12
+        assert dd <= 1e-11
+        assert dk <= 1e-10 * np.max(np.abs(want))
