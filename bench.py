@@ -80,6 +80,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--options", default=None, help="plan options, e.g. 'tiles=2'")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -102,7 +103,7 @@ def main():
     n_pairs = system.n_pairs
 
     def run(prec, steps, warmup, profile):
-        plan = hfx.Plan(spec, prec, device=dev)
+        plan = hfx.Plan(spec, prec, options=args.options, device=dev)
         p = psi0.clone()
         kpsi = torch.empty(p.shape, dtype=plan.kpsi_dtype, device=dev)
         ex = torch.empty(1, dtype=torch.float64, device=dev)
@@ -201,7 +202,8 @@ def main():
                                f"erfc w={system.param}; step = orthonormalise + K psi (all "
                                f"{n_pairs} pairs) + E_x + exchange matrix",
                    "n": system.n, "n_orb": system.n_orb, "pairs": n_pairs,
-                   "precision": "fp32 FFT/kernel, fp64 orthonormalisation and sums"},
+                   "precision": "fp32 FFT/kernel, fp64 orthonormalisation and sums",
+                   "plan_options": args.options},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,
