@@ -36,7 +36,10 @@
  *
  * Streams: work is enqueued asynchronously on `stream` (a hipStream_t, NULL
  * for the default stream); no call synchronises the device except
- * hfx_plan_create and hfx_plan_destroy.
+ * hfx_plan_create and hfx_plan_destroy.  A plan with several systems forks
+ * them onto its own streams (default priority) after an event recorded on
+ * `stream` and joins them back before returning, so they overlap on the GPU
+ * while the caller sees ordinary stream order.
  *
  * Errors: status codes only.  Arguments are validated before any HIP call;
  * HIP failures map to HFX_EDEVICE.  hfx_last_error() returns a thread-local
@@ -168,6 +171,25 @@ typedef enum {
 hfx_status hfx_profile_enable(hfx_plan plan, int enable);
 hfx_status hfx_profile_read(hfx_plan plan, double* ms_host, double* bytes_host,
                             double* flops_host, long long* launches_host, int n);
+
+/*
+ * Graphs: capture the complete launch sequence of one call for the given
+ * buffers into a HIP graph, then replay it with hfx_graph_launch on any
+ * stream (the same buffers are reused on every replay; their contents may
+ * change).  Operations: HFX_GRAPH_ENERGY (hfx_exchange_energy; kpsi, m unused),
+ * HFX_GRAPH_APPLY (hfx_apply_exchange; ex nullable, m unused), HFX_GRAPH_STEP
+ * (hfx_orthonormalize of psi in place, hfx_apply_exchange, then
+ * hfx_exchange_matrix; ex nullable).  Capture runs on a plan-owned stream and
+ * launches nothing; the plan must outlive its graphs.  Systems of a batched
+ * plan become parallel branches of one graph.
+ */
+typedef struct hfx_graph_t* hfx_graph;
+typedef enum { HFX_GRAPH_ENERGY = 0, HFX_GRAPH_APPLY = 1, HFX_GRAPH_STEP = 2 } hfx_graph_op;
+
+hfx_status hfx_graph_create(hfx_plan plan, int op, double* psi, void* kpsi, double* ex,
+                            double* m, void* ws, size_t ws_bytes, hfx_graph* out);
+hfx_status hfx_graph_launch(hfx_graph graph, void* stream);
+hfx_status hfx_graph_destroy(hfx_graph graph);
 
 /* Static description of a status code. */
 const char* hfx_status_string(hfx_status s);

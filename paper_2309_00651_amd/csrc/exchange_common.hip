@@ -29,20 +29,26 @@ __global__ void __launch_bounds__(256) k_zero(uint4* __restrict__ p, size_t n16,
     for (size_t i = threadIdx.x; i < ntail; i += blockDim.x) tail[i] = 0;
 }
 
-// out[0] = scale * sum(partials), summed in a fixed order by one workgroup.
+// out[0] = scale * sum(partials) + dc_scale * sum(mean^2), summed in a fixed
+// order by one workgroup.  The second term is the G = 0 part of the pair
+// energies when the pair-density means were taken out of the transforms.
 __global__ void __launch_bounds__(256) k_energy_reduce(const double* __restrict__ partials,
                                                        long long n, double scale,
+                                                       const double* __restrict__ mean,
+                                                       long long nmean, double dc_scale,
                                                        double* __restrict__ out) {
   __shared__ double red[256];
-  double s = 0.0;
+  double s = 0.0, d = 0.0;
   for (long long i = threadIdx.x; i < n; i += 256) s += partials[i];
-  red[threadIdx.x] = s;
+  if (mean)
+    for (long long i = threadIdx.x; i < nmean; i += 256) d += mean[i] * mean[i];
+  red[threadIdx.x] = scale * s + dc_scale * d;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = scale * red[0];
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 template <typename S>
@@ -88,9 +94,10 @@ void launch_scale_to_f64(const void* src, int src_is_f64, double* dst, size_t n,
                        static_cast<const float*>(src), dst, n, scale, gscale);
 }
 
-void launch_energy_reduce(const double* partials, long long n, double scale, double* out,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, s, partials, n, scale, out);
+void launch_energy_reduce(const double* partials, long long n, double scale, const double* mean,
+                          int n_orb, double dc_scale, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, s, partials, n, scale, mean,
+                     (long long)n_orb * n_orb, dc_scale, out);
 }
 
 }  // namespace hfx

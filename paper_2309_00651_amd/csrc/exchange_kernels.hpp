@@ -56,13 +56,16 @@ constexpr int pow2_at_least() {
 
 // ---------------------------------------------------------------------------
 // Pass 1: pair product + forward z FFT on bricks.
-// Thread tid forms the products at brick points p = tid + k NT (k < PT,
-// contiguous x for coalesced psi reads) and writes them to LDS in natural
-// order; the transform starts from there and its last stage stores straight
-// to HBM.  psi of the tile's J block stays in registers for the whole tile.
+// Two pair grids are transformed together: LDS holds [z][2W] with the brick
+// of grid g in columns [gW, gW + W).  Thread tid forms the products at brick
+// points p = tid + k NT (k < PT, contiguous x for coalesced psi reads) for both
+// grids; the transform starts from LDS and its last stage stores straight to
+// HBM.  psi of the tile's J block stays in registers for the whole tile.
 template <typename T, int N, int W, int NT, int TT, class SZF>
 __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
-  using G = Geom<T, N, W, NT, true, W, 1>;
+  static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
+  constexpr int W2 = 2 * W;
+  using G = Geom<T, N, W2, NT, true, W2, 1>;
   using L = LastStage<G, SZF>;
   using E = FFT<G, false, SZF>;
   constexpr int RL = SchedInfo<SZF>::last;
@@ -72,7 +75,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   constexpr int PT = (P + NT - 1) / NT;
   constexpr long long NR = (long long)N * N * N;
   constexpr int ZSL = (N / RL) * N * N;  // offset between legs of a last-stage butterfly
-  __shared__ cpx<T> lds[N * W];
+  __shared__ cpx<T> lds[N * W2];
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const int t = lg / BR, br = lg - t * BR;
@@ -82,7 +85,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   const TwEntry<T>* __restrict__ tw = static_cast<const TwEntry<T>*>(a.tw_zf);
   cpx<T>* __restrict__ grids = static_cast<cpx<T>*>(a.grids);
 
-  int offA[PT];
+  int offA[PT], ldsA[PT];
   bool vA[PT];
 #pragma unroll
   for (int k = 0; k < PT; ++k) {
@@ -90,15 +93,18 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
     const int z = p / W, m = p - (p / W) * W;
     vA[k] = p < P && (x0 + m) < N;
     offA[k] = vA[k] ? (z * N + y) * N + x0 + m : 0;
+    ldsA[k] = z * W2 + m;
   }
-  int offL[L::PER];
+  int offL[L::PER], gL[L::PER];
   bool vL[L::PER];
 #pragma unroll
   for (int i = 0; i < L::PER; ++i) {
     int m = 0, j = 0;
     L::mj(tid, i, m, j);
-    vL[i] = L::valid(tid, i) && (x0 + m) < N;
-    offL[i] = vL[i] ? (j * N + y) * N + x0 + m : 0;
+    gL[i] = m / W;
+    const int mx = m - gL[i] * W;
+    vL[i] = L::valid(tid, i) && (x0 + mx) < N;
+    offL[i] = vL[i] ? (j * N + y) * N + x0 + mx : 0;
   }
 
   T pj[TT][PT];
@@ -115,40 +121,60 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
     T pa[PT];
 #pragma unroll
     for (int k = 0; k < PT; ++k) pa[k] = vA[k] ? pa_ptr[offA[k]] : T(0);
-    static_for<0, TT / 2>([&](auto bp) {
-      constexpr int b0 = 2 * decltype(bp)::value, b1 = b0 + 1;
-      if (b0 >= td.nJ) return;
-      if (td.diag && b1 < ia) return;
+    static_for<0, TT / 4>([&](auto bq) {
+      constexpr int b0 = 4 * decltype(bq)::value;  // pairs (a, b0 .. b0 + 3), grids 2bq, 2bq+1
+      // grid g carries pairs (a, b0 + 2g) and (a, b0 + 2g + 1)
+      const bool use0 = b0 < td.nJ && !(td.diag && b0 + 1 < ia);
+      const bool use1 = b0 + 2 < td.nJ && !(td.diag && b0 + 3 < ia);
+      if (!use0 && !use1) return;
+      // pair-density means (float32 plans): transforms see zero-mean densities
+      T mu[4] = {T(0), T(0), T(0), T(0)};
+      if (a.mean) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (b0 + q < td.nJ) mu[q] = (T)a.mean[(long long)(td.i0 + ia) * a.n_orb + td.j0 + b0 + q];
+      }
 #pragma unroll
       for (int k = 0; k < PT; ++k)
-        if (tid + k * NT < P) lds[tid + k * NT] = {pa[k] * pj[b0][k], pa[k] * pj[b1][k]};
+        if (tid + k * NT < P) {
+          const T in = vA[k] ? T(1) : T(0);  // columns beyond the grid stay zero
+          lds[ldsA[k]] = {pa[k] * pj[b0][k] - in * mu[0], pa[k] * pj[b0 + 1][k] - in * mu[1]};
+          lds[ldsA[k] + W] = {pa[k] * pj[b0 + 2][k] - in * mu[2],
+                              pa[k] * pj[b0 + 3][k] - in * mu[3]};
+        }
       __syncthreads();
       cpx<T> out[L::VALS];
       E::lds2reg(lds, tw, tid, out);
-      cpx<T>* g = grids + (long long)(td.slot0 + ia * (TT / 2) + decltype(bp)::value) * NR;
+      const int slot0 = td.slot0 + ia * (TT / 2) + 2 * decltype(bq)::value;
 #pragma unroll
-      for (int i = 0; i < L::PER; ++i)
-        if (vL[i])
+      for (int i = 0; i < L::PER; ++i) {
+        const bool use = gL[i] == 0 ? use0 : use1;
+        if (vL[i] && use) {
+          cpx<T>* g = grids + (long long)(slot0 + gL[i]) * NR;
 #pragma unroll
           for (int r = 0; r < RL; ++r) g[offL[i] + r * ZSL] = out[i * RL + r];
+        }
+      }
     });
   }
 }
 
 // ---------------------------------------------------------------------------
 // Pass 3: inverse z FFT + pair energies + K psi accumulation on bricks.
-// The inverse transform leaves the potentials of one grid in LDS in natural
-// order; the accumulation then uses its own point map: thread tid owns brick
-// points p = tid + k NT (k < PT), i.e. contiguous x for coalesced K psi
-// traffic.  psi of the tile's J block and the J-side accumulators stay in
-// registers for the whole tile; the pair energy of a thread's points is
-// summed in the working precision per pair and added to a float64
-// accumulator once per pair.
+// Two pair grids are transformed together ([z][2W] in LDS, as in pass 1).
+// The inverse transform leaves the potentials in LDS in natural order; the
+// accumulation then uses its own point map: thread tid owns brick points
+// p = tid + k NT (k < PT), contiguous x for coalesced K psi traffic.  psi of
+// the tile's J block and the J-side accumulators stay in registers for the
+// whole tile; the pair energy of a thread's points is summed in the working
+// precision per pair and added to a float64 accumulator once per pair.
 template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC>
-__global__ void __launch_bounds__(NT) k_inv_acc(PassArgs a) {
-  using G = Geom<T, N, W, NT, true, W, 1>;
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && N >= 64 && N <= 96) ? 4 : 1)))
+k_inv_acc(PassArgs a) {
+  static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
+  constexpr int W2 = 2 * W;
+  using G = Geom<T, N, W2, NT, true, W2, 1>;
   using F = FirstStage<G, SZI>;
-  using L = LastStage<G, SZI>;
   using E = FFT<G, true, SZI>;
   constexpr int RF = SchedInfo<SZI>::first;
   constexpr int NXB = (N + W - 1) / W;
@@ -157,7 +183,7 @@ __global__ void __launch_bounds__(NT) k_inv_acc(PassArgs a) {
   constexpr int PT = (P + NT - 1) / NT;    // accumulation points per thread
   constexpr long long NR = (long long)N * N * N;
   constexpr int ZSF = (N / RF) * N * N;    // offset between legs of a first-stage butterfly
-  __shared__ cpx<T> lds[N * W];
+  __shared__ cpx<T> lds[N * W2];
   __shared__ double red[pow2_at_least<NT>()];
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
@@ -169,16 +195,18 @@ __global__ void __launch_bounds__(NT) k_inv_acc(PassArgs a) {
   const TwEntry<T>* __restrict__ tw = static_cast<const TwEntry<T>*>(a.tw_zi);
   const cpx<T>* __restrict__ grids = static_cast<const cpx<T>*>(a.grids);
 
-  int offF[F::PER];
+  int offF[F::PER], gF[F::PER];
   bool vF[F::PER];
 #pragma unroll
   for (int i = 0; i < F::PER; ++i) {
     int m = 0, j = 0;
     F::mj(tid, i, m, j);
-    vF[i] = F::valid(tid, i) && (x0 + m) < N;
-    offF[i] = vF[i] ? (j * N + y) * N + x0 + m : 0;
+    gF[i] = m / W;
+    const int mx = m - gF[i] * W;
+    vF[i] = F::valid(tid, i) && (x0 + mx) < N;
+    offF[i] = vF[i] ? (j * N + y) * N + x0 + mx : 0;
   }
-  int offA[PT];
+  int offA[PT], ldsA[PT];
   bool vA[PT];
 #pragma unroll
   for (int k = 0; k < PT; ++k) {
@@ -186,6 +214,7 @@ __global__ void __launch_bounds__(NT) k_inv_acc(PassArgs a) {
     const int z = p / W, m = p - (p / W) * W;
     vA[k] = p < P && (x0 + m) < N;
     offA[k] = vA[k] ? (z * N + y) * N + x0 + m : 0;
+    ldsA[k] = z * W2 + m;
   }
 
   T pj[TT][PT];
@@ -212,47 +241,59 @@ __global__ void __launch_bounds__(NT) k_inv_acc(PassArgs a) {
       pa[k] = vA[k] ? pa_ptr[offA[k]] : T(0);
       acca[k] = T(0);
     }
-    static_for<0, TT / 2>([&](auto bp) {
-      constexpr int b0 = 2 * decltype(bp)::value;
-      if (b0 >= td.nJ) return;
-      if (td.diag && b0 + 1 < ia) return;
-      const cpx<T>* g = grids + (long long)(td.slot0 + ia * (TT / 2) + decltype(bp)::value) * NR;
+    static_for<0, TT / 4>([&](auto bq) {
+      constexpr int b0 = 4 * decltype(bq)::value;
+      const bool use0 = b0 < td.nJ && !(td.diag && b0 + 1 < ia);
+      const bool use1 = b0 + 2 < td.nJ && !(td.diag && b0 + 3 < ia);
+      if (!use0 && !use1) return;
+      const int slot0 = td.slot0 + ia * (TT / 2) + 2 * decltype(bq)::value;
       cpx<T> v[F::VALS];
 #pragma unroll
-      for (int i = 0; i < F::PER; ++i)
+      for (int i = 0; i < F::PER; ++i) {
+        const bool use = gF[i] == 0 ? use0 : use1;
+        const cpx<T>* g = grids + (long long)(slot0 + gF[i]) * NR;
 #pragma unroll
         for (int r = 0; r < RF; ++r)
-          v[i * RF + r] = vF[i] ? g[offF[i] + r * ZSF] : cpx<T>{T(0), T(0)};
+          v[i * RF + r] = (vF[i] && use) ? g[offF[i] + r * ZSF] : cpx<T>{T(0), T(0)};
+      }
       {
-        cpx<T> out[L::VALS];
+        cpx<T> out[LastStage<G, SZI>::VALS];
         E::reg2reg(v, lds, tw, tid, out);
         E::store_last(out, lds, tid);
       }
       __syncthreads();
+      // one grid's potentials at a time (bounded registers)
       cpx<T> pot[PT];
+      static_for<0, 4>([&](auto q) {
+        constexpr int gq = decltype(q)::value / 2, half = decltype(q)::value % 2;
+        constexpr int b = b0 + decltype(q)::value;
+        if constexpr (half == 0) {
 #pragma unroll
-      for (int k = 0; k < PT; ++k)
-        pot[k] = (tid + k * NT < P) ? lds[tid + k * NT] : cpx<T>{T(0), T(0)};
-      __syncthreads();  // LDS is rewritten by the next transform
-      static_for<0, 2>([&](auto half) {
-        constexpr int b = b0 + decltype(half)::value;
+          for (int k = 0; k < PT; ++k)
+            pot[k] = tid + k * NT < P ? lds[ldsA[k] + gq * W] : cpx<T>{T(0), T(0)};
+        }
         if (b >= td.nJ) return;
+        if (!(gq == 0 ? use0 : use1)) return;
         // weight of e_ab in sum_{i,j} e_ij: 2 for a != b, 1 for a == b
         const int w = td.diag ? (b > ia ? 2 : (b == ia ? 1 : 0)) : 2;
         if (w == 0) return;
+        // G = 0 part of v_ab when the mean was taken out of the transform;
+        // its energy v0 * Omega * mu_ab^2 is added in float64 at the reduction
+        const T dc = a.mean ? (T)(a.v0 * a.mean[(long long)oa * a.n_orb + td.j0 + b]) : T(0);
         T es = T(0);
 #pragma unroll
         for (int k = 0; k < PT; ++k) {
-          const T vv = decltype(half)::value ? pot[k].im : pot[k].re;
-          const T vb = vv * pj[b][k];  // v_ab psi_b
-          es += vb * pa[k];            // rho_ab v_ab
+          const T vz = half ? pot[k].im : pot[k].re;  // zero-mean part
+          es += vz * pj[b][k] * pa[k];                        // rho_ab v_ab
           if constexpr (ACC) {
+            const T vv = vz + dc;
             accJ[b][k] -= vv * pa[k];
-            if (w == 2) acca[k] -= vb;
+            if (w == 2) acca[k] -= vv * pj[b][k];
           }
         }
         eacc += (double)w * (double)es;
       });
+      __syncthreads();  // LDS is rewritten by the next transform
     });
     if constexpr (ACC) {
       T* ka = kpsi + (long long)oa * NR;

@@ -89,36 +89,17 @@ HFX_HD T mulk(T x, double c) {
   }
 }
 
-// Stage twiddle table entry.  float64: the value itself.  float32: hi + lo
-// split of the float64 value, applied with a compensated product for the same
-// reason as mulk (no one-sided gain error from rounding the table).
+// Stage twiddle table entry.  float32 tables hold norm-optimised values
+// (unit_f32 in twiddle.hpp), so a plain complex product keeps the transform
+// gain unbiased.
 template <typename T>
 struct TwEntry {
   cpx<T> w;
-};
-template <>
-struct TwEntry<float> {
-  cpx<float> hi, lo;
 };
 
 template <bool CONJ, typename T>
 HFX_HD cpx<T> twmul(cpx<T> a, const TwEntry<T>& t) {
   return cmul<CONJ>(a, t.w);
-}
-template <bool CONJ>
-HFX_HD cpx<float> twmul(cpx<float> a, const TwEntry<float>& t) {
-  const cpx<float> h = t.hi, l = t.lo;
-  if constexpr (CONJ) {
-    const float re_l = a.re * l.re + a.im * l.im;
-    const float im_l = a.im * l.re - a.re * l.im;
-    return {__builtin_fmaf(a.re, h.re, __builtin_fmaf(a.im, h.im, re_l)),
-            __builtin_fmaf(a.im, h.re, __builtin_fmaf(-a.re, h.im, im_l))};
-  } else {
-    const float re_l = a.re * l.re - a.im * l.im;
-    const float im_l = a.re * l.im + a.im * l.re;
-    return {__builtin_fmaf(a.re, h.re, __builtin_fmaf(-a.im, h.im, re_l)),
-            __builtin_fmaf(a.re, h.im, __builtin_fmaf(a.im, h.re, im_l))};
-  }
 }
 
 template <int B, int E, class F>

@@ -21,7 +21,7 @@ namespace hfx {
 namespace {
 constexpr int TM = 64;        // C tile
 constexpr int KB = 32;        // grid points per LDS stage
-constexpr int KFOLD = 256;    // float32 accumulation length before folding
+constexpr int KFOLD = 32;     // float32 accumulation length before folding
 constexpr int PAD = 1;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));

@@ -68,6 +68,8 @@ struct SystemPlan {
   // offsets inside the caller's workspace
   size_t off_psi32 = 0, off_grids = 0, off_partials = 0, off_gemm = 0, off_ortho = 0;
   size_t off_grad = 0;  // float32 K psi staging of the gradient (float32 plans)
+  size_t off_mean = 0;  // float32 plans: pair-density means (n_orb x n_orb float64)
+  double v0 = 0.0;      // v(G = 0)
   size_t ws_end = 0;
   // offsets inside concatenated user buffers
   long long psi_off = 0, m_off = 0;
@@ -88,8 +90,21 @@ struct hfx_plan_t {
   size_t ws_bytes = 0;
   int device = 0;
   bool prof = false;
+  bool capturing = false;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
+  // multi-system plans: one side stream per system (default priority) and
+  // fork/join events; capture stream for graphs
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipStream_t cap = nullptr;
+};
+
+struct hfx_graph_t {
+  hfx_plan plan = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -208,8 +223,10 @@ void build_schedule(SystemPlan& sp, long long tiles_cap) {
   sp.n_partials = part;
 }
 
+// v(G)/N_r on the FFT grid.  zero_dc: store 0 at G = 0 (float32 plans take the
+// G = 0 term out of the transforms, see run_exchange).
 template <typename T>
-std::vector<T> kernel_table(const hfx_system& s, int n) {
+std::vector<T> kernel_table(const hfx_system& s, int n, bool zero_dc) {
   const double pi = 3.14159265358979323846;
   const double om = s.L[0] * s.L[1] * s.L[2];
   const double nr = (double)n * n * n;
@@ -237,7 +254,17 @@ std::vector<T> kernel_table(const hfx_system& s, int n) {
         }
         out[((size_t)z * n + y) * n + x] = T(v / nr);
       }
+  if (zero_dc) out[0] = T(0);
   return out;
+}
+
+double kernel_g0(const hfx_system& s) {
+  const double pi = 3.14159265358979323846;
+  if (s.kernel == HFX_KERNEL_TRUNCATED) {
+    const double rc = std::cbrt(3.0 * s.L[0] * s.L[1] * s.L[2] / (4.0 * pi));
+    return 2 * pi * rc * rc;
+  }
+  return pi / (s.param * s.param);
 }
 
 template <typename T>
@@ -247,20 +274,13 @@ hfx_status upload(const std::vector<T>& h, void** d) {
   return HFX_OK;
 }
 
-// float64 tables hold (re, im); float32 tables hold (hi.re, hi.im, lo.re, lo.im)
-// with hi = fl32(w) and lo = fl32(w - hi) (see TwEntry in fft.hpp).
+// float64 tables hold (re, im); float32 tables hold norm-optimised values
+// (unit_f32 in twiddle.hpp).
 hfx_status upload_twiddles(const int* r, int nr_, int prec, void** d) {
   const std::vector<double> t = twiddle_table(r, nr_);
   if (prec == HFX_FP64) return upload(t, d);
-  std::vector<float> f;
-  f.reserve(t.size() * 2);
-  for (size_t i = 0; i < t.size(); i += 2) {
-    const float hr = (float)t[i], hi = (float)t[i + 1];
-    f.push_back(hr);
-    f.push_back(hi);
-    f.push_back((float)(t[i] - (double)hr));
-    f.push_back((float)(t[i + 1] - (double)hi));
-  }
+  std::vector<float> f(t.size());
+  for (size_t i = 0; i < t.size(); i += 2) unit_f32(t[i], t[i + 1], &f[i], &f[i + 1]);
   return upload(f, d);
 }
 
@@ -302,12 +322,12 @@ struct Bracket {
   hipStream_t st;
   hipEvent_t start = nullptr;
   Bracket(hfx_plan p, int ps, hipStream_t s) : plan(p), pass(ps), st(s) {
-    if (!plan->prof) return;
+    if (!plan->prof || plan->capturing) return;
     start = take_event(plan);
     if (start) (void)hipEventRecord(start, st);
   }
   void done(double bytes, double flops) {
-    if (!plan->prof || !start) return;
+    if (!plan->prof || plan->capturing || !start) return;
     hipEvent_t stop = take_event(plan);
     if (!stop) return;
     (void)hipEventRecord(stop, st);
@@ -352,6 +372,20 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
     br.done(orb_pts * 12.0, 0.0);
     psi_w = p32;
   }
+  // float32 plans: exact pair-density means mu_ab = (1/N_r) sum_r psi_a psi_b
+  // (float64 MFMA).  Transforming rho_ab - mu_ab keeps the large G = 0
+  // coefficient out of the float32 FFTs; v(0) mu_ab is added back to the
+  // potentials and v(0) Omega mu_ab^2 to the energy in float64.
+  const double* mean = nullptr;
+  if (plan->prec == HFX_FP32) {
+    double* mu = reinterpret_cast<double*>(ws + sp.off_mean);
+    double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
+    Bracket br(plan, HFX_PASS_CONTRACT, st);
+    launch_xtx_f64(psi, psi, sp.sys.n_orb, sp.nr, 1.0 / (double)sp.nr, part, sp.gemm_chunks, mu,
+                   st);
+    br.done(orb_pts * 8.0, 2.0 * (double)sp.sys.n_orb * orb_pts);
+    mean = mu;
+  }
   if (acc) {
     Bracket br(plan, HFX_PASS_ZERO, st);
     launch_zero(kpsi, (size_t)sp.sys.n_orb * sp.nr * elem, st);
@@ -370,6 +404,8 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   a.tw_yf = sp.tw[4];
   a.tw_yi = sp.tw[5];
   a.partials = partials;
+  a.mean = mean;
+  a.v0 = sp.v0;
   a.n_orb = sp.sys.n_orb;
   const int br = bricks_per_tile(v);
   const int n = v->n;
@@ -428,10 +464,100 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   }
   if (ex) {
     Bracket bk(plan, HFX_PASS_ENERGY_REDUCE, st);
-    launch_energy_reduce(partials, sp.n_partials, -0.5 * sp.dv, ex, st);
+    const double om = sp.dv * (double)sp.nr;
+    launch_energy_reduce(partials, sp.n_partials, -0.5 * sp.dv, mean, sp.sys.n_orb,
+                         -0.5 * om * sp.v0, ex, st);
     bk.done((double)sp.n_partials * 8.0, 0.0);
   }
   HIP_TRY(hipGetLastError());
+  return HFX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Per-system launch sequences of each entry point.
+
+hfx_status enq_energy(hfx_plan plan, SystemPlan& sp, const double* psi, double* ex, char* ws,
+                      hipStream_t st) {
+  return run_exchange(plan, sp, psi + sp.psi_off, nullptr, ex, ws, st, false);
+}
+
+hfx_status enq_apply(hfx_plan plan, SystemPlan& sp, const double* psi, void* kpsi, double* ex,
+                     char* ws, hipStream_t st) {
+  const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
+  void* kp = static_cast<char*>(kpsi) + (size_t)sp.psi_off * elem;
+  return run_exchange(plan, sp, psi + sp.psi_off, kp, ex, ws, st, true);
+}
+
+hfx_status enq_gradient(hfx_plan plan, SystemPlan& sp, const double* psi, const double* gscale,
+                        double* grad, char* ws, hipStream_t st) {
+  double* g = grad + sp.psi_off;
+  void* kp = plan->prec == HFX_FP64 ? static_cast<void*>(g) : static_cast<void*>(ws + sp.off_grad);
+  hfx_status s = run_exchange(plan, sp, psi + sp.psi_off, kp, nullptr, ws, st, true);
+  if (s != HFX_OK) return s;
+  Bracket bk(plan, HFX_PASS_SCALE, st);
+  launch_scale_to_f64(kp, plan->prec == HFX_FP64, g, (size_t)sp.sys.n_orb * sp.nr, 2.0 * sp.dv,
+                      gscale, st);
+  bk.done((double)sp.sys.n_orb * sp.nr * (plan->prec == HFX_FP64 ? 16.0 : 12.0), 0.0);
+  HIP_TRY(hipGetLastError());
+  return HFX_OK;
+}
+
+hfx_status enq_matrix(hfx_plan plan, SystemPlan& sp, const double* psi, const void* kpsi,
+                      double* m, char* ws, hipStream_t st) {
+  const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
+  double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
+  const char* kp = static_cast<const char*>(kpsi) + (size_t)sp.psi_off * elem;
+  const double nn = (double)sp.sys.n_orb, npts = (double)sp.nr;
+  Bracket bk(plan, HFX_PASS_CONTRACT, st);
+  if (plan->prec == HFX_FP32)
+    launch_xtx_split(psi + sp.psi_off, reinterpret_cast<const float*>(kp), sp.sys.n_orb, sp.nr,
+                     sp.dv, part, sp.gemm_chunks, m + sp.m_off, st);
+  else
+    launch_xtx_f64(psi + sp.psi_off, reinterpret_cast<const double*>(kp), sp.sys.n_orb, sp.nr,
+                   sp.dv, part, sp.gemm_chunks, m + sp.m_off, st);
+  // split precision: two float32 products per term
+  bk.done(nn * npts * (8.0 + elem), 2.0 * nn * nn * npts * (plan->prec == HFX_FP32 ? 2.0 : 1.0));
+  HIP_TRY(hipGetLastError());
+  return HFX_OK;
+}
+
+hfx_status enq_ortho(hfx_plan plan, SystemPlan& sp, double* psi, char* ws, hipStream_t st) {
+  const int n = sp.sys.n_orb;
+  double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
+  double* work = reinterpret_cast<double*>(ws + sp.off_ortho);
+  double* smat = work;                     // n x n overlap, replaced by S^(-1/2)
+  double* ns_work = work + (size_t)n * n;  // 5 n^2 doubles + flags
+  double* tmp = reinterpret_cast<double*>(ws + align_up(sp.off_ortho + (size_t)6 * n * n * 8 + 64));
+  double* p = psi + sp.psi_off;
+  const double nn = n, npts = (double)sp.nr;
+  {
+    Bracket bk(plan, HFX_PASS_CONTRACT, st);
+    launch_xtx_f64(p, p, n, sp.nr, sp.dv, part, sp.gemm_chunks, smat, st);
+    bk.done(nn * npts * 8.0, 2.0 * nn * nn * npts);
+  }
+  Bracket bk(plan, HFX_PASS_ORTHO, st);
+  HIP_TRY(launch_inverse_sqrt(smat, n, ns_work, 60, st));
+  launch_apply_left(smat, p, n, sp.nr, tmp, st);
+  bk.done(nn * npts * 16.0, 2.0 * nn * nn * npts);
+  HIP_TRY(hipGetLastError());
+  return HFX_OK;
+}
+
+// Runs fn(system, stream) for every system.  One system: on the caller's
+// stream.  Several: forked onto the plan's side streams after an event on the
+// caller's stream and joined back with one event per system, so independent
+// systems overlap while the call keeps stream semantics.
+template <class F>
+hfx_status dispatch(hfx_plan plan, hipStream_t user, F&& fn) {
+  if (plan->sys.size() == 1) return fn(0, user);
+  HIP_TRY(hipEventRecord(plan->fork, user));
+  for (size_t i = 0; i < plan->sys.size(); ++i) {
+    HIP_TRY(hipStreamWaitEvent(plan->side[i], plan->fork, 0));
+    hfx_status s = fn(i, plan->side[i]);
+    if (s != HFX_OK) return s;
+    HIP_TRY(hipEventRecord(plan->join[i], plan->side[i]));
+    HIP_TRY(hipStreamWaitEvent(user, plan->join[i], 0));
+  }
   return HFX_OK;
 }
 
@@ -507,6 +633,8 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     off = align_up(off + (size_t)tiles * tiles * sp.gemm_chunks * 64 * 64 * 8);
     sp.off_grad = off;
     if (precision == HFX_FP32) off = align_up(off + (size_t)sys[i].n_orb * sp.nr * 4);
+    sp.off_mean = off;
+    if (precision == HFX_FP32) off = align_up(off + (size_t)sys[i].n_orb * sys[i].n_orb * 8);
     sp.off_ortho = off;
     off = align_up(off + (size_t)6 * sys[i].n_orb * sys[i].n_orb * 8 + 64);
     off = align_up(off + (size_t)sys[i].n_orb * std::min<long long>(sp.nr, 32768) * 8);
@@ -534,10 +662,11 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
       if (e != hipSuccess)
         return cleanup(fail(HFX_EDEVICE, std::string("kernel set-up: ") + hipGetErrorString(e)));
     }
+    sp.v0 = kernel_g0(sp.sys);
     if (precision == HFX_FP64)
-      s = upload(kernel_table<double>(sp.sys, sp.n), &sp.vtab);
+      s = upload(kernel_table<double>(sp.sys, sp.n, false), &sp.vtab);
     else
-      s = upload(kernel_table<float>(sp.sys, sp.n), &sp.vtab);
+      s = upload(kernel_table<float>(sp.sys, sp.n, true), &sp.vtab);
     if (s != HFX_OK) return cleanup(s);
     const Variant* v = sp.var;
     const int* rs[6] = {v->zf, v->zi, v->xf, v->xi, v->yf, v->yi};
@@ -553,6 +682,19 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     s = upload(sp.active, &d);
     if (s != HFX_OK) return cleanup(s);
     sp.d_active = static_cast<int*>(d);
+  }
+  if (p->sys.size() > 1) {
+    if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess)
+      return cleanup(fail(HFX_EDEVICE, "event creation failed"));
+    for (size_t i = 0; i < p->sys.size(); ++i) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+        return cleanup(fail(HFX_EDEVICE, "stream/event creation failed"));
+      p->side.push_back(st);
+      p->join.push_back(ev);
+    }
   }
   *out = p;
   return HFX_OK;
@@ -602,6 +744,10 @@ hfx_status hfx_plan_destroy(hfx_plan plan) {
     (void)hipEventDestroy(r.stop);
   }
   for (auto& ev : plan->pool) (void)hipEventDestroy(ev);
+  for (auto& st : plan->side) (void)hipStreamDestroy(st);
+  for (auto& ev : plan->join) (void)hipEventDestroy(ev);
+  if (plan->fork) (void)hipEventDestroy(plan->fork);
+  if (plan->cap) (void)hipStreamDestroy(plan->cap);
   for (auto& sp : plan->sys) free_system(sp);
   delete plan;
   if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("pending device error: ") + hipGetErrorString(e));
@@ -620,14 +766,9 @@ hfx_status hfx_exchange_energy(hfx_plan plan, const double* psi, double* ex, voi
   hfx_status s = check_call(plan, psi, ws, ws_bytes);
   if (s != HFX_OK) return s;
   if (!ex) return fail(HFX_EINVAL, "null ex");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  for (size_t i = 0; i < plan->sys.size(); ++i) {
-    SystemPlan& sp = plan->sys[i];
-    s = run_exchange(plan, sp, psi + sp.psi_off, nullptr, ex + i, static_cast<char*>(ws), st,
-                     false);
-    if (s != HFX_OK) return s;
-  }
-  return HFX_OK;
+  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
+    return enq_energy(plan, plan->sys[i], psi, ex + i, static_cast<char*>(ws), st);
+  });
 }
 
 hfx_status hfx_apply_exchange(hfx_plan plan, const double* psi, void* kpsi, double* ex,
@@ -635,16 +776,10 @@ hfx_status hfx_apply_exchange(hfx_plan plan, const double* psi, void* kpsi, doub
   hfx_status s = check_call(plan, psi, ws, ws_bytes);
   if (s != HFX_OK) return s;
   if (!kpsi) return fail(HFX_EINVAL, "null kpsi");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
-  for (size_t i = 0; i < plan->sys.size(); ++i) {
-    SystemPlan& sp = plan->sys[i];
-    void* kp = static_cast<char*>(kpsi) + (size_t)sp.psi_off * elem;
-    s = run_exchange(plan, sp, psi + sp.psi_off, kp, ex ? ex + i : nullptr,
-                     static_cast<char*>(ws), st, true);
-    if (s != HFX_OK) return s;
-  }
-  return HFX_OK;
+  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
+    return enq_apply(plan, plan->sys[i], psi, kpsi, ex ? ex + i : nullptr, static_cast<char*>(ws),
+                     st);
+  });
 }
 
 hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double* gscale,
@@ -652,21 +787,10 @@ hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double*
   hfx_status s = check_call(plan, psi, ws, ws_bytes);
   if (s != HFX_OK) return s;
   if (!grad) return fail(HFX_EINVAL, "null grad");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  for (size_t i = 0; i < plan->sys.size(); ++i) {
-    SystemPlan& sp = plan->sys[i];
-    double* g = grad + sp.psi_off;
-    void* kp = plan->prec == HFX_FP64 ? static_cast<void*>(g)
-                                      : static_cast<void*>(static_cast<char*>(ws) + sp.off_grad);
-    s = run_exchange(plan, sp, psi + sp.psi_off, kp, nullptr, static_cast<char*>(ws), st, true);
-    if (s != HFX_OK) return s;
-    Bracket bk(plan, HFX_PASS_SCALE, st);
-    launch_scale_to_f64(kp, plan->prec == HFX_FP64, g, (size_t)sp.sys.n_orb * sp.nr,
-                        2.0 * sp.dv, gscale ? gscale + i : nullptr, st);
-    bk.done((double)sp.sys.n_orb * sp.nr * (plan->prec == HFX_FP64 ? 16.0 : 12.0), 0.0);
-  }
-  HIP_TRY(hipGetLastError());
-  return HFX_OK;
+  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
+    return enq_gradient(plan, plan->sys[i], psi, gscale ? gscale + i : nullptr, grad,
+                        static_cast<char*>(ws), st);
+  });
 }
 
 hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, const void* kpsi, double* m,
@@ -675,24 +799,9 @@ hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, const void* kps
   if (s != HFX_OK) return s;
   if (!kpsi) return fail(HFX_EINVAL, "null kpsi");
   if (!m) return fail(HFX_EINVAL, "null m");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
-  for (auto& sp : plan->sys) {
-    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + sp.off_gemm);
-    const char* kp = static_cast<const char*>(kpsi) + (size_t)sp.psi_off * elem;
-    const double nn = (double)sp.sys.n_orb, npts = (double)sp.nr;
-    Bracket bk(plan, HFX_PASS_CONTRACT, st);
-    if (plan->prec == HFX_FP32)
-      launch_xtx_split(psi + sp.psi_off, reinterpret_cast<const float*>(kp), sp.sys.n_orb, sp.nr,
-                       sp.dv, part, sp.gemm_chunks, m + sp.m_off, st);
-    else
-      launch_xtx_f64(psi + sp.psi_off, reinterpret_cast<const double*>(kp), sp.sys.n_orb, sp.nr,
-                     sp.dv, part, sp.gemm_chunks, m + sp.m_off, st);
-    // split precision: two float32 products per term
-    bk.done(nn * npts * (8.0 + elem), 2.0 * nn * nn * npts * (plan->prec == HFX_FP32 ? 2.0 : 1.0));
-  }
-  HIP_TRY(hipGetLastError());
-  return HFX_OK;
+  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
+    return enq_matrix(plan, plan->sys[i], psi, kpsi, m, static_cast<char*>(ws), st);
+  });
 }
 
 hfx_status hfx_orthonormalize(hfx_plan plan, double* psi, int method, void* ws, size_t ws_bytes,
@@ -700,28 +809,73 @@ hfx_status hfx_orthonormalize(hfx_plan plan, double* psi, int method, void* ws, 
   hfx_status s = check_call(plan, psi, ws, ws_bytes);
   if (s != HFX_OK) return s;
   if (method != HFX_ORTHO_LOWDIN) return fail(HFX_EUNSUPPORTED, "only Loewdin is implemented");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  for (auto& sp : plan->sys) {
-    const int n = sp.sys.n_orb;
-    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + sp.off_gemm);
-    double* work = reinterpret_cast<double*>(static_cast<char*>(ws) + sp.off_ortho);
-    double* smat = work;  // n x n overlap, replaced by S^(-1/2)
-    double* ns_work = work + (size_t)n * n;  // 5 n^2 doubles + flags
-    double* tmp = reinterpret_cast<double*>(
-        static_cast<char*>(ws) + align_up(sp.off_ortho + (size_t)6 * n * n * 8 + 64));
-    double* p = psi + sp.psi_off;
-    const double nn = n, npts = (double)sp.nr;
-    {
-      Bracket bk(plan, HFX_PASS_CONTRACT, st);
-      launch_xtx_f64(p, p, n, sp.nr, sp.dv, part, sp.gemm_chunks, smat, st);
-      bk.done(nn * npts * 8.0, 2.0 * nn * nn * npts);
-    }
-    Bracket bk(plan, HFX_PASS_ORTHO, st);
-    HIP_TRY(launch_inverse_sqrt(smat, n, ns_work, 60, st));
-    launch_apply_left(smat, p, n, sp.nr, tmp, st);
-    bk.done(nn * npts * 16.0, 2.0 * nn * nn * npts);
+  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
+    return enq_ortho(plan, plan->sys[i], psi, static_cast<char*>(ws), st);
+  });
+}
+
+hfx_status hfx_graph_create(hfx_plan plan, int op, double* psi, void* kpsi, double* ex,
+                            double* m, void* ws, size_t ws_bytes, hfx_graph* out) {
+  if (!out) return fail(HFX_EINVAL, "null output graph pointer");
+  *out = nullptr;
+  hfx_status s = check_call(plan, psi, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (op != HFX_GRAPH_ENERGY && op != HFX_GRAPH_APPLY && op != HFX_GRAPH_STEP)
+    return fail(HFX_EINVAL, "unknown graph operation");
+  if (op == HFX_GRAPH_ENERGY && !ex) return fail(HFX_EINVAL, "null ex");
+  if (op != HFX_GRAPH_ENERGY && !kpsi) return fail(HFX_EINVAL, "null kpsi");
+  if (op == HFX_GRAPH_STEP && !m) return fail(HFX_EINVAL, "null m");
+  if (!plan->cap) HIP_TRY(hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking));
+  hfx_graph g = new hfx_graph_t();
+  g->plan = plan;
+  plan->capturing = true;
+  hipError_t e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    plan->capturing = false;
+    delete g;
+    return fail(HFX_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
   }
-  HIP_TRY(hipGetLastError());
+  char* w = static_cast<char*>(ws);
+  s = dispatch(plan, plan->cap, [&](size_t i, hipStream_t st) {
+    SystemPlan& sp = plan->sys[i];
+    hfx_status r = HFX_OK;
+    if (op == HFX_GRAPH_ENERGY) return enq_energy(plan, sp, psi, ex + i, w, st);
+    if (op == HFX_GRAPH_STEP) r = enq_ortho(plan, sp, psi, w, st);
+    if (r == HFX_OK) r = enq_apply(plan, sp, psi, kpsi, ex ? ex + i : nullptr, w, st);
+    if (r == HFX_OK && op == HFX_GRAPH_STEP) r = enq_matrix(plan, sp, psi, kpsi, m, w, st);
+    return r;
+  });
+  e = hipStreamEndCapture(plan->cap, &g->graph);
+  plan->capturing = false;
+  if (s != HFX_OK || e != hipSuccess) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    if (s != HFX_OK) return s;
+    return fail(HFX_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return fail(HFX_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return HFX_OK;
+}
+
+hfx_status hfx_graph_launch(hfx_graph g, void* stream) {
+  if (!g || !g->exec) return fail(HFX_EINVAL, "null graph");
+  HIP_TRY(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+  return HFX_OK;
+}
+
+hfx_status hfx_graph_destroy(hfx_graph g) {
+  if (!g) return fail(HFX_EINVAL, "null graph");
+  hipError_t e = hipSuccess;
+  if (g->exec) e = hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("hipGraphExecDestroy: ") + hipGetErrorString(e));
   return HFX_OK;
 }
 

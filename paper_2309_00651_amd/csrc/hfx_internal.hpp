@@ -34,6 +34,9 @@ struct PassArgs {
   const void* tw_yi;
   double* partials;       // per-workgroup energy partial sums
   long long part_base;    // first partial of this launch
+  const double* mean;     // float32 plans: pair-density means mu_ab = (1/N_r) sum psi_a psi_b
+                          // (n_orb x n_orb), subtracted before the forward FFT; else null
+  double v0;              // v(G = 0), re-added to the potentials as v0 * mu_ab
   int n_orb;
   int n_tiles;
   int n_active;
@@ -77,8 +80,9 @@ void launch_zero(void* p, size_t bytes, hipStream_t s);
 // for float64)
 void launch_scale_to_f64(const void* src, int src_is_f64, double* dst, size_t n, double scale,
                          const double* gscale, hipStream_t s);
-void launch_energy_reduce(const double* partials, long long n, double scale, double* out,
-                          hipStream_t s);
+// out[0] = scale * sum(partials) + dc_scale * sum_ab mean[a][b]^2 (mean: n x n, nullable)
+void launch_energy_reduce(const double* partials, long long n, double scale, const double* mean,
+                          int n_orb, double dc_scale, double* out, hipStream_t s);
 
 // Dense products (gemm.hip)
 // C[k][l] = alpha * sum_r A[k][r] B[l][r], A float64 split into hi + lo

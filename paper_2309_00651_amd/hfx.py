@@ -26,6 +26,9 @@ ERFC = 1
 FP32 = 0
 FP64 = 1
 ORTHO_LOWDIN = 0
+GRAPH_ENERGY = 0
+GRAPH_APPLY = 1
+GRAPH_STEP = 2
 PASSES = ("stage", "zero", "pair_fwd", "plane", "rows_fwd", "cols_conv", "rows_inv", "inv_acc",
           "inv_energy", "energy_reduce", "contract", "ortho", "scale")
 
@@ -69,6 +72,9 @@ def load_library(path=None):
     lib.hfx_profile_enable.argtypes = [vp, i]
     lib.hfx_profile_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
                                      ctypes.POINTER(ctypes.c_longlong), i]
+    lib.hfx_graph_create.argtypes = [vp, i, vp, vp, vp, vp, vp, sz, ctypes.POINTER(vp)]
+    lib.hfx_graph_launch.argtypes = [vp, vp]
+    lib.hfx_graph_destroy.argtypes = [vp]
     lib.hfx_status_string.argtypes = [i]
     lib.hfx_status_string.restype = ctypes.c_char_p
     lib.hfx_last_error.argtypes = []
@@ -76,7 +82,8 @@ def load_library(path=None):
     for name in ("hfx_plan_create", "hfx_plan_destroy", "hfx_workspace_size",
                  "hfx_exchange_energy", "hfx_apply_exchange", "hfx_exchange_matrix",
                  "hfx_orthonormalize", "hfx_exchange_gradient", "hfx_profile_enable",
-                 "hfx_profile_read"):
+                 "hfx_profile_read", "hfx_graph_create", "hfx_graph_launch",
+                 "hfx_graph_destroy"):
         getattr(lib, name).restype = i
     if path is None:
         _lib = lib
@@ -229,6 +236,15 @@ class Plan:
                                        _stream()))
         return psi
 
+    def graph(self, op, psi, kpsi=None, ex=None, m=None):
+        """Capture one call (GRAPH_ENERGY / GRAPH_APPLY / GRAPH_STEP) for these buffers."""
+        self._check_psi(psi)
+        ws = self.workspace()
+        h = ctypes.c_void_p()
+        _check(_lib.hfx_graph_create(self._h, int(op), _ptr(psi), _ptr(kpsi), _ptr(ex), _ptr(m),
+                                     _ptr(ws), self.ws_bytes, ctypes.byref(h)))
+        return Graph(h, self, (psi, kpsi, ex, m, ws))
+
     def profile(self, enable=True):
         _check(_lib.hfx_profile_enable(self._h, 1 if enable else 0))
 
@@ -249,6 +265,29 @@ class Plan:
             out.append(flat.reshape(-1)[off:off + k].view(s.n_orb, s.n, s.n, s.n))
             off += k
         return out
+
+
+class Graph:
+    """A captured libhfx call; launch() replays it on the current stream."""
+
+    def __init__(self, handle, plan, keep):
+        self._h = handle
+        self.plan = plan          # the plan must outlive the graph
+        self._keep = keep         # buffers baked into the graph
+
+    def launch(self):
+        _check(_lib.hfx_graph_launch(self._h, _stream()))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(_lib.hfx_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _plans = {}

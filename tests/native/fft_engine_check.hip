@@ -26,9 +26,7 @@ std::vector<TwEntry<T>> make_tw(const std::vector<int>& radices) {
     if constexpr (sizeof(T) == 8) {
       out[i].w = {t[2 * i], t[2 * i + 1]};
     } else {
-      const float hr = (float)t[2 * i], hi = (float)t[2 * i + 1];
-      out[i].hi = {hr, hi};
-      out[i].lo = {(float)(t[2 * i] - (double)hr), (float)(t[2 * i + 1] - (double)hi)};
+      unit_f32(t[2 * i], t[2 * i + 1], &out[i].w.re, &out[i].w.im);
     }
   }
   return out;
@@ -274,9 +272,9 @@ int main() {
   check<float, 128, 128, 512, false, Sched<8, 16>, Sched<16, 8>>("f32 N128 rows (8,16)", 1e-6);
   check<float, 120, 16, 64, true, Sched<2, 6, 10>, Sched<10, 6, 2>>("f32 N120 pencil (2,6,10)", 1e-6);
   {
-    const double b96 = energy_bias<float, 96, 16, 64, Sched<8, 12>, Sched<12, 8>>(40);
-    const double b120 = energy_bias<float, 120, 16, 64, Sched<8, 15>, Sched<15, 8>>(40);
-    const double b80 = energy_bias<float, 80, 16, 64, Sched<4, 4, 5>, Sched<5, 4, 4>>(40);
+    const double b96 = energy_bias<float, 96, 16, 64, Sched<8, 12>, Sched<12, 8>>(400);
+    const double b120 = energy_bias<float, 120, 16, 64, Sched<8, 15>, Sched<15, 8>>(400);
+    const double b80 = energy_bias<float, 80, 16, 64, Sched<4, 4, 5>, Sched<5, 4, 4>>(400);
     std::printf("f32 convolution energy bias: N96 %.2e  N120 %.2e  N80 %.2e\n", b96, b120, b80);
     if (std::fabs(b96) > 1e-8 || std::fabs(b120) > 1e-8 || std::fabs(b80) > 1e-8) g_fail++;
   }
