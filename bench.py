@@ -80,7 +80,11 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--options", default=None, help="plan options, e.g. 'tiles=2'")
+    ap.add_argument("--options", default=None, help="float32 plan options, e.g. 'tiles=2'")
+    ap.add_argument("--fp64-options", default=None, help="float64 plan options")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (5 times): the "
+                         "reference dispatch for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -90,6 +94,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = 1 << 28  # 2^28 float32 = 1 GiB read + 1 GiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "copies": 5}), flush=True)
+        return
 
     from paper_2309_00651_amd import hfx
     from workloads import configs
@@ -103,7 +117,8 @@ def main():
     n_pairs = system.n_pairs
 
     def run(prec, steps, warmup, profile):
-        plan = hfx.Plan(spec, prec, options=args.options, device=dev)
+        opts = args.fp64_options if prec == hfx.FP64 else args.options
+        plan = hfx.Plan(spec, prec, options=opts, device=dev)
         p = psi0.clone()
         kpsi = torch.empty(p.shape, dtype=plan.kpsi_dtype, device=dev)
         ex = torch.empty(1, dtype=torch.float64, device=dev)
@@ -203,7 +218,7 @@ def main():
                                f"{n_pairs} pairs) + E_x + exchange matrix",
                    "n": system.n, "n_orb": system.n_orb, "pairs": n_pairs,
                    "precision": "fp32 FFT/kernel, fp64 orthonormalisation and sums",
-                   "plan_options": args.options},
+                   "plan_options": args.options, "fp64_plan_options": args.fp64_options},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -81,7 +81,8 @@ typedef struct hfx_plan_t* hfx_plan;
  * Create a plan for n_sys systems at the given precision (hfx_precision).
  * Supported grids: n in {24, 64, 72, 80, 96, 108, 120, 128}.  `options` is a
  * nullable "key=value;key=value" string: tiles=<k> caps the orbital tiles per
- * batch; maxws=<bytes> caps the workspace.  The environment variable
+ * batch; maxws=<bytes> caps the workspace; variant=<name> picks a compiled
+ * kernel configuration (see hfx_variants).  The environment variable
  * HFX_MAX_WORKSPACE_BYTES also caps the workspace.  Uploads the plan's tables
  * (synchronous).  Errors: HFX_EINVAL for null out/sys, n_sys < 1, n <= 0,
  * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0;
@@ -190,6 +191,14 @@ hfx_status hfx_graph_create(hfx_plan plan, int op, double* psi, void* kpsi, doub
                             double* m, void* ws, size_t ws_bytes, hfx_graph* out);
 hfx_status hfx_graph_launch(hfx_graph graph, void* stream);
 hfx_status hfx_graph_destroy(hfx_graph graph);
+
+/*
+ * Names of the compiled kernel configurations for an n^3 grid at the given
+ * precision, ';'-separated, default first ("" if the size is unsupported).
+ * A single-system plan selects one with the option "variant=<name>".
+ * The returned string is thread-local and valid until the next call.
+ */
+const char* hfx_variants(int n, int precision);
 
 /* Static description of a status code. */
 const char* hfx_status_string(hfx_status s);

@@ -3,31 +3,79 @@
 
 namespace hfx {
 namespace {
-// FusedPipeline<T, N, W, pencil threads, tile, z fwd, z inv,
-//               plane threads, x fwd, x inv, y fwd, y inv>
-using P24 = FusedPipeline<float, 24, 16, 64, 8, Sched<4, 6>, Sched<6, 4>, 144, Sched<4, 6>,
+// FusedPipeline<T, N, W, tile, z fwd, z inv, plane threads, x fwd, x inv,
+//               y fwd, y inv [, swizzle, pair_fwd threads, inv_acc threads]>
+// Plane threads: the plane takes N (N + 1) * 8 bytes of LDS, so from N = 96 at
+// most two planes fit in a compute unit; more threads per plane then buy the
+// occupancy that hides the LDS and HBM latencies.
+using P24 = FusedPipeline<float, 24, 16, 8, Sched<4, 6>, Sched<6, 4>, 144, Sched<4, 6>,
                           Sched<6, 4>, Sched<4, 6>, Sched<6, 4>>;
-using P64 = FusedPipeline<float, 64, 16, 128, 8, Sched<8, 8>, Sched<8, 8>, 256, Sched<8, 8>,
+using P64 = FusedPipeline<float, 64, 16, 8, Sched<8, 8>, Sched<8, 8>, 256, Sched<8, 8>,
                           Sched<8, 8>, Sched<8, 8>, Sched<8, 8>>;
-using P72 = FusedPipeline<float, 72, 16, 144, 8, Sched<8, 9>, Sched<9, 8>, 216, Sched<8, 9>,
+using P64q512 = FusedPipeline<float, 64, 16, 8, Sched<8, 8>, Sched<8, 8>, 512, Sched<8, 8>,
+                              Sched<8, 8>, Sched<8, 8>, Sched<8, 8>>;
+using P72 = FusedPipeline<float, 72, 16, 8, Sched<8, 9>, Sched<9, 8>, 576, Sched<8, 9>,
                           Sched<9, 8>, Sched<8, 9>, Sched<9, 8>>;
-using P80 = FusedPipeline<float, 80, 16, 160, 8, Sched<8, 10>, Sched<10, 8>, 320, Sched<8, 10>,
+using P72q216 = FusedPipeline<float, 72, 16, 8, Sched<8, 9>, Sched<9, 8>, 216, Sched<8, 9>,
+                              Sched<9, 8>, Sched<8, 9>, Sched<9, 8>>;
+using P80 = FusedPipeline<float, 80, 16, 8, Sched<8, 10>, Sched<10, 8>, 640, Sched<8, 10>,
                           Sched<10, 8>, Sched<8, 10>, Sched<10, 8>>;
-using P96 = FusedPipeline<float, 96, 16, 192, 8, Sched<8, 12>, Sched<12, 8>, 384, Sched<8, 12>,
+using P80q320 = FusedPipeline<float, 80, 16, 8, Sched<8, 10>, Sched<10, 8>, 320, Sched<8, 10>,
+                              Sched<10, 8>, Sched<8, 10>, Sched<10, 8>>;
+using P96 = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
                           Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
-using P108 = FusedPipeline<float, 108, 16, 192, 8, Sched<12, 9>, Sched<9, 12>, 324, Sched<12, 9>,
+// alternatives for the autotuner: radix-12-first inverse z; plane threads;
+// swizzled plane LDS; accumulation threads; psi J block in LDS with prefetch;
+// radix-12-first forward z
+using P96z12 = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<12, 8>, 768, Sched<8, 12>,
+                             Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
+using P96q384 = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 384, Sched<8, 12>,
+                              Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
+using P96sw = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
+                            Sched<12, 8>, Sched<8, 12>, Sched<12, 8>, true>;
+using P96i768 = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
+                              Sched<12, 8>, Sched<8, 12>, Sched<12, 8>, false, 256, 768>;
+using P96lp = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
+                            Sched<12, 8>, Sched<8, 12>, Sched<12, 8>, false, 256, 512, true, true>;
+using P96f12 = FusedPipeline<float, 96, 16, 8, Sched<12, 8>, Sched<8, 12>, 768, Sched<8, 12>,
+                             Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
+using P108 = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
                            Sched<9, 12>, Sched<12, 9>, Sched<9, 12>>;
-using P120 = FusedPipeline<float, 120, 16, 240, 8, Sched<8, 15>, Sched<15, 8>, 480, Sched<10, 12>,
+using P108i512 = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
+                               Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 512>;
+using P120 = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
                            Sched<12, 10>, Sched<10, 12>, Sched<12, 10>>;
-using P128 = FusedPipeline<float, 128, 16, 256, 8, Sched<8, 16>, Sched<16, 8>, 512, Sched<8, 16>,
+using P120i512 = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960,
+                               Sched<10, 12>, Sched<12, 10>, Sched<10, 12>, Sched<12, 10>, false,
+                               256, 512>;
+using P128 = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
                            Sched<16, 8>, Sched<8, 16>, Sched<16, 8>>;
+using P128i512 = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
+                               Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 512>;
 }  // namespace
 
 const Variant* variants_f32(int* count) {
   static const Variant v[] = {
-      P24::describe("f32-n24"),   P64::describe("f32-n64"),   P72::describe("f32-n72"),
-      P80::describe("f32-n80"),   P96::describe("f32-n96"),   P108::describe("f32-n108"),
-      P120::describe("f32-n120"), P128::describe("f32-n128"),
+      P24::describe("f32-n24"),
+      P64::describe("f32-n64"),
+      P64q512::describe("f32-n64-q512"),
+      P72::describe("f32-n72"),
+      P72q216::describe("f32-n72-q216"),
+      P80::describe("f32-n80"),
+      P80q320::describe("f32-n80-q320"),
+      P96::describe("f32-n96"),
+      P96z12::describe("f32-n96-z12"),
+      P96q384::describe("f32-n96-q384"),
+      P96sw::describe("f32-n96-sw"),
+      P96i768::describe("f32-n96-i768"),
+      P96lp::describe("f32-n96-lp"),
+      P96f12::describe("f32-n96-f12"),
+      P108::describe("f32-n108"),
+      P108i512::describe("f32-n108-i512"),
+      P120::describe("f32-n120"),
+      P120i512::describe("f32-n120-i512"),
+      P128::describe("f32-n128"),
+      P128i512::describe("f32-n128-i512"),
   };
   *count = (int)(sizeof(v) / sizeof(v[0]));
   return v;

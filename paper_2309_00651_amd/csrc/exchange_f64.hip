@@ -4,17 +4,30 @@
 
 namespace hfx {
 namespace {
-using P24 = FusedPipeline<double, 24, 16, 64, 8, Sched<4, 6>, Sched<6, 4>, 144, Sched<4, 6>,
+// Plane threads: a float64 plane of 64^2 points or more leaves room for one
+// or two workgroups per compute unit, so the plane kernels take 8 threads
+// per row (the alternatives with 4 per row are kept for the autotuner).
+using P24 = FusedPipeline<double, 24, 16, 8, Sched<4, 6>, Sched<6, 4>, 144, Sched<4, 6>,
                           Sched<6, 4>, Sched<4, 6>, Sched<6, 4>>;
-using P64 = FusedPipeline<double, 64, 16, 128, 8, Sched<8, 8>, Sched<8, 8>, 256, Sched<8, 8>,
+using P64 = FusedPipeline<double, 64, 16, 8, Sched<8, 8>, Sched<8, 8>, 512, Sched<8, 8>,
                           Sched<8, 8>, Sched<8, 8>, Sched<8, 8>>;
-using P72 = FusedPipeline<double, 72, 16, 144, 8, Sched<8, 9>, Sched<9, 8>, 216, Sched<8, 9>,
+using P72 = FusedPipeline<double, 72, 16, 8, Sched<8, 9>, Sched<9, 8>, 576, Sched<8, 9>,
                           Sched<9, 8>, Sched<8, 9>, Sched<9, 8>>;
-using P80 = FusedPipeline<double, 80, 16, 160, 8, Sched<8, 10>, Sched<10, 8>, 320, Sched<8, 10>,
+using P80 = FusedPipeline<double, 80, 16, 8, Sched<8, 10>, Sched<10, 8>, 640, Sched<8, 10>,
                           Sched<10, 8>, Sched<8, 10>, Sched<10, 8>>;
-using P96 = FusedPipeline<double, 96, 16, 192, 8, Sched<8, 12>, Sched<12, 8>, 384, Sched<8, 12>,
+using P96 = FusedPipeline<double, 96, 16, 8, Sched<8, 12>, Sched<12, 8>, 768, Sched<8, 12>,
                           Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
-// SplitPipeline<T, N, W, pencil threads, tile, z fwd, z inv, rows per wg,
+using P64q256 = FusedPipeline<double, 64, 16, 8, Sched<8, 8>, Sched<8, 8>, 256, Sched<8, 8>,
+                              Sched<8, 8>, Sched<8, 8>, Sched<8, 8>>;
+using P72q216 = FusedPipeline<double, 72, 16, 8, Sched<8, 9>, Sched<9, 8>, 216, Sched<8, 9>,
+                              Sched<9, 8>, Sched<8, 9>, Sched<9, 8>>;
+using P80q320 = FusedPipeline<double, 80, 16, 8, Sched<8, 10>, Sched<10, 8>, 320, Sched<8, 10>,
+                              Sched<10, 8>, Sched<8, 10>, Sched<10, 8>>;
+using P96q384 = FusedPipeline<double, 96, 16, 8, Sched<8, 12>, Sched<12, 8>, 384, Sched<8, 12>,
+                              Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
+using P96z8 = FusedPipeline<double, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
+                            Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
+// SplitPipeline<T, N, W, column threads, tile, z fwd, z inv, rows per wg,
 //               row threads, x fwd, x inv, y fwd, y inv>
 using P108 = SplitPipeline<double, 108, 16, 192, 8, Sched<12, 9>, Sched<9, 12>, 16, 192,
                            Sched<12, 9>, Sched<9, 12>, Sched<12, 9>, Sched<9, 12>>;
@@ -26,9 +39,19 @@ using P128 = SplitPipeline<double, 128, 16, 256, 8, Sched<8, 16>, Sched<16, 8>, 
 
 const Variant* variants_f64(int* count) {
   static const Variant v[] = {
-      P24::describe("f64-n24"),   P64::describe("f64-n64"),   P72::describe("f64-n72"),
-      P80::describe("f64-n80"),   P96::describe("f64-n96"),   P108::describe("f64-n108"),
-      P120::describe("f64-n120"), P128::describe("f64-n128"),
+      P24::describe("f64-n24"),
+      P64::describe("f64-n64"),
+      P64q256::describe("f64-n64-q256"),
+      P72::describe("f64-n72"),
+      P72q216::describe("f64-n72-q216"),
+      P80::describe("f64-n80"),
+      P80q320::describe("f64-n80-q320"),
+      P96::describe("f64-n96"),
+      P96q384::describe("f64-n96-q384"),
+      P96z8::describe("f64-n96-z8"),
+      P108::describe("f64-n108"),
+      P120::describe("f64-n120"),
+      P128::describe("f64-n128"),
   };
   *count = (int)(sizeof(v) / sizeof(v[0]));
   return v;

@@ -54,6 +54,35 @@ constexpr int pow2_at_least() {
   return NT <= 64 ? 64 : NT <= 128 ? 128 : NT <= 256 ? 256 : NT <= 512 ? 512 : 1024;
 }
 
+// Stage twiddle tables live in LDS for the whole workgroup: a few hundred
+// bytes, copied once.  Read from global memory inside a transform, a twiddle
+// load would make the wave wait for every vector memory operation issued
+// before it (loads in flight for the next step, stores of the previous one),
+// since one in-order counter tracks them all.
+template <typename T, class S>
+constexpr int tw_slots() {
+  return SchedInfo<S>::tw_count() > 0 ? SchedInfo<S>::tw_count() : 1;
+}
+template <typename T, class S, int NT>
+__device__ __forceinline__ void stage_twiddles(TwEntry<T>* dst, const void* src, int tid) {
+  const TwEntry<T>* s = static_cast<const TwEntry<T>*>(src);
+  for (int i = tid; i < SchedInfo<S>::tw_count(); i += NT) dst[i] = s[i];
+}
+
+// scale * (pair-density mean) for the TT x TT pairs of a tile, [a][b], zero
+// outside the tile or without means (float64 plans): staged in LDS so that
+// the loops below issue no global loads besides their own data.
+template <typename T, int TT, int NT>
+__device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const TileDesc& td,
+                                            double scale, int tid) {
+  for (int q = tid; q < TT * TT; q += NT) {
+    const int ia = q / TT, b = q - ia * TT;
+    dst[q] = (a.mean && ia < td.nI && b < td.nJ)
+                 ? (T)(scale * a.mean[(long long)(td.i0 + ia) * a.n_orb + td.j0 + b])
+                 : T(0);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pass 1: pair product + forward z FFT on bricks.
 // Two pair grids are transformed together: LDS holds [z][2W] with the brick
@@ -76,13 +105,18 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   constexpr long long NR = (long long)N * N * N;
   constexpr int ZSL = (N / RL) * N * N;  // offset between legs of a last-stage butterfly
   __shared__ cpx<T> lds[N * W2];
+  __shared__ TwEntry<T> twl[tw_slots<T, SZF>()];
+  __shared__ T mul[TT * TT];  // pair-density means of the tile, [a][b]
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const int t = lg / BR, br = lg - t * BR;
   const int y = br / NXB, x0 = (br - y * NXB) * W;
   const TileDesc td = a.tiles[t];
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
-  const TwEntry<T>* __restrict__ tw = static_cast<const TwEntry<T>*>(a.tw_zf);
+  stage_twiddles<T, SZF, NT>(twl, a.tw_zf, tid);
+  stage_means<T, TT, NT>(mul, a, td, 1.0, tid);
+  __syncthreads();
+  const TwEntry<T>* tw = twl;
   cpx<T>* __restrict__ grids = static_cast<cpx<T>*>(a.grids);
 
   int offA[PT], ldsA[PT];
@@ -128,12 +162,9 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
       const bool use1 = b0 + 2 < td.nJ && !(td.diag && b0 + 3 < ia);
       if (!use0 && !use1) return;
       // pair-density means (float32 plans): transforms see zero-mean densities
-      T mu[4] = {T(0), T(0), T(0), T(0)};
-      if (a.mean) {
+      T mu[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (b0 + q < td.nJ) mu[q] = (T)a.mean[(long long)(td.i0 + ia) * a.n_orb + td.j0 + b0 + q];
-      }
+      for (int q = 0; q < 4; ++q) mu[q] = mul[ia * TT + b0 + q];
 #pragma unroll
       for (int k = 0; k < PT; ++k)
         if (tid + k * NT < P) {
@@ -164,15 +195,24 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
 // Two pair grids are transformed together ([z][2W] in LDS, as in pass 1).
 // The inverse transform leaves the potentials in LDS in natural order; the
 // accumulation then uses its own point map: thread tid owns brick points
-// p = tid + k NT (k < PT), contiguous x for coalesced K psi traffic.  psi of
-// the tile's J block and the J-side accumulators stay in registers for the
-// whole tile; the pair energy of a thread's points is summed in the working
-// precision per pair and added to a float64 accumulator once per pair.
-template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 4 && N >= 64 && N <= 96) ? 4 : 1)))
-k_inv_acc(PassArgs a) {
+// p = tid + k NT (k < PT), contiguous x for coalesced K psi traffic.  The
+// J-side accumulators stay in registers for the whole tile; psi of the J
+// block stays in registers too, or (PJL) in LDS, where each thread reads
+// back only the points it wrote (no barrier needed).  The pair energy of a
+// thread's points is summed in the working precision per pair and added to a
+// float64 accumulator once per pair.
+//
+// Latency hiding: the old K psi values of orbital a are loaded with its psi,
+// so the update at the end of the orbital is a plain store.  With PF, while
+// one grid pair is transformed the loads of the next one are in flight
+// (second register buffer), and the next orbital's psi and old K psi values
+// are loaded one step ahead.
+template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC, bool PJL, bool PF>
+__global__ void __launch_bounds__(NT)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_inv_acc(PassArgs a) {
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
   constexpr int W2 = 2 * W;
+  constexpr int QB = TT / 4;               // grid pairs per orbital a
   using G = Geom<T, N, W2, NT, true, W2, 1>;
   using F = FirstStage<G, SZI>;
   using E = FFT<G, true, SZI>;
@@ -185,6 +225,9 @@ k_inv_acc(PassArgs a) {
   constexpr int ZSF = (N / RF) * N * N;    // offset between legs of a first-stage butterfly
   __shared__ cpx<T> lds[N * W2];
   __shared__ double red[pow2_at_least<NT>()];
+  __shared__ T pjl[PJL ? TT * PT * NT : 1];  // [b][k][tid]
+  __shared__ TwEntry<T> twl[tw_slots<T, SZI>()];
+  __shared__ T dcl[TT * TT];  // v(0) * pair-density mean, [a][b]
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const int t = lg / BR, br = lg - t * BR;
@@ -192,7 +235,10 @@ k_inv_acc(PassArgs a) {
   const TileDesc td = a.tiles[t];
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
   T* __restrict__ kpsi = static_cast<T*>(a.kpsi);
-  const TwEntry<T>* __restrict__ tw = static_cast<const TwEntry<T>*>(a.tw_zi);
+  stage_twiddles<T, SZI, NT>(twl, a.tw_zi, tid);
+  stage_means<T, TT, NT>(dcl, a, td, a.v0, tid);
+  __syncthreads();
+  const TwEntry<T>* tw = twl;
   const cpx<T>* __restrict__ grids = static_cast<const cpx<T>*>(a.grids);
 
   int offF[F::PER], gF[F::PER];
@@ -217,100 +263,197 @@ k_inv_acc(PassArgs a) {
     ldsA[k] = z * W2 + m;
   }
 
-  T pj[TT][PT];
+  T pjr[PJL ? 1 : TT][PT];
+  auto pj = [&](int b, int k) -> T { return PJL ? pjl[(b * PT + k) * NT + tid] : pjr[PJL ? 0 : b][k]; };
   T accJ[ACC ? TT : 1][PT];
+  // psi of the J block (zero off the grid); for LDS, four orbitals at a time,
+  // all loads before the stores
+  static_for<0, TT / 4>([&](auto hc) {
+    constexpr int b0 = 4 * decltype(hc)::value;
+    T x[4][PT];
 #pragma unroll
-  for (int b = 0; b < TT; ++b) {
-    const bool bv = b < td.nJ;
-    const T* pb = psi + (long long)(td.j0 + (bv ? b : 0)) * NR;
+    for (int q = 0; q < 4; ++q) {
+      const bool bv = b0 + q < td.nJ;
+      const T* pb = psi + (long long)(td.j0 + (bv ? b0 + q : 0)) * NR;
 #pragma unroll
-    for (int k = 0; k < PT; ++k) pj[b][k] = (bv && vA[k]) ? pb[offA[k]] : T(0);
-  }
+      for (int k = 0; k < PT; ++k) x[q][k] = pb[offA[k]];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool bv = b0 + q < td.nJ;
+#pragma unroll
+      for (int k = 0; k < PT; ++k) {
+        const T v = (bv && vA[k]) ? x[q][k] : T(0);
+        if constexpr (PJL) pjl[((b0 + q) * PT + k) * NT + tid] = v;
+        else pjr[PJL ? 0 : b0 + q][k] = v;
+      }
+    }
+  });
 #pragma unroll
   for (int b = 0; b < (ACC ? TT : 1); ++b)
 #pragma unroll
     for (int k = 0; k < PT; ++k) accJ[b][k] = T(0);
   double eacc = 0.0;
+  T pa[PT], acca[PT], kold[ACC ? PT : 1];
+  T pa_n[PF ? PT : 1], kold_n[(PF && ACC) ? PT : 1];
 
-  for (int ia = 0; ia < td.nI; ++ia) {
-    const int oa = td.i0 + ia;
-    const T* pa_ptr = psi + (long long)oa * NR;
-    T pa[PT], acca[PT];
+  // grid pair bq of orbital a carries pairs (a, 4bq .. 4bq + 3)
+  auto uses = [&](int ia, int bq, bool& u0, bool& u1) {
+    const int b0 = 4 * bq;
+    u0 = b0 < td.nJ && !(td.diag && b0 + 1 < ia);
+    u1 = b0 + 2 < td.nJ && !(td.diag && b0 + 3 < ia);
+  };
+  // Loads below are issued unconditionally and their values used as loaded:
+  // masked-off lanes read a valid dummy address (data written earlier in the
+  // batch: finite).  With no branches or selects after them, the compiler
+  // counts the loads in flight and waits only for the ones needed.  Dummy
+  // values are harmless: a grid of an unused pair is transformed but its
+  // potentials are never used, and at points outside the grid psi_b = 0 (set
+  // at the tile load), so energies and K psi_a get exact zeros there, while
+  // K psi_b is not stored there.
+  auto load_pair = [&](int ia, int bq, cpx<T>* v) {
+    bool u0, u1;
+    uses(ia, bq, u0, u1);
+    const int slot0 = td.slot0 + ia * (TT / 2) + 2 * bq;
+#pragma unroll
+    for (int i = 0; i < F::PER; ++i) {
+      const bool ok = vF[i] && (gF[i] == 0 ? u0 : u1);
+      const cpx<T>* g = ok ? grids + (long long)(slot0 + gF[i]) * NR + offF[i]
+                           : grids + (long long)td.slot0 * NR;
+#pragma unroll
+      for (int r = 0; r < RF; ++r) v[i * RF + r] = g[ok ? r * ZSF : 0];
+    }
+  };
+  // psi and old K psi of orbital a at the thread's points (offA = 0 off the grid)
+  auto load_orbital = [&](int ia, T* p, T* ko) {
+    const T* pa_ptr = psi + (long long)(td.i0 + ia) * NR;
+    const T* ka = kpsi + (long long)(td.i0 + ia) * NR;
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
-      pa[k] = vA[k] ? pa_ptr[offA[k]] : T(0);
-      acca[k] = T(0);
+      p[k] = pa_ptr[offA[k]];
+      if constexpr (ACC) ko[k] = ka[offA[k]];
     }
-    static_for<0, TT / 4>([&](auto bq) {
-      constexpr int b0 = 4 * decltype(bq)::value;
-      const bool use0 = b0 < td.nJ && !(td.diag && b0 + 1 < ia);
-      const bool use1 = b0 + 2 < td.nJ && !(td.diag && b0 + 3 < ia);
-      if (!use0 && !use1) return;
-      const int slot0 = td.slot0 + ia * (TT / 2) + 2 * decltype(bq)::value;
-      cpx<T> v[F::VALS];
+  };
+  // inverse transform of the grid pair in v, then energies and K psi updates
+  auto process = [&](auto bqc, int ia, cpx<T>* v) {
+    constexpr int b0 = 4 * decltype(bqc)::value;
+    bool use0, use1;
+    uses(ia, decltype(bqc)::value, use0, use1);
+    if (!use0 && !use1) return;
+    {
+      cpx<T> out[LastStage<G, SZI>::VALS];
+      E::reg2reg(v, lds, tw, tid, out);
+      E::store_last(out, lds, tid);
+    }
+    __syncthreads();
+    // one grid's potentials at a time (bounded registers)
+    cpx<T> pot[PT];
+    static_for<0, 4>([&](auto q) {
+      constexpr int gq = decltype(q)::value / 2, half = decltype(q)::value % 2;
+      constexpr int b = b0 + decltype(q)::value;
+      if constexpr (half == 0) {
 #pragma unroll
-      for (int i = 0; i < F::PER; ++i) {
-        const bool use = gF[i] == 0 ? use0 : use1;
-        const cpx<T>* g = grids + (long long)(slot0 + gF[i]) * NR;
-#pragma unroll
-        for (int r = 0; r < RF; ++r)
-          v[i * RF + r] = (vF[i] && use) ? g[offF[i] + r * ZSF] : cpx<T>{T(0), T(0)};
+        for (int k = 0; k < PT; ++k)
+          pot[k] = tid + k * NT < P ? lds[ldsA[k] + gq * W] : cpx<T>{T(0), T(0)};
       }
-      {
-        cpx<T> out[LastStage<G, SZI>::VALS];
-        E::reg2reg(v, lds, tw, tid, out);
-        E::store_last(out, lds, tid);
+      if (b >= td.nJ) return;
+      if (!(gq == 0 ? use0 : use1)) return;
+      // weight of e_ab in sum_{i,j} e_ij: 2 for a != b, 1 for a == b
+      const int w = td.diag ? (b > ia ? 2 : (b == ia ? 1 : 0)) : 2;
+      if (w == 0) return;
+      // G = 0 part of v_ab when the mean was taken out of the transform;
+      // its energy v0 * Omega * mu_ab^2 is added in float64 at the reduction
+      const T dc = dcl[ia * TT + b];
+      T es = T(0);
+#pragma unroll
+      for (int k = 0; k < PT; ++k) {
+        const T vz = half ? pot[k].im : pot[k].re;  // zero-mean part
+        const T pjb = pj(b, k);
+        es += vz * pjb * pa[k];                     // rho_ab v_ab
+        if constexpr (ACC) {
+          const T vv = vz + dc;
+          accJ[b][k] -= vv * pa[k];
+          if (w == 2) acca[k] -= vv * pjb;
+        }
       }
-      __syncthreads();
-      // one grid's potentials at a time (bounded registers)
-      cpx<T> pot[PT];
-      static_for<0, 4>([&](auto q) {
-        constexpr int gq = decltype(q)::value / 2, half = decltype(q)::value % 2;
-        constexpr int b = b0 + decltype(q)::value;
-        if constexpr (half == 0) {
-#pragma unroll
-          for (int k = 0; k < PT; ++k)
-            pot[k] = tid + k * NT < P ? lds[ldsA[k] + gq * W] : cpx<T>{T(0), T(0)};
-        }
-        if (b >= td.nJ) return;
-        if (!(gq == 0 ? use0 : use1)) return;
-        // weight of e_ab in sum_{i,j} e_ij: 2 for a != b, 1 for a == b
-        const int w = td.diag ? (b > ia ? 2 : (b == ia ? 1 : 0)) : 2;
-        if (w == 0) return;
-        // G = 0 part of v_ab when the mean was taken out of the transform;
-        // its energy v0 * Omega * mu_ab^2 is added in float64 at the reduction
-        const T dc = a.mean ? (T)(a.v0 * a.mean[(long long)oa * a.n_orb + td.j0 + b]) : T(0);
-        T es = T(0);
-#pragma unroll
-        for (int k = 0; k < PT; ++k) {
-          const T vz = half ? pot[k].im : pot[k].re;  // zero-mean part
-          es += vz * pj[b][k] * pa[k];                        // rho_ab v_ab
-          if constexpr (ACC) {
-            const T vv = vz + dc;
-            accJ[b][k] -= vv * pa[k];
-            if (w == 2) acca[k] -= vv * pj[b][k];
-          }
-        }
-        eacc += (double)w * (double)es;
-      });
-      __syncthreads();  // LDS is rewritten by the next transform
+      eacc += (double)w * (double)es;
     });
+    __syncthreads();  // LDS is rewritten by the next transform
+  };
+
+  auto store_orbital = [&](int ia) {
     if constexpr (ACC) {
-      T* ka = kpsi + (long long)oa * NR;
+      T* ka = kpsi + (long long)(td.i0 + ia) * NR;
 #pragma unroll
       for (int k = 0; k < PT; ++k)
-        if (vA[k]) ka[offA[k]] += acca[k];
+        if (vA[k]) ka[offA[k]] = kold[k] + acca[k];
+    }
+  };
+  if constexpr (PF) {
+    cpx<T> vc[F::VALS], vn[F::VALS];
+    if (td.nI > 0) {
+      load_orbital(0, pa, kold);
+      load_pair(0, 0, vc);
+    }
+    for (int ia = 0; ia < td.nI; ++ia) {
+#pragma unroll
+      for (int k = 0; k < PT; ++k) acca[k] = T(0);
+      static_for<0, QB>([&](auto bq) {
+        constexpr int q = decltype(bq)::value;
+        // next step's loads go out before this step's transform
+        if constexpr (q + 1 < QB) {
+          load_pair(ia, q + 1, vn);
+        } else if (ia + 1 < td.nI) {
+          load_orbital(ia + 1, pa_n, kold_n);
+          load_pair(ia + 1, 0, vn);
+        }
+        process(bq, ia, vc);
+#pragma unroll
+        for (int e = 0; e < F::VALS; ++e) vc[e] = vn[e];
+      });
+      store_orbital(ia);
+#pragma unroll
+      for (int k = 0; k < PT; ++k) {
+        pa[k] = pa_n[k];
+        if constexpr (ACC) kold[k] = kold_n[k];
+      }
+    }
+  } else {
+    for (int ia = 0; ia < td.nI; ++ia) {
+      load_orbital(ia, pa, kold);
+#pragma unroll
+      for (int k = 0; k < PT; ++k) acca[k] = T(0);
+      static_for<0, QB>([&](auto bq) {
+        bool u0, u1;
+        uses(ia, decltype(bq)::value, u0, u1);
+        if (!u0 && !u1) return;
+        cpx<T> v[F::VALS];
+        load_pair(ia, decltype(bq)::value, v);
+        process(bq, ia, v);
+      });
+      store_orbital(ia);
     }
   }
   if constexpr (ACC) {
+    // four orbitals at a time: all old values first (one wait), then the stores
+    static_for<0, TT / 4>([&](auto hc) {
+      constexpr int b0 = 4 * decltype(hc)::value;
+      T old[4][PT];
 #pragma unroll
-    for (int b = 0; b < TT; ++b) {
-      if (b >= td.nJ) break;
-      T* kb = kpsi + (long long)(td.j0 + b) * NR;
+      for (int q = 0; q < 4; ++q) {
+        const bool bv = b0 + q < td.nJ;
+        const T* kb = kpsi + (long long)(td.j0 + (bv ? b0 + q : 0)) * NR;
 #pragma unroll
-      for (int k = 0; k < PT; ++k)
-        if (vA[k]) kb[offA[k]] += accJ[b][k];
-    }
+        for (int k = 0; k < PT; ++k) old[q][k] = kb[offA[k]];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T* kb = kpsi + (long long)(td.j0 + b0 + q) * NR;
+#pragma unroll
+        for (int k = 0; k < PT; ++k)
+          if (b0 + q < td.nJ && vA[k]) kb[offA[k]] = old[q][k] + accJ[b0 + q][k];
+      }
+    });
   }
   const double s = block_sum<NT>(eacc, red);
   if (tid == 0) a.partials[a.part_base + lg] = s;
@@ -318,11 +461,12 @@ k_inv_acc(PassArgs a) {
 
 // ---------------------------------------------------------------------------
 // Pass 2: fused plane convolution for one kz plane of one pair grid.
-template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI>
+template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, bool SW = false>
 __global__ void __launch_bounds__(NT) k_plane_conv(PassArgs a) {
+  static_assert(!SW || N % 8 == 0, "swizzle needs whole blocks of 8");
   constexpr int P = N + 1;
-  using GX = Geom<T, N, N, NT, false, 1, P>;  // rows: sequence m = y, element n = x
-  using GY = Geom<T, N, N, NT, true, P, 1>;   // columns: sequence m = x, element n = y
+  using GX = Geom<T, N, N, NT, false, 1, P, SW ? 1 : 0>;  // rows: sequence m = y, element n = x
+  using GY = Geom<T, N, N, NT, true, P, 1, SW ? 2 : 0>;   // columns: sequence m = x, element n = y
   using EXF = FFT<GX, false, SXF>;
   using EXI = FFT<GX, true, SXI>;
   using EYF = FFT<GY, false, SYF>;
@@ -340,31 +484,40 @@ __global__ void __launch_bounds__(NT) k_plane_conv(PassArgs a) {
   cpx<T>* plane = reinterpret_cast<cpx<T>*>(smem_raw);
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
-  const int kz = lg / a.n_active, ai = lg - kz * a.n_active;
-  const int slot = a.active[ai];
-  cpx<T>* __restrict__ base = static_cast<cpx<T>*>(a.grids) + (long long)slot * NR + (long long)kz * N * N;
-  const T* __restrict__ vt = static_cast<const T*>(a.vtab) + (long long)kz * N * N;
+  const int total = a.n_active * N;  // planes of this launch, kz-major
+  cpx<T>* __restrict__ gbase = static_cast<cpx<T>*>(a.grids);
 
-  // x forward: stage-0 inputs straight from HBM (rows, x contiguous)
-  cpx<T> v[FX::VALS];
-#pragma unroll
-  for (int i = 0; i < FX::PER; ++i) {
-    if (!FX::valid(tid, i)) continue;
-    int m, j;
-    FX::mj(tid, i, m, j);
-#pragma unroll
-    for (int r = 0; r < SchedInfo<SXF>::first; ++r)
-      v[i * SchedInfo<SXF>::first + r] = base[m * N + FX::in_pos(j, r)];
-  }
+  const int L = lg;  // plane of this launch, kz-major over the active grids
+  if (L >= total) return;
+  __shared__ TwEntry<T> twxf[tw_slots<T, SXF>()], twyf[tw_slots<T, SYF>()],
+      twyi[tw_slots<T, SYI>()], twxi[tw_slots<T, SXI>()];
+  stage_twiddles<T, SXF, NT>(twxf, a.tw_xf, tid);  // visible after the first barrier
+  stage_twiddles<T, SYF, NT>(twyf, a.tw_yf, tid);
+  stage_twiddles<T, SYI, NT>(twyi, a.tw_yi, tid);
+  stage_twiddles<T, SXI, NT>(twxi, a.tw_xi, tid);
+  const int kz = L / a.n_active, ai = L - kz * a.n_active;
+  cpx<T>* __restrict__ base = gbase + (long long)a.active[ai] * NR + (long long)kz * N * N;
+  const T* __restrict__ vt = static_cast<const T*>(a.vtab) + (long long)kz * N * N;
   {
+    // x-forward stage-0 inputs straight from HBM (rows, x contiguous)
+    cpx<T> v[FX::VALS];
+#pragma unroll
+    for (int i = 0; i < FX::PER; ++i) {
+      if (!FX::valid(tid, i)) continue;
+      int m, j;
+      FX::mj(tid, i, m, j);
+#pragma unroll
+      for (int r = 0; r < SchedInfo<SXF>::first; ++r)
+        v[i * SchedInfo<SXF>::first + r] = base[m * N + FX::in_pos(j, r)];
+    }
     cpx<T> o[LXF::VALS];
-    EXF::reg2reg(v, plane, static_cast<const TwEntry<T>*>(a.tw_xf), tid, o);
+    EXF::reg2reg(v, plane, twxf, tid, o);
     EXF::store_last(o, plane, tid);
   }
   __syncthreads();
   // y forward, multiply by v(G)/N_r, y inverse (hand-over in registers)
   cpx<T> oy[LY::VALS];
-  EYF::lds2reg(plane, static_cast<const TwEntry<T>*>(a.tw_yf), tid, oy);
+  EYF::lds2reg(plane, twyf, tid, oy);
 #pragma unroll
   for (int i = 0; i < LY::PER; ++i) {
     if (!LY::valid(tid, i)) continue;
@@ -378,13 +531,13 @@ __global__ void __launch_bounds__(NT) k_plane_conv(PassArgs a) {
   }
   {
     cpx<T> o[LYI::VALS];
-    EYI::reg2reg(oy, plane, static_cast<const TwEntry<T>*>(a.tw_yi), tid, o);
+    EYI::reg2reg(oy, plane, twyi, tid, o);
     EYI::store_last(o, plane, tid);
   }
   __syncthreads();
   // x inverse, results straight to HBM
   cpx<T> ox[LXI::VALS];
-  EXI::lds2reg(plane, static_cast<const TwEntry<T>*>(a.tw_xi), tid, ox);
+  EXI::lds2reg(plane, twxi, tid, ox);
 #pragma unroll
   for (int i = 0; i < LXI::PER; ++i) {
     if (!LXI::valid(tid, i)) continue;
@@ -416,7 +569,9 @@ __global__ void __launch_bounds__(NT) k_rows(PassArgs a) {
   const int slot = a.active[ai];
   cpx<T>* __restrict__ base = static_cast<cpx<T>*>(a.grids) + (long long)slot * NR;
   const long long row0 = (long long)rb * RW;
-  const TwEntry<T>* tw = static_cast<const TwEntry<T>*>(INV ? a.tw_xi : a.tw_xf);
+  __shared__ TwEntry<T> twl[tw_slots<T, SX>()];
+  stage_twiddles<T, SX, NT>(twl, INV ? a.tw_xi : a.tw_xf, tid);  // visible after the first barrier
+  const TwEntry<T>* tw = twl;
   cpx<T> v[F::VALS];
 #pragma unroll
   for (int i = 0; i < F::PER; ++i) {
@@ -457,7 +612,10 @@ __global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
   constexpr int NXB = (N + W - 1) / W;
   constexpr long long NR = (long long)N * N * N;
   __shared__ cpx<T> lds[N * W];
+  __shared__ TwEntry<T> twf[tw_slots<T, SYF>()], twi[tw_slots<T, SYI>()];
   const int tid = threadIdx.x;
+  stage_twiddles<T, SYF, NT>(twf, a.tw_yf, tid);  // visible after the first barrier
+  stage_twiddles<T, SYI, NT>(twi, a.tw_yi, tid);
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const int per_grid = N * NXB;
   const int ai = lg / per_grid, rem = lg - ai * per_grid;
@@ -477,7 +635,7 @@ __global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
           ok ? base[F::in_pos(j, r) * N + x0 + m] : cpx<T>{T(0), T(0)};
   }
   cpx<T> o[LF::VALS];
-  EF::reg2reg(v, lds, static_cast<const TwEntry<T>*>(a.tw_yf), tid, o);
+  EF::reg2reg(v, lds, twf, tid, o);
 #pragma unroll
   for (int i = 0; i < LF::PER; ++i) {
     int m = 0, j = 0;
@@ -490,7 +648,7 @@ __global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
     }
   }
   cpx<T> b[LI::VALS];
-  EI::reg2reg(o, lds, static_cast<const TwEntry<T>*>(a.tw_yi), tid, b);
+  EI::reg2reg(o, lds, twi, tid, b);
 #pragma unroll
   for (int i = 0; i < LI::PER; ++i) {
     int m = 0, j = 0;
@@ -505,13 +663,20 @@ __global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
 // ---------------------------------------------------------------------------
 // Registry glue: one compiled pipeline configuration.
 
-// Brick points per thread of the pair_fwd / inv_acc passes: 4 in float32,
-// 2 in float64 (keeps the tile's psi and accumulators in registers at >= 3-4
-// wavefronts per SIMD), and 4 for float64 bricks too large for 768 threads
-// (more threads per workgroup would cap the registers at 128 and spill).
-template <typename T, int N, int W>
-constexpr int pts_per_thread() {
-  return sizeof(T) == 4 ? 4 : (N * W / 2 > 768 ? 4 : 2);
+// Threads of the pair_fwd (FWD) and inv_acc passes.  float32: 256 for the
+// product pass (fewer, longer wavefronts measured fastest), and for the
+// accumulation pass 512, or 1024 for bricks of more than 1536 points (3
+// points per thread keep the tile's psi and accumulators within 128
+// registers, so that whole workgroups fill the compute unit).  float64: 2
+// brick points per thread, or 4 for bricks too large for 768 threads (more
+// threads per workgroup would cap the registers at 128 and spill).
+template <typename T, int N, int W, bool FWD>
+constexpr int pencil_threads() {
+  if constexpr (sizeof(T) == 4) {
+    return FWD ? 256 : (N * W > 1536 ? 1024 : 512);
+  } else {
+    return N * W / 2 > 768 ? (N * W + 3) / 4 : (N * W + 1) / 2;
+  }
 }
 template <int... R>
 constexpr void fill_radices(int* dst, int& n, Sched<R...>) {
@@ -520,26 +685,30 @@ constexpr void fill_radices(int* dst, int& n, Sched<R...>) {
   for (int i = 0; i < n; ++i) dst[i] = r[i];
 }
 
-template <typename T, int N, int W, int NTP, int TT, class SZF, class SZI, int NTQ, class SXF,
-          class SXI, class SYF, class SYI, int NTA = (N * W + pts_per_thread<T, N, W>() - 1) / pts_per_thread<T, N, W>()>
+// Fused three-pass pipeline: W-wide z bricks, TT-orbital tiles, plane
+// kernel of NTQ threads with the plane in LDS.
+template <typename T, int N, int W, int TT, class SZF, class SZI, int NTQ, class SXF, class SXI,
+          class SYF, class SYI, bool SW = false,
+          int NTF = pencil_threads<T, N, W, true>(), int NTI = pencil_threads<T, N, W, false>(),
+          bool PJL = false, bool PF = false>
 struct FusedPipeline {
   static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
   static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTA, TT, SZF>), dim3(nb), dim3(NTA), 0, s, a);
+    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF>), dim3(nb), dim3(NTF), 0, s, a);
   }
   static void plane(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI>), dim3(nb), dim3(NTQ), lds, s,
-                       a);
+    hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW>), dim3(nb), dim3(NTQ), lds,
+                       s, a);
   }
   static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTA, TT, SZI, true>), dim3(nb), dim3(NTA), 0, s, a);
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF>), dim3(nb), dim3(NTI), 0, s, a);
   }
   static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTA, TT, SZI, false>), dim3(nb), dim3(NTA), 0, s, a);
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF>), dim3(nb), dim3(NTI), 0, s, a);
   }
   static hipError_t prepare() {
     return hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI>),
+        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
   static Variant describe(const char* name) {
@@ -549,8 +718,10 @@ struct FusedPipeline {
     v.prec = sizeof(T) == 8 ? 1 : 0;
     v.brick = W;
     v.tile = TT;
-    v.nt_pencil = NTP;
+    v.nt_fwd = NTF;
+    v.nt_acc = NTI;
     v.nt_plane = NTQ;
+    v.nt_cols = 0;
     v.plane_mode = 0;
     v.rows_per_wg = 0;
     fill_radices(v.zf, v.nzf, SZF{});
@@ -569,13 +740,16 @@ struct FusedPipeline {
   }
 };
 
-template <typename T, int N, int W, int NTP, int TT, class SZF, class SZI, int RW, int NTQ,
+// Split pipeline (plane too large for LDS): RW-row x kernels of NTQ threads,
+// y-column kernel of NTC threads.
+template <typename T, int N, int W, int NTC, int TT, class SZF, class SZI, int RW, int NTQ,
           class SXF, class SXI, class SYF, class SYI,
-          int NTA = (N * W + pts_per_thread<T, N, W>() - 1) / pts_per_thread<T, N, W>()>
+          int NTF = pencil_threads<T, N, W, true>(), int NTI = pencil_threads<T, N, W, false>(),
+          bool PJL = false, bool PF = false>
 struct SplitPipeline {
   static constexpr size_t lds = (size_t)RW * (N + 1) * sizeof(cpx<T>);
   static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTA, TT, SZF>), dim3(nb), dim3(NTA), 0, s, a);
+    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF>), dim3(nb), dim3(NTF), 0, s, a);
   }
   static void rows_fwd(const PassArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXF, false>), dim3(nb), dim3(NTQ), lds, s, a);
@@ -584,13 +758,13 @@ struct SplitPipeline {
     hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXI, true>), dim3(nb), dim3(NTQ), lds, s, a);
   }
   static void cols_conv(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_cols_conv<T, N, W, NTP, SYF, SYI>), dim3(nb), dim3(NTP), 0, s, a);
+    hipLaunchKernelGGL((k_cols_conv<T, N, W, NTC, SYF, SYI>), dim3(nb), dim3(NTC), 0, s, a);
   }
   static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTA, TT, SZI, true>), dim3(nb), dim3(NTA), 0, s, a);
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF>), dim3(nb), dim3(NTI), 0, s, a);
   }
   static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTA, TT, SZI, false>), dim3(nb), dim3(NTA), 0, s, a);
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF>), dim3(nb), dim3(NTI), 0, s, a);
   }
   static hipError_t prepare() {
     hipError_t e = hipFuncSetAttribute(
@@ -607,8 +781,10 @@ struct SplitPipeline {
     v.prec = sizeof(T) == 8 ? 1 : 0;
     v.brick = W;
     v.tile = TT;
-    v.nt_pencil = NTP;
+    v.nt_fwd = NTF;
+    v.nt_acc = NTI;
     v.nt_plane = NTQ;
+    v.nt_cols = NTC;
     v.plane_mode = 1;
     v.rows_per_wg = RW;
     fill_radices(v.zf, v.nzf, SZF{});

@@ -264,7 +264,13 @@ template <bool INV, typename T> struct DFT<16, INV, T> : DFTPQ<4, 4, INV, T> {};
 
 // ---------------------------------------------------------------------------
 // Geometry of one batched transform inside a workgroup.
-template <typename T_, int N_, int M_, int NT_, bool MFAST_, int ES_, int TS_>
+// SWZ: LDS index swizzle for a square plane with pitch P stored [y][x]:
+//   0 none: element (m, n) at m*TS + n*ES
+//   1 rows (m = y, n = x) and 2 columns (m = x, n = y): element (y, x) at
+//     y*P + (x ^ ((x >> 3) & 7)), an XOR inside each block of 8 along x that
+//     spreads the stride-8 first-stage writes of the row transforms over the
+//     banks without extra LDS (needs N % 8 == 0).
+template <typename T_, int N_, int M_, int NT_, bool MFAST_, int ES_, int TS_, int SWZ_ = 0>
 struct Geom {
   using T = T_;
   static constexpr int N = N_;     // transform length
@@ -273,6 +279,16 @@ struct Geom {
   static constexpr bool MFAST = MFAST_;
   static constexpr int ES = ES_;   // LDS stride between elements of a sequence
   static constexpr int TS = TS_;   // LDS stride between sequences
+  static constexpr int SWZ = SWZ_;
+  HFX_HD static int idx(int m, int n) {
+    if constexpr (SWZ == 1) {
+      return m * TS + (n ^ ((n >> 3) & 7));
+    } else if constexpr (SWZ == 2) {
+      return n * ES + (m ^ ((m >> 3) & 7));
+    } else {
+      return m * TS + n * ES;
+    }
+  }
 };
 
 template <class G, int R, int NS>
@@ -332,7 +348,7 @@ struct Stage {
       int m, j;
       mj(tid, i, m, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i * R + r] = lds[m * G::TS + in_pos(j, r) * G::ES];
+      for (int r = 0; r < R; ++r) v[i * R + r] = lds[G::idx(m, in_pos(j, r))];
     }
   }
 
@@ -343,7 +359,7 @@ struct Stage {
       int m, j;
       mj(tid, i, m, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[m * G::TS + out_pos(j, r) * G::ES] = v[i * R + r];
+      for (int r = 0; r < R; ++r) lds[G::idx(m, out_pos(j, r))] = v[i * R + r];
     }
   }
 };

@@ -109,12 +109,27 @@ struct hfx_graph_t {
 
 namespace {
 
-const Variant* find_variant(int n, int prec) {
+// First compiled variant for grid size n (the default), or the one named.
+const Variant* find_variant(int n, int prec, const std::string& name = "") {
   int count = 0;
   const Variant* v = prec == HFX_FP64 ? variants_f64(&count) : variants_f32(&count);
   for (int i = 0; i < count; ++i)
-    if (v[i].n == n) return &v[i];
+    if (v[i].n == n && (name.empty() || name == v[i].name)) return &v[i];
   return nullptr;
+}
+
+std::string parse_option_str(const char* opts, const char* key) {
+  if (!opts) return "";
+  const std::string s(opts), k = std::string(key) + "=";
+  size_t p = 0;
+  while (p < s.size()) {
+    size_t e = s.find(';', p);
+    if (e == std::string::npos) e = s.size();
+    const std::string item = s.substr(p, e - p);
+    if (item.compare(0, k.size(), k) == 0) return item.substr(k.size());
+    p = e + 1;
+  }
+  return "";
 }
 
 long long parse_option(const char* opts, const char* key, long long def) {
@@ -578,6 +593,19 @@ const char* hfx_status_string(hfx_status s) {
 
 const char* hfx_last_error(void) { return g_last_error.c_str(); }
 
+const char* hfx_variants(int n, int precision) {
+  static thread_local std::string out;
+  out.clear();
+  int count = 0;
+  const Variant* v = precision == HFX_FP64 ? variants_f64(&count) : variants_f32(&count);
+  for (int i = 0; i < count; ++i)
+    if (v[i].n == n) {
+      if (!out.empty()) out += ";";
+      out += v[i].name;
+    }
+  return out.c_str();
+}
+
 hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int precision,
                            const char* options) {
   g_last_error.clear();
@@ -596,6 +624,11 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
                                         ")");
   }
   const long long tiles_cap = parse_option(options, "tiles", 0);
+  const std::string vname = parse_option_str(options, "variant");
+  if (!vname.empty() && n_sys > 1)
+    return fail(HFX_EINVAL, "variant= applies to single-system plans only");
+  if (!vname.empty() && !find_variant(sys[0].n[0], precision, vname))
+    return fail(HFX_EINVAL, "unknown variant '" + vname + "' for this grid and precision");
   long long ws_cap = parse_option(options, "maxws", 0);
   if (const char* env = std::getenv("HFX_MAX_WORKSPACE_BYTES")) {
     const long long e = std::atoll(env);
@@ -611,7 +644,7 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   for (int i = 0; i < n_sys; ++i) {
     SystemPlan& sp = p->sys[i];
     sp.sys = sys[i];
-    sp.var = find_variant(sys[i].n[0], precision);
+    sp.var = find_variant(sys[i].n[0], precision, vname);
     sp.n = sys[i].n[0];
     sp.nr = (long long)sp.n * sp.n * sp.n;
     sp.dv = sys[i].L[0] * sys[i].L[1] * sys[i].L[2] / (double)sp.nr;

@@ -52,8 +52,10 @@ struct Variant {
   int prec;        // 0 float32, 1 float64
   int brick;       // pencil width W (x values per workgroup)
   int tile;        // orbital tile T
-  int nt_pencil;   // threads per pencil workgroup
-  int nt_plane;    // threads per plane workgroup (or per row/column workgroup)
+  int nt_fwd;      // threads per pair_fwd workgroup
+  int nt_acc;      // threads per inv_acc workgroup
+  int nt_plane;    // threads per plane workgroup (plane_mode 1: per row workgroup)
+  int nt_cols;     // plane_mode 1: threads per column workgroup
   int plane_mode;  // 0: fused xy plane in LDS; 1: x rows + y columns passes
   int rows_per_wg; // plane_mode 1: rows per row-FFT workgroup
   int zf[4], nzf, zi[4], nzi;  // z radix schedules (forward, inverse)

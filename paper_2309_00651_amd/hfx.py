@@ -36,6 +36,12 @@ _STATUS = {0: "HFX_OK", 1: "HFX_EINVAL", 2: "HFX_EUNSUPPORTED", 3: "HFX_ENOMEM",
            4: "HFX_EDEVICE"}
 
 
+def variants(n, precision=FP32):
+    """Names of the compiled kernel configurations for an n^3 grid (default first)."""
+    v = load_library().hfx_variants(int(n), int(precision)).decode()
+    return [x for x in v.split(";") if x]
+
+
 class HfxError(RuntimeError):
     def __init__(self, status, detail):
         self.status = status
@@ -75,6 +81,8 @@ def load_library(path=None):
     lib.hfx_graph_create.argtypes = [vp, i, vp, vp, vp, vp, vp, sz, ctypes.POINTER(vp)]
     lib.hfx_graph_launch.argtypes = [vp, vp]
     lib.hfx_graph_destroy.argtypes = [vp]
+    lib.hfx_variants.argtypes = [i, i]
+    lib.hfx_variants.restype = ctypes.c_char_p
     lib.hfx_status_string.argtypes = [i]
     lib.hfx_status_string.restype = ctypes.c_char_p
     lib.hfx_last_error.argtypes = []

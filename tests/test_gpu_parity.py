@@ -214,3 +214,25 @@ def test_workspace_too_small_is_rejected():
                                  ctypes.c_void_p(ex.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                  plan.ws_bytes - 1, ctypes.c_void_p(0))
     assert st == 3 and "workspace too small" in lib.hfx_last_error().decode()
+
+
+def test_every_compiled_variant():
+    """All kernel configurations of every grid size agree with the oracle."""
+    for n, L, n_orb, fam, kernel, param in VARIANTS:
+        for prec in (hfx.FP32, hfx.FP64):
+            names = hfx.variants(n, prec)
+            if len(names) < 2:
+                continue
+            psi = make_inputs(n, L, n_orb, fam, seed=2000 + n)
+            ref = oracle_run(psi, L, kernel, param)
+            for v in names:
+                print(f"case n={n} prec={prec} variant={v}", flush=True)
+                got = gpu_run(psi, L, kernel, param, prec, options=f"variant={v}")
+                check(ref, got, prec, L, psi)
+
+
+def test_unknown_variant_rejected():
+    _dev()
+    with pytest.raises(hfx.HfxError) as e:
+        hfx.Plan(hfx.SystemSpec(24, (10.0,) * 3, 3), hfx.FP32, options="variant=nope")
+    assert e.value.status == 1
