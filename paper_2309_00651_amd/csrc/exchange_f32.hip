@@ -14,44 +14,51 @@ using P64 = FusedPipeline<float, 64, 16, 8, Sched<8, 8>, Sched<8, 8>, 256, Sched
                           Sched<8, 8>, Sched<8, 8>, Sched<8, 8>>;
 using P64q512 = FusedPipeline<float, 64, 16, 8, Sched<8, 8>, Sched<8, 8>, 512, Sched<8, 8>,
                               Sched<8, 8>, Sched<8, 8>, Sched<8, 8>>;
+using P64r = FusedPipeline<float, 64, 16, 8, Sched<8, 8>, Sched<8, 8>, 256, Sched<8, 8>,
+                           Sched<8, 8>, Sched<8, 8>, Sched<8, 8>, false, 256, 512, false, false>;
 using P72 = FusedPipeline<float, 72, 16, 8, Sched<8, 9>, Sched<9, 8>, 576, Sched<8, 9>,
                           Sched<9, 8>, Sched<8, 9>, Sched<9, 8>>;
 using P72q216 = FusedPipeline<float, 72, 16, 8, Sched<8, 9>, Sched<9, 8>, 216, Sched<8, 9>,
                               Sched<9, 8>, Sched<8, 9>, Sched<9, 8>>;
+using P72r = FusedPipeline<float, 72, 16, 8, Sched<8, 9>, Sched<9, 8>, 576, Sched<8, 9>,
+                           Sched<9, 8>, Sched<8, 9>, Sched<9, 8>, false, 256, 512, false, false>;
 using P80 = FusedPipeline<float, 80, 16, 8, Sched<8, 10>, Sched<10, 8>, 640, Sched<8, 10>,
                           Sched<10, 8>, Sched<8, 10>, Sched<10, 8>>;
 using P80q320 = FusedPipeline<float, 80, 16, 8, Sched<8, 10>, Sched<10, 8>, 320, Sched<8, 10>,
                               Sched<10, 8>, Sched<8, 10>, Sched<10, 8>>;
+using P80r = FusedPipeline<float, 80, 16, 8, Sched<8, 10>, Sched<10, 8>, 640, Sched<8, 10>,
+                           Sched<10, 8>, Sched<8, 10>, Sched<10, 8>, false, 256, 512, false, false>;
 using P96 = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
                           Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
-// alternatives for the autotuner: radix-12-first inverse z; plane threads;
-// swizzled plane LDS; accumulation threads; psi J block in LDS with prefetch;
-// radix-12-first forward z
+// alternatives for the autotuner (here and below): psi J block in registers
+// without prefetch (-r) or in LDS with prefetch (-lp); radix-12-first inverse z; plane threads; swizzled plane LDS;
+// psi I block in LDS
+using P96r = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
+                           Sched<12, 8>, Sched<8, 12>, Sched<12, 8>, false, 256, 512, false, false>;
 using P96z12 = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<12, 8>, 768, Sched<8, 12>,
                              Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
 using P96q384 = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 384, Sched<8, 12>,
                               Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
 using P96sw = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
                             Sched<12, 8>, Sched<8, 12>, Sched<12, 8>, true>;
-using P96i768 = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
-                              Sched<12, 8>, Sched<8, 12>, Sched<12, 8>, false, 256, 768>;
-using P96lp = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
-                            Sched<12, 8>, Sched<8, 12>, Sched<12, 8>, false, 256, 512, true, true>;
-using P96f12 = FusedPipeline<float, 96, 16, 8, Sched<12, 8>, Sched<8, 12>, 768, Sched<8, 12>,
-                             Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
+using P96pi = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
+                            Sched<12, 8>, Sched<8, 12>, Sched<12, 8>, false, 512, 512, true, true,
+                            true>;
 using P108 = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
                            Sched<9, 12>, Sched<12, 9>, Sched<9, 12>>;
-using P108i512 = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
-                               Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 512>;
+using P108r = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
+                            Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, false,
+                            false>;
 using P120 = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
                            Sched<12, 10>, Sched<10, 12>, Sched<12, 10>>;
-using P120i512 = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960,
-                               Sched<10, 12>, Sched<12, 10>, Sched<10, 12>, Sched<12, 10>, false,
-                               256, 512>;
+using P120lp = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
+                             Sched<12, 10>, Sched<10, 12>, Sched<12, 10>, false, 256, 1024, true,
+                             true>;
 using P128 = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
                            Sched<16, 8>, Sched<8, 16>, Sched<16, 8>>;
-using P128i512 = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
-                               Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 512>;
+using P128lp = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
+                             Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, true,
+                             true>;
 }  // namespace
 
 const Variant* variants_f32(int* count) {
@@ -59,23 +66,25 @@ const Variant* variants_f32(int* count) {
       P24::describe("f32-n24"),
       P64::describe("f32-n64"),
       P64q512::describe("f32-n64-q512"),
+      P64r::describe("f32-n64-r"),
       P72::describe("f32-n72"),
       P72q216::describe("f32-n72-q216"),
+      P72r::describe("f32-n72-r"),
       P80::describe("f32-n80"),
       P80q320::describe("f32-n80-q320"),
+      P80r::describe("f32-n80-r"),
       P96::describe("f32-n96"),
+      P96r::describe("f32-n96-r"),
       P96z12::describe("f32-n96-z12"),
       P96q384::describe("f32-n96-q384"),
       P96sw::describe("f32-n96-sw"),
-      P96i768::describe("f32-n96-i768"),
-      P96lp::describe("f32-n96-lp"),
-      P96f12::describe("f32-n96-f12"),
+      P96pi::describe("f32-n96-pi"),
       P108::describe("f32-n108"),
-      P108i512::describe("f32-n108-i512"),
+      P108r::describe("f32-n108-r"),
       P120::describe("f32-n120"),
-      P120i512::describe("f32-n120-i512"),
+      P120lp::describe("f32-n120-lp"),
       P128::describe("f32-n128"),
-      P128i512::describe("f32-n128-i512"),
+      P128lp::describe("f32-n128-lp"),
   };
   *count = (int)(sizeof(v) / sizeof(v[0]));
   return v;

@@ -90,7 +90,12 @@ __device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const Til
 // points p = tid + k NT (k < PT, contiguous x for coalesced psi reads) for both
 // grids; the transform starts from LDS and its last stage stores straight to
 // HBM.  psi of the tile's J block stays in registers for the whole tile.
-template <typename T, int N, int W, int NT, int TT, class SZF>
+// With PIL the I block is loaded once too, into LDS (each thread reads back
+// only what it wrote), so the loop over orbitals issues no global loads: its
+// HBM stores are never waited for (one in-order counter tracks loads and
+// stores, so a later load would wait for them).  Without PIL, psi_a is loaded
+// per orbital.
+template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL>
 __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
   constexpr int W2 = 2 * W;
@@ -107,6 +112,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   __shared__ cpx<T> lds[N * W2];
   __shared__ TwEntry<T> twl[tw_slots<T, SZF>()];
   __shared__ T mul[TT * TT];  // pair-density means of the tile, [a][b]
+  __shared__ T pil[PIL ? TT * PT * NT : 1];  // psi of the I block, [a][k][tid]
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const int t = lg / BR, br = lg - t * BR;
@@ -115,7 +121,6 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
   stage_twiddles<T, SZF, NT>(twl, a.tw_zf, tid);
   stage_means<T, TT, NT>(mul, a, td, 1.0, tid);
-  __syncthreads();
   const TwEntry<T>* tw = twl;
   cpx<T>* __restrict__ grids = static_cast<cpx<T>*>(a.grids);
 
@@ -141,20 +146,44 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
     offL[i] = vL[i] ? (j * N + y) * N + x0 + mx : 0;
   }
 
+  // psi of the J block (registers) and, with PIL, of the I block (LDS),
+  // zero off the grid; loads issued four orbitals at a time before any use
   T pj[TT][PT];
+  static_for<0, TT / 4>([&](auto hc) {
+    constexpr int b0 = 4 * decltype(hc)::value;
+    T xj[4][PT], xi[PIL ? 4 : 1][PT];
 #pragma unroll
-  for (int b = 0; b < TT; ++b) {
-    const bool bv = b < td.nJ;
-    const T* p = psi + (long long)(td.j0 + (bv ? b : 0)) * NR;
+    for (int q = 0; q < 4; ++q) {
+      const T* pb = psi + (long long)(td.j0 + (b0 + q < td.nJ ? b0 + q : 0)) * NR;
 #pragma unroll
-    for (int k = 0; k < PT; ++k) pj[b][k] = (bv && vA[k]) ? p[offA[k]] : T(0);
-  }
+      for (int k = 0; k < PT; ++k) xj[q][k] = pb[offA[k]];
+      if constexpr (PIL) {
+        const T* pa = psi + (long long)(td.i0 + (b0 + q < td.nI ? b0 + q : 0)) * NR;
+#pragma unroll
+        for (int k = 0; k < PT; ++k) xi[q][k] = pa[offA[k]];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < PT; ++k) {
+        pj[b0 + q][k] = (b0 + q < td.nJ && vA[k]) ? xj[q][k] : T(0);
+        if constexpr (PIL)
+          pil[((b0 + q) * PT + k) * NT + tid] = (b0 + q < td.nI && vA[k]) ? xi[PIL ? q : 0][k] : T(0);
+      }
+  });
+  __syncthreads();
 
   for (int ia = 0; ia < td.nI; ++ia) {
-    const T* pa_ptr = psi + (long long)(td.i0 + ia) * NR;
     T pa[PT];
+    if constexpr (PIL) {
 #pragma unroll
-    for (int k = 0; k < PT; ++k) pa[k] = vA[k] ? pa_ptr[offA[k]] : T(0);
+      for (int k = 0; k < PT; ++k) pa[k] = pil[(ia * PT + k) * NT + tid];
+    } else {
+      const T* pa_ptr = psi + (long long)(td.i0 + ia) * NR;
+#pragma unroll
+      for (int k = 0; k < PT; ++k) pa[k] = vA[k] ? pa_ptr[offA[k]] : T(0);
+    }
     static_for<0, TT / 4>([&](auto bq) {
       constexpr int b0 = 4 * decltype(bq)::value;  // pairs (a, b0 .. b0 + 3), grids 2bq, 2bq+1
       // grid g carries pairs (a, b0 + 2g) and (a, b0 + 2g + 1)
@@ -678,6 +707,12 @@ constexpr int pencil_threads() {
     return N * W / 2 > 768 ? (N * W + 3) / 4 : (N * W + 1) / 2;
   }
 }
+// psi_J block in LDS and next-step prefetch in inv_acc: float32 bricks of up
+// to 1728 points (measured faster there; larger bricks spill with it).
+template <typename T, int N, int W>
+constexpr bool pencil_prefetch() {
+  return sizeof(T) == 4 && N * W <= 1728;
+}
 template <int... R>
 constexpr void fill_radices(int* dst, int& n, Sched<R...>) {
   const int r[] = {R...};
@@ -690,11 +725,12 @@ constexpr void fill_radices(int* dst, int& n, Sched<R...>) {
 template <typename T, int N, int W, int TT, class SZF, class SZI, int NTQ, class SXF, class SXI,
           class SYF, class SYI, bool SW = false,
           int NTF = pencil_threads<T, N, W, true>(), int NTI = pencil_threads<T, N, W, false>(),
-          bool PJL = false, bool PF = false>
+          bool PJL = pencil_prefetch<T, N, W>(), bool PF = pencil_prefetch<T, N, W>(),
+          bool PIL = false>
 struct FusedPipeline {
   static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
   static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF>), dim3(nb), dim3(NTF), 0, s, a);
+    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL>), dim3(nb), dim3(NTF), 0, s, a);
   }
   static void plane(const PassArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW>), dim3(nb), dim3(NTQ), lds,
@@ -745,11 +781,11 @@ struct FusedPipeline {
 template <typename T, int N, int W, int NTC, int TT, class SZF, class SZI, int RW, int NTQ,
           class SXF, class SXI, class SYF, class SYI,
           int NTF = pencil_threads<T, N, W, true>(), int NTI = pencil_threads<T, N, W, false>(),
-          bool PJL = false, bool PF = false>
+          bool PJL = false, bool PF = false, bool PIL = false>
 struct SplitPipeline {
   static constexpr size_t lds = (size_t)RW * (N + 1) * sizeof(cpx<T>);
   static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF>), dim3(nb), dim3(NTF), 0, s, a);
+    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL>), dim3(nb), dim3(NTF), 0, s, a);
   }
   static void rows_fwd(const PassArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXF, false>), dim3(nb), dim3(NTQ), lds, s, a);

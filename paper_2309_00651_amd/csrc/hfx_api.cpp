@@ -73,7 +73,6 @@ struct SystemPlan {
   size_t ws_end = 0;
   // offsets inside concatenated user buffers
   long long psi_off = 0, m_off = 0;
-  int gemm_chunks = 1;
 };
 
 }  // namespace
@@ -396,8 +395,7 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
     double* mu = reinterpret_cast<double*>(ws + sp.off_mean);
     double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
     Bracket br(plan, HFX_PASS_CONTRACT, st);
-    launch_xtx_f64(psi, psi, sp.sys.n_orb, sp.nr, 1.0 / (double)sp.nr, part, sp.gemm_chunks, mu,
-                   st);
+    launch_xtx_f64(psi, psi, sp.sys.n_orb, sp.nr, 1.0 / (double)sp.nr, part, mu, st);
     br.done(orb_pts * 8.0, 2.0 * (double)sp.sys.n_orb * orb_pts);
     mean = mu;
   }
@@ -526,10 +524,10 @@ hfx_status enq_matrix(hfx_plan plan, SystemPlan& sp, const double* psi, const vo
   Bracket bk(plan, HFX_PASS_CONTRACT, st);
   if (plan->prec == HFX_FP32)
     launch_xtx_split(psi + sp.psi_off, reinterpret_cast<const float*>(kp), sp.sys.n_orb, sp.nr,
-                     sp.dv, part, sp.gemm_chunks, m + sp.m_off, st);
+                     sp.dv, part, m + sp.m_off, st);
   else
     launch_xtx_f64(psi + sp.psi_off, reinterpret_cast<const double*>(kp), sp.sys.n_orb, sp.nr,
-                   sp.dv, part, sp.gemm_chunks, m + sp.m_off, st);
+                   sp.dv, part, m + sp.m_off, st);
   // split precision: two float32 products per term
   bk.done(nn * npts * (8.0 + elem), 2.0 * nn * nn * npts * (plan->prec == HFX_FP32 ? 2.0 : 1.0));
   HIP_TRY(hipGetLastError());
@@ -547,7 +545,7 @@ hfx_status enq_ortho(hfx_plan plan, SystemPlan& sp, double* psi, char* ws, hipSt
   const double nn = n, npts = (double)sp.nr;
   {
     Bracket bk(plan, HFX_PASS_CONTRACT, st);
-    launch_xtx_f64(p, p, n, sp.nr, sp.dv, part, sp.gemm_chunks, smat, st);
+    launch_xtx_f64(p, p, n, sp.nr, sp.dv, part, smat, st);
     bk.done(nn * npts * 8.0, 2.0 * nn * nn * npts);
   }
   Bracket bk(plan, HFX_PASS_ORTHO, st);
@@ -653,7 +651,6 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     sp.m_off = m_off;
     psi_off += (long long)sys[i].n_orb * sp.nr;
     m_off += (long long)sys[i].n_orb * sys[i].n_orb;
-    sp.gemm_chunks = gemm_chunks(sys[i].n_orb, sp.nr);
     // workspace layout of this system
     sp.off_psi32 = off;
     if (precision == HFX_FP32) off = align_up(off + (size_t)sys[i].n_orb * sp.nr * 4);
@@ -662,8 +659,7 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     sp.off_partials = off;
     off = align_up(off + (size_t)sp.n_partials * 8);
     sp.off_gemm = off;
-    const int tiles = (sys[i].n_orb + 63) / 64;
-    off = align_up(off + (size_t)tiles * tiles * sp.gemm_chunks * 64 * 64 * 8);
+    off = align_up(off + gemm_partial_bytes(sys[i].n_orb, sp.nr));
     sp.off_grad = off;
     if (precision == HFX_FP32) off = align_up(off + (size_t)sys[i].n_orb * sp.nr * 4);
     sp.off_mean = off;

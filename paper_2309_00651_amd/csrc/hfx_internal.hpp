@@ -86,16 +86,16 @@ void launch_scale_to_f64(const void* src, int src_is_f64, double* dst, size_t n,
 void launch_energy_reduce(const double* partials, long long n, double scale, const double* mean,
                           int n_orb, double dc_scale, double* out, hipStream_t s);
 
-// Dense products (gemm.hip)
+// Dense products (gemm.hip); `partial` holds gemm_partial_bytes(n_orb, nr).
 // C[k][l] = alpha * sum_r A[k][r] B[l][r], A float64 split into hi + lo
 // float32 parts, B float32, float32 MFMA with float64 accumulation across
 // k-blocks; partials then reduced in a fixed order.
 void launch_xtx_split(const double* a, const float* b, int n_orb, long long nr, double alpha,
-                      double* partial, int n_chunks, double* c, hipStream_t s);
-// C = alpha * A B^T with A, B float64 [n][nr] (float64 MFMA)
+                      double* partial, double* c, hipStream_t s);
+// C = alpha * A B^T with A, B float64 [n][nr] (float64 MFMA; a == b: symmetric)
 void launch_xtx_f64(const double* a, const double* b, int n_orb, long long nr, double alpha,
-                    double* partial, int n_chunks, double* c, hipStream_t s);
-int gemm_chunks(int n_orb, long long nr);
+                    double* partial, double* c, hipStream_t s);
+size_t gemm_partial_bytes(int n_orb, long long nr);
 
 // Orthonormalisation helpers (ortho.hip)
 hipError_t launch_inverse_sqrt(double* s, int n, double* work, int max_iter, hipStream_t st);
