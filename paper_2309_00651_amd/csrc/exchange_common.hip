@@ -32,23 +32,43 @@ __global__ void __launch_bounds__(256) k_zero(uint4* __restrict__ p, size_t n16,
 // out[0] = scale * sum(partials) + dc_scale * sum(mean^2), summed in a fixed
 // order by one workgroup.  The second term is the G = 0 part of the pair
 // energies when the pair-density means were taken out of the transforms.
-__global__ void __launch_bounds__(256) k_energy_reduce(const double* __restrict__ partials,
-                                                       long long n, double scale,
-                                                       const double* __restrict__ mean,
-                                                       long long nmean, double dc_scale,
-                                                       double* __restrict__ out) {
-  __shared__ double red[256];
-  double s = 0.0, d = 0.0;
-  for (long long i = threadIdx.x; i < n; i += 256) s += partials[i];
-  if (mean)
-    for (long long i = threadIdx.x; i < nmean; i += 256) d += mean[i] * mean[i];
-  red[threadIdx.x] = scale * s + dc_scale * d;
+// One workgroup; each thread keeps U independent partial sums (loads in
+// flight together) combined in a fixed order, then a fixed tree: the result
+// is bitwise reproducible.
+__global__ void __launch_bounds__(1024) k_energy_reduce(const double* __restrict__ partials,
+                                                        long long n, double scale,
+                                                        const double* __restrict__ mean,
+                                                        long long nmean, double dc_scale,
+                                                        double* __restrict__ out) {
+  constexpr int NT = 1024, U = 8;
+  __shared__ double red[NT];
+  const int tid = threadIdx.x;
+  auto sum = [&](const double* v, long long len, bool square) {
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0.0;
+    for (long long i0 = 0; i0 < len; i0 += (long long)NT * U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long long i = i0 + tid + (long long)NT * u;
+        const double x = i < len ? v[i] : 0.0;
+        acc[u] += square ? x * x : x;
+      }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += acc[u];
+    return s;
+  };
+  const double s = sum(partials, n, false);
+  const double d = mean ? sum(mean, nmean, true) : 0.0;
+  red[tid] = scale * s + dc_scale * d;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (tid == 0) out[0] = red[0];
 }
 
 template <typename S>
@@ -96,7 +116,7 @@ void launch_scale_to_f64(const void* src, int src_is_f64, double* dst, size_t n,
 
 void launch_energy_reduce(const double* partials, long long n, double scale, const double* mean,
                           int n_orb, double dc_scale, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, s, partials, n, scale, mean,
+  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(1024), 0, s, partials, n, scale, mean,
                      (long long)n_orb * n_orb, dc_scale, out);
 }
 

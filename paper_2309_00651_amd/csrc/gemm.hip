@@ -76,7 +76,9 @@ GemmShape gemm_shape(int n, long long nr, bool sym) {
   g.tiles_m = (n + C::TM - 1) / C::TM;
   g.tiles_n = (n + C::TN - 1) / C::TN;
   g.n_tiles = sym ? g.tiles_m * (g.tiles_m + 1) / 2 : g.tiles_m * g.tiles_n;
-  long long chunks = (TARGET_WG + g.n_tiles - 1) / g.n_tiles;
+  // whole rounds: TARGET_WG workgroups run at once, one more would double
+  // the time of the product
+  long long chunks = TARGET_WG / g.n_tiles;
   const long long max_chunks = (nr + 4 * KB - 1) / (4 * KB);  // at least 4 K-blocks each
   if (chunks > max_chunks) chunks = max_chunks;
   if (chunks < 1) chunks = 1;

@@ -549,7 +549,7 @@ hfx_status enq_ortho(hfx_plan plan, SystemPlan& sp, double* psi, char* ws, hipSt
     bk.done(nn * npts * 8.0, 2.0 * nn * nn * npts);
   }
   Bracket bk(plan, HFX_PASS_ORTHO, st);
-  HIP_TRY(launch_inverse_sqrt(smat, n, ns_work, 60, st));
+  HIP_TRY(launch_inverse_sqrt(smat, n, ns_work, 40, st));
   launch_apply_left(smat, p, n, sp.nr, tmp, st);
   bk.done(nn * npts * 16.0, 2.0 * nn * nn * npts);
   HIP_TRY(hipGetLastError());
@@ -684,6 +684,11 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   };
   if (hipGetDevice(&p->device) != hipSuccess)
     return cleanup(fail(HFX_EDEVICE, "no HIP device available"));
+  {
+    hipError_t e = prepare_apply_left();
+    if (e != hipSuccess)
+      return cleanup(fail(HFX_EDEVICE, std::string("kernel set-up: ") + hipGetErrorString(e)));
+  }
   for (auto& sp : p->sys) {
     hfx_status s;
     if (sp.var->prepare) {

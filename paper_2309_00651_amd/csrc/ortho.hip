@@ -2,13 +2,14 @@
 // storage), S = dV Psi Psi^T.
 //
 // S^(-1/2) comes from the coupled Newton-Schulz iteration
-//   Y_0 = S / c, Z_0 = I, c = ||S||_F (so the spectrum lies in (0, 1]),
+//   Y_0 = S / c, Z_0 = I, c = max row sum of |S| (so the spectrum lies in
+//   (0, 1]; c = 1 for orthonormal input, which then converges in two steps),
 //   T_k = (3 I - Z_k Y_k) / 2,  Y_{k+1} = Y_k T_k,  Z_{k+1} = T_k Z_k,
 // whose Z_k converges quadratically to (S/c)^(-1/2); then S^(-1/2) = Z / sqrt(c).
-// Every step is a dense float64 product on the matrix cores.  Convergence is
-// decided on the device: once max|Z Y - I| < 1e-10 one more step is applied
-// and a flag in device memory turns the remaining launches into no-ops, so
-// the host never waits.
+// Every step is three dense float64 products on the matrix cores.
+// Convergence is decided on the device: the step in which max|Z Y - I| <
+// 1e-10 is the last one applied, and a flag in device memory turns the
+// remaining launches into no-ops, so the host never waits.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -84,46 +85,27 @@ __global__ void __launch_bounds__(256) k_gemm_nn_f64(const double* __restrict__ 
       }
 }
 
-// state: [0] done flag, [1] converge-after-this-step flag; scal: [0] = c
+// Newton-Schulz state in device memory: st[0] done flag, st[1] completed
+// steps; err: max |Z Y - I| of the current step as the bits of a
+// non-negative double (ordered like the value, so an integer atomic max
+// applies); scal[0] = c.
+struct NsState {
+  int done, steps, pad[2];
+  unsigned long long err;
+  double c;
+};
+
+// c = max row sum of |S| (a bound on the spectral radius of the symmetric S,
+// tight when S is close to diagonal); Y0 = S / c, Z0 = I.
 __global__ void __launch_bounds__(256) k_ns_init(const double* __restrict__ s, int n,
                                                  double* __restrict__ y, double* __restrict__ z,
-                                                 int* __restrict__ state,
-                                                 double* __restrict__ scal) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  const long long nn = (long long)n * n;
-  for (long long i = threadIdx.x; i < nn; i += 256) acc += s[i] * s[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double c = sqrt(red[0]);
-  for (long long i = threadIdx.x; i < nn; i += 256) {
-    y[i] = s[i] / c;
-    z[i] = (i / n == i % n) ? 1.0 : 0.0;
-  }
-  if (threadIdx.x == 0) {
-    scal[0] = c;
-    state[0] = 0;
-    state[1] = 0;
-  }
-}
-
-// t = (3 I - p) / 2 and convergence test on max|p - I| (one workgroup).
-__global__ void __launch_bounds__(256) k_ns_tform(const double* __restrict__ p, int n,
-                                                  double* __restrict__ t,
-                                                  int* __restrict__ state) {
-  if (state[0]) return;
+                                                 NsState* __restrict__ st) {
   __shared__ double red[256];
   double m = 0.0;
-  const long long nn = (long long)n * n;
-  for (long long i = threadIdx.x; i < nn; i += 256) {
-    const double id = (i / n == i % n) ? 1.0 : 0.0;
-    const double d = p[i] - id;
-    m = fmax(m, fabs(d));
-    t[i] = id - 0.5 * d;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    double r = 0.0;
+    for (int j = 0; j < n; ++j) r += fabs(s[(long long)i * n + j]);
+    m = fmax(m, r);
   }
   red[threadIdx.x] = m;
   __syncthreads();
@@ -131,32 +113,98 @@ __global__ void __launch_bounds__(256) k_ns_tform(const double* __restrict__ p, 
     if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0 && red[0] < 1e-10) state[1] = 1;
-}
-
-// y <- y2, z <- z2; latch the done flag after a converged step.
-__global__ void __launch_bounds__(256) k_ns_commit(double* __restrict__ y,
-                                                   const double* __restrict__ y2,
-                                                   double* __restrict__ z,
-                                                   const double* __restrict__ z2, long long nn,
-                                                   int* __restrict__ state) {
-  if (state[0]) return;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nn) {
-    y[i] = y2[i];
-    z[i] = z2[i];
+  const double c = red[0];
+  const long long nn = (long long)n * n;
+  for (long long i = threadIdx.x; i < nn; i += 256) {
+    y[i] = s[i] / c;
+    z[i] = (i / n == i % n) ? 1.0 : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    st->c = c;
+    st->done = 0;
+    st->steps = 0;
+    st->err = 0ull;
   }
 }
 
-__global__ void k_ns_latch(int* __restrict__ state) {
-  if (state[1]) state[0] = 1;
+// One n x n x n float64 product C = A B on 32 x 32 tiles (4 wavefronts, one
+// 16 x 16 MFMA block each), skipped once the iteration is done.  EPI: the
+// first product of a step, P = Z Y, is stored as T = (3 I - P) / 2 and
+// max |P - I| goes to st->err.
+template <bool EPI>
+__global__ void __launch_bounds__(256) k_ns_gemm(const double* __restrict__ a,
+                                                 const double* __restrict__ b,
+                                                 double* __restrict__ c, int n,
+                                                 NsState* __restrict__ st) {
+  if (st->done) return;
+  constexpr int T = 32, KB = 16;
+  __shared__ double as[T][KB + 1];
+  __shared__ double bs[KB][T + 1];
+  __shared__ double red[256];
+  const int tiles = (n + T - 1) / T;
+  const int row0 = (blockIdx.x / tiles) * T, col0 = (blockIdx.x % tiles) * T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 16, wc = (wave & 1) * 16;
+  const int lr = lane & 15, lk = lane >> 4;
+  typedef double f64x4 __attribute__((ext_vector_type(4)));
+  f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < n; k0 += KB) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = tid + 256 * u;
+      const int ar = e / KB, ak = e % KB;
+      as[ar][ak] = (row0 + ar < n && k0 + ak < n) ? a[(long long)(row0 + ar) * n + k0 + ak] : 0.0;
+      const int bk = e / T, bc = e % T;
+      bs[bk][bc] = (k0 + bk < n && col0 + bc < n) ? b[(long long)(k0 + bk) * n + col0 + bc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KB; kk += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(as[wr + lr][kk + lk], bs[kk + lk][wc + lr], acc,
+                                                 0, 0, 0);
+    __syncthreads();
+  }
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = row0 + wr + lk + 4 * i, cc = col0 + wc + lr;
+    if (r < n && cc < n) {
+      if constexpr (EPI) {
+        const double d = acc[i] - (r == cc ? 1.0 : 0.0);
+        m = fmax(m, fabs(d));
+        c[(long long)r * n + cc] = (r == cc ? 1.0 : 0.0) - 0.5 * d;
+      } else {
+        c[(long long)r * n + cc] = acc[i];
+      }
+    }
+  }
+  if constexpr (EPI) {
+    red[tid] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+      __syncthreads();
+    }
+    if (tid == 0) atomicMax(&st->err, (unsigned long long)__double_as_longlong(red[0]));
+  }
 }
 
-__global__ void __launch_bounds__(256) k_ns_final(const double* __restrict__ z, long long nn,
-                                                  const double* __restrict__ scal,
+// End of a step: count it; once max |Z Y - I| < 1e-10 the step just applied
+// is the last one.
+__global__ void k_ns_latch(NsState* __restrict__ st) {
+  if (st->done) return;
+  st->steps += 1;
+  if (__longlong_as_double((long long)st->err) < 1e-10) st->done = 1;
+  st->err = 0ull;
+}
+
+__global__ void __launch_bounds__(256) k_ns_final(const double* __restrict__ z0,
+                                                  const double* __restrict__ z1, long long nn,
+                                                  const NsState* __restrict__ st,
                                                   double* __restrict__ out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nn) out[i] = z[i] / sqrt(scal[0]);
+  const double* z = (st->steps & 1) ? z1 : z0;
+  if (i < nn) out[i] = z[i] / sqrt(st->c);
 }
 
 __global__ void __launch_bounds__(256) k_copy_cols(const double* __restrict__ tmp, int n,
@@ -177,32 +225,152 @@ static void gemm_nn(const double* a, int lda, const double* b, long long ldb, do
 }
 
 // s: n x n overlap in, S^(-1/2) out.  work: >= 5 n^2 doubles + 64 bytes.
+// Step k reads (Y, Z)[k % 2] and writes (Y, Z)[(k + 1) % 2]; the final
+// result is Z[steps % 2], read on the device.
 hipError_t launch_inverse_sqrt(double* s, int n, double* work, int max_iter, hipStream_t st) {
   const long long nn = (long long)n * n;
-  double* y = work;
-  double* z = y + nn;
-  double* p = z + nn;
-  double* y2 = p + nn;
-  double* z2 = y2 + nn;
-  int* state = reinterpret_cast<int*>(z2 + nn);
-  double* scal = reinterpret_cast<double*>(state + 4);
-  hipLaunchKernelGGL(k_ns_init, dim3(1), dim3(256), 0, st, s, n, y, z, state, scal);
-  const unsigned eb = (unsigned)((nn + 255) / 256);
+  double* y[2] = {work, work + nn};
+  double* z[2] = {work + 2 * nn, work + 3 * nn};
+  double* t = work + 4 * nn;
+  NsState* state = reinterpret_cast<NsState*>(work + 5 * nn);
+  hipLaunchKernelGGL(k_ns_init, dim3(1), dim3(256), 0, st, s, n, y[0], z[0], state);
+  const int tiles = (n + 31) / 32;
+  const unsigned g = (unsigned)(tiles * tiles);
   for (int it = 0; it < max_iter; ++it) {
-    gemm_nn(z, n, y, n, p, n, n, n, n, 1.0, state, st);                // p = Z Y
-    hipLaunchKernelGGL(k_ns_tform, dim3(1), dim3(256), 0, st, p, n, p, state);  // p <- T
-    gemm_nn(y, n, p, n, y2, n, n, n, n, 1.0, state, st);               // Y T
-    gemm_nn(p, n, z, n, z2, n, n, n, n, 1.0, state, st);               // T Z
-    hipLaunchKernelGGL(k_ns_commit, dim3(eb), dim3(256), 0, st, y, y2, z, z2, nn, state);
+    const int cur = it & 1, nxt = cur ^ 1;
+    hipLaunchKernelGGL(k_ns_gemm<true>, dim3(g), dim3(256), 0, st, z[cur], y[cur], t, n, state);
+    hipLaunchKernelGGL(k_ns_gemm<false>, dim3(g), dim3(256), 0, st, y[cur], t, y[nxt], n, state);
+    hipLaunchKernelGGL(k_ns_gemm<false>, dim3(g), dim3(256), 0, st, t, z[cur], z[nxt], n, state);
     hipLaunchKernelGGL(k_ns_latch, dim3(1), dim3(1), 0, st, state);
   }
-  hipLaunchKernelGGL(k_ns_final, dim3(eb), dim3(256), 0, st, z, nn, scal, s);
+  const unsigned eb = (unsigned)((nn + 255) / 256);
+  hipLaunchKernelGGL(k_ns_final, dim3(eb), dim3(256), 0, st, z[0], z[1], nn, state, s);
   return hipGetLastError();
 }
 
-// psi <- m psi in column chunks through tmp (n x chunk doubles).
+// psi <- m psi in place, one block of CB grid points per workgroup: the
+// block (all n orbitals) is staged in LDS, so the workgroup may overwrite it
+// in HBM; m (n x n, a few hundred KB) is read by every workgroup and stays in
+// L2.  4 wavefronts share the output rows, BM 16-row MFMA blocks each.  The
+// contraction index k is permuted per lane (lane group g = l / 16 takes
+// k = k0 + 4 g + j for MFMA step j) so that each lane reads four consecutive
+// m values per row with one vector load; the block rows are read from LDS in
+// the same order.
+template <int BM, int CB>
+__global__ void __launch_bounds__(256) k_apply_left(const double* __restrict__ m, int n,
+                                                    double* __restrict__ psi, long long nr) {
+  constexpr int BN = CB / 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* blk = reinterpret_cast<double*>(smem_raw);  // [k][CB + 2], k < npad
+  constexpr int LD = CB + 2;                            // 16-byte aligned rows
+  const int npad = (n + 15) / 16 * 16;
+  const long long c0 = (long long)blockIdx.x * CB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, g = lane >> 4;
+  // stage the block (rows beyond n and columns beyond nr as zeros), two
+  // doubles per load: nr is even (n^3, n even) and c0 a multiple of CB
+  constexpr int PR = CB / 2;  // pairs per row
+  constexpr int U = 8;        // loads in flight per thread
+  const int total = npad * PR;
+  for (int e0 = 0; e0 < total; e0 += 256 * U) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + tid + 256 * u;
+      const int k = e / PR, cc = 2 * (e - k * PR);
+      v[u] = double2{0.0, 0.0};
+      if (e < total && k < n && c0 + cc + 1 < nr) {
+        v[u] = *reinterpret_cast<const double2*>(psi + (long long)k * nr + c0 + cc);
+      } else if (e < total && k < n && c0 + cc < nr) {
+        v[u].x = psi[(long long)k * nr + c0 + cc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + tid + 256 * u;
+      const int k = e / PR, cc = 2 * (e - k * PR);
+      if (e < total) *reinterpret_cast<double2*>(blk + k * LD + cc) = v[u];
+    }
+  }
+  typedef double f64x4 __attribute__((ext_vector_type(4)));
+  f64x4 acc[BM][BN];
+#pragma unroll
+  for (int p = 0; p < BM; ++p)
+#pragma unroll
+    for (int q = 0; q < BN; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // m fragments of rows (wave + 4 p) * 16 + lr, k = k0 + 4 g + (0..3)
+  auto load_m = [&](int k0, double (*av)[4]) {
+    const int kb = k0 + 4 * g;
+#pragma unroll
+    for (int p = 0; p < BM; ++p) {
+      const int row = (wave + 4 * p) * 16 + lr;
+      if (row < n && kb + 4 <= n && (n & 1) == 0) {  // 16-byte aligned rows
+        const double2* src = reinterpret_cast<const double2*>(m + (long long)row * n + kb);
+        const double2 x = src[0], y = src[1];
+        av[p][0] = x.x;
+        av[p][1] = x.y;
+        av[p][2] = y.x;
+        av[p][3] = y.y;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          av[p][j] = (row < n && kb + j < n) ? m[(long long)row * n + kb + j] : 0.0;
+      }
+    }
+  };
+  double av[BM][4], an[BM][4];
+  load_m(0, av);
+  __syncthreads();
+  for (int k0 = 0; k0 < npad; k0 += 16) {
+    if (k0 + 16 < npad) load_m(k0 + 16, an);  // next fragments in flight
+    const int kb = k0 + 4 * g;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double bv[BN];
+#pragma unroll
+      for (int q = 0; q < BN; ++q) bv[q] = blk[(kb + j) * LD + 16 * q + lr];
+#pragma unroll
+      for (int p = 0; p < BM; ++p)
+#pragma unroll
+        for (int q = 0; q < BN; ++q)
+          acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p][j], bv[q], acc[p][q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int p = 0; p < BM; ++p)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) av[p][j] = an[p][j];
+  }
+  // result i of lane l: row (l / 16) + 4 i of the block, column l % 16
+#pragma unroll
+  for (int p = 0; p < BM; ++p)
+#pragma unroll
+    for (int q = 0; q < BN; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = (wave + 4 * p) * 16 + g + 4 * i;
+        const long long col = c0 + 16 * q + lr;
+        if (row < n && col < nr) psi[(long long)row * nr + col] = acc[p][q][i];
+      }
+}
+
+// psi <- m psi (n x n times n x nr).  n <= 512: in place (k_apply_left);
+// larger n: column chunks through tmp (n x 32768 doubles) and a copy back.
 void launch_apply_left(const double* m, double* psi, int n, long long nr, double* tmp,
                        hipStream_t st) {
+  if (n <= 256) {
+    constexpr int CB = 32;
+    const size_t lds = (size_t)((n + 15) / 16 * 16) * (CB + 2) * 8;
+    hipLaunchKernelGGL((k_apply_left<4, CB>), dim3((unsigned)((nr + CB - 1) / CB)), dim3(256),
+                       lds, st, m, n, psi, nr);
+    return;
+  }
+  if (n <= 512) {
+    constexpr int CB = 16;
+    const size_t lds = (size_t)((n + 15) / 16 * 16) * (CB + 2) * 8;
+    hipLaunchKernelGGL((k_apply_left<8, CB>), dim3((unsigned)((nr + CB - 1) / CB)), dim3(256),
+                       lds, st, m, n, psi, nr);
+    return;
+  }
   const long long cc = 32768;
   for (long long c0 = 0; c0 < nr; c0 += cc) {
     const long long w = c0 + cc <= nr ? cc : nr - c0;
@@ -211,6 +379,16 @@ void launch_apply_left(const double* m, double* psi, int n, long long nr, double
     hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, tmp,
                        n, w, psi, nr, c0);
   }
+}
+
+// Raise the dynamic-LDS limit of the in-place kernels (once per process).
+hipError_t prepare_apply_left() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_left<4, 32>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     256 * 34 * 8);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_left<8, 16>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 512 * 18 * 8);
 }
 
 }  // namespace hfx
