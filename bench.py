@@ -34,20 +34,37 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# sources of the pair-pipeline kernels: a recorded traffic figure applies only
+# to the kernels built from exactly these files
+TRAFFIC_SOURCES = ("fft.hpp", "exchange_kernels.hpp", "exchange_f32.hip", "exchange_f64.hip")
+
+
+def kernel_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2309_00651_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def traffic_from_profiles(kernel_pass, workload):
-    """HBM bytes per launch measured by rocprofv3 counters, if recorded."""
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/), or None
+    when none are recorded or the kernels' sources changed since."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_pass}_{workload}.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             rec = json.load(f)
+        if rec.get("sources_sha1") != kernel_sources_sha1():
+            return None
         return rec.get("bytes_per_launch")
     except Exception:
         return None
 
 
-def cpu_baseline(system, psi, seconds_target=15.0):
+def cpu_baseline(system, psi, seconds_target=10.0):
     """Time the float64 oracle on a subset of orbitals of the same workload."""
     import numpy as np
 
@@ -69,6 +86,78 @@ def cpu_baseline(system, psi, seconds_target=15.0):
             "kind": "oracle",
             "sample": f"{k} of {system.n_orb} orbitals ({pairs} pairs) of the {system.name} "
                       f"workload, float64, scipy FFT, {cores} worker processes, {dt:.1f} s"}
+
+
+def bench_batched6(args):
+    """Six systems of different grids in one plan: K psi + E_x for all of them,
+    (a) replayed from a captured hipGraph, (b) launched eagerly from the same
+    plan (systems on forked streams), (c) six single-system plans in turn."""
+    import numpy as np
+    import torch
+
+    from paper_2309_00651_amd import hfx
+    from workloads import configs
+
+    systems = configs.BATCHED6
+    dev = torch.device("cuda:0")
+    specs = [hfx.SystemSpec(s.n, s.box, s.n_orb, s.kernel, s.param) for s in systems]
+    n_pairs = sum(s.n_pairs for s in systems)
+    log(f"generating batched6: {len(systems)} systems, {n_pairs} pairs")
+    parts = []
+    for s in systems:
+        parts.append(torch.from_numpy(s.orbitals().reshape(-1)).to(dev))
+    psi = torch.cat(parts)
+    del parts
+    plan = hfx.Plan(specs, hfx.FP32, options=args.options, device=dev)
+    kpsi = torch.empty(psi.shape, dtype=torch.float32, device=dev)
+    ex = torch.empty(len(systems), dtype=torch.float64, device=dev)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    log("batched6: graph replay")
+    g = plan.graph(hfx.GRAPH_APPLY, psi, kpsi, ex)
+    ms_graph = timed(g.launch, args.steps, args.warmup)
+    ex_graph = ex.clone()
+    log("batched6: eager multi-system plan")
+    ms_eager = timed(lambda: plan.apply_exchange(psi, kpsi=kpsi, ex=ex), args.steps, args.warmup)
+    assert torch.equal(ex, ex_graph), "graph replay and eager launch disagree"
+    g.close()
+    del plan
+    log("batched6: six single-system plans in turn")
+    singles = [hfx.Plan(sp, hfx.FP32, device=dev) for sp in specs]
+    views, off = [], 0
+    for s in systems:
+        k = s.n_orb * s.n ** 3
+        views.append((psi[off:off + k], kpsi[off:off + k]))
+        off += k
+
+    def seq():
+        for pl, (pv, kv) in zip(singles, views):
+            pl.apply_exchange(pv, kpsi=kv)
+    ms_seq = timed(seq, args.steps, args.warmup)
+    line = {
+        "metric": "pair-exchange evals/s, six systems of different grids in one batch",
+        "value": n_pairs / (ms_graph * 1e-3), "unit": "pair-exchange evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched6: grids 64^3..120^3 at spacing 23.5/96 bohr, 64..384 "
+                               "random plane-wave orbitals (5 Ha), truncated Coulomb; step = "
+                               "K psi + E_x for all six systems",
+                   "pairs": n_pairs, "plan_options": args.options},
+        "extra": {"ms_graph_replay": ms_graph, "ms_eager_one_plan": ms_eager,
+                  "ms_six_single_plans": ms_seq,
+                  "ex": [float(x) for x in ex_graph.cpu()]},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -103,6 +192,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 4 * n, "copies": 5}), flush=True)
+        return
+
+    if args.workload == "batched6":
+        bench_batched6(args)
         return
 
     from paper_2309_00651_amd import hfx
@@ -162,7 +255,8 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / MFMA_FP32_PEAK_TFLOPS, "traffic": None}
     else:
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        tr = traffic_from_profiles(dname, system.name)
+        # counters were taken with the default plan options
+        tr = traffic_from_profiles(dname, system.name) if not args.options else None
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": tr}
     roof["kernel"] = dname

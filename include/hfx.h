@@ -82,7 +82,11 @@ typedef struct hfx_plan_t* hfx_plan;
  * Supported grids: n in {24, 64, 72, 80, 96, 108, 120, 128}.  `options` is a
  * nullable "key=value;key=value" string: tiles=<k> caps the orbital tiles per
  * batch; maxws=<bytes> caps the workspace; variant=<name> picks a compiled
- * kernel configuration (see hfx_variants).  The environment variable
+ * kernel configuration (see hfx_variants); streams=2 runs consecutive batches
+ * alternately on the call's stream and on a stream the plan owns, with a second
+ * pair-grid buffer in the workspace (results are bitwise those of streams=1,
+ * the default; graphs captured from such a plan run the batches on one
+ * stream).  The environment variable
  * HFX_MAX_WORKSPACE_BYTES also caps the workspace.  Uploads the plan's tables
  * (synchronous).  Errors: HFX_EINVAL for null out/sys, n_sys < 1, n <= 0,
  * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0;

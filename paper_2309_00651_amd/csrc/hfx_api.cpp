@@ -71,6 +71,12 @@ struct SystemPlan {
   size_t off_mean = 0;  // float32 plans: pair-density means (n_orb x n_orb float64)
   double v0 = 0.0;      // v(G = 0)
   size_t ws_end = 0;
+  // batch streams: 2 = consecutive batches alternate between the call's
+  // stream and an owned stream, each with its own pair-grid buffer
+  int nstreams = 1;
+  size_t grid_bytes = 0;  // one pair-grid buffer
+  hipStream_t bstream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_acc[2] = {nullptr, nullptr};
   // offsets inside concatenated user buffers
   long long psi_off = 0, m_off = 0;
 };
@@ -323,10 +329,15 @@ void free_system(SystemPlan& sp) {
     if (p) (void)hipFree(p);
   if (sp.d_tiles) (void)hipFree(sp.d_tiles);
   if (sp.d_active) (void)hipFree(sp.d_active);
+  if (sp.bstream) (void)hipStreamDestroy(sp.bstream);
+  for (hipEvent_t e : {sp.ev_fork, sp.ev_join, sp.ev_acc[0], sp.ev_acc[1]})
+    if (e) (void)hipEventDestroy(e);
   sp.vtab = nullptr;
   for (auto& p : sp.tw) p = nullptr;
   sp.d_tiles = nullptr;
   sp.d_active = nullptr;
+  sp.bstream = nullptr;
+  sp.ev_fork = sp.ev_join = sp.ev_acc[0] = sp.ev_acc[1] = nullptr;
 }
 
 // Event bracket around one launch when profiling is on.
@@ -408,7 +419,6 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   PassArgs a{};
   a.psi = psi_w;
   a.kpsi = kpsi;
-  a.grids = ws + sp.off_grids;
   a.vtab = sp.vtab;
   a.tw_zf = sp.tw[0];
   a.tw_zi = sp.tw[1];
@@ -426,7 +436,24 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   const double nr = (double)sp.nr, ce = 2.0 * elem;  // complex element bytes
   // FFT flops per complex grid and axis pass: 5 N_r log2(N) (radix-2 count)
   const double fft_axis = 5.0 * nr * std::log2((double)n);
-  for (const Batch& b : sp.batches) {
+  // Two batch streams: batch k runs on stream k % 2 with grid buffer k % 2.
+  // Its inv_acc waits for batch k-1's, so K psi receives its updates in the
+  // serial order (identical results) while the transforms of one batch
+  // overlap the other batch's passes.  Consecutive batches of one tile round
+  // touch disjoint orbitals anyway; across rounds the wait is needed.
+  // Graph capture keeps the batches on the one stream (the two-stream form
+  // is not captured): a captured graph equals that of a streams=1 plan.
+  const bool two = sp.nstreams == 2 && sp.batches.size() > 1 && !plan->capturing;
+  if (two) {
+    HIP_TRY(hipEventRecord(sp.ev_fork, st));
+    HIP_TRY(hipStreamWaitEvent(sp.bstream, sp.ev_fork, 0));
+  }
+  char* grids0 = ws + sp.off_grids;
+  for (size_t k = 0; k < sp.batches.size(); ++k) {
+    const Batch& b = sp.batches[k];
+    const int q = two ? (int)(k & 1) : 0;
+    const hipStream_t bs = q ? sp.bstream : st;
+    a.grids = grids0 + (size_t)q * sp.grid_bytes;
     a.tiles = sp.d_tiles + b.tile_off;
     a.active = sp.d_active + b.active_off;
     a.n_tiles = b.n_tiles;
@@ -439,41 +466,47 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
     }
     const double grids = (double)b.n_active;
     {
-      Bracket bk(plan, HFX_PASS_PAIR_FWD, st);
-      v->pair_fwd(a, b.n_tiles * br, st);
+      Bracket bk(plan, HFX_PASS_PAIR_FWD, bs);
+      v->pair_fwd(a, b.n_tiles * br, bs);
       bk.done(orbs * nr * elem + grids * nr * ce, grids * fft_axis);
     }
     if (v->plane_mode == 0) {
-      Bracket bk(plan, HFX_PASS_PLANE, st);
-      v->plane(a, b.n_active * n, st);
+      Bracket bk(plan, HFX_PASS_PLANE, bs);
+      v->plane(a, b.n_active * n, bs);
       bk.done(grids * nr * ce * 2.0, grids * fft_axis * 4.0);
     } else {
       const int rb = (n * n + v->rows_per_wg - 1) / v->rows_per_wg;
       {
-        Bracket bk(plan, HFX_PASS_ROWS_FWD, st);
-        v->rows_fwd(a, b.n_active * rb, st);
+        Bracket bk(plan, HFX_PASS_ROWS_FWD, bs);
+        v->rows_fwd(a, b.n_active * rb, bs);
         bk.done(grids * nr * ce * 2.0, grids * fft_axis);
       }
       {
-        Bracket bk(plan, HFX_PASS_COLS_CONV, st);
-        v->cols_conv(a, b.n_active * n * nxb, st);
+        Bracket bk(plan, HFX_PASS_COLS_CONV, bs);
+        v->cols_conv(a, b.n_active * n * nxb, bs);
         bk.done(grids * nr * ce * 2.0, grids * fft_axis * 2.0);
       }
       {
-        Bracket bk(plan, HFX_PASS_ROWS_INV, st);
-        v->rows_inv(a, b.n_active * rb, st);
+        Bracket bk(plan, HFX_PASS_ROWS_INV, bs);
+        v->rows_inv(a, b.n_active * rb, bs);
         bk.done(grids * nr * ce * 2.0, grids * fft_axis);
       }
     }
+    if (two && k > 0) HIP_TRY(hipStreamWaitEvent(bs, sp.ev_acc[q ^ 1], 0));
     if (acc) {
-      Bracket bk(plan, HFX_PASS_INV_ACC, st);
-      v->inv_acc(a, b.n_tiles * br, st);
+      Bracket bk(plan, HFX_PASS_INV_ACC, bs);
+      v->inv_acc(a, b.n_tiles * br, bs);
       bk.done(grids * nr * ce + orbs * nr * elem * 3.0, grids * fft_axis);
     } else {
-      Bracket bk(plan, HFX_PASS_INV_ENERGY, st);
-      v->inv_energy(a, b.n_tiles * br, st);
+      Bracket bk(plan, HFX_PASS_INV_ENERGY, bs);
+      v->inv_energy(a, b.n_tiles * br, bs);
       bk.done(grids * nr * ce + orbs * nr * elem, grids * fft_axis);
     }
+    if (two) HIP_TRY(hipEventRecord(sp.ev_acc[q], bs));
+  }
+  if (two) {
+    HIP_TRY(hipEventRecord(sp.ev_join, sp.bstream));
+    HIP_TRY(hipStreamWaitEvent(st, sp.ev_join, 0));
   }
   if (ex) {
     Bracket bk(plan, HFX_PASS_ENERGY_REDUCE, st);
@@ -628,6 +661,9 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   if (!vname.empty() && !find_variant(sys[0].n[0], precision, vname))
     return fail(HFX_EINVAL, "unknown variant '" + vname + "' for this grid and precision");
   long long ws_cap = parse_option(options, "maxws", 0);
+  const long long batch_streams = parse_option(options, "streams", 1);
+  if (batch_streams != 1 && batch_streams != 2)
+    return fail(HFX_EINVAL, "streams= must be 1 or 2");
   if (const char* env = std::getenv("HFX_MAX_WORKSPACE_BYTES")) {
     const long long e = std::atoll(env);
     if (e > 0) ws_cap = ws_cap > 0 ? std::min(ws_cap, e) : e;
@@ -654,8 +690,10 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     // workspace layout of this system
     sp.off_psi32 = off;
     if (precision == HFX_FP32) off = align_up(off + (size_t)sys[i].n_orb * sp.nr * 4);
+    sp.nstreams = (sp.batches.size() > 1 && batch_streams == 2) ? 2 : 1;
     sp.off_grids = off;
-    off = align_up(off + (size_t)sp.slots_per_batch * sp.nr * 2 * elem);
+    sp.grid_bytes = align_up((size_t)sp.slots_per_batch * sp.nr * 2 * elem);
+    off = align_up(off + sp.grid_bytes * sp.nstreams);
     sp.off_partials = off;
     off = align_up(off + (size_t)sp.n_partials * 8);
     sp.off_gemm = off;
@@ -716,6 +754,14 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     s = upload(sp.active, &d);
     if (s != HFX_OK) return cleanup(s);
     sp.d_active = static_cast<int*>(d);
+    if (sp.nstreams == 2) {
+      if (hipStreamCreateWithFlags(&sp.bstream, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&sp.ev_fork, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&sp.ev_join, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&sp.ev_acc[0], hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&sp.ev_acc[1], hipEventDisableTiming) != hipSuccess)
+        return cleanup(fail(HFX_EDEVICE, "stream/event creation failed"));
+    }
   }
   if (p->sys.size() > 1) {
     if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess)

@@ -60,12 +60,16 @@ def test_batched_plan_equals_single_plans(prec):
         assert abs(float(ex[i]) - ref["ex"]) <= tol * abs(ref["ex"])
 
 
-def test_graph_replays_match_eager():
+# streams=2 with one tile per batch: eager calls alternate the batches over two
+# streams, the captured graph keeps them on one; both must agree bit for bit
+@pytest.mark.parametrize("options", [None, "tiles=1;streams=2"], ids=["default", "two_streams"])
+def test_graph_replays_match_eager(options):
     dev = _dev()
     psis = _inputs()
     specs = [hfx.SystemSpec(n, (L, L, L), no, k, w) for n, L, no, k, w in SYSTEMS]
     flat = torch.from_numpy(np.concatenate([p.reshape(-1) for p in psis])).to(dev)
-    plan = hfx.Plan(specs, hfx.FP32, device=dev)
+    print(f"case graph replay options={options}", flush=True)
+    plan = hfx.Plan(specs, hfx.FP32, options=options, device=dev)
     # eager references
     k_ref, e_ref = plan.apply_exchange(flat)
     k_ref, e_ref = k_ref.clone(), e_ref.clone()

@@ -130,6 +130,32 @@ def test_bitwise_repeatable():
     assert torch.equal(k1, k2) and torch.equal(e1, e2)
 
 
+@pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
+def test_two_batch_streams_bitwise(prec):
+    """streams=2 (batches alternating over two streams, each with its own
+    pair-grid buffer) gives the single-stream results bit for bit: one tile
+    per batch, so consecutive batches also cross tile rounds."""
+    psi = make_inputs(24, 10.0, 37, "pw", seed=8)
+    dev = _dev()
+    spec = hfx.SystemSpec(24, (10.0,) * 3, 37)
+    pt = torch.from_numpy(psi).to(dev)
+    out = []
+    for opts in ("tiles=1", "tiles=1;streams=2"):
+        print(f"case streams {opts} prec={prec}", flush=True)
+        plan = hfx.Plan(spec, prec, options=opts, device=dev)
+        k, e = plan.apply_exchange(pt)
+        m = plan.exchange_matrix(pt, k)
+        e_only = plan.exchange_energy(pt)
+        torch.cuda.synchronize()
+        out.append((k.clone(), e.clone(), m.clone(), e_only.clone()))
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+    ref = oracle.exchange(psi, (10.0,) * 3, oracle.coulomb_kernel((24,) * 3, (10.0,) * 3,
+                                                                    hfx.TRUNCATED, 0.0))
+    tol = 1e-7 if prec == hfx.FP32 else 1e-12
+    assert abs(float(out[1][1][0]) - ref["ex"]) <= tol * abs(ref["ex"])
+
+
 def test_tiny_workload_orthonormalised():
     """Workload 1 end to end: raw orbitals -> Loewdin on each side -> exchange."""
     from workloads import configs
@@ -154,22 +180,26 @@ def test_tiny_workload_orthonormalised():
         check(ref, got, prec, s.L, psi_o)
 
 
-def test_orthonormalize_matches_oracle_lowdin():
-    psi = make_inputs(24, 10.0, 13, "pw", seed=3)
+# 13: in-place apply with 32-point blocks; 300: in-place with 16-point blocks
+# (257..512 orbitals); 520: chunked product through the workspace (> 512)
+@pytest.mark.parametrize("n_orb", [13, 300, 520])
+def test_orthonormalize_matches_oracle_lowdin(n_orb):
+    psi = make_inputs(24, 10.0, n_orb, "pw", seed=3)
     rng = np.random.default_rng(4)
     psi = psi + 0.3 * rng.standard_normal(psi.shape) * 0.05
     dv = 1000.0 / 24 ** 3
     ref, lam = oracle.lowdin(psi, dv)
     assert lam > 1e-3
     dev = _dev()
-    plan = hfx.Plan(hfx.SystemSpec(24, (10.0,) * 3, 13), hfx.FP64, device=dev)
+    print(f"case lowdin n_orb={n_orb}", flush=True)
+    plan = hfx.Plan(hfx.SystemSpec(24, (10.0,) * 3, n_orb), hfx.FP64, device=dev)
     pt = torch.from_numpy(psi).to(dev)
     plan.orthonormalize(pt)
     torch.cuda.synchronize()
     got = pt.cpu().numpy()
     assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
     s = oracle.overlap(got, dv)
-    assert np.max(np.abs(s - np.eye(13))) <= 1e-12
+    assert np.max(np.abs(s - np.eye(n_orb))) <= 1e-12
 
 
 @pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
