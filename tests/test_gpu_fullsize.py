@@ -59,3 +59,47 @@ def test_fullsize_against_oracle(name, prec):
         assert rel <= 1e-12
         assert dd <= 1e-11
         assert dk <= 1e-10 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
+def test_grad72_directional_derivatives(prec):
+    """The autograd workload: 72^3, 128 raw (not orthonormalised) orbitals, 16
+    seeded directions D with dV sum D^2 = 1.  E_x is a quartic in the step, so
+    the 5-point stencil with h = 1e-4 is exact apart from rounding; it is taken
+    from the float64 plan's energies and compared with sum(grad * D) from
+    hfx_exchange_gradient of the plan under test.  A random direction is
+    nearly orthogonal to the gradient (dE/de ~ 1e-3 against |grad| ~ 20), so
+    the difference is measured against the Cauchy-Schwarz scale |grad| |D|
+    (float64: 1e-9; float32: 1e-7).  The Euler identity sum(grad * psi) = 4 E_x
+    (E_x is homogeneous of degree 4) checks the O(1) direction."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = configs.GRAD72
+    dev = torch.device("cuda:0")
+    spec = hfx.SystemSpec(s.n, s.box, s.n_orb, s.kernel, s.param)
+    print(f"case grad72 directional derivatives prec={prec}", flush=True)
+    psi = torch.from_numpy(s.orbitals()).to(dev)
+    dv = s.box[0] * s.box[1] * s.box[2] / s.n ** 3
+    e64 = hfx.Plan(spec, hfx.FP64, device=dev)
+    plan = e64 if prec == hfx.FP64 else hfx.Plan(spec, prec, device=dev)
+    grad = plan.exchange_gradient(psi)
+    ex = float(e64.exchange_energy(psi)[0])
+    # |grad| in the norm dual to dV sum D^2: sqrt(sum grad^2 / dV)
+    gnorm = float(torch.sqrt(torch.sum(grad * grad) / dv))
+    euler = float(torch.sum(grad * psi))
+    print(f"  |grad| {gnorm:.3e}  Euler rel {abs(euler - 4 * ex) / abs(4 * ex):.2e}", flush=True)
+    assert abs(euler - 4.0 * ex) <= (1e-11 if prec == hfx.FP64 else 1e-7) * abs(4.0 * ex)
+    gen = torch.Generator(device="cpu").manual_seed(s.seed + 16)
+    h = 1e-4
+    worst = 0.0
+    for k in range(16):
+        d = torch.randn(psi.shape, generator=gen, dtype=torch.float64).to(dev)
+        d /= torch.sqrt(dv * torch.sum(d * d))
+        e = {}
+        for m in (-2, -1, 1, 2):
+            e[m] = float(e64.exchange_energy((psi + (m * h) * d).contiguous())[0])
+        fd = (e[-2] - 8.0 * e[-1] + 8.0 * e[1] - e[2]) / (12.0 * h)
+        an = float(torch.sum(grad * d))
+        worst = max(worst, abs(fd - an) / gnorm)
+    print(f"  worst |FD - analytic| / (|grad||D|) over 16 directions {worst:.2e}", flush=True)
+    assert worst <= (1e-9 if prec == hfx.FP64 else 1e-7)
