@@ -12,6 +12,8 @@ What it computes (Methods, "MTACE Method for H-AIMD Simulation"):
              the pair density rho_ij = psi_i psi_j (a Poisson solve)
 * Eq. (HFX): the exchange energy (prefactor reading below)
 * ACE matrix M_kl = <psi_k | V_X | psi_l>  (same subsection, definition of M)
+* ACE operator, Eq. (vx_ace): V_X^ACE = - sum_k |P_k><P_k| with P = W L^(-T),
+  W_i = V_X psi_i and -M = L L^T (Cholesky)
 
 The FFT evaluates the periodic discrete convolution exactly up to rounding,
 so the oracle is the plain definition written out, one pair at a time, in
@@ -50,6 +52,7 @@ __all__ = [
     "TRUNCATED", "ERFC", "volume", "grid_g2", "coulomb_kernel",
     "pair_potential", "pair_energy", "exchange", "apply_exchange_rows",
     "exchange_matrix", "overlap", "lowdin", "cholesky_orthonormalize",
+    "ace_projectors", "ace_apply",
 ]
 
 TRUNCATED = 0
@@ -234,3 +237,23 @@ def cholesky_orthonormalize(psi, dv):
     a = psi.reshape(psi.shape[0], -1)
     out = np.linalg.solve(low, a)
     return out.reshape(psi.shape)
+
+
+def ace_projectors(kpsi, m):
+    """P = W L^(-T) of Eq. (vx_ace): W_i = V_X psi_i (rows of ``kpsi``), L the
+    lower Cholesky factor of -M.  Returned as rows, P[k] = |P_k>, i.e. the
+    rows of L^(-1) W (column k of W L^(-T) is sum_i W_i (L^(-1))_ki).
+    Raises if -M is not positive definite."""
+    low = np.linalg.cholesky(-np.asarray(m, dtype=np.float64))
+    w = kpsi.reshape(kpsi.shape[0], -1).astype(np.float64)
+    return np.linalg.solve(low, w).reshape(kpsi.shape)
+
+
+def ace_apply(p, phi, dv):
+    """V_X^ACE phi_j = - sum_k P_k <P_k | phi_j> for every row of ``phi``
+    (Eq. (vx_ace), inner product of reading 5)."""
+    a = p.reshape(p.shape[0], -1)
+    b = phi.reshape(phi.shape[0], -1)
+    c = dv * (a @ b.T)          # <P_k | phi_j>
+    return (-(c.T @ a)).reshape(phi.shape)
+

@@ -335,3 +335,71 @@ def test_lowdin_and_cholesky(small_system):
     # Cholesky orthonormalisation is classical Gram-Schmidt in orbital order.
     cho = oracle.cholesky_orthonormalize(raw, dv)
     assert np.max(np.abs(cho - gram_schmidt(raw, dv))) <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# ACE operator (Eq. (vx_ace)): V_X^ACE = -sum_k |P_k><P_k|, P = W L^(-T)
+
+def _ace_setup(small_system):
+    psi, box, vg = small_system
+    res = oracle.exchange(psi, box, vg)
+    m = oracle.exchange_matrix(psi, res["kpsi"], res["dv"])
+    return psi, res, m, oracle.ace_projectors(res["kpsi"], m)
+
+
+def test_ace_reproduces_exchange_on_the_orbitals(small_system):
+    """<P_k|psi_j> = (L^-1 M)_kj = -L^T, so V^ACE psi_j = (L P)_j = W_j exactly
+    (the orbitals need not be orthonormal: small_system's are raw)."""
+    psi, res, m, p = _ace_setup(small_system)
+    out = oracle.ace_apply(p, psi, res["dv"])
+    assert np.max(np.abs(out - res["kpsi"])) <= 1e-12 * np.max(np.abs(res["kpsi"]))
+    # <P_k | psi_j> = -L^T (upper triangular) for the Cholesky factor of -M
+    low = np.linalg.cholesky(-m)
+    c = res["dv"] * (p.reshape(len(p), -1) @ psi.reshape(len(psi), -1).T)
+    assert np.max(np.abs(c + low.T)) <= 1e-12 * np.max(np.abs(low))
+
+
+def test_ace_equals_w_minv_w(small_system):
+    """Another route to the same operator: V^ACE phi = W M^-1 <W|phi> (linear
+    solve with M instead of the Cholesky factor), for random phi."""
+    psi, res, m, p = _ace_setup(small_system)
+    rng = np.random.default_rng(5)
+    phi = rng.standard_normal((3,) + psi.shape[1:])
+    w = res["kpsi"].reshape(len(psi), -1)
+    c = res["dv"] * (w @ phi.reshape(3, -1).T)            # <W_i | phi_j>
+    want = (np.linalg.solve(m, c).T @ w).reshape(phi.shape)
+    got = oracle.ace_apply(p, phi, res["dv"])
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+def test_ace_is_negative_semidefinite_and_vanishes_off_span(small_system):
+    psi, res, m, p = _ace_setup(small_system)
+    dv = res["dv"]
+    rng = np.random.default_rng(6)
+    phi = rng.standard_normal((4,) + psi.shape[1:])
+    out = oracle.ace_apply(p, phi, dv)
+    quad = dv * np.sum(phi.reshape(4, -1) * out.reshape(4, -1), axis=1)
+    assert np.all(quad <= 0)
+    # remove the span of W from phi: the operator then gives zero
+    w = res["kpsi"].reshape(len(psi), -1)
+    q, _ = np.linalg.qr(w.T)
+    f = phi.reshape(4, -1)
+    f = f - (f @ q) @ q.T
+    z = oracle.ace_apply(p, f.reshape(phi.shape), dv)
+    assert np.max(np.abs(z)) <= 1e-12 * np.max(np.abs(out))
+
+
+def test_ace_pins_catch_planted_mistakes(small_system):
+    """The reproduction identity fails for plausible slips in building P:
+    solving with L^T instead of L, multiplying by L instead of solving, and
+    a dropped sign in the application."""
+    psi, res, m, p = _ace_setup(small_system)
+    w = res["kpsi"].reshape(len(psi), -1)
+    low = np.linalg.cholesky(-m)
+    ref = res["kpsi"]
+    scale = np.max(np.abs(ref))
+    for bad in (np.linalg.solve(low.T, w), low @ w):
+        out = oracle.ace_apply(bad.reshape(psi.shape), psi, res["dv"])
+        assert np.max(np.abs(out - ref)) > 1e-6 * scale
+    out = -oracle.ace_apply(p, psi, res["dv"])
+    assert np.max(np.abs(out - ref)) > 1e-6 * scale
