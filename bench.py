@@ -239,8 +239,50 @@ def main():
         prof = plan.profile_read() if profile else None
         plan.profile(False)
         out = dict(ms=ev_ms / steps, wall_ms=1e3 * wall / steps, prof=prof, ex=float(ex[0]),
-                   m=m, kpsi=kpsi)
+                   m=m, kpsi=kpsi, psi=p)
         return out, plan
+
+    def time_ace(plan, r, reps=3):
+        """ACE (Eq. (vx_ace)) from the step's K psi and M: projector build and
+        one application to all orbitals, each timed with HIP events; E_x from
+        1/2 sum <psi|V^ACE psi> as a check."""
+        p = plan.ace_build(r["kpsi"], r["m"])
+        o = plan.ace_apply(p, r["psi"])
+        torch.cuda.synchronize()
+
+        def ev(fn):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            b.synchronize()
+            return a.elapsed_time(b) / reps
+        t_build = ev(lambda: plan.ace_build(r["kpsi"], r["m"], p=p))
+        t_apply = ev(lambda: plan.ace_apply(p, r["psi"], out=o))
+        dv = system.L ** 3 / system.n ** 3
+        ex_ace = 0.5 * dv * float(torch.sum(r["psi"] * o))
+        del p, o
+        return t_build, t_apply, ex_ace
+
+    # achievable HBM rate on this device: device-to-device copy of 1 GiB
+    # (1 GiB read + 1 GiB written), median of 5, timed with HIP events
+    def copy_rate():
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        times = []
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            dst.copy_(src)
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        del src, dst
+        return 2.0 * (1 << 30) / (sorted(times)[2] * 1e-3) / 1e9
+    copy_gbps = copy_rate()
+    log(f"device copy: {copy_gbps:.0f} GB/s")
 
     log(f"fp32: {args.warmup} warm-up + {args.steps} timed steps")
     r32, plan32 = run(hfx.FP32, args.steps, args.warmup, True)
@@ -273,7 +315,17 @@ def main():
     exch_frac = hbm_pair_bytes / args.steps / (pair_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
     log(f"fp32 {ms:.2f} ms/step, dominant pass {dname} {achieved:.1f}")
 
+    ace_build_ms, ace_apply_ms, ex_ace = time_ace(plan32, r32)
+    log(f"ace: build {ace_build_ms:.2f} ms, apply {ace_apply_ms:.2f} ms")
+    del r32["kpsi"], r32["m"], r32["psi"]
+
     extra = {"kpsi_ms_per_step_fp32": pair_ms, "pair_pipeline_hbm_frac": exch_frac,
+             "ace_build_ms": ace_build_ms, "ace_apply_ms": ace_apply_ms,
+             "ace_apply_fp64_tflops": 4.0 * system.n_orb ** 2 * system.n ** 3 / (ace_apply_ms * 1e-3) / 1e12,
+             "rel_dEx_ace_vs_exact": abs(ex_ace - r32["ex"]) / abs(r32["ex"]),
+             "device_copy_GBps": copy_gbps,
+             "pair_pipeline_frac_of_device_copy": exch_frac * HBM_PEAK_GBS / copy_gbps,
+             "dominant_frac_of_device_copy": (achieved / copy_gbps) if roof["bound"] == "hbm" else None,
              "passes": passes, "ex_fp32": r32["ex"]}
     if not args.no_fp64:
         log(f"fp64: 1 warm-up + {args.fp64_steps} timed steps")

@@ -148,6 +148,30 @@ hfx_status hfx_orthonormalize(hfx_plan plan, double* psi, int method, void* ws,
                               size_t ws_bytes, void* stream);
 
 /*
+ * Adaptively compressed exchange (Methods, MTACE subsection, Eq. (vx_ace)):
+ * V_X^ACE = - sum_k |P_k><P_k| with P = W L^(-T), W_i = V_X psi_i and
+ * -M = L L^T the Cholesky factorisation of the exchange matrix.
+ *
+ * hfx_ace_build: from kpsi (W, as written by hfx_apply_exchange: float32 in
+ * float32 plans, float64 in float64 plans) and m (M from hfx_exchange_matrix,
+ * float64, per system n_orb x n_orb row-major, systems concatenated) writes
+ * p (float64, the layout of psi): row k of each system is |P_k>, i.e. the
+ * rows of L^(-1) W.  Factorisation and triangular inverse in float64.  A
+ * matrix -M that is not positive definite (dependent orbitals) gives NaN in p.
+ *
+ * hfx_ace_apply: out = V_X^ACE phi, row by row (phi, out: float64, the layout
+ * of psi; phi may be any set of n_orb functions per system, e.g. the current
+ * orbitals of an SCF iteration).  out must not alias p or phi.
+ *
+ * Both are asynchronous on `stream`, use the workspace like the calls above,
+ * and return HFX_EINVAL for null pointers, HFX_ENOMEM for a short workspace.
+ */
+hfx_status hfx_ace_build(hfx_plan plan, const void* kpsi, const double* m, double* p, void* ws,
+                         size_t ws_bytes, void* stream);
+hfx_status hfx_ace_apply(hfx_plan plan, const double* p, const double* phi, double* out,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Per-pass timing (tracing aid).  While enabled, every kernel launch of the
  * plan is bracketed by a pair of HIP events recorded on the caller's stream,
  * and the pass's algorithmic HBM bytes (each operand read or written once;
@@ -170,6 +194,8 @@ typedef enum {
   HFX_PASS_CONTRACT,       /* Psi^T (K Psi) or Psi^T Psi on MFMA + reduction */
   HFX_PASS_ORTHO,          /* Newton-Schulz S^(-1/2) and Psi <- S^(-1/2) Psi */
   HFX_PASS_SCALE,          /* gradient scaling                               */
+  HFX_PASS_ACE_BUILD,      /* Cholesky of -M, L^(-1), P = L^(-1) W           */
+  HFX_PASS_ACE_APPLY,      /* -P (P^T phi): contraction and apply            */
   HFX_PASS_COUNT
 } hfx_pass;
 

@@ -490,8 +490,20 @@ __global__ void __launch_bounds__(NT)
 
 // ---------------------------------------------------------------------------
 // Pass 2: fused plane convolution for one kz plane of one pair grid.
+// Waves per SIMD that the plane's LDS allows (planes per compute unit x
+// wavefronts per plane / 4 SIMDs): register use is capped so that registers
+// never admit fewer planes than LDS does.
+template <typename T, int N, int NT>
+constexpr int plane_waves_per_eu() {
+  constexpr int lds = N * (N + 1) * (int)sizeof(cpx<T>) + 4096;  // plane + twiddle tables
+  constexpr int planes = (160 * 1024) / lds > 0 ? (160 * 1024) / lds : 1;
+  constexpr int w = (planes * ((NT + 63) / 64) + 3) / 4;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, bool SW = false>
-__global__ void __launch_bounds__(NT) k_plane_conv(PassArgs a) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<T, N, NT>())))
+k_plane_conv(PassArgs a) {
   static_assert(!SW || N % 8 == 0, "swizzle needs whole blocks of 8");
   constexpr int P = N + 1;
   using GX = Geom<T, N, N, NT, false, 1, P, SW ? 1 : 0>;  // rows: sequence m = y, element n = x

@@ -567,6 +567,46 @@ hfx_status enq_matrix(hfx_plan plan, SystemPlan& sp, const double* psi, const vo
   return HFX_OK;
 }
 
+// ACE projectors: L = chol(-M), X = L^(-1), P = X W (Eq. (vx_ace)).
+hfx_status enq_ace_build(hfx_plan plan, SystemPlan& sp, const void* kpsi, const double* m,
+                         double* p, char* ws, hipStream_t st) {
+  const int n = sp.sys.n_orb;
+  const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
+  double* work = reinterpret_cast<double*>(ws + sp.off_ortho);
+  double* low = work;                      // n x n
+  double* inv = work + (size_t)n * n;      // n x n
+  double* tmp = reinterpret_cast<double*>(ws + align_up(sp.off_ortho + (size_t)6 * n * n * 8 + 64));
+  const char* kp = static_cast<const char*>(kpsi) + (size_t)sp.psi_off * elem;
+  double* pp = p + sp.psi_off;
+  const double nn = n, npts = (double)sp.nr;
+  Bracket bk(plan, HFX_PASS_ACE_BUILD, st);
+  launch_chol_neg(m + sp.m_off, n, low, st);
+  launch_trinv(low, n, inv, st);
+  launch_scale_to_f64(kp, plan->prec == HFX_FP64 ? 1 : 0, pp, (size_t)n * sp.nr, 1.0, nullptr,
+                      st);
+  launch_apply_left(inv, pp, n, sp.nr, tmp, st);
+  bk.done(nn * npts * (elem + 8.0 + 16.0), 2.0 * nn * nn * npts);
+  HIP_TRY(hipGetLastError());
+  return HFX_OK;
+}
+
+// out = V^ACE phi = -sum_k P_k <P_k|phi>: G = -dV phi P^T, out = G P.
+hfx_status enq_ace_apply(hfx_plan plan, SystemPlan& sp, const double* p, const double* phi,
+                         double* out, char* ws, hipStream_t st) {
+  const int n = sp.sys.n_orb;
+  double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
+  double* g = reinterpret_cast<double*>(ws + sp.off_ortho) + (size_t)2 * n * n;
+  double* tmp = reinterpret_cast<double*>(ws + align_up(sp.off_ortho + (size_t)6 * n * n * 8 + 64));
+  const double nn = n, npts = (double)sp.nr;
+  Bracket bk(plan, HFX_PASS_ACE_APPLY, st);
+  launch_xtx_f64(phi + sp.psi_off, p + sp.psi_off, n, sp.nr, -sp.dv, part, g, st);
+  launch_scale_to_f64(p + sp.psi_off, 1, out + sp.psi_off, (size_t)n * sp.nr, 1.0, nullptr, st);
+  launch_apply_left(g, out + sp.psi_off, n, sp.nr, tmp, st);
+  bk.done(nn * npts * 8.0 * 5.0, 4.0 * nn * nn * npts);
+  HIP_TRY(hipGetLastError());
+  return HFX_OK;
+}
+
 hfx_status enq_ortho(hfx_plan plan, SystemPlan& sp, double* psi, char* ws, hipStream_t st) {
   const int n = sp.sys.n_orb;
   double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
@@ -891,6 +931,31 @@ hfx_status hfx_orthonormalize(hfx_plan plan, double* psi, int method, void* ws, 
   if (method != HFX_ORTHO_LOWDIN) return fail(HFX_EUNSUPPORTED, "only Loewdin is implemented");
   return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
     return enq_ortho(plan, plan->sys[i], psi, static_cast<char*>(ws), st);
+  });
+}
+
+hfx_status hfx_ace_build(hfx_plan plan, const void* kpsi, const double* m, double* p, void* ws,
+                         size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  hfx_status s = check_call(plan, kpsi, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (!m) return fail(HFX_EINVAL, "null m");
+  if (!p) return fail(HFX_EINVAL, "null p");
+  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
+    return enq_ace_build(plan, plan->sys[i], kpsi, m, p, static_cast<char*>(ws), st);
+  });
+}
+
+hfx_status hfx_ace_apply(hfx_plan plan, const double* p, const double* phi, double* out,
+                         void* ws, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  hfx_status s = check_call(plan, p, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (!phi) return fail(HFX_EINVAL, "null phi");
+  if (!out) return fail(HFX_EINVAL, "null out");
+  if (out == p || out == phi) return fail(HFX_EINVAL, "out must not alias p or phi");
+  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
+    return enq_ace_apply(plan, plan->sys[i], p, phi, out, static_cast<char*>(ws), st);
   });
 }
 

@@ -30,7 +30,7 @@ GRAPH_ENERGY = 0
 GRAPH_APPLY = 1
 GRAPH_STEP = 2
 PASSES = ("stage", "zero", "pair_fwd", "plane", "rows_fwd", "cols_conv", "rows_inv", "inv_acc",
-          "inv_energy", "energy_reduce", "contract", "ortho", "scale")
+          "inv_energy", "energy_reduce", "contract", "ortho", "scale", "ace_build", "ace_apply")
 
 _STATUS = {0: "HFX_OK", 1: "HFX_EINVAL", 2: "HFX_EUNSUPPORTED", 3: "HFX_ENOMEM",
            4: "HFX_EDEVICE"}
@@ -78,6 +78,8 @@ def load_library(path=None):
     lib.hfx_profile_enable.argtypes = [vp, i]
     lib.hfx_profile_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
                                      ctypes.POINTER(ctypes.c_longlong), i]
+    lib.hfx_ace_build.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.hfx_ace_apply.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.hfx_graph_create.argtypes = [vp, i, vp, vp, vp, vp, vp, sz, ctypes.POINTER(vp)]
     lib.hfx_graph_launch.argtypes = [vp, vp]
     lib.hfx_graph_destroy.argtypes = [vp]
@@ -91,7 +93,7 @@ def load_library(path=None):
                  "hfx_exchange_energy", "hfx_apply_exchange", "hfx_exchange_matrix",
                  "hfx_orthonormalize", "hfx_exchange_gradient", "hfx_profile_enable",
                  "hfx_profile_read", "hfx_graph_create", "hfx_graph_launch",
-                 "hfx_graph_destroy"):
+                 "hfx_graph_destroy", "hfx_ace_build", "hfx_ace_apply"):
         getattr(lib, name).restype = i
     if path is None:
         _lib = lib
@@ -243,6 +245,33 @@ class Plan:
         _check(_lib.hfx_orthonormalize(self._h, _ptr(psi), int(method), _ptr(ws), self.ws_bytes,
                                        _stream()))
         return psi
+
+    def ace_build(self, kpsi, m, p=None):
+        """ACE projectors P = W L^(-T) (rows |P_k>, float64, the layout of psi)
+        from W = K psi (apply_exchange) and M (exchange_matrix)."""
+        if kpsi.dtype != self.kpsi_dtype or kpsi.numel() != self.total_orb_points:
+            raise ValueError("kpsi must come from apply_exchange of this plan")
+        if m.dtype != torch.float64 or m.numel() != sum(s.n_orb ** 2 for s in self.systems):
+            raise ValueError("m must come from exchange_matrix of this plan")
+        if p is None:
+            p = torch.empty(kpsi.shape, dtype=torch.float64, device=self.device)
+        self._check_psi(p)
+        ws = self.workspace()
+        _check(_lib.hfx_ace_build(self._h, _ptr(kpsi), _ptr(m), _ptr(p), _ptr(ws), self.ws_bytes,
+                                  _stream()))
+        return p
+
+    def ace_apply(self, p, phi, out=None):
+        """out = V_X^ACE phi = -sum_k P_k <P_k|phi>, row by row (float64)."""
+        self._check_psi(p)
+        self._check_psi(phi)
+        if out is None:
+            out = torch.empty(phi.shape, dtype=torch.float64, device=self.device)
+        self._check_psi(out)
+        ws = self.workspace()
+        _check(_lib.hfx_ace_apply(self._h, _ptr(p), _ptr(phi), _ptr(out), _ptr(ws), self.ws_bytes,
+                                  _stream()))
+        return out
 
     def graph(self, op, psi, kpsi=None, ex=None, m=None):
         """Capture one call (GRAPH_ENERGY / GRAPH_APPLY / GRAPH_STEP) for these buffers."""
