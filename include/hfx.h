@@ -86,7 +86,11 @@ typedef struct hfx_plan_t* hfx_plan;
  * alternately on the call's stream and on a stream the plan owns, with a second
  * pair-grid buffer in the workspace (results are bitwise those of streams=1,
  * the default; graphs captured from such a plan run the batches on one
- * stream).  The environment variable
+ * stream); shard=<g>/<R> restricts the plan to the tile rounds r with
+ * r % R == g, one of R virtual groups of the pair list (the way the pairs
+ * would be dealt over R GPUs): K psi, E_x, M and the gradient are then that
+ * group's partial sums, which add up over g = 0..R-1 to the full result (the
+ * G = 0 energy of the pair means is added by group 0).  The environment variable
  * HFX_MAX_WORKSPACE_BYTES also caps the workspace.  Uploads the plan's tables
  * (synchronous).  Errors: HFX_EINVAL for null out/sys, n_sys < 1, n <= 0,
  * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0;

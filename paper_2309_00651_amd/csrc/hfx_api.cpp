@@ -75,6 +75,9 @@ struct SystemPlan {
   // stream and an owned stream, each with its own pair-grid buffer
   int nstreams = 1;
   size_t grid_bytes = 0;  // one pair-grid buffer
+  // virtual group (emulated shard) of the tile rounds: rounds r with
+  // r % shards == shard; group 0 also adds the G = 0 energy
+  int shard = 0, shards = 1;
   hipStream_t bstream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_acc[2] = {nullptr, nullptr};
   // offsets inside concatenated user buffers
@@ -193,6 +196,7 @@ int bricks_per_tile(const Variant* v) {
 }
 
 void build_schedule(SystemPlan& sp, long long tiles_cap) {
+  // (rounds outside this plan's virtual group are skipped below)
   const Variant* v = sp.var;
   const int T = v->tile;
   const int nb = (sp.sys.n_orb + T - 1) / T;
@@ -209,7 +213,9 @@ void build_schedule(SystemPlan& sp, long long tiles_cap) {
   sp.active.clear();
   sp.batches.clear();
   long long part = 0;
-  for (auto& round : rounds) {
+  for (size_t ri = 0; ri < rounds.size(); ++ri) {
+    if ((int)(ri % (size_t)sp.shards) != sp.shard) continue;
+    const auto& round = rounds[ri];
     for (size_t s = 0; s < round.size(); s += tpb) {
       Batch b{};
       b.tile_off = (int)sp.tiles.size();
@@ -511,8 +517,10 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   if (ex) {
     Bracket bk(plan, HFX_PASS_ENERGY_REDUCE, st);
     const double om = sp.dv * (double)sp.nr;
-    launch_energy_reduce(partials, sp.n_partials, -0.5 * sp.dv, mean, sp.sys.n_orb,
-                         -0.5 * om * sp.v0, ex, st);
+    // the G = 0 energy of the means is not pair work: added by group 0 only
+    const bool dc = sp.shard == 0;
+    launch_energy_reduce(partials, sp.n_partials, -0.5 * sp.dv, dc ? mean : nullptr,
+                         sp.sys.n_orb, dc ? -0.5 * om * sp.v0 : 0.0, ex, st);
     bk.done((double)sp.n_partials * 8.0, 0.0);
   }
   HIP_TRY(hipGetLastError());
@@ -695,6 +703,19 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
                                         ")");
   }
   const long long tiles_cap = parse_option(options, "tiles", 0);
+  int shard = 0, shards = 1;
+  {
+    const std::string sv = parse_option_str(options, "shard");
+    if (!sv.empty()) {
+      const size_t slash = sv.find('/');
+      if (slash == std::string::npos)
+        return fail(HFX_EINVAL, "shard= takes <group>/<groups>");
+      shard = std::atoi(sv.substr(0, slash).c_str());
+      shards = std::atoi(sv.substr(slash + 1).c_str());
+      if (shards < 1 || shard < 0 || shard >= shards)
+        return fail(HFX_EINVAL, "shard=<g>/<R> needs 0 <= g < R");
+    }
+  }
   const std::string vname = parse_option_str(options, "variant");
   if (!vname.empty() && n_sys > 1)
     return fail(HFX_EINVAL, "variant= applies to single-system plans only");
@@ -722,6 +743,8 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     sp.n = sys[i].n[0];
     sp.nr = (long long)sp.n * sp.n * sp.n;
     sp.dv = sys[i].L[0] * sys[i].L[1] * sys[i].L[2] / (double)sp.nr;
+    sp.shard = shard;
+    sp.shards = shards;
     build_schedule(sp, tiles_cap);
     sp.psi_off = psi_off;
     sp.m_off = m_off;

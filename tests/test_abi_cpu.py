@@ -112,3 +112,10 @@ def test_null_plan_calls(lib):
 def test_status_strings(lib):
     for code in range(5):
         assert lib.hfx_status_string(code).decode().startswith("HFX_")
+
+
+@pytest.mark.parametrize("opts", [b"shard=2/2", b"shard=1", b"shard=-1/3", b"shard=0/0",
+                                  b"streams=3"])
+def test_bad_plan_options_rejected_before_device(lib, opts):
+    st, h, err = _create(lib, [GOOD], opts=opts)
+    assert st == 1 and not h.value and err
