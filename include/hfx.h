@@ -39,7 +39,12 @@
  * hfx_plan_create and hfx_plan_destroy.  A plan with several systems forks
  * them onto its own streams (default priority) after an event recorded on
  * `stream` and joins them back before returning, so they overlap on the GPU
- * while the caller sees ordinary stream order.
+ * while the caller sees ordinary stream order.  Calls on one plan share the
+ * plan's side streams, events and workspace layout: issue them from one host
+ * thread at a time and, when they go to different streams, order those
+ * streams so the calls do not overlap on the device (one workspace each is not
+ * enough: the side streams and events are per plan).  Separate plans are
+ * independent.
  *
  * Errors: status codes only.  Arguments are validated before any HIP call;
  * HIP failures map to HFX_EDEVICE.  hfx_last_error() returns a thread-local
