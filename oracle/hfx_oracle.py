@@ -14,6 +14,8 @@ What it computes (Methods, "MTACE Method for H-AIMD Simulation"):
 * ACE matrix M_kl = <psi_k | V_X | psi_l>  (same subsection, definition of M)
 * ACE operator, Eq. (vx_ace): V_X^ACE = - sum_k |P_k><P_k| with P = W L^(-T),
   W_i = V_X psi_i and -M = L L^T (Cholesky)
+* s-MTACE screening (same Methods subsection): only pairs with
+  int |phi_i phi_j| dr >= rho_cut enter the exchange sums
 
 The FFT evaluates the periodic discrete convolution exactly up to rounding,
 so the oracle is the plain definition written out, one pair at a time, in
@@ -52,7 +54,7 @@ __all__ = [
     "TRUNCATED", "ERFC", "volume", "grid_g2", "coulomb_kernel",
     "pair_potential", "pair_energy", "exchange", "apply_exchange_rows",
     "exchange_matrix", "overlap", "lowdin", "cholesky_orthonormalize",
-    "ace_projectors", "ace_apply",
+    "ace_projectors", "ace_apply", "pair_overlap_abs", "screen_pairs",
 ]
 
 TRUNCATED = 0
@@ -132,12 +134,14 @@ def pair_energy(psi_i, psi_j, vg, dv):
 
 
 def _rows_worker(args):
-    psi, vg, dv, rows, want_kpsi = args
+    psi, vg, dv, rows, want_kpsi, keep = args
     n_orb = psi.shape[0]
     kpsi = np.zeros_like(psi) if want_kpsi else None
     e = np.zeros((n_orb, n_orb))
     for i in rows:
         for j in range(i, n_orb):
+            if keep is not None and not keep[i, j]:
+                continue                      # screened pair (s-MTACE)
             rho = psi[i] * psi[j]
             vij = pair_potential(rho, vg)
             e_ij = dv * float(np.sum(rho * vij))
@@ -151,7 +155,7 @@ def _rows_worker(args):
     return kpsi, e
 
 
-def exchange(psi, box, vg, want_kpsi=True, workers=1):
+def exchange(psi, box, vg, want_kpsi=True, workers=1, keep=None):
     """Exact exchange of real orbitals psi[orb, z, y, x] (float64).
 
     Returns a dict with
@@ -163,12 +167,14 @@ def exchange(psi, box, vg, want_kpsi=True, workers=1):
     Pairs i <= j are evaluated once each; v_ij = v_ji because the pair density
     is symmetric in (i, j).  ``workers`` > 1 splits the rows i over forked
     processes; their private K psi blocks are summed in a fixed order.
+    ``keep`` (symmetric boolean N_orb x N_orb, optional) restricts the sums
+    to the pairs it marks, as the s-MTACE screening does (``screen_pairs``).
     """
     psi = np.ascontiguousarray(psi, dtype=np.float64)
     n_orb = psi.shape[0]
     dv = volume(box) / psi[0].size
     if workers <= 1 or n_orb < 2:
-        kpsi, e = _rows_worker((psi, vg, dv, range(n_orb), want_kpsi))
+        kpsi, e = _rows_worker((psi, vg, dv, range(n_orb), want_kpsi, keep))
     else:
         import multiprocessing as mp
         # Balance rows: row i has n_orb - i pairs; deal them round-robin.
@@ -176,7 +182,7 @@ def exchange(psi, box, vg, want_kpsi=True, workers=1):
         ctx = mp.get_context("fork")
         with ctx.Pool(workers) as pool:
             parts = pool.map(_rows_worker,
-                             [(psi, vg, dv, c, want_kpsi) for c in chunks])
+                             [(psi, vg, dv, c, want_kpsi, keep) for c in chunks])
         kpsi = np.zeros_like(psi) if want_kpsi else None
         e = np.zeros((n_orb, n_orb))
         for kp, ep in parts:          # fixed summation order
@@ -256,4 +262,18 @@ def ace_apply(p, phi, dv):
     b = phi.reshape(phi.shape[0], -1)
     c = dv * (a @ b.T)          # <P_k | phi_j>
     return (-(c.T @ a)).reshape(phi.shape)
+
+
+def pair_overlap_abs(psi, dv):
+    """A_ij = int |phi_i(r) phi_j(r)| dr = dV sum_n |phi_i| |phi_j| (the
+    quantity the s-MTACE screening compares with rho_cut)."""
+    a = np.abs(psi.reshape(psi.shape[0], -1))
+    return dv * (a @ a.T)
+
+
+def screen_pairs(psi, dv, rho_cut):
+    """Pairs kept by the s-MTACE criterion A_ij >= rho_cut (symmetric boolean
+    matrix; the diagonal of normalised orbitals is 1 and always kept for
+    rho_cut <= 1)."""
+    return pair_overlap_abs(psi, dv) >= rho_cut
 

@@ -63,7 +63,7 @@ def mut_erfc_sign(shape, box, kind, param=0.0):
 
 
 def mut_rows_index_swapped(args):
-    psi, vg, dv, rows, want_kpsi = args
+    psi, vg, dv, rows, want_kpsi = args[:5]
     n = psi.shape[0]
     kpsi = np.zeros_like(psi)
     e = np.zeros((n, n))
@@ -79,7 +79,7 @@ def mut_rows_index_swapped(args):
 
 
 def mut_rows_offdiag_once(args):
-    psi, vg, dv, rows, want_kpsi = args
+    psi, vg, dv, rows, want_kpsi = args[:5]
     n = psi.shape[0]
     kpsi = np.zeros_like(psi)
     e = np.zeros((n, n))
@@ -95,7 +95,7 @@ def mut_rows_offdiag_once(args):
 
 
 def mut_rows_missing_symmetric_update(args):
-    psi, vg, dv, rows, want_kpsi = args
+    psi, vg, dv, rows, want_kpsi = args[:5]
     n = psi.shape[0]
     kpsi = np.zeros_like(psi)
     e = np.zeros((n, n))

@@ -403,3 +403,58 @@ def test_ace_pins_catch_planted_mistakes(small_system):
         assert np.max(np.abs(out - ref)) > 1e-6 * scale
     out = -oracle.ace_apply(p, psi, res["dv"])
     assert np.max(np.abs(out - ref)) > 1e-6 * scale
+
+
+# --------------------------------------------------------------------------
+# s-MTACE pair screening: int |phi_i phi_j| >= rho_cut
+
+def test_pair_overlap_abs_two_gaussians_closed_form():
+    """psi_k = (2 pi s^2)^(-3/4) exp(-|r - R_k|^2 / 4 s^2): int psi_1 psi_2 =
+    exp(-d^2 / 8 s^2) (both positive, so the absolute value changes nothing);
+    box large enough for the periodic images to vanish."""
+    n, L, s = 64, 24.0, 1.0
+    x = np.arange(n) * (L / n)
+    zz, yy, xx = np.meshgrid(x, x, x, indexing="ij")
+    r1, r2 = np.array([10.0, 11.0, 12.0]), np.array([13.0, 11.5, 10.0])
+
+    def g(c):
+        d2 = (xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2
+        return (2 * math.pi * s * s) ** -0.75 * np.exp(-d2 / (4 * s * s))
+    psi = np.stack([g(r1), -g(r2)])          # a sign flip: |.| makes it positive
+    a = oracle.pair_overlap_abs(psi, (L / n) ** 3)
+    d2 = float(np.sum((r1 - r2) ** 2))
+    assert abs(a[0, 1] - math.exp(-d2 / (8 * s * s))) <= 1e-10
+    assert abs(a[0, 0] - 1.0) <= 1e-10 and abs(a[1, 1] - 1.0) <= 1e-10
+
+
+def test_screening_limits(small_system):
+    psi, box, vg = small_system
+    dv = box[0] * box[1] * box[2] / psi[0].size
+    a = oracle.pair_overlap_abs(psi, dv)
+    full = oracle.exchange(psi, box, vg)
+    # below every overlap: nothing is screened
+    keep = oracle.screen_pairs(psi, dv, 0.5 * float(np.min(a)))
+    assert keep.all()
+    low = oracle.exchange(psi, box, vg, keep=keep)
+    assert low["ex"] == full["ex"] and np.array_equal(low["kpsi"], full["kpsi"])
+    # above every off-diagonal overlap: only the self terms remain
+    off = a[~np.eye(len(psi), dtype=bool)]
+    diag = np.diag(a)
+    cut = 0.5 * (float(off.max()) + float(diag.min()))
+    assert off.max() < cut < diag.min()
+    keep = oracle.screen_pairs(psi, dv, cut)
+    assert np.array_equal(keep, np.eye(len(psi), dtype=bool))
+    res = oracle.exchange(psi, box, vg, keep=keep)
+    want_e = -0.5 * sum(oracle.pair_energy(p, p, vg, dv) for p in psi)
+    want_k = np.stack([-oracle.pair_potential(p * p, vg) * p for p in psi])
+    assert abs(res["ex"] - want_e) <= 1e-13 * abs(want_e)
+    assert np.max(np.abs(res["kpsi"] - want_k)) <= 1e-13 * np.max(np.abs(want_k))
+
+
+def test_screening_keeps_symmetric_pairs_and_diagonal(small_system):
+    psi, box, vg = small_system
+    dv = box[0] * box[1] * box[2] / psi[0].size
+    a = oracle.pair_overlap_abs(psi, dv)
+    keep = oracle.screen_pairs(psi, dv, float(np.median(a)))
+    assert np.array_equal(keep, keep.T)
+    assert np.diag(keep).all()
