@@ -181,6 +181,40 @@ hfx_status hfx_ace_apply(hfx_plan plan, const double* p, const double* phi, doub
                          void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Pair screening of the s-MTACE variant (Methods, MTACE subsection: pairs
+ * whose orbitals barely overlap are dropped from the exchange sums).
+ *
+ * hfx_screen evaluates A_ab = dV sum_r |psi_a(r)| |psi_b(r)| (float64 MFMA)
+ * for the float64 orbitals psi (device, the layout of the other calls) and
+ * keeps the pairs with A_ab >= rho_cut (decided once per unordered pair, on
+ * A's upper triangle).  It then rebuilds every system's tile schedule over
+ * the kept pairs: orbitals are put in reverse Cuthill-McKee order of the
+ * graph of kept pairs, tile pairs without a kept pair are dropped, and the
+ * rest are packed first-fit into batches of disjoint orbital blocks.  Every
+ * later energy, K psi and gradient call of the plan sums over the kept pairs
+ * only (the G = 0 energy of float32 plans too): K psi_a = -sum_{b kept} v_ab
+ * psi_b.  rho_cut <= 0 restores the unscreened schedule (results identical
+ * to a fresh plan).
+ *
+ * kept (host, one entry per system, may be NULL) receives the number of
+ * kept unordered pairs a <= b.  The call waits for `stream` and returns
+ * after the new schedule is uploaded (host-synchronous).  Graphs captured
+ * earlier keep the schedule they were captured with.  HFX_EINVAL: null plan
+ * or psi, a non-finite rho_cut, or a call during graph capture; HFX_ENOMEM:
+ * short workspace.
+ */
+hfx_status hfx_screen(hfx_plan plan, const double* psi, double rho_cut, long long* kept, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/*
+ * Size of a system's current tile schedule (host query, no device work):
+ * info[0] batches, info[1] tile pairs, info[2] pair grids (complex grids,
+ * two orbital pairs each) per exchange call, info[3] orbital pairs a <= b
+ * evaluated.  HFX_EINVAL: null plan or info, system index out of range.
+ */
+hfx_status hfx_schedule_info(hfx_plan plan, int system, long long* info);
+
+/*
  * Per-pass timing (tracing aid).  While enabled, every kernel launch of the
  * plan is bracketed by a pair of HIP events recorded on the caller's stream,
  * and the pass's algorithmic HBM bytes (each operand read or written once;

@@ -82,9 +82,19 @@ __global__ void __launch_bounds__(256) k_scale_to_f64(const S* __restrict__ src,
     dst[i] = f * (double)src[i];
 }
 
+__global__ void __launch_bounds__(256) k_mask(double* __restrict__ m,
+                                             const unsigned char* __restrict__ keep, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !keep[i]) m[i] = 0.0;
+}
+
 static int grid_for(size_t work) {
   const size_t b = (work + 255) / 256;
   return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+void launch_mask(double* m, const unsigned char* keep, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, m, keep, n);
 }
 
 void launch_cast_f64_f32(const double* in, float* out, size_t n, hipStream_t s) {

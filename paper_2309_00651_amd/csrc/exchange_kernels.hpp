@@ -69,6 +69,20 @@ __device__ __forceinline__ void stage_twiddles(TwEntry<T>* dst, const void* src,
   for (int i = tid; i < SchedInfo<S>::tw_count(); i += NT) dst[i] = s[i];
 }
 
+// Orbital index of tile position p (screened plans reorder the orbitals).
+__device__ __forceinline__ int orb_at(const PassArgs& a, int p) {
+  return a.perm ? a.perm[p] : p;
+}
+
+// Whether pair (a, b) of a tile is evaluated: inside the blocks, a <= b on a
+// diagonal tile, and kept by the screening mask (8-orbital tiles).
+template <int TT>
+__device__ __forceinline__ bool pair_live(const TileDesc& td, int ia, int b) {
+  if (b >= td.nJ || (td.diag && b < ia)) return false;
+  if constexpr (TT == 8) return (td.keep >> (8 * ia + b)) & 1ull;
+  return true;
+}
+
 // scale * (pair-density mean) for the TT x TT pairs of a tile, [a][b], zero
 // outside the tile or without means (float64 plans): staged in LDS so that
 // the loops below issue no global loads besides their own data.
@@ -78,7 +92,8 @@ __device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const Til
   for (int q = tid; q < TT * TT; q += NT) {
     const int ia = q / TT, b = q - ia * TT;
     dst[q] = (a.mean && ia < td.nI && b < td.nJ)
-                 ? (T)(scale * a.mean[(long long)(td.i0 + ia) * a.n_orb + td.j0 + b])
+                 ? (T)(scale * a.mean[(long long)orb_at(a, td.i0 + ia) * a.n_orb +
+                                      orb_at(a, td.j0 + b)])
                  : T(0);
   }
 }
@@ -154,11 +169,11 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
     T xj[4][PT], xi[PIL ? 4 : 1][PT];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const T* pb = psi + (long long)(td.j0 + (b0 + q < td.nJ ? b0 + q : 0)) * NR;
+      const T* pb = psi + (long long)orb_at(a, td.j0 + (b0 + q < td.nJ ? b0 + q : 0)) * NR;
 #pragma unroll
       for (int k = 0; k < PT; ++k) xj[q][k] = pb[offA[k]];
       if constexpr (PIL) {
-        const T* pa = psi + (long long)(td.i0 + (b0 + q < td.nI ? b0 + q : 0)) * NR;
+        const T* pa = psi + (long long)orb_at(a, td.i0 + (b0 + q < td.nI ? b0 + q : 0)) * NR;
 #pragma unroll
         for (int k = 0; k < PT; ++k) xi[q][k] = pa[offA[k]];
       }
@@ -180,27 +195,33 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
 #pragma unroll
       for (int k = 0; k < PT; ++k) pa[k] = pil[(ia * PT + k) * NT + tid];
     } else {
-      const T* pa_ptr = psi + (long long)(td.i0 + ia) * NR;
+      const T* pa_ptr = psi + (long long)orb_at(a, td.i0 + ia) * NR;
 #pragma unroll
       for (int k = 0; k < PT; ++k) pa[k] = vA[k] ? pa_ptr[offA[k]] : T(0);
     }
     static_for<0, TT / 4>([&](auto bq) {
       constexpr int b0 = 4 * decltype(bq)::value;  // pairs (a, b0 .. b0 + 3), grids 2bq, 2bq+1
       // grid g carries pairs (a, b0 + 2g) and (a, b0 + 2g + 1)
-      const bool use0 = b0 < td.nJ && !(td.diag && b0 + 1 < ia);
-      const bool use1 = b0 + 2 < td.nJ && !(td.diag && b0 + 3 < ia);
+      const bool use0 = pair_live<TT>(td, ia, b0) || pair_live<TT>(td, ia, b0 + 1);
+      const bool use1 = pair_live<TT>(td, ia, b0 + 2) || pair_live<TT>(td, ia, b0 + 3);
       if (!use0 && !use1) return;
       // pair-density means (float32 plans): transforms see zero-mean densities
-      T mu[4];
+      T mu[4], on[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) mu[q] = mul[ia * TT + b0 + q];
+      for (int q = 0; q < 4; ++q) {
+        mu[q] = mul[ia * TT + b0 + q];
+        // pairs not evaluated (screened, or below the diagonal) transform as
+        // zeros, so they add no rounding to the pair sharing their grid
+        on[q] = pair_live<TT>(td, ia, b0 + q) ? T(1) : T(0);
+      }
 #pragma unroll
       for (int k = 0; k < PT; ++k)
         if (tid + k * NT < P) {
           const T in = vA[k] ? T(1) : T(0);  // columns beyond the grid stay zero
-          lds[ldsA[k]] = {pa[k] * pj[b0][k] - in * mu[0], pa[k] * pj[b0 + 1][k] - in * mu[1]};
-          lds[ldsA[k] + W] = {pa[k] * pj[b0 + 2][k] - in * mu[2],
-                              pa[k] * pj[b0 + 3][k] - in * mu[3]};
+          lds[ldsA[k]] = {on[0] * (pa[k] * pj[b0][k] - in * mu[0]),
+                          on[1] * (pa[k] * pj[b0 + 1][k] - in * mu[1])};
+          lds[ldsA[k] + W] = {on[2] * (pa[k] * pj[b0 + 2][k] - in * mu[2]),
+                              on[3] * (pa[k] * pj[b0 + 3][k] - in * mu[3])};
         }
       __syncthreads();
       cpx<T> out[L::VALS];
@@ -303,7 +324,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const bool bv = b0 + q < td.nJ;
-      const T* pb = psi + (long long)(td.j0 + (bv ? b0 + q : 0)) * NR;
+      const T* pb = psi + (long long)orb_at(a, td.j0 + (bv ? b0 + q : 0)) * NR;
 #pragma unroll
       for (int k = 0; k < PT; ++k) x[q][k] = pb[offA[k]];
     }
@@ -329,8 +350,8 @@ __global__ void __launch_bounds__(NT)
   // grid pair bq of orbital a carries pairs (a, 4bq .. 4bq + 3)
   auto uses = [&](int ia, int bq, bool& u0, bool& u1) {
     const int b0 = 4 * bq;
-    u0 = b0 < td.nJ && !(td.diag && b0 + 1 < ia);
-    u1 = b0 + 2 < td.nJ && !(td.diag && b0 + 3 < ia);
+    u0 = pair_live<TT>(td, ia, b0) || pair_live<TT>(td, ia, b0 + 1);
+    u1 = pair_live<TT>(td, ia, b0 + 2) || pair_live<TT>(td, ia, b0 + 3);
   };
   // Loads below are issued unconditionally and their values used as loaded:
   // masked-off lanes read a valid dummy address (data written earlier in the
@@ -355,8 +376,9 @@ __global__ void __launch_bounds__(NT)
   };
   // psi and old K psi of orbital a at the thread's points (offA = 0 off the grid)
   auto load_orbital = [&](int ia, T* p, T* ko) {
-    const T* pa_ptr = psi + (long long)(td.i0 + ia) * NR;
-    const T* ka = kpsi + (long long)(td.i0 + ia) * NR;
+    const int oa = orb_at(a, td.i0 + ia);
+    const T* pa_ptr = psi + (long long)oa * NR;
+    const T* ka = kpsi + (long long)oa * NR;
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
       p[k] = pa_ptr[offA[k]];
@@ -387,9 +409,10 @@ __global__ void __launch_bounds__(NT)
       }
       if (b >= td.nJ) return;
       if (!(gq == 0 ? use0 : use1)) return;
-      // weight of e_ab in sum_{i,j} e_ij: 2 for a != b, 1 for a == b
-      const int w = td.diag ? (b > ia ? 2 : (b == ia ? 1 : 0)) : 2;
-      if (w == 0) return;
+      // weight of e_ab in sum_{i,j} e_ij: 2 for a != b, 1 for a == b, 0 for
+      // pairs not evaluated
+      if (!pair_live<TT>(td, ia, b)) return;
+      const int w = (td.diag && b == ia) ? 1 : 2;
       // G = 0 part of v_ab when the mean was taken out of the transform;
       // its energy v0 * Omega * mu_ab^2 is added in float64 at the reduction
       const T dc = dcl[ia * TT + b];
@@ -412,7 +435,7 @@ __global__ void __launch_bounds__(NT)
 
   auto store_orbital = [&](int ia) {
     if constexpr (ACC) {
-      T* ka = kpsi + (long long)(td.i0 + ia) * NR;
+      T* ka = kpsi + (long long)orb_at(a, td.i0 + ia) * NR;
 #pragma unroll
       for (int k = 0; k < PT; ++k)
         if (vA[k]) ka[offA[k]] = kold[k] + acca[k];
@@ -471,13 +494,13 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const bool bv = b0 + q < td.nJ;
-        const T* kb = kpsi + (long long)(td.j0 + (bv ? b0 + q : 0)) * NR;
+        const T* kb = kpsi + (long long)orb_at(a, td.j0 + (bv ? b0 + q : 0)) * NR;
 #pragma unroll
         for (int k = 0; k < PT; ++k) old[q][k] = kb[offA[k]];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        T* kb = kpsi + (long long)(td.j0 + b0 + q) * NR;
+        T* kb = kpsi + (long long)orb_at(a, td.j0 + (b0 + q < td.nJ ? b0 + q : 0)) * NR;
 #pragma unroll
         for (int k = 0; k < PT; ++k)
           if (b0 + q < td.nJ && vA[k]) kb[offA[k]] = old[q][k] + accJ[b0 + q][k];

@@ -33,10 +33,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // MODE 0: float64 A and B, float64 MFMA.  MODE 1: split A, float32 B.
+// MODE 2: as 0 on |A| and |B| (the screening overlaps int |phi_i phi_j|).
 template <int MODE>
 struct Cfg {
   static constexpr int TM = 128;                 // C tile rows (A rows)
-  static constexpr int TN = MODE == 0 ? 128 : 64;  // C tile columns (B rows)
+  static constexpr int TN = MODE == 1 ? 64 : 128;  // C tile columns (B rows)
   static constexpr int WM = 64;                  // rows per wavefront (2 x 2 wavefronts)
   static constexpr int WN = TN / 2;
   static constexpr int BM = WM / 16, BN = WN / 16;  // 16 x 16 MFMA blocks per wavefront
@@ -178,6 +179,12 @@ k_gram(const double* __restrict__ a, const void* __restrict__ bv, int n, long lo
     }
   };
   auto stage = [&](int buf) {
+    if constexpr (MODE == 2) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ra[u] = fabs(ra[u]);
+#pragma unroll
+      for (int u = 0; u < BPT; ++u) rb[u] = fabs(rb[u]);
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       if constexpr (SPLIT) {
@@ -349,6 +356,11 @@ void launch_xtx_split(const double* a, const float* b, int n, long long nr, doub
 void launch_xtx_f64(const double* a, const double* b, int n, long long nr, double alpha,
                     double* part, double* c, hipStream_t s) {
   launch_gram<0>(a, b, n, nr, alpha, a == b, part, c, s);
+}
+
+void launch_xtx_abs(const double* a, int n, long long nr, double alpha, double* part, double* c,
+                    hipStream_t s) {
+  launch_gram<2>(a, a, n, nr, alpha, true, part, c, s);
 }
 
 }  // namespace hfx

@@ -78,6 +78,11 @@ struct SystemPlan {
   // virtual group (emulated shard) of the tile rounds: rounds r with
   // r % shards == shard; group 0 also adds the G = 0 energy
   int shard = 0, shards = 1;
+  long long tiles_cap = 0;
+  // pair screening (s-MTACE): orbital order of the tiles and the kept pairs
+  // (n_orb x n_orb bytes, original orbital indices); null when unscreened
+  int* d_perm = nullptr;
+  unsigned char* d_keep = nullptr;
   hipStream_t bstream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_acc[2] = {nullptr, nullptr};
   // offsets inside concatenated user buffers
@@ -231,6 +236,7 @@ void build_schedule(SystemPlan& sp, long long tiles_cap) {
         td.nJ = std::min(T, sp.sys.n_orb - td.j0);
         td.diag = bi == bj ? 1 : 0;
         td.slot0 = (int)(k - s) * T * (T / 2);
+        td.keep = ~0ull;
         for (int ia = 0; ia < td.nI; ++ia)
           for (int bp = 0; bp < T / 2; ++bp) {
             const int b0 = 2 * bp;
@@ -245,6 +251,118 @@ void build_schedule(SystemPlan& sp, long long tiles_cap) {
       part += (long long)b.n_tiles * br;
       sp.batches.push_back(b);
     }
+  }
+  sp.n_partials = part;
+}
+
+// Reverse Cuthill-McKee order of the orbitals on the graph of kept pairs:
+// orbitals that overlap get nearby positions, so whole tile pairs far from the
+// diagonal are screened away.  Deterministic (ties broken by index).
+std::vector<int> rcm_order(int n, const std::vector<unsigned char>& keep) {
+  std::vector<int> deg(n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (i != j && keep[(size_t)i * n + j]) ++deg[i];
+  std::vector<int> order;
+  std::vector<char> seen(n, 0);
+  while ((int)order.size() < n) {
+    int start = -1;
+    for (int i = 0; i < n; ++i)
+      if (!seen[i] && (start < 0 || deg[i] < deg[start])) start = i;
+    seen[start] = 1;
+    size_t head = order.size();
+    order.push_back(start);
+    while (head < order.size()) {
+      const int u = order[head++];
+      std::vector<int> nbr;
+      for (int v = 0; v < n; ++v)
+        if (!seen[v] && v != u && keep[(size_t)u * n + v]) nbr.push_back(v);
+      std::sort(nbr.begin(), nbr.end(), [&](int a, int b) {
+        return deg[a] != deg[b] ? deg[a] < deg[b] : a < b;
+      });
+      for (int v : nbr) {
+        seen[v] = 1;
+        order.push_back(v);
+      }
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+// Schedule of a screened plan: tile pairs of the reordered orbitals that keep
+// at least one pair, packed greedily (first fit, in (I, J) order) into
+// batches of tiles_per_batch tile pairs with disjoint orbital blocks.  Keeps
+// the unscreened plan's tiles_per_batch, so the workspace still fits.
+void build_screened_schedule(SystemPlan& sp, const std::vector<unsigned char>& keep,
+                             const std::vector<int>& perm) {
+  const Variant* v = sp.var;
+  const int T = v->tile, n = sp.sys.n_orb;
+  const int nb = (n + T - 1) / T;
+  const int br = bricks_per_tile(v);
+  const int tpb = sp.tiles_per_batch;
+  struct TP {
+    int bi, bj;
+    unsigned long long mask;
+  };
+  std::vector<TP> tps;
+  for (int bi = 0; bi < nb; ++bi)
+    for (int bj = bi; bj < nb; ++bj) {
+      unsigned long long mask = 0;
+      for (int a = 0; a < T; ++a)
+        for (int b = 0; b < T; ++b) {
+          const int pa = bi * T + a, pb = bj * T + b;
+          if (pa >= n || pb >= n || (bi == bj && b < a)) continue;
+          if (keep[(size_t)perm[pa] * n + perm[pb]]) mask |= 1ull << (8 * a + b);
+        }
+      if (mask) tps.push_back({bi, bj, mask});
+    }
+  std::vector<std::vector<TP>> batches;
+  std::vector<std::vector<char>> used;
+  for (const TP& t : tps) {
+    size_t k = 0;
+    for (; k < batches.size(); ++k)
+      if ((int)batches[k].size() < tpb && !used[k][t.bi] && !used[k][t.bj]) break;
+    if (k == batches.size()) {
+      batches.emplace_back();
+      used.emplace_back(nb, 0);
+    }
+    batches[k].push_back(t);
+    used[k][t.bi] = used[k][t.bj] = 1;
+  }
+  sp.tiles.clear();
+  sp.active.clear();
+  sp.batches.clear();
+  long long part = 0;
+  for (size_t k = 0; k < batches.size(); ++k) {
+    if ((int)(k % (size_t)sp.shards) != sp.shard) continue;
+    Batch b{};
+    b.tile_off = (int)sp.tiles.size();
+    b.active_off = (int)sp.active.size();
+    b.part_base = part;
+    for (size_t q = 0; q < batches[k].size(); ++q) {
+      const TP& t = batches[k][q];
+      TileDesc td{};
+      td.i0 = t.bi * T;
+      td.nI = std::min(T, n - td.i0);
+      td.j0 = t.bj * T;
+      td.nJ = std::min(T, n - td.j0);
+      td.diag = t.bi == t.bj ? 1 : 0;
+      td.slot0 = (int)q * T * (T / 2);
+      td.keep = t.mask;
+      auto live = [&](int a, int bb) {
+        return bb < td.nJ && !(td.diag && bb < a) && ((t.mask >> (8 * a + bb)) & 1ull);
+      };
+      for (int ia = 0; ia < td.nI; ++ia)
+        for (int bp = 0; bp < T / 2; ++bp)
+          if (live(ia, 2 * bp) || live(ia, 2 * bp + 1))
+            sp.active.push_back(td.slot0 + ia * (T / 2) + bp);
+      sp.tiles.push_back(td);
+    }
+    b.n_tiles = (int)sp.tiles.size() - b.tile_off;
+    b.n_active = (int)sp.active.size() - b.active_off;
+    part += (long long)b.n_tiles * br;
+    sp.batches.push_back(b);
   }
   sp.n_partials = part;
 }
@@ -335,6 +453,10 @@ void free_system(SystemPlan& sp) {
     if (p) (void)hipFree(p);
   if (sp.d_tiles) (void)hipFree(sp.d_tiles);
   if (sp.d_active) (void)hipFree(sp.d_active);
+  if (sp.d_perm) (void)hipFree(sp.d_perm);
+  if (sp.d_keep) (void)hipFree(sp.d_keep);
+  sp.d_perm = nullptr;
+  sp.d_keep = nullptr;
   if (sp.bstream) (void)hipStreamDestroy(sp.bstream);
   for (hipEvent_t e : {sp.ev_fork, sp.ev_join, sp.ev_acc[0], sp.ev_acc[1]})
     if (e) (void)hipEventDestroy(e);
@@ -413,6 +535,8 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
     double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
     Bracket br(plan, HFX_PASS_CONTRACT, st);
     launch_xtx_f64(psi, psi, sp.sys.n_orb, sp.nr, 1.0 / (double)sp.nr, part, mu, st);
+    // screened pairs contribute no G = 0 energy either
+    if (sp.d_keep) launch_mask(mu, sp.d_keep, (size_t)sp.sys.n_orb * sp.sys.n_orb, st);
     br.done(orb_pts * 8.0, 2.0 * (double)sp.sys.n_orb * orb_pts);
     mean = mu;
   }
@@ -435,6 +559,7 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   a.partials = partials;
   a.mean = mean;
   a.v0 = sp.v0;
+  a.perm = sp.d_perm;
   a.n_orb = sp.sys.n_orb;
   const int br = bricks_per_tile(v);
   const int n = v->n;
@@ -745,6 +870,7 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     sp.dv = sys[i].L[0] * sys[i].L[1] * sys[i].L[2] / (double)sp.nr;
     sp.shard = shard;
     sp.shards = shards;
+    sp.tiles_cap = tiles_cap;
     build_schedule(sp, tiles_cap);
     sp.psi_off = psi_off;
     sp.m_off = m_off;
@@ -758,7 +884,13 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     sp.grid_bytes = align_up((size_t)sp.slots_per_batch * sp.nr * 2 * elem);
     off = align_up(off + sp.grid_bytes * sp.nstreams);
     sp.off_partials = off;
-    off = align_up(off + (size_t)sp.n_partials * 8);
+    {
+      // room for every tile pair of the system: a screened schedule (or
+      // another virtual group's share) never needs more
+      const long long nb = (sys[i].n_orb + sp.var->tile - 1) / sp.var->tile;
+      const long long all = nb * (nb + 1) / 2 * bricks_per_tile(sp.var);
+      off = align_up(off + (size_t)std::max(sp.n_partials, all) * 8);
+    }
     sp.off_gemm = off;
     off = align_up(off + gemm_partial_bytes(sys[i].n_orb, sp.nr));
     sp.off_grad = off;
@@ -980,6 +1112,93 @@ hfx_status hfx_ace_apply(hfx_plan plan, const double* p, const double* phi, doub
   return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
     return enq_ace_apply(plan, plan->sys[i], p, phi, out, static_cast<char*>(ws), st);
   });
+}
+
+// s-MTACE pair screening: keep pairs with int |psi_a psi_b| dV >= rho_cut and
+// rebuild the tile schedule of every system over them.
+hfx_status hfx_screen(hfx_plan plan, const double* psi, double rho_cut, long long* kept, void* ws,
+                      size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  hfx_status s = check_call(plan, psi, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (!std::isfinite(rho_cut)) return fail(HFX_EINVAL, "rho_cut must be finite");
+  if (plan->capturing) return fail(HFX_EINVAL, "hfx_screen cannot be captured");
+  for (const SystemPlan& sp : plan->sys)
+    if (sp.var->tile != 8) return fail(HFX_EUNSUPPORTED, "screening needs 8-orbital tiles");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  for (size_t i = 0; i < plan->sys.size(); ++i) {
+    SystemPlan& sp = plan->sys[i];
+    const int n = sp.sys.n_orb;
+    std::vector<unsigned char> keep((size_t)n * n, 1);
+    std::vector<int> perm(n);
+    for (int k = 0; k < n; ++k) perm[k] = k;
+    const bool screened = rho_cut > 0.0;
+    if (screened) {
+      double* part = reinterpret_cast<double*>(w + sp.off_gemm);
+      double* amat = reinterpret_cast<double*>(w + sp.off_ortho);
+      launch_xtx_abs(psi + sp.psi_off, n, sp.nr, sp.dv, part, amat, st);
+      HIP_TRY(hipGetLastError());
+      std::vector<double> h((size_t)n * n);
+      HIP_TRY(hipMemcpyAsync(h.data(), amat, h.size() * 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      // A is symmetric up to rounding; decide each unordered pair once
+      for (int a = 0; a < n; ++a)
+        for (int b = a; b < n; ++b) {
+          const unsigned char k = h[(size_t)a * n + b] >= rho_cut ? 1 : 0;
+          keep[(size_t)a * n + b] = keep[(size_t)b * n + a] = k;
+        }
+      perm = rcm_order(n, keep);
+    } else {
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (kept) {
+      long long c = 0;
+      for (int a = 0; a < n; ++a)
+        for (int b = a; b < n; ++b) c += keep[(size_t)a * n + b];
+      kept[i] = c;
+    }
+    if (screened)
+      build_screened_schedule(sp, keep, perm);
+    else
+      build_schedule(sp, sp.tiles_cap);
+    // replace the device tables (the stream is idle: synchronised above)
+    for (void* d : {(void*)sp.d_tiles, (void*)sp.d_active, (void*)sp.d_perm, (void*)sp.d_keep})
+      if (d) HIP_TRY(hipFree(d));
+    sp.d_tiles = nullptr;
+    sp.d_active = nullptr;
+    sp.d_perm = nullptr;
+    sp.d_keep = nullptr;
+    void* d = nullptr;
+    if ((s = upload(sp.tiles, &d)) != HFX_OK) return s;
+    sp.d_tiles = static_cast<TileDesc*>(d);
+    if ((s = upload(sp.active, &d)) != HFX_OK) return s;
+    sp.d_active = static_cast<int*>(d);
+    if (screened) {
+      if ((s = upload(perm, &d)) != HFX_OK) return s;
+      sp.d_perm = static_cast<int*>(d);
+      if ((s = upload(keep, &d)) != HFX_OK) return s;
+      sp.d_keep = static_cast<unsigned char*>(d);
+    }
+  }
+  return HFX_OK;
+}
+
+hfx_status hfx_schedule_info(hfx_plan plan, int system, long long* info) {
+  if (!plan) return fail(HFX_EINVAL, "null plan");
+  if (!info) return fail(HFX_EINVAL, "null info");
+  if (system < 0 || system >= (int)plan->sys.size()) return fail(HFX_EINVAL, "no such system");
+  const SystemPlan& sp = plan->sys[system];
+  long long pairs = 0;
+  for (const TileDesc& td : sp.tiles)
+    for (int a = 0; a < td.nI; ++a)
+      for (int b = 0; b < td.nJ; ++b)
+        if (!(td.diag && b < a) && ((td.keep >> (8 * a + b)) & 1ull)) ++pairs;
+  info[0] = (long long)sp.batches.size();
+  info[1] = (long long)sp.tiles.size();
+  info[2] = (long long)sp.active.size();
+  info[3] = pairs;
+  return HFX_OK;
 }
 
 hfx_status hfx_graph_create(hfx_plan plan, int op, double* psi, void* kpsi, double* ex,

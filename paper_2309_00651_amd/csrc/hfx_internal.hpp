@@ -14,8 +14,14 @@ namespace hfx {
 // tiles (the same block twice) take a <= b.  Packed pair-grid slot of
 // (a - i0, b - j0) is slot0 + (a - i0) * (tile / 2) + (b - j0) / 2: the two
 // pairs (a, 2p) and (a, 2p+1) share one complex grid (real and imaginary part).
+// One tile pair of orbital blocks: positions i0..i0+nI-1 (I) and j0..j0+nJ-1
+// (J) in the plan's orbital order (see PassArgs::perm); diag when I == J (pairs
+// a <= b only); slot0 = first pair-grid slot.  keep: bit 8 a + b set when the
+// pair (position a of I, position b of J) is evaluated (all set unless the
+// pairs are screened; only 8-orbital tiles are screened).
 struct TileDesc {
   int i0, nI, j0, nJ, diag, slot0;
+  unsigned long long keep;
 };
 
 // Arguments of one exchange pass over one batch of tiles of one system.
@@ -37,6 +43,7 @@ struct PassArgs {
   const double* mean;     // float32 plans: pair-density means mu_ab = (1/N_r) sum psi_a psi_b
                           // (n_orb x n_orb), subtracted before the forward FFT; else null
   double v0;              // v(G = 0), re-added to the potentials as v0 * mu_ab
+  const int* perm;        // orbital at each position of the tile order (null: identity)
   int n_orb;
   int n_tiles;
   int n_active;
@@ -78,6 +85,8 @@ const Variant* variants_f64(int* count);
 // Elementwise helpers (exchange_common.hip)
 void launch_cast_f64_f32(const double* in, float* out, size_t n, hipStream_t s);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+// m[i] = keep[i] ? m[i] : 0 (n values)
+void launch_mask(double* m, const unsigned char* keep, size_t n, hipStream_t s);
 // grad[i] = scale * gscale[0 or nothing] * src[i] (src float32 or float64, in place allowed
 // for float64)
 void launch_scale_to_f64(const void* src, int src_is_f64, double* dst, size_t n, double scale,
@@ -95,6 +104,9 @@ void launch_xtx_split(const double* a, const float* b, int n_orb, long long nr, 
 // C = alpha * A B^T with A, B float64 [n][nr] (float64 MFMA; a == b: symmetric)
 void launch_xtx_f64(const double* a, const double* b, int n_orb, long long nr, double alpha,
                     double* partial, double* c, hipStream_t s);
+// C = alpha |A| |A|^T (float64 MFMA, symmetric)
+void launch_xtx_abs(const double* a, int n_orb, long long nr, double alpha, double* partial,
+                    double* c, hipStream_t s);
 size_t gemm_partial_bytes(int n_orb, long long nr);
 
 // Orthonormalisation helpers (ortho.hip)

@@ -80,6 +80,8 @@ def load_library(path=None):
                                      ctypes.POINTER(ctypes.c_longlong), i]
     lib.hfx_ace_build.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.hfx_ace_apply.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.hfx_screen.argtypes = [vp, vp, d, ctypes.POINTER(ctypes.c_longlong), vp, sz, vp]
+    lib.hfx_schedule_info.argtypes = [vp, i, ctypes.POINTER(ctypes.c_longlong)]
     lib.hfx_graph_create.argtypes = [vp, i, vp, vp, vp, vp, vp, sz, ctypes.POINTER(vp)]
     lib.hfx_graph_launch.argtypes = [vp, vp]
     lib.hfx_graph_destroy.argtypes = [vp]
@@ -93,7 +95,8 @@ def load_library(path=None):
                  "hfx_exchange_energy", "hfx_apply_exchange", "hfx_exchange_matrix",
                  "hfx_orthonormalize", "hfx_exchange_gradient", "hfx_profile_enable",
                  "hfx_profile_read", "hfx_graph_create", "hfx_graph_launch",
-                 "hfx_graph_destroy", "hfx_ace_build", "hfx_ace_apply"):
+                 "hfx_graph_destroy", "hfx_ace_build", "hfx_ace_apply", "hfx_screen",
+                 "hfx_schedule_info"):
         getattr(lib, name).restype = i
     if path is None:
         _lib = lib
@@ -272,6 +275,23 @@ class Plan:
         _check(_lib.hfx_ace_apply(self._h, _ptr(p), _ptr(phi), _ptr(out), _ptr(ws), self.ws_bytes,
                                   _stream()))
         return out
+
+    def screen(self, psi, rho_cut):
+        """s-MTACE pair screening: later calls sum over the pairs with
+        int |psi_a psi_b| >= rho_cut only (rho_cut <= 0: all pairs again).
+        Returns the number of kept pairs a <= b of each system."""
+        self._check_psi(psi)
+        kept = (ctypes.c_longlong * len(self.systems))()
+        ws = self.workspace()
+        _check(_lib.hfx_screen(self._h, _ptr(psi), float(rho_cut), kept, _ptr(ws), self.ws_bytes,
+                               _stream()))
+        return list(kept)
+
+    def schedule_info(self, system=0):
+        """(batches, tile pairs, pair grids, orbital pairs) of the current schedule."""
+        info = (ctypes.c_longlong * 4)()
+        _check(_lib.hfx_schedule_info(self._h, int(system), info))
+        return tuple(info)
 
     def graph(self, op, psi, kpsi=None, ex=None, m=None):
         """Capture one call (GRAPH_ENERGY / GRAPH_APPLY / GRAPH_STEP) for these buffers."""
