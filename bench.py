@@ -169,6 +169,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-smtace", action="store_true",
+                    help="skip the s-MTACE screening timings (profiled runs of the step)")
     ap.add_argument("--options", default=None, help="float32 plan options, e.g. 'tiles=2'")
     ap.add_argument("--fp64-options", default=None, help="float64 plan options")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -265,6 +267,39 @@ def main():
         del p, o
         return t_build, t_apply, ex_ace
 
+    def time_screen(psi_o, rho_cut, reps=3):
+        """s-MTACE screening (pairs with int |psi_a psi_b| >= rho_cut) of the
+        step's orthonormal orbitals: the screening call (host wall time) and
+        K psi + E_x over the kept pairs, against the unscreened call, each
+        timed with HIP events on a fresh float32 plan."""
+        plan = hfx.Plan(spec, hfx.FP32, options=args.options, device=dev)
+        kpsi = torch.empty(psi_o.shape, dtype=plan.kpsi_dtype, device=dev)
+        ex = torch.empty(1, dtype=torch.float64, device=dev)
+
+        def ev():
+            plan.apply_exchange(psi_o, kpsi=kpsi, ex=ex)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                plan.apply_exchange(psi_o, kpsi=kpsi, ex=ex)
+            b.record()
+            b.synchronize()
+            return a.elapsed_time(b) / reps, float(ex[0])
+        t_full, e_full = ev()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kept = plan.screen(psi_o, rho_cut)[0]
+        t_scr = 1e3 * (time.perf_counter() - t0)
+        info = plan.schedule_info()
+        t_kept, e_kept = ev()
+        out = {"rho_cut": rho_cut, "pairs_kept": kept, "pairs": n_pairs,
+               "pair_grids": info[2], "tile_pairs": info[1], "batches": info[0],
+               "screen_call_ms": t_scr, "kpsi_ms_screened": t_kept, "kpsi_ms_all_pairs": t_full,
+               "speedup": t_full / t_kept, "rel_dEx_screening": abs(e_kept - e_full) / abs(e_full)}
+        del plan, kpsi
+        return out
+
     # achievable HBM rate on this device: device-to-device copy of 1 GiB
     # (1 GiB read + 1 GiB written), median of 5, timed with HIP events
     def copy_rate():
@@ -317,6 +352,10 @@ def main():
 
     ace_build_ms, ace_apply_ms, ex_ace = time_ace(plan32, r32)
     log(f"ace: build {ace_build_ms:.2f} ms, apply {ace_apply_ms:.2f} ms")
+    smtace = [] if args.no_smtace else [time_screen(r32["psi"], rc) for rc in (2.5e-2, 2.0e-3)]
+    for sc in smtace:
+        log(f"s-MTACE rho_cut {sc['rho_cut']:g}: {sc['pairs_kept']} of {n_pairs} pairs, "
+            f"K psi {sc['kpsi_ms_screened']:.2f} ms (all pairs {sc['kpsi_ms_all_pairs']:.2f} ms)")
     del r32["kpsi"], r32["m"], r32["psi"]
 
     extra = {"kpsi_ms_per_step_fp32": pair_ms, "pair_pipeline_hbm_frac": exch_frac,
@@ -326,7 +365,7 @@ def main():
              "device_copy_GBps": copy_gbps,
              "pair_pipeline_frac_of_device_copy": exch_frac * HBM_PEAK_GBS / copy_gbps,
              "dominant_frac_of_device_copy": (achieved / copy_gbps) if roof["bound"] == "hbm" else None,
-             "passes": passes, "ex_fp32": r32["ex"]}
+             "passes": passes, "ex_fp32": r32["ex"], "s_mtace": smtace}
     if not args.no_fp64:
         log(f"fp64: 1 warm-up + {args.fp64_steps} timed steps")
         r64, _ = run(hfx.FP64, args.fp64_steps, 1, False)

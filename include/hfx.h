@@ -188,9 +188,10 @@ hfx_status hfx_ace_apply(hfx_plan plan, const double* p, const double* phi, doub
  * for the float64 orbitals psi (device, the layout of the other calls) and
  * keeps the pairs with A_ab >= rho_cut (decided once per unordered pair, on
  * A's upper triangle).  It then rebuilds every system's tile schedule over
- * the kept pairs: orbitals are put in reverse Cuthill-McKee order of the
- * graph of kept pairs, tile pairs without a kept pair are dropped, and the
- * rest are packed first-fit into batches of disjoint orbital blocks.  Every
+ * the kept pairs: orbitals are grouped into tiles of strongly overlapping
+ * orbitals (greedy clustering on A), tile pairs without a kept pair are
+ * dropped, and the rest are packed first-fit into batches of disjoint
+ * orbital blocks.  Every
  * later energy, K psi and gradient call of the plan sums over the kept pairs
  * only (the G = 0 energy of float32 plans too): K psi_a = -sum_{b kept} v_ab
  * psi_b.  rho_cut <= 0 restores the unscreened schedule (results identical

@@ -255,38 +255,40 @@ void build_schedule(SystemPlan& sp, long long tiles_cap) {
   sp.n_partials = part;
 }
 
-// Reverse Cuthill-McKee order of the orbitals on the graph of kept pairs:
-// orbitals that overlap get nearby positions, so whole tile pairs far from the
-// diagonal are screened away.  Deterministic (ties broken by index).
-std::vector<int> rcm_order(int n, const std::vector<unsigned char>& keep) {
-  std::vector<int> deg(n, 0);
+// Orbital order of a screened plan: consecutive runs of `tile` orbitals that
+// overlap strongly, so that whole tile pairs drop out.  Greedy clustering on
+// the overlap measure A (symmetric, n x n): a cluster starts at the
+// unassigned orbital with the fewest unassigned kept partners (the edge of
+// what is left) and grows by the unassigned orbital with the largest summed
+// A to the cluster's members.  Deterministic: ties go to the lower index.
+std::vector<int> cluster_order(int n, int tile, const std::vector<double>& a,
+                               const std::vector<unsigned char>& keep) {
+  std::vector<int> deg(n, 0), order;
+  std::vector<char> done(n, 0);
+  std::vector<double> score(n);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j)
       if (i != j && keep[(size_t)i * n + j]) ++deg[i];
-  std::vector<int> order;
-  std::vector<char> seen(n, 0);
+  auto take = [&](int u) {
+    done[u] = 1;
+    order.push_back(u);
+    for (int j = 0; j < n; ++j)
+      if (j != u && keep[(size_t)j * n + u]) --deg[j];
+  };
   while ((int)order.size() < n) {
-    int start = -1;
+    int seed = -1;
     for (int i = 0; i < n; ++i)
-      if (!seen[i] && (start < 0 || deg[i] < deg[start])) start = i;
-    seen[start] = 1;
-    size_t head = order.size();
-    order.push_back(start);
-    while (head < order.size()) {
-      const int u = order[head++];
-      std::vector<int> nbr;
-      for (int v = 0; v < n; ++v)
-        if (!seen[v] && v != u && keep[(size_t)u * n + v]) nbr.push_back(v);
-      std::sort(nbr.begin(), nbr.end(), [&](int a, int b) {
-        return deg[a] != deg[b] ? deg[a] < deg[b] : a < b;
-      });
-      for (int v : nbr) {
-        seen[v] = 1;
-        order.push_back(v);
-      }
+      if (!done[i] && (seed < 0 || deg[i] < deg[seed])) seed = i;
+    take(seed);
+    for (int j = 0; j < n; ++j) score[j] = a[(size_t)j * n + seed];
+    for (int m = 1; m < tile && (int)order.size() < n; ++m) {
+      int best = -1;
+      for (int j = 0; j < n; ++j)
+        if (!done[j] && (best < 0 || score[j] > score[best])) best = j;
+      take(best);
+      for (int j = 0; j < n; ++j) score[j] += a[(size_t)j * n + best];
     }
   }
-  std::reverse(order.begin(), order.end());
   return order;
 }
 
@@ -1142,13 +1144,15 @@ hfx_status hfx_screen(hfx_plan plan, const double* psi, double rho_cut, long lon
       std::vector<double> h((size_t)n * n);
       HIP_TRY(hipMemcpyAsync(h.data(), amat, h.size() * 8, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
-      // A is symmetric up to rounding; decide each unordered pair once
+      // A is symmetric up to rounding: take the upper triangle, so that each
+      // unordered pair is decided once
       for (int a = 0; a < n; ++a)
         for (int b = a; b < n; ++b) {
+          h[(size_t)b * n + a] = h[(size_t)a * n + b];
           const unsigned char k = h[(size_t)a * n + b] >= rho_cut ? 1 : 0;
           keep[(size_t)a * n + b] = keep[(size_t)b * n + a] = k;
         }
-      perm = rcm_order(n, keep);
+      perm = cluster_order(n, sp.var->tile, h, keep);
     } else {
       HIP_TRY(hipStreamSynchronize(st));
     }

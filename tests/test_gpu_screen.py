@@ -2,7 +2,7 @@
 
 The oracle evaluates the screened sums directly: the pairs kept by
 int |phi_a phi_b| >= rho_cut (``oracle.screen_pairs``), each once, in plain
-order.  The GPU plan reorders the orbitals (reverse Cuthill-McKee), drops
+order.  The GPU plan reorders the orbitals (clusters of overlapping orbitals), drops
 whole tile pairs and packs the rest into new batches, so a wrong permutation,
 mask bit or packing shows up as a missing or doubled pair.  rho_cut is put in
 the middle of a wide gap of the oracle's A values, so that both sides keep the
