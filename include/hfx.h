@@ -69,7 +69,7 @@ typedef enum {
 
 typedef enum { HFX_KERNEL_TRUNCATED = 0, HFX_KERNEL_ERFC = 1 } hfx_kernel;
 typedef enum { HFX_FP32 = 0, HFX_FP64 = 1 } hfx_precision;
-typedef enum { HFX_ORTHO_LOWDIN = 0 } hfx_ortho_method;
+typedef enum { HFX_ORTHO_LOWDIN = 0, HFX_ORTHO_CHOLESKY = 1 } hfx_ortho_method;
 
 /* One periodic system. */
 typedef struct {
@@ -95,10 +95,16 @@ typedef struct hfx_plan_t* hfx_plan;
  * r % R == g, one of R virtual groups of the pair list (the way the pairs
  * would be dealt over R GPUs): K psi, E_x, M and the gradient are then that
  * group's partial sums, which add up over g = 0..R-1 to the full result (the
- * G = 0 energy of the pair means is added by group 0).  The environment variable
- * HFX_MAX_WORKSPACE_BYTES also caps the workspace.  Uploads the plan's tables
+ * G = 0 energy of the pair means is added by group 0); mix=<a>, 0 < a <= 1,
+ * is a hybrid functional's exact-exchange fraction: the kernel is scaled by a,
+ * so E_x, K psi, M, the gradient and the ACE operator are a times the full
+ * exchange (default 1).  Open-shell systems are two systems of one plan, the
+ * spin-up and the spin-down orbitals on the same box: pairs never mix spins,
+ * and the total exchange energy is the sum of the two E_x.  The environment
+ * variable HFX_MAX_WORKSPACE_BYTES also caps the workspace.  Uploads the plan's tables
  * (synchronous).  Errors: HFX_EINVAL for null out/sys, n_sys < 1, n <= 0,
- * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0;
+ * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0, a malformed
+ * option value;
  * HFX_EUNSUPPORTED for a non-cubic or unsupported grid size; HFX_EDEVICE or
  * HFX_ENOMEM when device set-up fails.  *out is NULL on failure.
  */
@@ -147,11 +153,13 @@ hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double*
                                  double* grad, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * In-place Loewdin orthonormalisation of psi in float64:
- * Psi <- Psi S^(-1/2), S = dV Psi^T Psi (the occupied Kohn-Sham orbitals on
- * which V_X acts are orthonormal).  S^(-1/2) comes from a coupled
- * Newton-Schulz iteration run to float64 convergence.  method must be
- * HFX_ORTHO_LOWDIN.
+ * In-place orthonormalisation of psi in float64, S = dV Psi^T Psi (the
+ * occupied Kohn-Sham orbitals on which V_X acts are orthonormal):
+ *   HFX_ORTHO_LOWDIN:   Psi <- S^(-1/2) Psi (rows), S^(-1/2) from a coupled
+ *                       Newton-Schulz iteration run to float64 convergence;
+ *   HFX_ORTHO_CHOLESKY: Psi <- L^(-1) Psi with S = L L^T (orbital k mixes only
+ *                       orbitals 0..k); a rank-deficient set gives NaN.
+ * HFX_EINVAL for any other method.
  */
 hfx_status hfx_orthonormalize(hfx_plan plan, double* psi, int method, void* ws,
                               size_t ws_bytes, void* stream);

@@ -1,6 +1,8 @@
 // Adaptively compressed exchange (ACE), Eq. (vx_ace) in the Methods' MTACE
 // subsection: V_X^ACE = - sum_k |P_k><P_k| with P = W L^(-T), W_i = V_X psi_i
-// and -M = L L^T (Cholesky).  Rows of P are the rows of L^(-1) W.
+// and -M = L L^T (Cholesky).  Rows of P are the rows of L^(-1) W.  The same
+// factorisation and inverse give the Cholesky orthonormalisation
+// Psi <- L^(-1) Psi with S = L L^T.
 //
 // The n x n factorisation and the triangular inverse are small (n = N_orb)
 // and run in one workgroup each on the L2-resident matrix; the grid-sized
@@ -18,16 +20,17 @@ namespace {
 constexpr int NT = 1024;
 }
 
-// l <- lower Cholesky factor of -m (n x n, row-major, upper part zeroed).  A
-// pivot that is not positive (-M not positive definite: dependent or zero
-// orbitals) is stored as NaN, so everything built from L is NaN.
-__global__ void __launch_bounds__(NT) k_chol_neg(const double* __restrict__ m, int n,
-                                                 double* __restrict__ l) {
+// l <- lower Cholesky factor of sign * m (n x n, row-major, upper part
+// zeroed).  A pivot that is not positive (sign * m not positive definite:
+// dependent or zero orbitals) is stored as NaN, so everything built from L is
+// NaN.
+__global__ void __launch_bounds__(NT) k_chol(const double* __restrict__ m, int n, double sign,
+                                             double* __restrict__ l) {
   const int tid = threadIdx.x;
   const long long nn = (long long)n * n;
   for (long long e = tid; e < nn; e += NT) {
     const int i = (int)(e / n), k = (int)(e - (long long)i * n);
-    l[e] = k <= i ? -m[e] : 0.0;
+    l[e] = k <= i ? sign * m[e] : 0.0;
   }
   __shared__ double piv;
   __syncthreads();
@@ -86,8 +89,8 @@ __global__ void __launch_bounds__(NT) k_trinv(const double* __restrict__ l, int 
   }
 }
 
-void launch_chol_neg(const double* m, int n, double* l, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_neg, dim3(1), dim3(NT), 0, s, m, n, l);
+void launch_chol(const double* m, int n, double sign, double* l, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(NT), 0, s, m, n, sign, l);
 }
 
 void launch_trinv(const double* l, int n, double* x, hipStream_t s) {

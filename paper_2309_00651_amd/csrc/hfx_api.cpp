@@ -372,7 +372,7 @@ void build_screened_schedule(SystemPlan& sp, const std::vector<unsigned char>& k
 // v(G)/N_r on the FFT grid.  zero_dc: store 0 at G = 0 (float32 plans take the
 // G = 0 term out of the transforms, see run_exchange).
 template <typename T>
-std::vector<T> kernel_table(const hfx_system& s, int n, bool zero_dc) {
+std::vector<T> kernel_table(const hfx_system& s, int n, bool zero_dc, double scale) {
   const double pi = 3.14159265358979323846;
   const double om = s.L[0] * s.L[1] * s.L[2];
   const double nr = (double)n * n * n;
@@ -398,7 +398,7 @@ std::vector<T> kernel_table(const hfx_system& s, int n, bool zero_dc) {
           const double w = s.param;
           v = g2 == 0.0 ? pi / (w * w) : -4 * pi * std::expm1(-g2 / (4 * w * w)) / g2;
         }
-        out[((size_t)z * n + y) * n + x] = T(v / nr);
+        out[((size_t)z * n + y) * n + x] = T(scale * v / nr);
       }
   if (zero_dc) out[0] = T(0);
   return out;
@@ -715,7 +715,7 @@ hfx_status enq_ace_build(hfx_plan plan, SystemPlan& sp, const void* kpsi, const 
   double* pp = p + sp.psi_off;
   const double nn = n, npts = (double)sp.nr;
   Bracket bk(plan, HFX_PASS_ACE_BUILD, st);
-  launch_chol_neg(m + sp.m_off, n, low, st);
+  launch_chol(m + sp.m_off, n, -1.0, low, st);
   launch_trinv(low, n, inv, st);
   launch_scale_to_f64(kp, plan->prec == HFX_FP64 ? 1 : 0, pp, (size_t)n * sp.nr, 1.0, nullptr,
                       st);
@@ -742,7 +742,8 @@ hfx_status enq_ace_apply(hfx_plan plan, SystemPlan& sp, const double* p, const d
   return HFX_OK;
 }
 
-hfx_status enq_ortho(hfx_plan plan, SystemPlan& sp, double* psi, char* ws, hipStream_t st) {
+hfx_status enq_ortho(hfx_plan plan, SystemPlan& sp, double* psi, int method, char* ws,
+                     hipStream_t st) {
   const int n = sp.sys.n_orb;
   double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
   double* work = reinterpret_cast<double*>(ws + sp.off_ortho);
@@ -757,8 +758,17 @@ hfx_status enq_ortho(hfx_plan plan, SystemPlan& sp, double* psi, char* ws, hipSt
     bk.done(nn * npts * 8.0, 2.0 * nn * nn * npts);
   }
   Bracket bk(plan, HFX_PASS_ORTHO, st);
-  HIP_TRY(launch_inverse_sqrt(smat, n, ns_work, 40, st));
-  launch_apply_left(smat, p, n, sp.nr, tmp, st);
+  if (method == HFX_ORTHO_CHOLESKY) {
+    // S = L L^T, Psi <- L^(-1) Psi
+    double* low = work + (size_t)n * n;
+    double* inv = work + (size_t)2 * n * n;
+    launch_chol(smat, n, 1.0, low, st);
+    launch_trinv(low, n, inv, st);
+    launch_apply_left(inv, p, n, sp.nr, tmp, st);
+  } else {
+    HIP_TRY(launch_inverse_sqrt(smat, n, ns_work, 40, st));
+    launch_apply_left(smat, p, n, sp.nr, tmp, st);
+  }
   bk.done(nn * npts * 16.0, 2.0 * nn * nn * npts);
   HIP_TRY(hipGetLastError());
   return HFX_OK;
@@ -841,6 +851,16 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
       shards = std::atoi(sv.substr(slash + 1).c_str());
       if (shards < 1 || shard < 0 || shard >= shards)
         return fail(HFX_EINVAL, "shard=<g>/<R> needs 0 <= g < R");
+    }
+  }
+  double mix = 1.0;
+  {
+    const std::string mv = parse_option_str(options, "mix");
+    if (!mv.empty()) {
+      char* end = nullptr;
+      mix = std::strtod(mv.c_str(), &end);
+      if (end == mv.c_str() || *end != '\0' || !(mix > 0.0 && mix <= 1.0))
+        return fail(HFX_EINVAL, "mix=<a> needs 0 < a <= 1");
     }
   }
   const std::string vname = parse_option_str(options, "variant");
@@ -931,11 +951,13 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
       if (e != hipSuccess)
         return cleanup(fail(HFX_EDEVICE, std::string("kernel set-up: ") + hipGetErrorString(e)));
     }
-    sp.v0 = kernel_g0(sp.sys);
+    // a hybrid mixing fraction scales the kernel, hence E_x, K psi, M and
+    // the gradient alike
+    sp.v0 = mix * kernel_g0(sp.sys);
     if (precision == HFX_FP64)
-      s = upload(kernel_table<double>(sp.sys, sp.n, false), &sp.vtab);
+      s = upload(kernel_table<double>(sp.sys, sp.n, false, mix), &sp.vtab);
     else
-      s = upload(kernel_table<float>(sp.sys, sp.n, true), &sp.vtab);
+      s = upload(kernel_table<float>(sp.sys, sp.n, true, mix), &sp.vtab);
     if (s != HFX_OK) return cleanup(s);
     const Variant* v = sp.var;
     const int* rs[6] = {v->zf, v->zi, v->xf, v->xi, v->yf, v->yi};
@@ -1085,9 +1107,10 @@ hfx_status hfx_orthonormalize(hfx_plan plan, double* psi, int method, void* ws, 
                               void* stream) {
   hfx_status s = check_call(plan, psi, ws, ws_bytes);
   if (s != HFX_OK) return s;
-  if (method != HFX_ORTHO_LOWDIN) return fail(HFX_EUNSUPPORTED, "only Loewdin is implemented");
+  if (method != HFX_ORTHO_LOWDIN && method != HFX_ORTHO_CHOLESKY)
+    return fail(HFX_EINVAL, "unknown orthonormalisation method");
   return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
-    return enq_ortho(plan, plan->sys[i], psi, static_cast<char*>(ws), st);
+    return enq_ortho(plan, plan->sys[i], psi, method, static_cast<char*>(ws), st);
   });
 }
 
@@ -1231,7 +1254,7 @@ hfx_status hfx_graph_create(hfx_plan plan, int op, double* psi, void* kpsi, doub
     SystemPlan& sp = plan->sys[i];
     hfx_status r = HFX_OK;
     if (op == HFX_GRAPH_ENERGY) return enq_energy(plan, sp, psi, ex + i, w, st);
-    if (op == HFX_GRAPH_STEP) r = enq_ortho(plan, sp, psi, w, st);
+    if (op == HFX_GRAPH_STEP) r = enq_ortho(plan, sp, psi, HFX_ORTHO_LOWDIN, w, st);
     if (r == HFX_OK) r = enq_apply(plan, sp, psi, kpsi, ex ? ex + i : nullptr, w, st);
     if (r == HFX_OK && op == HFX_GRAPH_STEP) r = enq_matrix(plan, sp, psi, kpsi, m, w, st);
     return r;

@@ -115,8 +115,8 @@ void launch_apply_left(const double* m, double* psi, int n, long long nr, double
                        hipStream_t st);
 hipError_t prepare_apply_left();
 
-// ACE helpers (ace.hip): l = lower Cholesky factor of -m; x = l^(-1)
-void launch_chol_neg(const double* m, int n, double* l, hipStream_t s);
+// Cholesky helpers (ace.hip): l = lower Cholesky factor of sign * m; x = l^(-1)
+void launch_chol(const double* m, int n, double sign, double* l, hipStream_t s);
 void launch_trinv(const double* l, int n, double* x, hipStream_t s);
 
 }  // namespace hfx

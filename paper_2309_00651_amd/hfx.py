@@ -26,6 +26,7 @@ ERFC = 1
 FP32 = 0
 FP64 = 1
 ORTHO_LOWDIN = 0
+ORTHO_CHOLESKY = 1
 GRAPH_ENERGY = 0
 GRAPH_APPLY = 1
 GRAPH_STEP = 2

@@ -1,0 +1,123 @@
+"""Cells and channels beyond one closed-shell cubic box, against the oracle.
+
+* Orthorhombic boxes (three box lengths, cubic grid): the kernel table and
+  the volume element take each axis' own spacing.
+* Open shell: the spin-up and spin-down orbitals are two systems of one
+  plan; pairs never mix spins and the exchange energy is the sum of the two
+  channels' E_x (each evaluated by the oracle on its own orbitals).
+* Hybrid mixing fraction (plan option mix=a): E_x, K psi, the exchange
+  matrix and the gradient are a times the oracle's full exchange.
+
+Bars as in the parity tests: float32 |dE|/|E| <= 1e-7, max|dK psi| <= 1e-5
+(scaled by a for the mixed plan); float64 1e-12 and 1e-10 max|K psi|.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import generate
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2309_00651_amd import hfx  # noqa: E402
+
+PRECS = [hfx.FP32, hfx.FP64]
+IDS = ["fp32", "fp64"]
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def bars(prec, ref_kpsi, scale=1.0):
+    if prec == hfx.FP32:
+        return 1e-7, 1e-5 * scale
+    return 1e-12, 1e-10 * np.max(np.abs(ref_kpsi))
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=IDS)
+@pytest.mark.parametrize("n,box,kernel,param", [
+    (24, (9.0, 10.5, 12.0), hfx.TRUNCATED, 0.0),
+    (64, (20.0, 23.5, 27.0), hfx.ERFC, 0.106),
+])
+def test_orthorhombic_box(prec, n, box, kernel, param):
+    print(f"case orthorhombic n={n} box={box} prec={prec}", flush=True)
+    shape = (n, n, n)
+    n_orb = 7 if n == 24 else 12
+    psi = generate.random_pw(shape, box, n_orb, 5.0, seed=4400 + n)
+    vg = oracle.coulomb_kernel(shape, box, kernel, param)
+    ref = oracle.exchange(psi, box, vg, workers=4)
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec(n, box, n_orb, kernel, param), prec, device=dev)
+    pt = torch.from_numpy(psi).to(dev)
+    kpsi, ex = plan.apply_exchange(pt)
+    m = plan.exchange_matrix(pt, kpsi)
+    torch.cuda.synchronize()
+    e_bar, k_bar = bars(prec, ref["kpsi"])
+    rel = abs(float(ex[0]) - ref["ex"]) / abs(ref["ex"])
+    dk = np.max(np.abs(kpsi.double().cpu().numpy() - ref["kpsi"]))
+    print(f"  rel dE {rel:.2e} max dK {dk:.2e}", flush=True)
+    assert rel <= e_bar and dk <= k_bar
+    # E_x = tr(M) / 2 with the anisotropic volume element
+    assert abs(0.5 * float(torch.trace(m.view(n_orb, n_orb))) - float(ex[0])) <= \
+        2 * e_bar * abs(ref["ex"])
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=IDS)
+def test_open_shell_two_channels(prec):
+    print(f"case open shell prec={prec}", flush=True)
+    n, L = 24, 10.0
+    shape, box = (n, n, n), (L, L, L)
+    up = generate.random_pw(shape, box, 7, 5.0, seed=4501)
+    down = generate.random_pw(shape, box, 4, 5.0, seed=4502)
+    vg = oracle.coulomb_kernel(shape, box, hfx.ERFC, 0.3)
+    ref_up = oracle.exchange(up, box, vg)
+    ref_down = oracle.exchange(down, box, vg)
+    dev = _dev()
+    plan = hfx.Plan([hfx.SystemSpec(n, box, 7, hfx.ERFC, 0.3),
+                     hfx.SystemSpec(n, box, 4, hfx.ERFC, 0.3)], prec, device=dev)
+    pt = torch.from_numpy(np.concatenate([up, down])).to(dev)
+    kpsi, ex = plan.apply_exchange(pt)
+    torch.cuda.synchronize()
+    k = kpsi.double().cpu().numpy()
+    e_tot = float(ex[0]) + float(ex[1])
+    want = ref_up["ex"] + ref_down["ex"]
+    e_bar, _ = bars(prec, ref_up["kpsi"])
+    assert abs(e_tot - want) <= e_bar * abs(want)
+    for got, ref in ((k[:7], ref_up), (k[7:], ref_down)):
+        _, k_bar = bars(prec, ref["kpsi"])
+        assert np.max(np.abs(got - ref["kpsi"])) <= k_bar
+    # the channels do not interact: the closed-shell 11-orbital exchange differs
+    both = oracle.exchange(np.concatenate([up, down]), box, vg)
+    assert abs(both["ex"] - want) > 1e3 * e_bar * abs(want)
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=IDS)
+def test_mixing_fraction(prec):
+    print(f"case mix=0.25 prec={prec}", flush=True)
+    a, n, L, n_orb = 0.25, 24, 10.0, 6
+    shape, box = (n, n, n), (L, L, L)
+    psi = generate.random_pw(shape, box, n_orb, 5.0, seed=4601)
+    vg = oracle.coulomb_kernel(shape, box, hfx.TRUNCATED, 0.0)
+    ref = oracle.exchange(psi, box, vg)
+    dv = L ** 3 / n ** 3
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec(n, box, n_orb), prec, options="mix=0.25", device=dev)
+    pt = torch.from_numpy(psi).to(dev)
+    kpsi, ex = plan.apply_exchange(pt)
+    e_only = plan.exchange_energy(pt)
+    m = plan.exchange_matrix(pt, kpsi)
+    grad = plan.exchange_gradient(pt)
+    torch.cuda.synchronize()
+    e_bar, k_bar = bars(prec, a * ref["kpsi"], scale=a)
+    assert abs(float(ex[0]) - a * ref["ex"]) <= e_bar * abs(a * ref["ex"])
+    assert abs(float(e_only[0]) - float(ex[0])) <= 1e-13 * abs(float(ex[0]))
+    k = kpsi.double().cpu().numpy()
+    assert np.max(np.abs(k - a * ref["kpsi"])) <= k_bar
+    m_ref = oracle.exchange_matrix(psi, a * ref["kpsi"], dv)
+    assert np.max(np.abs(m.view(n_orb, n_orb).cpu().numpy() - m_ref)) <= \
+        np.sqrt(L ** 3) * k_bar + 1e-12
+    assert np.max(np.abs(grad.cpu().numpy() - 2 * dv * a * ref["kpsi"])) <= 2 * dv * k_bar

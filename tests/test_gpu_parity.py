@@ -202,6 +202,32 @@ def test_orthonormalize_matches_oracle_lowdin(n_orb):
     assert np.max(np.abs(s - np.eye(n_orb))) <= 1e-12
 
 
+@pytest.mark.parametrize("n_orb", [13, 300])
+def test_orthonormalize_matches_oracle_cholesky(n_orb):
+    psi = make_inputs(24, 10.0, n_orb, "pw", seed=5)
+    rng = np.random.default_rng(6)
+    psi = psi + 0.3 * rng.standard_normal(psi.shape) * 0.05
+    dv = 1000.0 / 24 ** 3
+    ref = oracle.cholesky_orthonormalize(psi, dv)
+    dev = _dev()
+    print(f"case cholesky n_orb={n_orb}", flush=True)
+    plan = hfx.Plan(hfx.SystemSpec(24, (10.0,) * 3, n_orb), hfx.FP64, device=dev)
+    pt = torch.from_numpy(psi).to(dev)
+    plan.orthonormalize(pt, method=hfx.ORTHO_CHOLESKY)
+    torch.cuda.synchronize()
+    got = pt.cpu().numpy()
+    d = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"  rel max diff {d:.2e}", flush=True)
+    assert d <= 1e-11
+    s = oracle.overlap(got, dv)
+    assert np.max(np.abs(s - np.eye(n_orb))) <= 1e-12
+    # orbital k is a combination of the input orbitals 0..k only
+    a = psi.reshape(n_orb, -1)
+    k = n_orb // 2
+    coef, *_ = np.linalg.lstsq(a[:k + 1].T, got.reshape(n_orb, -1)[k], rcond=None)
+    assert np.max(np.abs(a[:k + 1].T @ coef - got.reshape(n_orb, -1)[k])) <= 1e-10
+
+
 @pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
 def test_gradient_entry_point(prec):
     psi = make_inputs(24, 10.0, 6, "pw", seed=8)
