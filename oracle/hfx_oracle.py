@@ -193,16 +193,19 @@ def exchange(psi, box, vg, want_kpsi=True, workers=1, keep=None):
     return {"ex": ex, "e": e, "kpsi": kpsi, "dv": dv}
 
 
-def apply_exchange_rows(psi, box, vg, rows):
+def apply_exchange_rows(psi, box, vg, rows, keep=None):
     """K psi_i = -sum_j v_ij psi_j for the selected orbitals only.
 
     Lets a full-size run be checked on a sample of orbitals: each row costs
-    N_orb pair potentials.
+    N_orb pair potentials.  ``keep`` (symmetric boolean, optional) restricts
+    the sum to the kept pairs (i, j), as in ``exchange``.
     """
     psi = np.ascontiguousarray(psi, dtype=np.float64)
     out = np.zeros((len(rows),) + psi.shape[1:])
     for r, i in enumerate(rows):
         for j in range(psi.shape[0]):
+            if keep is not None and not keep[i, j]:
+                continue                      # screened pair (s-MTACE)
             out[r] -= pair_potential(psi[i] * psi[j], vg) * psi[j]
     return out
 

@@ -8,7 +8,13 @@ generators (``workloads/``).  Output ``tests/golden/<name>_oracle.json``:
   samples   K psi values of a few orbitals at seeded grid points
             (orbital index, flat point index, value)
 
-Usage: python tests/golden/make_golden.py water96 [--workers 8]
+With --screen RHO it writes ``<name>_smtace_oracle.json`` instead: the same
+quantities summed over the pairs kept by the s-MTACE criterion
+int |psi_a psi_b| >= rho_cut (``oracle.screen_pairs``), with rho_cut moved to
+the middle of the gap of A values that contains RHO (so that a different
+summation order of A keeps the same pairs), and the number of kept pairs.
+
+Usage: python tests/golden/make_golden.py water96 [--workers 8] [--screen 2.5e-2]
 The workload definitions live in workloads/configs.py; each record stores the
 generator parameters it was made from.
 """
@@ -35,6 +41,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("name")
     ap.add_argument("--workers", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--screen", type=float, default=None)
     a = ap.parse_args()
     s = configs.ALL[a.name]
     t0 = time.time()
@@ -43,22 +50,37 @@ def main():
     psi_o, lam_min = oracle.lowdin(psi, dv)
     del psi
     vg = oracle.coulomb_kernel(s.shape, s.box, s.kernel, s.param)
-    print(f"{s.name}: orthonormalised (min eig S {lam_min:.3e}), running {s.n_pairs} pairs "
+    keep, extra, suffix = None, {}, ""
+    if a.screen is not None:
+        amat = oracle.pair_overlap_abs(psi_o, dv)
+        vals = np.unique(amat[np.triu_indices(s.n_orb)])
+        hi = vals[vals >= a.screen].min()
+        lo = vals[vals < a.screen].max()
+        rho = 0.5 * (lo + hi)
+        keep = oracle.screen_pairs(psi_o, dv, rho)
+        n_keep = int(np.triu(keep).sum())
+        extra = {"rho_cut_requested": a.screen, "rho_cut": rho,
+                 "gap_rel": (hi - lo) / hi, "pairs_kept": n_keep}
+        suffix = "_smtace"
+        print(f"screening at rho_cut {rho:.6e} (gap {(hi - lo) / hi:.2e}): {n_keep} pairs kept",
+              flush=True)
+    print(f"{s.name}: orthonormalised (min eig S {lam_min:.3e}), running "
+          f"{s.n_pairs if keep is None else extra['pairs_kept']} pairs "
           f"on {a.workers} workers", flush=True)
-    res = oracle.exchange(psi_o, s.box, vg, want_kpsi=False, workers=a.workers)
+    res = oracle.exchange(psi_o, s.box, vg, want_kpsi=False, workers=a.workers, keep=keep)
     m_diag = -res["e"].sum(axis=1)
     print(f"E_x = {res['ex']:.15f}  ({time.time() - t0:.0f} s)", flush=True)
     rng = np.random.default_rng(12345)
     pts = rng.choice(psi_o[0].size, size=SAMPLE_POINTS, replace=False)
-    rows = oracle.apply_exchange_rows(psi_o, s.box, vg, list(SAMPLE_ORBITALS))
+    rows = oracle.apply_exchange_rows(psi_o, s.box, vg, list(SAMPLE_ORBITALS), keep=keep)
     samples = [[int(o), int(p), float(rows[k].reshape(-1)[p])]
                for k, o in enumerate(SAMPLE_ORBITALS) for p in pts]
     rec = {"name": s.name, "n": s.n, "L": s.L, "n_orb": s.n_orb, "kernel": s.kernel,
            "param": s.param, "family": s.family, "ecut": s.ecut, "seed": s.seed,
            "orthonormalisation": "Loewdin (oracle eigh)", "min_eig_overlap": lam_min,
            "ex": res["ex"], "m_diag": [float(x) for x in m_diag], "samples": samples,
-           "seconds": time.time() - t0, "workers": a.workers}
-    out = os.path.join(HERE, f"{s.name}_oracle.json")
+           "seconds": time.time() - t0, "workers": a.workers, **extra}
+    out = os.path.join(HERE, f"{s.name}{suffix}_oracle.json")
     with open(out, "w") as f:
         json.dump(rec, f)
     print(f"wrote {out} ({time.time() - t0:.0f} s)", flush=True)

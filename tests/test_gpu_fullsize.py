@@ -103,3 +103,47 @@ def test_grad72_directional_derivatives(prec):
         worst = max(worst, abs(fd - an) / gnorm)
     print(f"  worst |FD - analytic| / (|grad||D|) over 16 directions {worst:.2e}", flush=True)
     assert worst <= (1e-9 if prec == hfx.FP64 else 1e-7)
+
+
+SMTACE = [n for n in ("water96",)
+          if os.path.exists(os.path.join(GOLDEN, f"{n}_smtace_oracle.json"))]
+
+
+@pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("name", SMTACE)
+def test_fullsize_screened_against_oracle(name, prec):
+    """s-MTACE screening at full size (the screened timing of the benchmark):
+    the kept-pair count exactly, E_x, every <psi_i|K psi_i> and sampled K psi
+    of the screened sums, to the bars above."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    with open(os.path.join(GOLDEN, f"{name}_smtace_oracle.json")) as f:
+        g = json.load(f)
+    s = configs.ALL[name]
+    assert (g["n"], g["n_orb"], g["seed"], g["kernel"]) == (s.n, s.n_orb, s.seed, s.kernel)
+    print(f"case {name} screened rho_cut={g['rho_cut']:.6e} prec={prec}", flush=True)
+    dev = torch.device("cuda:0")
+    psi = torch.from_numpy(s.orbitals()).to(dev)
+    plan = hfx.Plan(hfx.SystemSpec(s.n, s.box, s.n_orb, s.kernel, s.param), prec, device=dev)
+    plan.orthonormalize(psi)
+    assert plan.screen(psi, g["rho_cut"]) == [g["pairs_kept"]]
+    kpsi, ex = plan.apply_exchange(psi)
+    m = plan.exchange_matrix(psi, kpsi)
+    torch.cuda.synchronize()
+    rel = abs(float(ex[0]) - g["ex"]) / abs(g["ex"])
+    mdiag = m.view(s.n_orb, s.n_orb).diagonal().cpu().numpy()
+    ref_d = np.array(g["m_diag"])
+    dd = np.max(np.abs(mdiag - ref_d) / np.abs(ref_d))
+    flat = kpsi.view(s.n_orb, -1)
+    got = np.array([float(flat[o, p]) for o, p, _ in g["samples"]])
+    want = np.array([v for _, _, v in g["samples"]])
+    dk = np.max(np.abs(got - want))
+    print(f"  rel dE {rel:.2e}  max rel dM_ii {dd:.2e}  max dK(samples) {dk:.2e}", flush=True)
+    if prec == hfx.FP32:
+        assert rel <= 1e-7
+        assert dd <= 1e-6
+        assert dk <= 1e-5
+    else:
+        assert rel <= 1e-12
+        assert dd <= 1e-11
+        assert dk <= 1e-10 * np.max(np.abs(want))

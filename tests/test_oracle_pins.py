@@ -458,3 +458,19 @@ def test_screening_keeps_symmetric_pairs_and_diagonal(small_system):
     keep = oracle.screen_pairs(psi, dv, float(np.median(a)))
     assert np.array_equal(keep, keep.T)
     assert np.diag(keep).all()
+
+
+def test_screened_rows_match_screened_exchange(small_system):
+    """Rows of K psi summed directly over the kept partners j agree with the
+    pair loop's i <= j sums with symmetric updates; a partial keep makes the
+    two differ from the unscreened rows."""
+    psi, box, vg = small_system
+    dv = box[0] * box[1] * box[2] / psi[0].size
+    a = oracle.pair_overlap_abs(psi, dv)
+    keep = oracle.screen_pairs(psi, dv, float(np.median(a)))
+    assert not keep.all()
+    res = oracle.exchange(psi, box, vg, keep=keep)
+    rows = oracle.apply_exchange_rows(psi, box, vg, list(range(len(psi))), keep=keep)
+    assert np.max(np.abs(rows - res["kpsi"])) <= 1e-13 * np.max(np.abs(rows))
+    full = oracle.apply_exchange_rows(psi, box, vg, list(range(len(psi))))
+    assert np.max(np.abs(full - rows)) > 1e-6 * np.max(np.abs(full))
