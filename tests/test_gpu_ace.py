@@ -29,9 +29,12 @@ def _system(n, L, n_orb, seed):
     return psi
 
 
+# 11 orbitals: one partial 32-block of the blocked Cholesky and inverse;
+# 70: two full blocks, a ragged third and two trailing updates
+@pytest.mark.parametrize("n_orb", [11, 70])
 @pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
-def test_ace_against_oracle(prec):
-    n, L, n_orb = 24, 10.0, 11
+def test_ace_against_oracle(prec, n_orb):
+    n, L = 24, 10.0
     psi = _system(n, L, n_orb, seed=41)
     dv = L ** 3 / n ** 3
     vg = oracle.coulomb_kernel((n,) * 3, (L,) * 3, hfx.TRUNCATED)
