@@ -1185,28 +1185,33 @@ hfx_status hfx_screen(hfx_plan plan, const double* psi, double rho_cut, long lon
         for (int b = a; b < n; ++b) c += keep[(size_t)a * n + b];
       kept[i] = c;
     }
+    // The new schedule goes into a copy; the plan keeps its old schedule and
+    // tables until every new table is on the device.
+    SystemPlan ns = sp;
     if (screened)
-      build_screened_schedule(sp, keep, perm);
+      build_screened_schedule(ns, keep, perm);
     else
-      build_schedule(sp, sp.tiles_cap);
-    // replace the device tables (the stream is idle: synchronised above)
-    for (void* d : {(void*)sp.d_tiles, (void*)sp.d_active, (void*)sp.d_perm, (void*)sp.d_keep})
-      if (d) HIP_TRY(hipFree(d));
-    sp.d_tiles = nullptr;
-    sp.d_active = nullptr;
-    sp.d_perm = nullptr;
-    sp.d_keep = nullptr;
-    void* d = nullptr;
-    if ((s = upload(sp.tiles, &d)) != HFX_OK) return s;
-    sp.d_tiles = static_cast<TileDesc*>(d);
-    if ((s = upload(sp.active, &d)) != HFX_OK) return s;
-    sp.d_active = static_cast<int*>(d);
-    if (screened) {
-      if ((s = upload(perm, &d)) != HFX_OK) return s;
-      sp.d_perm = static_cast<int*>(d);
-      if ((s = upload(keep, &d)) != HFX_OK) return s;
-      sp.d_keep = static_cast<unsigned char*>(d);
+      build_schedule(ns, sp.tiles_cap);
+    void *dt = nullptr, *da = nullptr, *dp = nullptr, *dk = nullptr;
+    if ((s = upload(ns.tiles, &dt)) != HFX_OK || (s = upload(ns.active, &da)) != HFX_OK ||
+        (screened && ((s = upload(perm, &dp)) != HFX_OK || (s = upload(keep, &dk)) != HFX_OK))) {
+      for (void* q : {dt, da, dp, dk})
+        if (q) (void)hipFree(q);
+      return s;
     }
+    // the stream is idle (synchronised above): the old tables can go
+    for (void* q : {(void*)sp.d_tiles, (void*)sp.d_active, (void*)sp.d_perm, (void*)sp.d_keep})
+      if (q) (void)hipFree(q);
+    sp.tiles = std::move(ns.tiles);
+    sp.active = std::move(ns.active);
+    sp.batches = std::move(ns.batches);
+    sp.n_partials = ns.n_partials;
+    sp.tiles_per_batch = ns.tiles_per_batch;
+    sp.slots_per_batch = ns.slots_per_batch;
+    sp.d_tiles = static_cast<TileDesc*>(dt);
+    sp.d_active = static_cast<int*>(da);
+    sp.d_perm = static_cast<int*>(dp);
+    sp.d_keep = static_cast<unsigned char*>(dk);
   }
   return HFX_OK;
 }
@@ -1217,10 +1222,11 @@ hfx_status hfx_schedule_info(hfx_plan plan, int system, long long* info) {
   if (system < 0 || system >= (int)plan->sys.size()) return fail(HFX_EINVAL, "no such system");
   const SystemPlan& sp = plan->sys[system];
   long long pairs = 0;
+  const bool masked = sp.var->tile == 8;  // keep masks exist for 8-orbital tiles
   for (const TileDesc& td : sp.tiles)
     for (int a = 0; a < td.nI; ++a)
       for (int b = 0; b < td.nJ; ++b)
-        if (!(td.diag && b < a) && ((td.keep >> (8 * a + b)) & 1ull)) ++pairs;
+        if (!(td.diag && b < a) && (!masked || ((td.keep >> (8 * a + b)) & 1ull))) ++pairs;
   info[0] = (long long)sp.batches.size();
   info[1] = (long long)sp.tiles.size();
   info[2] = (long long)sp.active.size();

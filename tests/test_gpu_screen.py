@@ -183,3 +183,56 @@ def test_screen_rejects_bad_cut():
     plan = plan_for(64, hfx.FP32)
     with pytest.raises(RuntimeError):
         plan.screen(pt, float("nan"))
+
+
+def test_screened_graph_replays_match_eager():
+    """A graph captured after screening replays the screened schedule: every
+    replay (with eager work and synchronisation between them) equals the
+    eager screened call bitwise."""
+    psi, rho, _, _ = case(64, 9101, 0.3)
+    dev = _dev()
+    pt = torch.from_numpy(psi).to(dev)
+    plan = plan_for(64, hfx.FP32)
+    plan.screen(pt, rho)
+    k_ref, e_ref = plan.apply_exchange(pt)
+    torch.cuda.synchronize()
+    k = torch.empty_like(k_ref)
+    e = torch.empty_like(e_ref)
+    g = plan.graph(hfx.GRAPH_APPLY, pt, kpsi=k, ex=e)
+    for rep in range(3):
+        k.fill_(float("nan"))
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(k, k_ref) and torch.equal(e, e_ref), rep
+        plan.exchange_energy(pt)          # eager work between replays
+        torch.cuda.synchronize()
+    g.close()
+
+
+def test_screened_open_shell_plan():
+    """hfx_screen on a two-system plan screens each system on its own
+    orbitals and reports one kept count per system."""
+    psi, rho, keep, ref = case(64, 9101, 0.3)
+    psi2, rho2, keep2, ref2 = case(61, 9102, 0.5)
+    dev = _dev()
+    # one cut for both systems: the first case's, checked to sit in a gap of
+    # the second system's A as well
+    dv = L ** 3 / psi2[0].size
+    a2 = oracle.pair_overlap_abs(psi2, dv)
+    vals = np.sort(a2[np.triu_indices(61)])
+    lo, hi = vals[vals < rho].max(), vals[vals >= rho].min()
+    assert (hi - lo) / hi > 1e-6 and abs(rho - lo) > 1e-9 * rho and abs(hi - rho) > 1e-9 * rho
+    keep2 = oracle.screen_pairs(psi2, dv, rho)
+    shape, box = (64, 64, 64), (L, L, L)
+    vg = oracle.coulomb_kernel(shape, box, ERFC, W)
+    ref2 = oracle.exchange(psi2, box, vg, keep=keep2, workers=8)
+    plan = hfx.Plan([hfx.SystemSpec(64, box, 64, ERFC, W), hfx.SystemSpec(64, box, 61, ERFC, W)],
+                    hfx.FP32, device=dev)
+    pt = torch.from_numpy(np.concatenate([psi, psi2])).to(dev)
+    kept = plan.screen(pt, rho)
+    assert kept == [int(np.triu(keep).sum()), int(np.triu(keep2).sum())]
+    kpsi, ex = plan.apply_exchange(pt)
+    torch.cuda.synchronize()
+    k = kpsi.double().cpu().numpy()
+    check(ref, float(ex[0]), k[:64], hfx.FP32)
+    check(ref2, float(ex[1]), k[64:], hfx.FP32)
