@@ -103,8 +103,8 @@ typedef struct hfx_plan_t* hfx_plan;
  * and the total exchange energy is the sum of the two E_x.  The environment
  * variable HFX_MAX_WORKSPACE_BYTES also caps the workspace.  Uploads the plan's tables
  * (synchronous).  Errors: HFX_EINVAL for null out/sys, n_sys < 1, n <= 0,
- * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0, a malformed
- * option value;
+ * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0, an unknown
+ * option key or a malformed option value;
  * HFX_EUNSUPPORTED for a non-cubic or unsupported grid size; HFX_EDEVICE or
  * HFX_ENOMEM when device set-up fails.  *out is NULL on failure.
  */

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -145,18 +146,45 @@ std::string parse_option_str(const char* opts, const char* key) {
   return "";
 }
 
-long long parse_option(const char* opts, const char* key, long long def) {
-  if (!opts) return def;
-  const std::string s(opts), k = std::string(key) + "=";
+// Integer option: def when absent; false when present but not a whole
+// non-negative decimal number.
+bool parse_option(const char* opts, const char* key, long long def, long long* out) {
+  *out = def;
+  const std::string v = parse_option_str(opts, key);
+  if (v.empty()) return opts == nullptr || std::string(opts).find(std::string(key) + "=") ==
+                                               std::string::npos;
+  char* end = nullptr;
+  errno = 0;
+  const long long x = std::strtoll(v.c_str(), &end, 10);
+  if (end == v.c_str() || *end != '\0' || errno != 0 || x < 0) return false;
+  *out = x;
+  return true;
+}
+
+// Every key of the option string is one of the known ones.
+bool options_known(const char* opts, std::string* bad) {
+  if (!opts) return true;
+  static const char* known[] = {"tiles", "maxws", "variant", "streams", "shard", "mix"};
+  const std::string s(opts);
   size_t p = 0;
   while (p < s.size()) {
     size_t e = s.find(';', p);
     if (e == std::string::npos) e = s.size();
     const std::string item = s.substr(p, e - p);
-    if (item.compare(0, k.size(), k) == 0) return std::atoll(item.c_str() + k.size());
     p = e + 1;
+    if (item.empty()) continue;
+    const std::string key = item.substr(0, item.find('='));
+    bool ok = item.find('=') != std::string::npos;
+    if (ok) {
+      ok = false;
+      for (const char* k : known) ok = ok || key == k;
+    }
+    if (!ok) {
+      *bad = item;
+      return false;
+    }
   }
-  return def;
+  return true;
 }
 
 // Round-robin (circle method) schedule of orbital blocks: each round lists
@@ -839,7 +867,18 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
                                         " is not supported (system " + std::to_string(i) +
                                         ")");
   }
-  const long long tiles_cap = parse_option(options, "tiles", 0);
+  {
+    std::string bad;
+    if (!options_known(options, &bad))
+      return fail(HFX_EINVAL, "unknown plan option '" + bad + "'");
+  }
+  long long tiles_cap = 0, ws_cap = 0, batch_streams = 1;
+  if (!parse_option(options, "tiles", 0, &tiles_cap))
+    return fail(HFX_EINVAL, "tiles= takes a non-negative integer");
+  if (!parse_option(options, "maxws", 0, &ws_cap))
+    return fail(HFX_EINVAL, "maxws= takes a non-negative integer (bytes)");
+  if (!parse_option(options, "streams", 1, &batch_streams))
+    return fail(HFX_EINVAL, "streams= must be 1 or 2");
   int shard = 0, shards = 1;
   {
     const std::string sv = parse_option_str(options, "shard");
@@ -868,8 +907,6 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     return fail(HFX_EINVAL, "variant= applies to single-system plans only");
   if (!vname.empty() && !find_variant(sys[0].n[0], precision, vname))
     return fail(HFX_EINVAL, "unknown variant '" + vname + "' for this grid and precision");
-  long long ws_cap = parse_option(options, "maxws", 0);
-  const long long batch_streams = parse_option(options, "streams", 1);
   if (batch_streams != 1 && batch_streams != 2)
     return fail(HFX_EINVAL, "streams= must be 1 or 2");
   if (const char* env = std::getenv("HFX_MAX_WORKSPACE_BYTES")) {
