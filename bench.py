@@ -82,8 +82,15 @@ def cpu_baseline(system, psi, seconds_target=10.0):
     oracle.exchange(sub, system.box, vg, workers=cores)
     dt = time.perf_counter() - t0
     pairs = k * (k + 1) // 2
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f
+                          if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": pairs / dt, "unit": "pair-exchange evals/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpus": os.cpu_count(), "cpu_model": model,
             "sample": f"{k} of {system.n_orb} orbitals ({pairs} pairs) of the {system.name} "
                       f"workload, float64, scipy FFT, {cores} worker processes, {dt:.1f} s"}
 
@@ -163,10 +170,10 @@ def bench_batched6(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="water96")
-    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-smtace", action="store_true",
@@ -241,7 +248,7 @@ def main():
         prof = plan.profile_read() if profile else None
         plan.profile(False)
         out = dict(ms=ev_ms / steps, wall_ms=1e3 * wall / steps, prof=prof, ex=float(ex[0]),
-                   m=m, kpsi=kpsi, psi=p)
+                   m=m, kpsi=kpsi, psi=p, describe=plan.describe())
         return out, plan
 
     def time_ace(plan, r, reps=3):
@@ -365,11 +372,13 @@ def main():
              "device_copy_GBps": copy_gbps,
              "pair_pipeline_frac_of_device_copy": exch_frac * HBM_PEAK_GBS / copy_gbps,
              "dominant_frac_of_device_copy": (achieved / copy_gbps) if roof["bound"] == "hbm" else None,
-             "passes": passes, "ex_fp32": r32["ex"], "s_mtace": smtace}
+             "passes": passes, "ex_fp32": r32["ex"], "s_mtace": smtace,
+             "kernel_config_fp32": r32["describe"]}
     if not args.no_fp64:
         log(f"fp64: 1 warm-up + {args.fp64_steps} timed steps")
         r64, _ = run(hfx.FP64, args.fp64_steps, 1, False)
         extra.update({"ms_per_step_fp64": r64["ms"], "ex_fp64": r64["ex"],
+                      "kernel_config_fp64": r64["describe"],
                       "fp32_speedup_vs_fp64": r64["ms"] / ms,
                       "rel_dEx_fp32_vs_fp64": abs(r32["ex"] - r64["ex"]) / abs(r64["ex"])})
         del r64

@@ -113,6 +113,7 @@ struct hfx_plan_t {
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
   hipStream_t cap = nullptr;
+  std::string desc;  // hfx_plan_describe's text
 };
 
 struct hfx_graph_t {
@@ -1251,6 +1252,35 @@ hfx_status hfx_screen(hfx_plan plan, const double* psi, double rho_cut, long lon
     sp.d_keep = static_cast<unsigned char*>(dk);
   }
   return HFX_OK;
+}
+
+const char* hfx_plan_describe(hfx_plan plan, int system) {
+  if (!plan || system < 0 || system >= (int)plan->sys.size()) {
+    (void)fail(HFX_EINVAL, "null plan or no such system");
+    return nullptr;
+  }
+  const SystemPlan& sp = plan->sys[system];
+  const Variant* v = sp.var;
+  auto sched = [](const int* r, int c) {
+    std::string o;
+    for (int i = 0; i < c; ++i) o += (i ? "x" : "") + std::to_string(r[i]);
+    return o;
+  };
+  std::string d = std::string("variant=") + v->name + " n=" + std::to_string(v->n) +
+                  " tile=" + std::to_string(v->tile) + " brick=" + std::to_string(v->brick) +
+                  " z=" + sched(v->zf, v->nzf) + "/" + sched(v->zi, v->nzi) +
+                  " x=" + sched(v->xf, v->nxf) + "/" + sched(v->xi, v->nxi) +
+                  " y=" + sched(v->yf, v->nyf) + "/" + sched(v->yi, v->nyi) +
+                  " threads=" + std::to_string(v->nt_fwd) + "/" +
+                  std::to_string(v->plane_mode == 0 ? v->nt_plane : v->nt_cols) + "/" +
+                  std::to_string(v->nt_acc) + " plane=" +
+                  (v->plane_mode == 0 ? "fused" : "split") +
+                  " tiles_per_batch=" + std::to_string(sp.tiles_per_batch) +
+                  " batches=" + std::to_string(sp.batches.size()) +
+                  " streams=" + std::to_string(sp.nstreams) +
+                  " screened=" + (sp.d_keep ? "yes" : "no");
+  plan->desc = d;
+  return plan->desc.c_str();
 }
 
 hfx_status hfx_schedule_info(hfx_plan plan, int system, long long* info) {

@@ -83,6 +83,8 @@ def load_library(path=None):
     lib.hfx_ace_apply.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.hfx_screen.argtypes = [vp, vp, d, ctypes.POINTER(ctypes.c_longlong), vp, sz, vp]
     lib.hfx_schedule_info.argtypes = [vp, i, ctypes.POINTER(ctypes.c_longlong)]
+    lib.hfx_plan_describe.argtypes = [vp, i]
+    lib.hfx_plan_describe.restype = ctypes.c_char_p
     lib.hfx_graph_create.argtypes = [vp, i, vp, vp, vp, vp, vp, sz, ctypes.POINTER(vp)]
     lib.hfx_graph_launch.argtypes = [vp, vp]
     lib.hfx_graph_destroy.argtypes = [vp]
@@ -293,6 +295,13 @@ class Plan:
         info = (ctypes.c_longlong * 4)()
         _check(_lib.hfx_schedule_info(self._h, int(system), info))
         return tuple(info)
+
+    def describe(self, system=0):
+        """Kernel configuration and schedule of one system, as one line."""
+        d = _lib.hfx_plan_describe(self._h, int(system))
+        if d is None:
+            raise HfxError(1, _lib.hfx_last_error().decode())
+        return d.decode()
 
     def graph(self, op, psi, kpsi=None, ex=None, m=None):
         """Capture one call (GRAPH_ENERGY / GRAPH_APPLY / GRAPH_STEP) for these buffers."""
