@@ -49,6 +49,10 @@ using P108 = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, S
 using P108r = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
                             Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, false,
                             false>;
+// persistent prefetching plane kernel (one plane per compute unit fits)
+using P128pp = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
+                             Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, false,
+                             false, false, true>;
 using P120 = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
                            Sched<12, 10>, Sched<10, 12>, Sched<12, 10>>;
 using P120lp = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
@@ -85,6 +89,7 @@ const Variant* variants_f32(int* count) {
       P120lp::describe("f32-n120-lp"),
       P128::describe("f32-n128"),
       P128lp::describe("f32-n128-lp"),
+      P128pp::describe("f32-n128-pp"),
   };
   *count = (int)(sizeof(v) / sizeof(v[0]));
   return v;

@@ -524,7 +524,15 @@ constexpr int plane_waves_per_eu() {
   return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, bool SW = false>
+// PP (persistent, prefetching): for planes that leave room for one plane per
+// compute unit, a workgroup per compute unit walks the planes of the launch
+// (L, L + grid, ...) with the twiddles staged once, and issues the HBM loads
+// of its next plane before the inverse x transform of the current one, so
+// they are in flight during that transform and the stores of the current
+// plane.  The v(G) loads come first, so waiting for them never waits for the
+// prefetch (one in-order counter tracks the loads).
+template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, bool SW = false,
+          bool PP = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<T, N, NT>())))
 k_plane_conv(PassArgs a) {
   static_assert(!SW || N % 8 == 0, "swizzle needs whole blocks of 8");
@@ -551,20 +559,19 @@ k_plane_conv(PassArgs a) {
   const int total = a.n_active * N;  // planes of this launch, kz-major
   cpx<T>* __restrict__ gbase = static_cast<cpx<T>*>(a.grids);
 
-  const int L = lg;  // plane of this launch, kz-major over the active grids
-  if (L >= total) return;
+  if (lg >= total) return;
   __shared__ TwEntry<T> twxf[tw_slots<T, SXF>()], twyf[tw_slots<T, SYF>()],
       twyi[tw_slots<T, SYI>()], twxi[tw_slots<T, SXI>()];
   stage_twiddles<T, SXF, NT>(twxf, a.tw_xf, tid);  // visible after the first barrier
   stage_twiddles<T, SYF, NT>(twyf, a.tw_yf, tid);
   stage_twiddles<T, SYI, NT>(twyi, a.tw_yi, tid);
   stage_twiddles<T, SXI, NT>(twxi, a.tw_xi, tid);
-  const int kz = L / a.n_active, ai = L - kz * a.n_active;
-  cpx<T>* __restrict__ base = gbase + (long long)a.active[ai] * NR + (long long)kz * N * N;
-  const T* __restrict__ vt = static_cast<const T*>(a.vtab) + (long long)kz * N * N;
-  {
-    // x-forward stage-0 inputs straight from HBM (rows, x contiguous)
-    cpx<T> v[FX::VALS];
+  auto plane_base = [&](int L) {
+    const int kz = L / a.n_active, ai = L - kz * a.n_active;
+    return gbase + (long long)a.active[ai] * NR + (long long)kz * N * N;
+  };
+  // x-forward stage-0 inputs straight from HBM (rows, x contiguous)
+  auto load_rows = [&](const cpx<T>* __restrict__ base, cpx<T>* v) {
 #pragma unroll
     for (int i = 0; i < FX::PER; ++i) {
       if (!FX::valid(tid, i)) continue;
@@ -574,42 +581,56 @@ k_plane_conv(PassArgs a) {
       for (int r = 0; r < SchedInfo<SXF>::first; ++r)
         v[i * SchedInfo<SXF>::first + r] = base[m * N + FX::in_pos(j, r)];
     }
-    cpx<T> o[LXF::VALS];
-    EXF::reg2reg(v, plane, twxf, tid, o);
-    EXF::store_last(o, plane, tid);
-  }
-  __syncthreads();
-  // y forward, multiply by v(G)/N_r, y inverse (hand-over in registers)
-  cpx<T> oy[LY::VALS];
-  EYF::lds2reg(plane, twyf, tid, oy);
-#pragma unroll
-  for (int i = 0; i < LY::PER; ++i) {
-    if (!LY::valid(tid, i)) continue;
-    int m, j;
-    LY::mj(tid, i, m, j);
-#pragma unroll
-    for (int r = 0; r < SchedInfo<SYF>::last; ++r) {
-      const T f = vt[LY::in_pos(j, r) * N + m];
-      oy[i * SchedInfo<SYF>::last + r] = cscale(oy[i * SchedInfo<SYF>::last + r], f);
+  };
+  cpx<T> v[FX::VALS];
+  int L = lg;
+  load_rows(plane_base(L), v);
+  while (true) {
+    cpx<T>* __restrict__ base = plane_base(L);
+    const T* __restrict__ vt = static_cast<const T*>(a.vtab) + (long long)(L / a.n_active) * N * N;
+    {
+      cpx<T> o[LXF::VALS];
+      EXF::reg2reg(v, plane, twxf, tid, o);
+      EXF::store_last(o, plane, tid);
     }
-  }
-  {
-    cpx<T> o[LYI::VALS];
-    EYI::reg2reg(oy, plane, twyi, tid, o);
-    EYI::store_last(o, plane, tid);
-  }
-  __syncthreads();
-  // x inverse, results straight to HBM
-  cpx<T> ox[LXI::VALS];
-  EXI::lds2reg(plane, twxi, tid, ox);
+    __syncthreads();
+    // y forward, multiply by v(G)/N_r, y inverse (hand-over in registers)
+    cpx<T> oy[LY::VALS];
+    EYF::lds2reg(plane, twyf, tid, oy);
 #pragma unroll
-  for (int i = 0; i < LXI::PER; ++i) {
-    if (!LXI::valid(tid, i)) continue;
-    int m, j;
-    LXI::mj(tid, i, m, j);
+    for (int i = 0; i < LY::PER; ++i) {
+      if (!LY::valid(tid, i)) continue;
+      int m, j;
+      LY::mj(tid, i, m, j);
 #pragma unroll
-    for (int r = 0; r < SchedInfo<SXI>::last; ++r)
-      base[m * N + LXI::in_pos(j, r)] = ox[i * SchedInfo<SXI>::last + r];
+      for (int r = 0; r < SchedInfo<SYF>::last; ++r) {
+        const T f = vt[LY::in_pos(j, r) * N + m];
+        oy[i * SchedInfo<SYF>::last + r] = cscale(oy[i * SchedInfo<SYF>::last + r], f);
+      }
+    }
+    const int next = PP ? L + (int)gridDim.x : total;
+    {
+      cpx<T> o[LYI::VALS];
+      EYI::reg2reg(oy, plane, twyi, tid, o);
+      EYI::store_last(o, plane, tid);
+    }
+    __syncthreads();
+    if (PP && next < total) load_rows(plane_base(next), v);
+    // x inverse, results straight to HBM
+    cpx<T> ox[LXI::VALS];
+    EXI::lds2reg(plane, twxi, tid, ox);
+#pragma unroll
+    for (int i = 0; i < LXI::PER; ++i) {
+      if (!LXI::valid(tid, i)) continue;
+      int m, j;
+      LXI::mj(tid, i, m, j);
+#pragma unroll
+      for (int r = 0; r < SchedInfo<SXI>::last; ++r)
+        base[m * N + LXI::in_pos(j, r)] = ox[i * SchedInfo<SXI>::last + r];
+    }
+    if (next >= total) break;
+    L = next;
+    __syncthreads();  // this plane's LDS reads end before the next plane's writes
   }
 }
 
@@ -761,15 +782,29 @@ template <typename T, int N, int W, int TT, class SZF, class SZI, int NTQ, class
           class SYF, class SYI, bool SW = false,
           int NTF = pencil_threads<T, N, W, true>(), int NTI = pencil_threads<T, N, W, false>(),
           bool PJL = pencil_prefetch<T, N, W>(), bool PF = pencil_prefetch<T, N, W>(),
-          bool PIL = false>
+          bool PIL = false, bool PP = false>
 struct FusedPipeline {
   static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
+  // persistent plane kernel: one workgroup per plane slot of the device
+  static int plane_grid(int planes) {
+    if (!PP) return planes;
+    static const int slots = [] {
+      int d = 0, cu = 0;
+      if (hipGetDevice(&d) != hipSuccess ||
+          hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess ||
+          cu <= 0)
+        cu = 256;
+      const int per_cu = (int)((160 * 1024) / (lds + 4096));
+      return cu * (per_cu > 0 ? per_cu : 1);
+    }();
+    return planes < slots ? planes : slots;
+  }
   static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL>), dim3(nb), dim3(NTF), 0, s, a);
   }
   static void plane(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW>), dim3(nb), dim3(NTQ), lds,
-                       s, a);
+    hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP>), dim3(plane_grid(nb)),
+                       dim3(NTQ), lds, s, a);
   }
   static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF>), dim3(nb), dim3(NTI), 0, s, a);
@@ -779,7 +814,7 @@ struct FusedPipeline {
   }
   static hipError_t prepare() {
     return hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW>),
+        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
   static Variant describe(const char* name) {

@@ -14,7 +14,15 @@ int |psi_a psi_b| >= rho_cut (``oracle.screen_pairs``), with rho_cut moved to
 the middle of the gap of A values that contains RHO (so that a different
 summation order of A keeps the same pairs), and the number of kept pairs.
 
+With --rows I,J,... it writes ``<name>_rows_oracle.json`` instead, for
+workloads too large for the full pair loop: K psi of the listed orbitals only
+(each row sums over all partners, ``oracle.apply_exchange_rows``), evaluated
+on the raw generated orbitals (no orthonormalisation, as the batched
+benchmark runs them), with <psi_i|K psi_i> of those rows and K psi at seeded
+sample points.
+
 Usage: python tests/golden/make_golden.py water96 [--workers 8] [--screen 2.5e-2]
+       python tests/golden/make_golden.py large128 --rows 0,1,255,511 [--workers 4]
 The workload definitions live in workloads/configs.py; each record stores the
 generator parameters it was made from.
 """
@@ -42,8 +50,12 @@ def main():
     ap.add_argument("name")
     ap.add_argument("--workers", type=int, default=os.cpu_count() or 1)
     ap.add_argument("--screen", type=float, default=None)
+    ap.add_argument("--rows", default=None)
     a = ap.parse_args()
     s = configs.ALL[a.name]
+    if a.rows is not None:
+        rows_mode(s, [int(r) for r in a.rows.split(",")], a.workers)
+        return
     t0 = time.time()
     psi = s.orbitals()
     dv = oracle.volume(s.box) / psi[0].size
@@ -84,6 +96,40 @@ def main():
     with open(out, "w") as f:
         json.dump(rec, f)
     print(f"wrote {out} ({time.time() - t0:.0f} s)", flush=True)
+
+
+_ROWS = {}  # inputs of the row jobs, inherited by the forked workers
+
+
+def _row_job(i):
+    return oracle.apply_exchange_rows(_ROWS["psi"], _ROWS["box"], _ROWS["vg"], [i])[0]
+
+
+def rows_mode(s, rows, workers):
+    import multiprocessing as mp
+    t0 = time.time()
+    psi = s.orbitals()
+    dv = oracle.volume(s.box) / psi[0].size
+    vg = oracle.coulomb_kernel(s.shape, s.box, s.kernel, s.param)
+    print(f"{s.name}: {len(rows)} rows of {s.n_orb} partners each on {workers} workers",
+          flush=True)
+    _ROWS.update(psi=psi, box=s.box, vg=vg)
+    with mp.get_context("fork").Pool(max(1, min(workers, len(rows)))) as pool:
+        out = pool.map(_row_job, rows)
+    rng = np.random.default_rng(12345)
+    pts = rng.choice(psi[0].size, size=SAMPLE_POINTS, replace=False)
+    samples = [[int(i), int(p), float(out[k].reshape(-1)[p])]
+               for k, i in enumerate(rows) for p in pts]
+    m_diag = [float(dv * np.sum(psi[i] * out[k])) for k, i in enumerate(rows)]
+    rec = {"name": s.name, "n": s.n, "L": s.L, "n_orb": s.n_orb, "kernel": s.kernel,
+           "param": s.param, "family": s.family, "ecut": s.ecut, "seed": s.seed,
+           "orthonormalisation": "none (raw generated orbitals)", "rows": rows,
+           "m_diag_rows": m_diag, "samples": samples, "seconds": time.time() - t0,
+           "workers": workers}
+    path = os.path.join(HERE, f"{s.name}_rows_oracle.json")
+    with open(path, "w") as f:
+        json.dump(rec, f)
+    print(f"wrote {path} ({time.time() - t0:.0f} s)", flush=True)
 
 
 if __name__ == "__main__":

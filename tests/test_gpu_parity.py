@@ -287,6 +287,21 @@ def test_every_compiled_variant():
                 check(ref, got, prec, L, psi)
 
 
+def test_persistent_plane_variant_walks_many_planes():
+    """The persistent plane kernel (one workgroup per compute unit looping
+    over planes, next plane prefetched): with 6 orbitals at 128^3 a launch
+    holds ~1500 planes, several per workgroup, so the loop and its prefetch
+    run; results equal the oracle's and the default variant's to the bars."""
+    n, L, n_orb = 128, 29.6, 6
+    if "f32-n128-pp" not in hfx.variants(n, hfx.FP32):
+        pytest.skip("variant not compiled")
+    psi = make_inputs(n, L, n_orb, "g", seed=4128)
+    print(f"case persistent plane n={n} n_orb={n_orb}", flush=True)
+    ref = oracle_run(psi, L, hfx.TRUNCATED, 0.0)
+    got = gpu_run(psi, L, hfx.TRUNCATED, 0.0, hfx.FP32, options="variant=f32-n128-pp")
+    check(ref, got, hfx.FP32, L, psi)
+
+
 def test_unknown_variant_rejected():
     _dev()
     with pytest.raises(hfx.HfxError) as e:

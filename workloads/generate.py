@@ -22,8 +22,10 @@ Every orbital is scaled to unit norm dV sum psi^2 = 1.  Arrays are float64
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft as sfft
 
 __all__ = ["random_pw", "gaussians", "ifft_real"]
 
@@ -46,7 +48,7 @@ def _gvecs(shape, box):
 
 def ifft_real(coef):
     """psi(r_n) = sum_G c(G) exp(i G r_n) for Hermitian c; returns the real part."""
-    out = np.fft.ifftn(coef) * coef.size
+    out = sfft.ifftn(coef, workers=os.cpu_count() or 1) * coef.size
     return np.ascontiguousarray(out.real)
 
 
@@ -95,8 +97,13 @@ def gaussians(shape, box, n_orb, ecut, seed, s_lo=1.2, s_hi=1.8):
     dv = box[0] * box[1] * box[2] / float(np.prod(shape))
     out = np.empty((n_orb,) + tuple(shape))
     for o in range(n_orb):
+        # exp(-s^2 G^2 / 2) exp(-i G.R) factorises over the three axes
         rx, ry, rz = centres[o]
-        phase = np.exp(-1j * (gx * rx + gy * ry + gz * rz))
-        coef = np.where(inside, np.exp(-0.5 * widths[o] ** 2 * g2) * phase, 0.0)
+        s2 = 0.5 * widths[o] ** 2
+        fx = np.exp(-s2 * gx ** 2 - 1j * gx * rx)
+        fy = np.exp(-s2 * gy ** 2 - 1j * gy * ry)
+        fz = np.exp(-s2 * gz ** 2 - 1j * gz * rz)
+        coef = (fz * fy) * fx
+        coef[~inside] = 0.0
         out[o] = ifft_real(coef)
     return _normalise(out, dv), centres, widths
