@@ -69,31 +69,35 @@ __device__ __forceinline__ void stage_twiddles(TwEntry<T>* dst, const void* src,
   for (int i = tid; i < SchedInfo<S>::tw_count(); i += NT) dst[i] = s[i];
 }
 
-// Orbital index of tile position p (screened plans reorder the orbitals).
+// Orbital index of tile position p: screened plans (SCR) reorder the
+// orbitals; unscreened plans keep the identity and compile without the table.
+template <bool SCR>
 __device__ __forceinline__ int orb_at(const PassArgs& a, int p) {
-  return a.perm ? a.perm[p] : p;
+  if constexpr (SCR) return a.perm[p];
+  return p;
 }
 
 // Whether pair (a, b) of a tile is evaluated: inside the blocks, a <= b on a
-// diagonal tile, and kept by the screening mask (8-orbital tiles).
-template <int TT>
+// diagonal tile, and, in screened plans, kept by the tile's mask (8-orbital
+// tiles).  Unscreened plans compile without the mask tests.
+template <int TT, bool SCR>
 __device__ __forceinline__ bool pair_live(const TileDesc& td, int ia, int b) {
   if (b >= td.nJ || (td.diag && b < ia)) return false;
-  if constexpr (TT == 8) return (td.keep >> (8 * ia + b)) & 1ull;
+  if constexpr (SCR && TT == 8) return (td.keep >> (8 * ia + b)) & 1ull;
   return true;
 }
 
 // scale * (pair-density mean) for the TT x TT pairs of a tile, [a][b], zero
 // outside the tile or without means (float64 plans): staged in LDS so that
 // the loops below issue no global loads besides their own data.
-template <typename T, int TT, int NT>
+template <typename T, int TT, int NT, bool SCR>
 __device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const TileDesc& td,
                                             double scale, int tid) {
   for (int q = tid; q < TT * TT; q += NT) {
     const int ia = q / TT, b = q - ia * TT;
     dst[q] = (a.mean && ia < td.nI && b < td.nJ)
-                 ? (T)(scale * a.mean[(long long)orb_at(a, td.i0 + ia) * a.n_orb +
-                                      orb_at(a, td.j0 + b)])
+                 ? (T)(scale * a.mean[(long long)orb_at<SCR>(a, td.i0 + ia) * a.n_orb +
+                                      orb_at<SCR>(a, td.j0 + b)])
                  : T(0);
   }
 }
@@ -110,7 +114,7 @@ __device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const Til
 // HBM stores are never waited for (one in-order counter tracks loads and
 // stores, so a later load would wait for them).  Without PIL, psi_a is loaded
 // per orbital.
-template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL>
+template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL, bool SCR>
 __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
   constexpr int W2 = 2 * W;
@@ -135,7 +139,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   const TileDesc td = a.tiles[t];
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
   stage_twiddles<T, SZF, NT>(twl, a.tw_zf, tid);
-  stage_means<T, TT, NT>(mul, a, td, 1.0, tid);
+  stage_means<T, TT, NT, SCR>(mul, a, td, 1.0, tid);
   const TwEntry<T>* tw = twl;
   cpx<T>* __restrict__ grids = static_cast<cpx<T>*>(a.grids);
 
@@ -169,11 +173,11 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
     T xj[4][PT], xi[PIL ? 4 : 1][PT];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const T* pb = psi + (long long)orb_at(a, td.j0 + (b0 + q < td.nJ ? b0 + q : 0)) * NR;
+      const T* pb = psi + (long long)orb_at<SCR>(a, td.j0 + (b0 + q < td.nJ ? b0 + q : 0)) * NR;
 #pragma unroll
       for (int k = 0; k < PT; ++k) xj[q][k] = pb[offA[k]];
       if constexpr (PIL) {
-        const T* pa = psi + (long long)orb_at(a, td.i0 + (b0 + q < td.nI ? b0 + q : 0)) * NR;
+        const T* pa = psi + (long long)orb_at<SCR>(a, td.i0 + (b0 + q < td.nI ? b0 + q : 0)) * NR;
 #pragma unroll
         for (int k = 0; k < PT; ++k) xi[q][k] = pa[offA[k]];
       }
@@ -195,15 +199,15 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
 #pragma unroll
       for (int k = 0; k < PT; ++k) pa[k] = pil[(ia * PT + k) * NT + tid];
     } else {
-      const T* pa_ptr = psi + (long long)orb_at(a, td.i0 + ia) * NR;
+      const T* pa_ptr = psi + (long long)orb_at<SCR>(a, td.i0 + ia) * NR;
 #pragma unroll
       for (int k = 0; k < PT; ++k) pa[k] = vA[k] ? pa_ptr[offA[k]] : T(0);
     }
     static_for<0, TT / 4>([&](auto bq) {
       constexpr int b0 = 4 * decltype(bq)::value;  // pairs (a, b0 .. b0 + 3), grids 2bq, 2bq+1
       // grid g carries pairs (a, b0 + 2g) and (a, b0 + 2g + 1)
-      const bool use0 = pair_live<TT>(td, ia, b0) || pair_live<TT>(td, ia, b0 + 1);
-      const bool use1 = pair_live<TT>(td, ia, b0 + 2) || pair_live<TT>(td, ia, b0 + 3);
+      const bool use0 = pair_live<TT, SCR>(td, ia, b0) || pair_live<TT, SCR>(td, ia, b0 + 1);
+      const bool use1 = pair_live<TT, SCR>(td, ia, b0 + 2) || pair_live<TT, SCR>(td, ia, b0 + 3);
       if (!use0 && !use1) return;
       // pair-density means (float32 plans): transforms see zero-mean densities
       T mu[4], on[4];
@@ -212,7 +216,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
         mu[q] = mul[ia * TT + b0 + q];
         // pairs not evaluated (screened, or below the diagonal) transform as
         // zeros, so they add no rounding to the pair sharing their grid
-        on[q] = pair_live<TT>(td, ia, b0 + q) ? T(1) : T(0);
+        on[q] = pair_live<TT, SCR>(td, ia, b0 + q) ? T(1) : T(0);
       }
 #pragma unroll
       for (int k = 0; k < PT; ++k)
@@ -257,7 +261,8 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
 // one grid pair is transformed the loads of the next one are in flight
 // (second register buffer), and the next orbital's psi and old K psi values
 // are loaded one step ahead.
-template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC, bool PJL, bool PF>
+template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC, bool PJL, bool PF,
+          bool SCR>
 __global__ void __launch_bounds__(NT)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_inv_acc(PassArgs a) {
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
@@ -286,7 +291,7 @@ __global__ void __launch_bounds__(NT)
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
   T* __restrict__ kpsi = static_cast<T*>(a.kpsi);
   stage_twiddles<T, SZI, NT>(twl, a.tw_zi, tid);
-  stage_means<T, TT, NT>(dcl, a, td, a.v0, tid);
+  stage_means<T, TT, NT, SCR>(dcl, a, td, a.v0, tid);
   __syncthreads();
   const TwEntry<T>* tw = twl;
   const cpx<T>* __restrict__ grids = static_cast<const cpx<T>*>(a.grids);
@@ -324,7 +329,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const bool bv = b0 + q < td.nJ;
-      const T* pb = psi + (long long)orb_at(a, td.j0 + (bv ? b0 + q : 0)) * NR;
+      const T* pb = psi + (long long)orb_at<SCR>(a, td.j0 + (bv ? b0 + q : 0)) * NR;
 #pragma unroll
       for (int k = 0; k < PT; ++k) x[q][k] = pb[offA[k]];
     }
@@ -350,8 +355,8 @@ __global__ void __launch_bounds__(NT)
   // grid pair bq of orbital a carries pairs (a, 4bq .. 4bq + 3)
   auto uses = [&](int ia, int bq, bool& u0, bool& u1) {
     const int b0 = 4 * bq;
-    u0 = pair_live<TT>(td, ia, b0) || pair_live<TT>(td, ia, b0 + 1);
-    u1 = pair_live<TT>(td, ia, b0 + 2) || pair_live<TT>(td, ia, b0 + 3);
+    u0 = pair_live<TT, SCR>(td, ia, b0) || pair_live<TT, SCR>(td, ia, b0 + 1);
+    u1 = pair_live<TT, SCR>(td, ia, b0 + 2) || pair_live<TT, SCR>(td, ia, b0 + 3);
   };
   // Loads below are issued unconditionally and their values used as loaded:
   // masked-off lanes read a valid dummy address (data written earlier in the
@@ -376,7 +381,7 @@ __global__ void __launch_bounds__(NT)
   };
   // psi and old K psi of orbital a at the thread's points (offA = 0 off the grid)
   auto load_orbital = [&](int ia, T* p, T* ko) {
-    const int oa = orb_at(a, td.i0 + ia);
+    const int oa = orb_at<SCR>(a, td.i0 + ia);
     const T* pa_ptr = psi + (long long)oa * NR;
     const T* ka = kpsi + (long long)oa * NR;
 #pragma unroll
@@ -411,7 +416,7 @@ __global__ void __launch_bounds__(NT)
       if (!(gq == 0 ? use0 : use1)) return;
       // weight of e_ab in sum_{i,j} e_ij: 2 for a != b, 1 for a == b, 0 for
       // pairs not evaluated
-      if (!pair_live<TT>(td, ia, b)) return;
+      if (!pair_live<TT, SCR>(td, ia, b)) return;
       const int w = (td.diag && b == ia) ? 1 : 2;
       // G = 0 part of v_ab when the mean was taken out of the transform;
       // its energy v0 * Omega * mu_ab^2 is added in float64 at the reduction
@@ -435,7 +440,7 @@ __global__ void __launch_bounds__(NT)
 
   auto store_orbital = [&](int ia) {
     if constexpr (ACC) {
-      T* ka = kpsi + (long long)orb_at(a, td.i0 + ia) * NR;
+      T* ka = kpsi + (long long)orb_at<SCR>(a, td.i0 + ia) * NR;
 #pragma unroll
       for (int k = 0; k < PT; ++k)
         if (vA[k]) ka[offA[k]] = kold[k] + acca[k];
@@ -494,13 +499,13 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const bool bv = b0 + q < td.nJ;
-        const T* kb = kpsi + (long long)orb_at(a, td.j0 + (bv ? b0 + q : 0)) * NR;
+        const T* kb = kpsi + (long long)orb_at<SCR>(a, td.j0 + (bv ? b0 + q : 0)) * NR;
 #pragma unroll
         for (int k = 0; k < PT; ++k) old[q][k] = kb[offA[k]];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        T* kb = kpsi + (long long)orb_at(a, td.j0 + (b0 + q < td.nJ ? b0 + q : 0)) * NR;
+        T* kb = kpsi + (long long)orb_at<SCR>(a, td.j0 + (b0 + q < td.nJ ? b0 + q : 0)) * NR;
 #pragma unroll
         for (int k = 0; k < PT; ++k)
           if (b0 + q < td.nJ && vA[k]) kb[offA[k]] = old[q][k] + accJ[b0 + q][k];
@@ -800,17 +805,30 @@ struct FusedPipeline {
     return planes < slots ? planes : slots;
   }
   static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL>), dim3(nb), dim3(NTF), 0, s, a);
+    if (a.perm)
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true>), dim3(nb), dim3(NTF), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false>), dim3(nb), dim3(NTF), 0, s, a);
   }
   static void plane(const PassArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP>), dim3(plane_grid(nb)),
                        dim3(NTQ), lds, s, a);
   }
   static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF>), dim3(nb), dim3(NTI), 0, s, a);
+    if (a.perm)
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, true>), dim3(nb), dim3(NTI), 0,
+                         s, a);
+    else
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, false>), dim3(nb), dim3(NTI),
+                         0, s, a);
   }
   static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF>), dim3(nb), dim3(NTI), 0, s, a);
+    if (a.perm)
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, true>), dim3(nb), dim3(NTI), 0,
+                         s, a);
+    else
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, false>), dim3(nb), dim3(NTI),
+                         0, s, a);
   }
   static hipError_t prepare() {
     return hipFuncSetAttribute(
@@ -855,7 +873,10 @@ template <typename T, int N, int W, int NTC, int TT, class SZF, class SZI, int R
 struct SplitPipeline {
   static constexpr size_t lds = (size_t)RW * (N + 1) * sizeof(cpx<T>);
   static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL>), dim3(nb), dim3(NTF), 0, s, a);
+    if (a.perm)
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true>), dim3(nb), dim3(NTF), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false>), dim3(nb), dim3(NTF), 0, s, a);
   }
   static void rows_fwd(const PassArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXF, false>), dim3(nb), dim3(NTQ), lds, s, a);
@@ -867,10 +888,20 @@ struct SplitPipeline {
     hipLaunchKernelGGL((k_cols_conv<T, N, W, NTC, SYF, SYI>), dim3(nb), dim3(NTC), 0, s, a);
   }
   static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF>), dim3(nb), dim3(NTI), 0, s, a);
+    if (a.perm)
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, true>), dim3(nb), dim3(NTI), 0,
+                         s, a);
+    else
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, false>), dim3(nb), dim3(NTI),
+                         0, s, a);
   }
   static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF>), dim3(nb), dim3(NTI), 0, s, a);
+    if (a.perm)
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, true>), dim3(nb), dim3(NTI), 0,
+                         s, a);
+    else
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, false>), dim3(nb), dim3(NTI),
+                         0, s, a);
   }
   static hipError_t prepare() {
     hipError_t e = hipFuncSetAttribute(
