@@ -746,10 +746,16 @@ hfx_status enq_ace_build(hfx_plan plan, SystemPlan& sp, const void* kpsi, const 
   Bracket bk(plan, HFX_PASS_ACE_BUILD, st);
   launch_chol(m + sp.m_off, n, -1.0, low, st);
   launch_trinv(low, n, inv, st);
-  launch_scale_to_f64(kp, plan->prec == HFX_FP64 ? 1 : 0, pp, (size_t)n * sp.nr, 1.0, nullptr,
-                      st);
-  launch_apply_left(inv, pp, n, sp.nr, tmp, st);
-  bk.done(nn * npts * (elem + 8.0 + 16.0), 2.0 * nn * nn * npts);
+  if (plan->prec == HFX_FP64) {
+    // P = X W straight from the float64 K psi
+    launch_apply_left(inv, reinterpret_cast<const double*>(kp), pp, n, sp.nr, tmp, st);
+    bk.done(nn * npts * 16.0, 2.0 * nn * nn * npts);
+  } else {
+    // float32 K psi: widen into P, then P <- X P in place
+    launch_scale_to_f64(kp, 0, pp, (size_t)n * sp.nr, 1.0, nullptr, st);
+    launch_apply_left(inv, pp, pp, n, sp.nr, tmp, st);
+    bk.done(nn * npts * (elem + 8.0 + 16.0), 2.0 * nn * nn * npts);
+  }
   HIP_TRY(hipGetLastError());
   return HFX_OK;
 }
@@ -764,9 +770,8 @@ hfx_status enq_ace_apply(hfx_plan plan, SystemPlan& sp, const double* p, const d
   const double nn = n, npts = (double)sp.nr;
   Bracket bk(plan, HFX_PASS_ACE_APPLY, st);
   launch_xtx_f64(phi + sp.psi_off, p + sp.psi_off, n, sp.nr, -sp.dv, part, g, st);
-  launch_scale_to_f64(p + sp.psi_off, 1, out + sp.psi_off, (size_t)n * sp.nr, 1.0, nullptr, st);
-  launch_apply_left(g, out + sp.psi_off, n, sp.nr, tmp, st);
-  bk.done(nn * npts * 8.0 * 5.0, 4.0 * nn * nn * npts);
+  launch_apply_left(g, p + sp.psi_off, out + sp.psi_off, n, sp.nr, tmp, st);
+  bk.done(nn * npts * 8.0 * 4.0, 4.0 * nn * nn * npts);
   HIP_TRY(hipGetLastError());
   return HFX_OK;
 }
@@ -793,10 +798,10 @@ hfx_status enq_ortho(hfx_plan plan, SystemPlan& sp, double* psi, int method, cha
     double* inv = work + (size_t)2 * n * n;
     launch_chol(smat, n, 1.0, low, st);
     launch_trinv(low, n, inv, st);
-    launch_apply_left(inv, p, n, sp.nr, tmp, st);
+    launch_apply_left(inv, p, p, n, sp.nr, tmp, st);
   } else {
     HIP_TRY(launch_inverse_sqrt(smat, n, ns_work, 40, st));
-    launch_apply_left(smat, p, n, sp.nr, tmp, st);
+    launch_apply_left(smat, p, p, n, sp.nr, tmp, st);
   }
   bk.done(nn * npts * 16.0, 2.0 * nn * nn * npts);
   HIP_TRY(hipGetLastError());

@@ -258,7 +258,8 @@ hipError_t launch_inverse_sqrt(double* s, int n, double* work, int max_iter, hip
 // the same order.
 template <int BM, int CB>
 __global__ void __launch_bounds__(256) k_apply_left(const double* __restrict__ m, int n,
-                                                    double* __restrict__ psi, long long nr) {
+                                                    const double* src, double* dst,
+                                                    long long nr) {
   constexpr int BN = CB / 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* blk = reinterpret_cast<double*>(smem_raw);  // [k][CB + 2], k < npad
@@ -280,9 +281,9 @@ __global__ void __launch_bounds__(256) k_apply_left(const double* __restrict__ m
       const int k = e / PR, cc = 2 * (e - k * PR);
       v[u] = double2{0.0, 0.0};
       if (e < total && k < n && c0 + cc + 1 < nr) {
-        v[u] = *reinterpret_cast<const double2*>(psi + (long long)k * nr + c0 + cc);
+        v[u] = *reinterpret_cast<const double2*>(src + (long long)k * nr + c0 + cc);
       } else if (e < total && k < n && c0 + cc < nr) {
-        v[u].x = psi[(long long)k * nr + c0 + cc];
+        v[u].x = src[(long long)k * nr + c0 + cc];
       }
     }
 #pragma unroll
@@ -349,35 +350,37 @@ __global__ void __launch_bounds__(256) k_apply_left(const double* __restrict__ m
       for (int i = 0; i < 4; ++i) {
         const int row = (wave + 4 * p) * 16 + g + 4 * i;
         const long long col = c0 + 16 * q + lr;
-        if (row < n && col < nr) psi[(long long)row * nr + col] = acc[p][q][i];
+        if (row < n && col < nr) dst[(long long)row * nr + col] = acc[p][q][i];
       }
 }
 
-// psi <- m psi (n x n times n x nr).  n <= 512: in place (k_apply_left);
-// larger n: column chunks through tmp (n x 32768 doubles) and a copy back.
-void launch_apply_left(const double* m, double* psi, int n, long long nr, double* tmp,
-                       hipStream_t st) {
+// dst <- m src (n x n times n x nr; dst == src allowed: each workgroup reads
+// its whole column block before writing it).  n <= 512: one pass
+// (k_apply_left); larger n: column chunks through tmp (n x 32768 doubles)
+// and a copy to dst.
+void launch_apply_left(const double* m, const double* src, double* dst, int n, long long nr,
+                       double* tmp, hipStream_t st) {
   if (n <= 256) {
     constexpr int CB = 32;
     const size_t lds = (size_t)((n + 15) / 16 * 16) * (CB + 2) * 8;
     hipLaunchKernelGGL((k_apply_left<4, CB>), dim3((unsigned)((nr + CB - 1) / CB)), dim3(256),
-                       lds, st, m, n, psi, nr);
+                       lds, st, m, n, src, dst, nr);
     return;
   }
   if (n <= 512) {
     constexpr int CB = 16;
     const size_t lds = (size_t)((n + 15) / 16 * 16) * (CB + 2) * 8;
     hipLaunchKernelGGL((k_apply_left<8, CB>), dim3((unsigned)((nr + CB - 1) / CB)), dim3(256),
-                       lds, st, m, n, psi, nr);
+                       lds, st, m, n, src, dst, nr);
     return;
   }
   const long long cc = 32768;
   for (long long c0 = 0; c0 < nr; c0 += cc) {
     const long long w = c0 + cc <= nr ? cc : nr - c0;
-    gemm_nn(m, n, psi + c0, nr, tmp, w, n, w, n, 1.0, nullptr, st);
+    gemm_nn(m, n, src + c0, nr, tmp, w, n, w, n, 1.0, nullptr, st);
     const long long tot = (long long)n * w;
     hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, tmp,
-                       n, w, psi, nr, c0);
+                       n, w, dst, nr, c0);
   }
 }
 
