@@ -750,8 +750,11 @@ hfx_status enq_ace_build(hfx_plan plan, SystemPlan& sp, const void* kpsi, const 
     // P = X W straight from the float64 K psi
     launch_apply_left(inv, reinterpret_cast<const double*>(kp), pp, n, sp.nr, tmp, st);
     bk.done(nn * npts * 16.0, 2.0 * nn * nn * npts);
+  } else if (launch_apply_left_f32(inv, reinterpret_cast<const float*>(kp), pp, n, sp.nr, st)) {
+    // float32 K psi widened while staged
+    bk.done(nn * npts * (elem + 8.0), 2.0 * nn * nn * npts);
   } else {
-    // float32 K psi: widen into P, then P <- X P in place
+    // larger sets: widen into P, then P <- X P in place
     launch_scale_to_f64(kp, 0, pp, (size_t)n * sp.nr, 1.0, nullptr, st);
     launch_apply_left(inv, pp, pp, n, sp.nr, tmp, st);
     bk.done(nn * npts * (elem + 8.0 + 16.0), 2.0 * nn * nn * npts);

@@ -113,6 +113,9 @@ size_t gemm_partial_bytes(int n_orb, long long nr);
 hipError_t launch_inverse_sqrt(double* s, int n, double* work, int max_iter, hipStream_t st);
 void launch_apply_left(const double* m, const double* src, double* dst, int n, long long nr,
                        double* tmp, hipStream_t st);
+// dst <- m widen(src), float32 src (n <= 512; false otherwise, nothing launched)
+bool launch_apply_left_f32(const double* m, const float* src, double* dst, int n, long long nr,
+                           hipStream_t st);
 hipError_t prepare_apply_left();
 
 // Cholesky helpers (ace.hip): l = lower Cholesky factor of sign * m; x = l^(-1)

@@ -256,10 +256,10 @@ hipError_t launch_inverse_sqrt(double* s, int n, double* work, int max_iter, hip
 // k = k0 + 4 g + j for MFMA step j) so that each lane reads four consecutive
 // m values per row with one vector load; the block rows are read from LDS in
 // the same order.
-template <int BM, int CB>
+// S: element type of the source (float32 sources are widened while staged).
+template <int BM, int CB, typename S>
 __global__ void __launch_bounds__(256) k_apply_left(const double* __restrict__ m, int n,
-                                                    const double* src, double* dst,
-                                                    long long nr) {
+                                                    const S* src, double* dst, long long nr) {
   constexpr int BN = CB / 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* blk = reinterpret_cast<double*>(smem_raw);  // [k][CB + 2], k < npad
@@ -281,9 +281,14 @@ __global__ void __launch_bounds__(256) k_apply_left(const double* __restrict__ m
       const int k = e / PR, cc = 2 * (e - k * PR);
       v[u] = double2{0.0, 0.0};
       if (e < total && k < n && c0 + cc + 1 < nr) {
-        v[u] = *reinterpret_cast<const double2*>(src + (long long)k * nr + c0 + cc);
+        if constexpr (sizeof(S) == 8) {
+          v[u] = *reinterpret_cast<const double2*>(src + (long long)k * nr + c0 + cc);
+        } else {
+          const float2 f = *reinterpret_cast<const float2*>(src + (long long)k * nr + c0 + cc);
+          v[u] = double2{(double)f.x, (double)f.y};
+        }
       } else if (e < total && k < n && c0 + cc < nr) {
-        v[u].x = src[(long long)k * nr + c0 + cc];
+        v[u].x = (double)src[(long long)k * nr + c0 + cc];
       }
     }
 #pragma unroll
@@ -363,14 +368,14 @@ void launch_apply_left(const double* m, const double* src, double* dst, int n, l
   if (n <= 256) {
     constexpr int CB = 32;
     const size_t lds = (size_t)((n + 15) / 16 * 16) * (CB + 2) * 8;
-    hipLaunchKernelGGL((k_apply_left<4, CB>), dim3((unsigned)((nr + CB - 1) / CB)), dim3(256),
+    hipLaunchKernelGGL((k_apply_left<4, CB, double>), dim3((unsigned)((nr + CB - 1) / CB)), dim3(256),
                        lds, st, m, n, src, dst, nr);
     return;
   }
   if (n <= 512) {
     constexpr int CB = 16;
     const size_t lds = (size_t)((n + 15) / 16 * 16) * (CB + 2) * 8;
-    hipLaunchKernelGGL((k_apply_left<8, CB>), dim3((unsigned)((nr + CB - 1) / CB)), dim3(256),
+    hipLaunchKernelGGL((k_apply_left<8, CB, double>), dim3((unsigned)((nr + CB - 1) / CB)), dim3(256),
                        lds, st, m, n, src, dst, nr);
     return;
   }
@@ -384,14 +389,39 @@ void launch_apply_left(const double* m, const double* src, double* dst, int n, l
   }
 }
 
+// dst <- m widen(src) for a float32 source (n <= 512, dst distinct from
+// src); returns false for larger n, where the caller widens first.
+bool launch_apply_left_f32(const double* m, const float* src, double* dst, int n, long long nr,
+                           hipStream_t st) {
+  if (n <= 256) {
+    constexpr int CB = 32;
+    const size_t lds = (size_t)((n + 15) / 16 * 16) * (CB + 2) * 8;
+    hipLaunchKernelGGL((k_apply_left<4, CB, float>), dim3((unsigned)((nr + CB - 1) / CB)),
+                       dim3(256), lds, st, m, n, src, dst, nr);
+    return true;
+  }
+  if (n <= 512) {
+    constexpr int CB = 16;
+    const size_t lds = (size_t)((n + 15) / 16 * 16) * (CB + 2) * 8;
+    hipLaunchKernelGGL((k_apply_left<8, CB, float>), dim3((unsigned)((nr + CB - 1) / CB)),
+                       dim3(256), lds, st, m, n, src, dst, nr);
+    return true;
+  }
+  return false;
+}
+
 // Raise the dynamic-LDS limit of the in-place kernels (once per process).
 hipError_t prepare_apply_left() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_left<4, 32>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     256 * 34 * 8);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_left<8, 16>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 512 * 18 * 8);
+  const void* k[4] = {reinterpret_cast<const void*>(&k_apply_left<4, 32, double>),
+                      reinterpret_cast<const void*>(&k_apply_left<8, 16, double>),
+                      reinterpret_cast<const void*>(&k_apply_left<4, 32, float>),
+                      reinterpret_cast<const void*>(&k_apply_left<8, 16, float>)};
+  const int bytes[4] = {256 * 34 * 8, 512 * 18 * 8, 256 * 34 * 8, 512 * 18 * 8};
+  for (int i = 0; i < 4; ++i) {
+    hipError_t e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[i]);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace hfx
