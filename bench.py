@@ -300,7 +300,14 @@ def main():
         t_scr = 1e3 * (time.perf_counter() - t0)
         info = plan.schedule_info()
         t_kept, e_kept = ev()
-        out = {"rho_cut": rho_cut, "pairs_kept": kept, "pairs": n_pairs,
+        plan.profile(True)
+        plan.apply_exchange(psi_o, kpsi=kpsi, ex=ex)
+        prof = plan.profile_read()
+        plan.profile(False)
+        passes = {k: {"ms": v["ms"], "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0
+                      else None}
+                  for k, v in prof.items() if k in ("pair_fwd", "plane", "inv_acc")}
+        out = {"rho_cut": rho_cut, "pairs_kept": kept, "pairs": n_pairs, "passes": passes,
                "pair_grids": info[2], "tile_pairs": info[1], "batches": info[0],
                "screen_call_ms": t_scr, "kpsi_ms_screened": t_kept, "kpsi_ms_all_pairs": t_full,
                "speedup": t_full / t_kept, "rel_dEx_screening": abs(e_kept - e_full) / abs(e_full)}

@@ -87,6 +87,40 @@ __device__ __forceinline__ bool pair_live(const TileDesc& td, int ia, int b) {
   return true;
 }
 
+// Screened plans: the rows (bit a) and columns (bit b) of a tile that take
+// part in at least one evaluated pair.  The others are neither loaded nor
+// updated (their products and K psi contributions are all zero).
+template <int TT, bool SCR>
+__device__ __forceinline__ unsigned live_rows(const TileDesc& td) {
+  if constexpr (SCR && TT == 8) {
+    unsigned r = 0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) r |= (((td.keep >> (8 * a)) & 0xffull) != 0 ? 1u : 0u) << a;
+    return r;
+  }
+  return ~0u;
+}
+template <int TT, bool SCR>
+__device__ __forceinline__ unsigned live_cols(const TileDesc& td) {
+  if constexpr (SCR && TT == 8) {
+    unsigned long long k = td.keep;
+    k |= k >> 32;
+    k |= k >> 16;
+    k |= k >> 8;
+    return (unsigned)(k & 0xffull);
+  }
+  return ~0u;
+}
+// Next row after ia with an evaluated pair (nI when none is left).
+template <bool SCR>
+__device__ __forceinline__ int next_live_row(unsigned rows, int ia, int nI) {
+  if constexpr (SCR) {
+    const unsigned rem = ia + 1 < 32 ? rows >> (ia + 1) : 0u;
+    return rem ? ia + 1 + __builtin_ctz(rem) : nI;
+  }
+  return ia + 1;
+}
+
 // scale * (pair-density mean) for the TT x TT pairs of a tile, [a][b], zero
 // outside the tile or without means (float64 plans): staged in LDS so that
 // the loops below issue no global loads besides their own data.
@@ -168,14 +202,22 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   // psi of the J block (registers) and, with PIL, of the I block (LDS),
   // zero off the grid; loads issued four orbitals at a time before any use
   T pj[TT][PT];
+  const unsigned cols = live_cols<TT, SCR>(td), rows = live_rows<TT, SCR>(td);
   static_for<0, TT / 4>([&](auto hc) {
     constexpr int b0 = 4 * decltype(hc)::value;
     T xj[4][PT], xi[PIL ? 4 : 1][PT];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const T* pb = psi + (long long)orb_at<SCR>(a, td.j0 + (b0 + q < td.nJ ? b0 + q : 0)) * NR;
+      if constexpr (SCR) {
+        // columns without an evaluated pair are not read
+        const bool live = (cols >> (b0 + q)) & 1u;
 #pragma unroll
-      for (int k = 0; k < PT; ++k) xj[q][k] = pb[offA[k]];
+        for (int k = 0; k < PT; ++k) xj[q][k] = live ? pb[offA[k]] : T(0);
+      } else {
+#pragma unroll
+        for (int k = 0; k < PT; ++k) xj[q][k] = pb[offA[k]];
+      }
       if constexpr (PIL) {
         const T* pa = psi + (long long)orb_at<SCR>(a, td.i0 + (b0 + q < td.nI ? b0 + q : 0)) * NR;
 #pragma unroll
@@ -194,6 +236,9 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   __syncthreads();
 
   for (int ia = 0; ia < td.nI; ++ia) {
+    if constexpr (SCR) {
+      if (!((rows >> ia) & 1u)) continue;  // no evaluated pair in this row
+    }
     T pa[PT];
     if constexpr (PIL) {
 #pragma unroll
@@ -321,6 +366,7 @@ __global__ void __launch_bounds__(NT)
   T pjr[PJL ? 1 : TT][PT];
   auto pj = [&](int b, int k) -> T { return PJL ? pjl[(b * PT + k) * NT + tid] : pjr[PJL ? 0 : b][k]; };
   T accJ[ACC ? TT : 1][PT];
+  const unsigned cols = live_cols<TT, SCR>(td), rows = live_rows<TT, SCR>(td);
   // psi of the J block (zero off the grid); for LDS, four orbitals at a time,
   // all loads before the stores
   static_for<0, TT / 4>([&](auto hc) {
@@ -330,8 +376,14 @@ __global__ void __launch_bounds__(NT)
     for (int q = 0; q < 4; ++q) {
       const bool bv = b0 + q < td.nJ;
       const T* pb = psi + (long long)orb_at<SCR>(a, td.j0 + (bv ? b0 + q : 0)) * NR;
+      if constexpr (SCR) {
+        const bool live = (cols >> (b0 + q)) & 1u;
 #pragma unroll
-      for (int k = 0; k < PT; ++k) x[q][k] = pb[offA[k]];
+        for (int k = 0; k < PT; ++k) x[q][k] = live ? pb[offA[k]] : T(0);
+      } else {
+#pragma unroll
+        for (int k = 0; k < PT; ++k) x[q][k] = pb[offA[k]];
+      }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -448,11 +500,13 @@ __global__ void __launch_bounds__(NT)
   };
   if constexpr (PF) {
     cpx<T> vc[F::VALS], vn[F::VALS];
-    if (td.nI > 0) {
-      load_orbital(0, pa, kold);
-      load_pair(0, 0, vc);
+    const int ia0 = next_live_row<SCR>(rows, -1, td.nI);
+    if (ia0 < td.nI) {
+      load_orbital(ia0, pa, kold);
+      load_pair(ia0, 0, vc);
     }
-    for (int ia = 0; ia < td.nI; ++ia) {
+    for (int ia = ia0; ia < td.nI;) {
+      const int nx = next_live_row<SCR>(rows, ia, td.nI);
 #pragma unroll
       for (int k = 0; k < PT; ++k) acca[k] = T(0);
       static_for<0, QB>([&](auto bq) {
@@ -460,9 +514,9 @@ __global__ void __launch_bounds__(NT)
         // next step's loads go out before this step's transform
         if constexpr (q + 1 < QB) {
           load_pair(ia, q + 1, vn);
-        } else if (ia + 1 < td.nI) {
-          load_orbital(ia + 1, pa_n, kold_n);
-          load_pair(ia + 1, 0, vn);
+        } else if (nx < td.nI) {
+          load_orbital(nx, pa_n, kold_n);
+          load_pair(nx, 0, vn);
         }
         process(bq, ia, vc);
 #pragma unroll
@@ -474,9 +528,11 @@ __global__ void __launch_bounds__(NT)
         pa[k] = pa_n[k];
         if constexpr (ACC) kold[k] = kold_n[k];
       }
+      ia = nx;
     }
   } else {
-    for (int ia = 0; ia < td.nI; ++ia) {
+    for (int ia = next_live_row<SCR>(rows, -1, td.nI); ia < td.nI;
+         ia = next_live_row<SCR>(rows, ia, td.nI)) {
       load_orbital(ia, pa, kold);
 #pragma unroll
       for (int k = 0; k < PT; ++k) acca[k] = T(0);
@@ -500,15 +556,23 @@ __global__ void __launch_bounds__(NT)
       for (int q = 0; q < 4; ++q) {
         const bool bv = b0 + q < td.nJ;
         const T* kb = kpsi + (long long)orb_at<SCR>(a, td.j0 + (bv ? b0 + q : 0)) * NR;
+        if constexpr (SCR) {
+          // columns without an evaluated pair keep their K psi untouched
+          const bool live = (cols >> (b0 + q)) & 1u;
 #pragma unroll
-        for (int k = 0; k < PT; ++k) old[q][k] = kb[offA[k]];
+          for (int k = 0; k < PT; ++k) old[q][k] = live ? kb[offA[k]] : T(0);
+        } else {
+#pragma unroll
+          for (int k = 0; k < PT; ++k) old[q][k] = kb[offA[k]];
+        }
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         T* kb = kpsi + (long long)orb_at<SCR>(a, td.j0 + (b0 + q < td.nJ ? b0 + q : 0)) * NR;
+        const bool live = !SCR || ((cols >> (b0 + q)) & 1u);
 #pragma unroll
         for (int k = 0; k < PT; ++k)
-          if (b0 + q < td.nJ && vA[k]) kb[offA[k]] = old[q][k] + accJ[b0 + q][k];
+          if (live && b0 + q < td.nJ && vA[k]) kb[offA[k]] = old[q][k] + accJ[b0 + q][k];
       }
     });
   }

@@ -624,7 +624,20 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
     double orbs = 0.0;  // orbital rows a batch reads (each tile's blocks once)
     for (int t = 0; t < b.n_tiles; ++t) {
       const TileDesc& td = sp.tiles[b.tile_off + t];
-      orbs += td.diag ? td.nJ : td.nI + td.nJ;
+      if (sp.d_keep) {
+        // screened: only rows and columns with an evaluated pair are touched
+        unsigned rows = 0, cols = 0;
+        for (int r = 0; r < 8; ++r)
+          for (int c = 0; c < 8; ++c)
+            if ((td.keep >> (8 * r + c)) & 1ull) {
+              rows |= 1u << r;
+              cols |= 1u << c;
+            }
+        orbs += td.diag ? __builtin_popcount(rows | cols)
+                        : __builtin_popcount(rows) + __builtin_popcount(cols);
+      } else {
+        orbs += td.diag ? td.nJ : td.nI + td.nJ;
+      }
     }
     const double grids = (double)b.n_active;
     {
