@@ -383,8 +383,11 @@ def main():
              "kernel_config_fp32": r32["describe"]}
     if not args.no_fp64:
         log(f"fp64: 1 warm-up + {args.fp64_steps} timed steps")
-        r64, _ = run(hfx.FP64, args.fp64_steps, 1, False)
-        extra.update({"ms_per_step_fp64": r64["ms"], "ex_fp64": r64["ex"],
+        r64, _ = run(hfx.FP64, args.fp64_steps, 1, True)
+        p64 = {k: {"ms_per_step": v["ms"] / args.fp64_steps,
+                   "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
+               for k, v in r64["prof"].items()}
+        extra.update({"ms_per_step_fp64": r64["ms"], "ex_fp64": r64["ex"], "passes_fp64": p64,
                       "kernel_config_fp64": r64["describe"],
                       "fp32_speedup_vs_fp64": r64["ms"] / ms,
                       "rel_dEx_fp32_vs_fp64": abs(r32["ex"] - r64["ex"]) / abs(r64["ex"])})
