@@ -16,6 +16,9 @@ What it computes (Methods, "MTACE Method for H-AIMD Simulation"):
   W_i = V_X psi_i and -M = L L^T (Cholesky)
 * s-MTACE screening (same Methods subsection): only pairs with
   int |phi_i phi_j| dr >= rho_cut enter the exchange sums
+* SCDM localisation of the orbitals the screening acts on (the same
+  subsection cites the selected-columns-of-the-density-matrix method of
+  Damle, Lin and Ying, 2015, without restating it; reading 6 below)
 
 The FFT evaluates the periodic discrete convolution exactly up to rounding,
 so the oracle is the plain definition written out, one pair at a time, in
@@ -38,6 +41,12 @@ Readings of points the paper leaves open (each repeated where it is used):
 4. FFT convention.  rho~(G) = (1/N_r) sum_n rho(r_n) exp(-i G r_n);
    f(r_n) = sum_G f~(G) exp(+i G r_n).
 5. Inner product.  <f|g> = dV sum_n f(r_n) g(r_n), dV = Omega / N_r.
+6. SCDM (Gamma point, real orbitals).  Grid points c_1..c_N are selected by
+   column-pivoted QR of the N_orb x N_r matrix Psi^T: step k takes the column
+   (grid point) whose residual after projecting out the columns selected so
+   far has the largest norm (ties: the smallest index).  The localised
+   functions are the density-matrix columns at those points,
+   xi_k(r) = sum_i psi_i(r) psi_i(c_k), orthonormalised by Loewdin.
 
 Array layout: orbitals are float64 arrays ``psi[orb, z, y, x]`` (x fastest);
 ``box`` is (Lx, Ly, Lz) in bohr.
@@ -55,6 +64,7 @@ __all__ = [
     "pair_potential", "pair_energy", "exchange", "apply_exchange_rows",
     "exchange_matrix", "overlap", "lowdin", "cholesky_orthonormalize",
     "ace_projectors", "ace_apply", "pair_overlap_abs", "screen_pairs",
+    "scdm_pivots", "scdm",
 ]
 
 TRUNCATED = 0
@@ -280,3 +290,41 @@ def screen_pairs(psi, dv, rho_cut):
     rho_cut <= 1)."""
     return pair_overlap_abs(psi, dv) >= rho_cut
 
+
+def scdm_pivots(psi):
+    """Grid points selected by column-pivoted QR of Psi^T (reading 6).
+
+    Plain greedy definition: keep the residual matrix R (initially Psi^T,
+    N_orb x N_r), pick the column of largest norm, normalise it to q and
+    remove its component from every column, R <- R - q (q^T R).  Returns the
+    flat point indices c_1..c_N and, for each step, the relative gap between
+    the largest and the second-largest residual norm (a tie test for callers
+    that compare pivots computed in another summation order)."""
+    r = np.array(psi.reshape(psi.shape[0], -1), dtype=np.float64)
+    n = r.shape[0]
+    piv, gaps = [], []
+    taken = np.zeros(r.shape[1], dtype=bool)
+    for _ in range(n):
+        norms = np.einsum("ij,ij->j", r, r)
+        norms[taken] = -1.0
+        p = int(np.argmax(norms))            # first index among equal maxima
+        top = norms[p]
+        norms[p] = -1.0
+        gaps.append((top - norms.max()) / top)
+        q = r[:, p] / math.sqrt(top)
+        r -= np.outer(q, q @ r)
+        taken[p] = True
+        piv.append(p)
+    return np.array(piv), np.array(gaps)
+
+
+def scdm(psi, dv):
+    """SCDM-localised orthonormal orbitals (reading 6): xi_k = sum_i psi_i
+    psi_i(c_k) at the pivots c_k of ``scdm_pivots``, then Loewdin in the
+    dV inner product.  Returns (phi, pivots)."""
+    a = psi.reshape(psi.shape[0], -1)
+    piv, _ = scdm_pivots(psi)
+    b = a[:, piv].T                          # b[k, i] = psi_i(c_k)
+    xi = (b @ a).reshape(psi.shape)
+    phi, _ = lowdin(xi, dv)
+    return phi, piv

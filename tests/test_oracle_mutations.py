@@ -147,3 +147,37 @@ def test_planted_mistake_is_caught(monkeypatch, name, fn):
     assert _count_failures() == 0          # the unmodified oracle passes every pin
     _patch(monkeypatch, name, fn)
     assert _count_failures() >= 1
+
+
+# --------------------------------------------------------------------------
+# SCDM: mistakes in the selection or in the density-matrix columns
+
+_orig_pivots = ho.scdm_pivots
+
+
+def mut_scdm_no_projection(psi):
+    """Top column norms of Psi^T, without removing the selected directions."""
+    a = psi.reshape(psi.shape[0], -1)
+    norms = np.einsum("ij,ij->j", a, a)
+    piv = np.argsort(-norms, kind="stable")[: a.shape[0]]
+    return piv, np.ones(a.shape[0])
+
+
+def mut_scdm_transposed_columns(psi, dv):
+    a = psi.reshape(psi.shape[0], -1)
+    piv, _ = _orig_pivots(psi)
+    b = a[:, piv]                            # b[i, k] where b[k, i] is meant
+    phi, _ = ho.lowdin((b @ a).reshape(psi.shape), dv)
+    return phi, piv
+
+
+def test_scdm_mutation_no_projection_is_caught(monkeypatch):
+    _patch(monkeypatch, "scdm_pivots", mut_scdm_no_projection)
+    with pytest.raises(AssertionError):
+        pins.test_scdm_pivots_match_lapack_qrcp("pw", 24, 8, 3)
+
+
+def test_scdm_mutation_transposed_columns_is_caught(monkeypatch):
+    _patch(monkeypatch, "scdm", mut_scdm_transposed_columns)
+    with pytest.raises(AssertionError):
+        pins.test_scdm_orthonormal_same_span_and_rotation_invariant()

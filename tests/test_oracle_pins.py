@@ -474,3 +474,63 @@ def test_screened_rows_match_screened_exchange(small_system):
     assert np.max(np.abs(rows - res["kpsi"])) <= 1e-13 * np.max(np.abs(rows))
     full = oracle.apply_exchange_rows(psi, box, vg, list(range(len(psi))))
     assert np.max(np.abs(full - rows)) > 1e-6 * np.max(np.abs(full))
+
+
+# --------------------------------------------------------------------------
+# SCDM localisation (reading 6 of the oracle)
+
+def _scdm_case(kind, n, n_orb, seed):
+    shape, box = (n, n, n), (10.0, 10.0, 10.0)
+    if kind == "pw":
+        psi = generate.random_pw(shape, box, n_orb, 5.0, seed)
+    else:
+        psi = generate.gaussians(shape, box, n_orb, 20.0 if n >= 32 else 5.0, seed)[0]
+    dv = 1000.0 / n ** 3
+    return oracle.lowdin(psi, dv)[0], dv
+
+
+@pytest.mark.parametrize("kind,n,n_orb,seed", [("pw", 24, 8, 3), ("pw", 24, 13, 4),
+                                                ("g", 32, 10, 5)])
+def test_scdm_pivots_match_lapack_qrcp(kind, n, n_orb, seed):
+    """The greedy selection equals LAPACK's column-pivoted QR (geqp3) of
+    Psi^T wherever no near-tie makes the choice rounding-dependent."""
+    import scipy.linalg as sl
+    psi, _ = _scdm_case(kind, n, n_orb, seed)
+    piv, gaps = oracle.scdm_pivots(psi)
+    assert gaps.min() > 1e-8
+    _, _, p = sl.qr(psi.reshape(n_orb, -1), pivoting=True, mode="economic")
+    assert np.array_equal(piv, p[:n_orb])
+
+
+def test_scdm_orthonormal_same_span_and_rotation_invariant():
+    psi, dv = _scdm_case("g", 32, 10, 5)
+    phi, piv = oracle.scdm(psi, dv)
+    a, f = psi.reshape(10, -1), phi.reshape(10, -1)
+    assert np.max(np.abs(dv * f @ f.T - np.eye(10))) <= 1e-12
+    o = dv * f @ a.T                    # overlaps <phi_k|psi_i>: orthogonal when the spans agree
+    assert np.max(np.abs(o @ o.T - np.eye(10))) <= 1e-12
+    # the density matrix, hence the selected columns, ignores any rotation of psi
+    rng = np.random.default_rng(8)
+    u, _ = np.linalg.qr(rng.standard_normal((10, 10)))
+    psi_u = (u.T @ a).reshape(psi.shape)
+    phi_u, piv_u = oracle.scdm(psi_u, dv)
+    assert np.array_equal(piv, piv_u)
+    assert np.max(np.abs(phi_u - phi)) <= 1e-11 * np.max(np.abs(phi))
+
+
+def test_scdm_relocalises_mixed_gaussians():
+    """Localised Gaussians mixed by a random rotation are delocalised; the
+    SCDM functions of the mixture are localised again (inverse participation
+    ratio sum |phi|^4 / (sum |phi|^2)^2 back near that of the Gaussians)."""
+    psi, dv = _scdm_case("g", 32, 10, 5)
+    a = psi.reshape(10, -1)
+    rng = np.random.default_rng(9)
+    u, _ = np.linalg.qr(rng.standard_normal((10, 10)))
+    mixed = (u.T @ a).reshape(psi.shape)
+    phi, _ = oracle.scdm(mixed, dv)
+
+    def ipr(x):
+        x = x.reshape(x.shape[0], -1)
+        return np.mean(np.sum(x ** 4, axis=1) / np.sum(x ** 2, axis=1) ** 2)
+    assert ipr(mixed) < 0.5 * ipr(psi)
+    assert ipr(phi) > 0.7 * ipr(psi)
