@@ -216,6 +216,24 @@ hfx_status hfx_screen(hfx_plan plan, const double* psi, double rho_cut, long lon
                       size_t ws_bytes, void* stream);
 
 /*
+ * SCDM localisation (the s-MTACE screening acts on SCDM-localised orbitals;
+ * Methods, MTACE subsection, citing the selected-columns-of-the-density-matrix
+ * method).  For every system: grid points c_1..c_N (N = n_orb) are chosen by
+ * column-pivoted QR of Psi^T (each step takes the point whose residual, after
+ * the chosen points' directions are projected out, has the largest norm;
+ * ties to the smallest index; float64); phi_k = sum_i psi_i psi_i(c_k), the
+ * density-matrix columns at those points, Loewdin-orthonormalised in the dV
+ * inner product.  psi, phi: float64, the layout of the other calls (phi may
+ * equal psi: in place).  pivots: nullable device int array of sum(n_orb)
+ * entries receiving the flat grid index (z n + y) n + x of c_k.  Asynchronous
+ * on `stream`; the workspace is used as by the other calls.  Linearly
+ * dependent orbitals give NaN.  HFX_EINVAL: null pointers or a call during
+ * graph capture; HFX_EUNSUPPORTED: more than 3500 orbitals in a system.
+ */
+hfx_status hfx_scdm(hfx_plan plan, const double* psi, double* phi, int* pivots, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/*
  * Size of a system's current tile schedule (host query, no device work):
  * info[0] batches, info[1] tile pairs, info[2] pair grids (complex grids,
  * two orbital pairs each) per exchange call, info[3] orbital pairs a <= b
@@ -259,6 +277,7 @@ typedef enum {
   HFX_PASS_SCALE,          /* gradient scaling                               */
   HFX_PASS_ACE_BUILD,      /* Cholesky of -M, L^(-1), P = L^(-1) W           */
   HFX_PASS_ACE_APPLY,      /* -P (P^T phi): contraction and apply            */
+  HFX_PASS_SCDM,           /* SCDM pivots and density-matrix columns         */
   HFX_PASS_COUNT
 } hfx_pass;
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhfx.so")
 SOURCES = ["hfx_api.cpp", "exchange_common.hip", "exchange_f32.hip", "exchange_f64.hip",
-           "gemm.hip", "ortho.hip", "ace.hip"]
+           "gemm.hip", "ortho.hip", "ace.hip", "scdm.hip"]
 ARCH = "gfx950"
 # packed float32 instructions stay off (see the design notes on v_pk_* ops)
 FLAGS = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC",

@@ -88,6 +88,7 @@ struct SystemPlan {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_acc[2] = {nullptr, nullptr};
   // offsets inside concatenated user buffers
   long long psi_off = 0, m_off = 0;
+  long long orb_off = 0;  // first orbital of this system (per-orbital arrays)
 };
 
 }  // namespace
@@ -824,6 +825,35 @@ hfx_status enq_ortho(hfx_plan plan, SystemPlan& sp, double* psi, int method, cha
   return HFX_OK;
 }
 
+// SCDM-localised orthonormal orbitals: pivots by column-pivoted QR of
+// Psi^T, density-matrix columns B Psi with b[k][i] = psi_i(c_k), then Loewdin.
+// Scratch: the pair-grid buffer (w and the argmax candidates, unused outside
+// the exchange calls) and the orthonormalisation region (q rows and B).
+hfx_status enq_scdm(hfx_plan plan, SystemPlan& sp, const double* psi, double* phi, int* pivots,
+                    char* ws, hipStream_t st) {
+  const int n = sp.sys.n_orb;
+  char* scratch = ws + sp.off_grids;
+  double* work = reinterpret_cast<double*>(ws + sp.off_ortho);
+  double* qm = work;
+  double* b = work + (size_t)n * n;
+  double* tmp = reinterpret_cast<double*>(ws + align_up(sp.off_ortho + (size_t)6 * n * n * 8 + 64));
+  int* piv = pivots ? pivots + sp.orb_off
+                    : reinterpret_cast<int*>(scratch + align_up(scdm_scratch_bytes(sp.nr)));
+  const double* ps = psi + sp.psi_off;
+  double* ph = phi + sp.psi_off;
+  const double nn = n, npts = (double)sp.nr;
+  {
+    Bracket bk(plan, HFX_PASS_SCDM, st);
+    launch_scdm_pivots(ps, n, sp.nr, scratch, qm, piv, st);
+    launch_scdm_gather(ps, n, sp.nr, piv, b, st);
+    launch_apply_left(b, ps, ph, n, sp.nr, tmp, st);
+    // every pivot step reads Psi once; the columns B Psi read and write it
+    bk.done(nn * npts * 8.0 * (nn + 2.0), 2.0 * nn * npts * (nn + 1.0) + 2.0 * nn * nn * npts);
+  }
+  HIP_TRY(hipGetLastError());
+  return enq_ortho(plan, sp, phi, HFX_ORTHO_LOWDIN, ws, st);
+}
+
 // Runs fn(system, stream) for every system.  One system: on the caller's
 // stream.  Several: forked onto the plan's side streams after an event on the
 // caller's stream and joined back with one event per system, so independent
@@ -940,7 +970,7 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   p->prec = precision;
   p->sys.resize(n_sys);
   size_t off = 0;
-  long long psi_off = 0, m_off = 0;
+  long long psi_off = 0, m_off = 0, orb_off = 0;
   const size_t elem = precision == HFX_FP64 ? 8 : 4;
   for (int i = 0; i < n_sys; ++i) {
     SystemPlan& sp = p->sys[i];
@@ -955,6 +985,8 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     build_schedule(sp, tiles_cap);
     sp.psi_off = psi_off;
     sp.m_off = m_off;
+    sp.orb_off = orb_off;
+    orb_off += sys[i].n_orb;
     psi_off += (long long)sys[i].n_orb * sp.nr;
     m_off += (long long)sys[i].n_orb * sys[i].n_orb;
     // workspace layout of this system
@@ -1302,6 +1334,23 @@ const char* hfx_plan_describe(hfx_plan plan, int system) {
                   " screened=" + (sp.d_keep ? "yes" : "no");
   plan->desc = d;
   return plan->desc.c_str();
+}
+
+hfx_status hfx_scdm(hfx_plan plan, const double* psi, double* phi, int* pivots, void* ws,
+                    size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  hfx_status s = check_call(plan, psi, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (!phi) return fail(HFX_EINVAL, "null phi");
+  if (plan->capturing) return fail(HFX_EINVAL, "hfx_scdm cannot be captured");
+  for (const SystemPlan& sp : plan->sys) {
+    // the pivot step keeps two n-vectors in LDS
+    if (sp.sys.n_orb > 3500) return fail(HFX_EUNSUPPORTED, "hfx_scdm supports up to 3500 orbitals");
+    if (sp.sys.n_orb > sp.nr) return fail(HFX_EINVAL, "more orbitals than grid points");
+  }
+  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
+    return enq_scdm(plan, plan->sys[i], psi, phi, pivots, static_cast<char*>(ws), st);
+  });
 }
 
 hfx_status hfx_schedule_info(hfx_plan plan, int system, long long* info) {

@@ -118,6 +118,17 @@ bool launch_apply_left_f32(const double* m, const float* src, double* dst, int n
                            hipStream_t st);
 hipError_t prepare_apply_left();
 
+// SCDM pivot selection (scdm.hip)
+constexpr int kScdmParts = 2048;  // workgroups of the grid-wide passes
+size_t scdm_scratch_bytes(long long nr);
+// piv[k] (k < n) = grid points chosen by column-pivoted QR of psi^T (n x nr);
+// scratch: scdm_scratch_bytes(nr); qm: n x n doubles (rows q_k)
+void launch_scdm_pivots(const double* psi, int n, long long nr, char* scratch, double* qm,
+                        int* piv, hipStream_t st);
+// b[k][i] = psi[i][piv[k]]
+void launch_scdm_gather(const double* psi, int n, long long nr, const int* piv, double* b,
+                        hipStream_t st);
+
 // Cholesky helpers (ace.hip): l = lower Cholesky factor of sign * m; x = l^(-1)
 void launch_chol(const double* m, int n, double sign, double* l, hipStream_t s);
 void launch_trinv(const double* l, int n, double* x, hipStream_t s);

@@ -31,7 +31,8 @@ GRAPH_ENERGY = 0
 GRAPH_APPLY = 1
 GRAPH_STEP = 2
 PASSES = ("stage", "zero", "pair_fwd", "plane", "rows_fwd", "cols_conv", "rows_inv", "inv_acc",
-          "inv_energy", "energy_reduce", "contract", "ortho", "scale", "ace_build", "ace_apply")
+          "inv_energy", "energy_reduce", "contract", "ortho", "scale", "ace_build", "ace_apply",
+          "scdm")
 
 _STATUS = {0: "HFX_OK", 1: "HFX_EINVAL", 2: "HFX_EUNSUPPORTED", 3: "HFX_ENOMEM",
            4: "HFX_EDEVICE"}
@@ -82,6 +83,7 @@ def load_library(path=None):
     lib.hfx_ace_build.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.hfx_ace_apply.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.hfx_screen.argtypes = [vp, vp, d, ctypes.POINTER(ctypes.c_longlong), vp, sz, vp]
+    lib.hfx_scdm.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.hfx_schedule_info.argtypes = [vp, i, ctypes.POINTER(ctypes.c_longlong)]
     lib.hfx_plan_describe.argtypes = [vp, i]
     lib.hfx_plan_describe.restype = ctypes.c_char_p
@@ -98,7 +100,7 @@ def load_library(path=None):
                  "hfx_exchange_energy", "hfx_apply_exchange", "hfx_exchange_matrix",
                  "hfx_orthonormalize", "hfx_exchange_gradient", "hfx_profile_enable",
                  "hfx_profile_read", "hfx_graph_create", "hfx_graph_launch",
-                 "hfx_graph_destroy", "hfx_ace_build", "hfx_ace_apply", "hfx_screen",
+                 "hfx_graph_destroy", "hfx_ace_build", "hfx_ace_apply", "hfx_screen", "hfx_scdm",
                  "hfx_schedule_info"):
         getattr(lib, name).restype = i
     if path is None:
@@ -289,6 +291,22 @@ class Plan:
         _check(_lib.hfx_screen(self._h, _ptr(psi), float(rho_cut), kept, _ptr(ws), self.ws_bytes,
                                _stream()))
         return list(kept)
+
+    def scdm(self, psi, phi=None, pivots=None):
+        """SCDM-localised orthonormal orbitals of psi (float64, the layout of
+        psi; phi may be psi itself) and the selected grid points (int32, one
+        per orbital, flat index (z n + y) n + x)."""
+        self._check_psi(psi)
+        if phi is None:
+            phi = torch.empty_like(psi)
+        self._check_psi(phi)
+        if pivots is None:
+            pivots = torch.empty(sum(s.n_orb for s in self.systems), dtype=torch.int32,
+                                 device=self.device)
+        ws = self.workspace()
+        _check(_lib.hfx_scdm(self._h, _ptr(psi), _ptr(phi), _ptr(pivots), _ptr(ws),
+                             self.ws_bytes, _stream()))
+        return phi, pivots
 
     def schedule_info(self, system=0):
         """(batches, tile pairs, pair grids, orbital pairs) of the current schedule."""

@@ -30,7 +30,8 @@ def test_header_declares_entry_points():
     for s in ("hfx_plan_create", "hfx_plan_destroy", "hfx_workspace_size",
               "hfx_exchange_energy", "hfx_apply_exchange", "hfx_exchange_matrix",
               "hfx_exchange_gradient", "hfx_orthonormalize", "hfx_ace_build",
-              "hfx_ace_apply", "hfx_screen", "hfx_schedule_info", "hfx_plan_describe", "hfx_status_string",
+              "hfx_ace_apply", "hfx_screen", "hfx_scdm", "hfx_schedule_info", "hfx_plan_describe",
+              "hfx_status_string",
               "hfx_last_error"):
         assert s in syms
 
@@ -111,6 +112,7 @@ def test_null_plan_calls(lib):
     assert lib.hfx_screen(vp(0), vp(8), 1e-3, None, vp(256), 0, vp(0)) == 1
     assert lib.hfx_schedule_info(vp(0), 0, None) == 1
     assert lib.hfx_plan_describe(vp(0), 0) is None
+    assert lib.hfx_scdm(vp(0), vp(8), vp(8), None, vp(256), 0, vp(0)) == 1
 
 
 def test_status_strings(lib):
