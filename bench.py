@@ -314,6 +314,23 @@ def main():
         del plan, kpsi
         return out
 
+    def time_scdm(psi_o, reps=2):
+        """SCDM localisation of the step's orthonormal orbitals (pivoted QR
+        pivots, density-matrix columns, Loewdin), timed with HIP events, and
+        the pairs an s-MTACE cut of 2.5e-2 keeps on its output."""
+        plan = hfx.Plan(spec, hfx.FP32, options=args.options, device=dev)
+        phi, piv = plan.scdm(psi_o)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            plan.scdm(psi_o, phi=phi, pivots=piv)
+        b.record()
+        b.synchronize()
+        kept = plan.screen(phi, 2.5e-2)[0]
+        del plan, phi
+        return {"scdm_ms": a.elapsed_time(b) / reps, "pairs_kept_rho_2.5e-2_after_scdm": kept}
+
     # achievable HBM rate on this device: device-to-device copy of 1 GiB
     # (1 GiB read + 1 GiB written), median of 5, timed with HIP events
     def copy_rate():
@@ -367,6 +384,9 @@ def main():
     ace_build_ms, ace_apply_ms, ex_ace = time_ace(plan32, r32)
     log(f"ace: build {ace_build_ms:.2f} ms, apply {ace_apply_ms:.2f} ms")
     smtace = [] if args.no_smtace else [time_screen(r32["psi"], rc) for rc in (2.5e-2, 2.0e-3)]
+    scdm = None if args.no_smtace else time_scdm(r32["psi"])
+    if scdm:
+        log(f"scdm: {scdm['scdm_ms']:.1f} ms")
     for sc in smtace:
         log(f"s-MTACE rho_cut {sc['rho_cut']:g}: {sc['pairs_kept']} of {n_pairs} pairs, "
             f"K psi {sc['kpsi_ms_screened']:.2f} ms (all pairs {sc['kpsi_ms_all_pairs']:.2f} ms)")
@@ -379,7 +399,7 @@ def main():
              "device_copy_GBps": copy_gbps,
              "pair_pipeline_frac_of_device_copy": exch_frac * HBM_PEAK_GBS / copy_gbps,
              "dominant_frac_of_device_copy": (achieved / copy_gbps) if roof["bound"] == "hbm" else None,
-             "passes": passes, "ex_fp32": r32["ex"], "s_mtace": smtace,
+             "passes": passes, "ex_fp32": r32["ex"], "s_mtace": smtace, "scdm": scdm,
              "kernel_config_fp32": r32["describe"]}
     if not args.no_fp64:
         log(f"fp64: 1 warm-up + {args.fp64_steps} timed steps")

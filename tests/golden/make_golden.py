@@ -21,6 +21,11 @@ on the raw generated orbitals (no orthonormalisation, as the batched
 benchmark runs them), with <psi_i|K psi_i> of those rows and K psi at seeded
 sample points.
 
+With --scdm it writes ``<name>_scdm_oracle.json``: the SCDM pivots of the
+Loewdin orbitals (``oracle.scdm_pivots``), the smallest relative lead of the
+chosen residual norm over the runner-up across the steps, and the localised
+orthonormal orbitals at seeded sample points.
+
 Usage: python tests/golden/make_golden.py water96 [--workers 8] [--screen 2.5e-2]
        python tests/golden/make_golden.py large128 --rows 0,1,255,511 [--workers 4]
 The workload definitions live in workloads/configs.py; each record stores the
@@ -51,8 +56,12 @@ def main():
     ap.add_argument("--workers", type=int, default=os.cpu_count() or 1)
     ap.add_argument("--screen", type=float, default=None)
     ap.add_argument("--rows", default=None)
+    ap.add_argument("--scdm", action="store_true")
     a = ap.parse_args()
     s = configs.ALL[a.name]
+    if a.scdm:
+        scdm_mode(s)
+        return
     if a.rows is not None:
         rows_mode(s, [int(r) for r in a.rows.split(",")], a.workers)
         return
@@ -130,6 +139,28 @@ def rows_mode(s, rows, workers):
     with open(path, "w") as f:
         json.dump(rec, f)
     print(f"wrote {path} ({time.time() - t0:.0f} s)", flush=True)
+
+
+def scdm_mode(s):
+    t0 = time.time()
+    psi = s.orbitals()
+    dv = oracle.volume(s.box) / psi[0].size
+    psi_o, _ = oracle.lowdin(psi, dv)
+    del psi
+    piv, gaps = oracle.scdm_pivots(psi_o)
+    phi, _ = oracle.scdm(psi_o, dv)
+    rng = np.random.default_rng(12345)
+    pts = rng.choice(phi[0].size, size=SAMPLE_POINTS, replace=False)
+    orbs = (0, 1, s.n_orb - 1)
+    samples = [[int(o), int(p), float(phi[o].reshape(-1)[p])] for o in orbs for p in pts]
+    rec = {"name": s.name, "n": s.n, "L": s.L, "n_orb": s.n_orb, "kernel": s.kernel,
+           "param": s.param, "family": s.family, "ecut": s.ecut, "seed": s.seed,
+           "orthonormalisation": "Loewdin (oracle eigh)", "pivots": [int(x) for x in piv],
+           "min_gap": float(gaps.min()), "samples": samples, "seconds": time.time() - t0}
+    path = os.path.join(HERE, f"{s.name}_scdm_oracle.json")
+    with open(path, "w") as f:
+        json.dump(rec, f)
+    print(f"wrote {path} (min gap {gaps.min():.2e}, {time.time() - t0:.0f} s)", flush=True)
 
 
 if __name__ == "__main__":
