@@ -73,7 +73,7 @@ typedef enum { HFX_ORTHO_LOWDIN = 0, HFX_ORTHO_CHOLESKY = 1 } hfx_ortho_method;
 
 /* One periodic system. */
 typedef struct {
-  int n[3];      /* grid points along x, y, z; must be equal (cubic grid)   */
+  int n[3];      /* grid points along x, y, z; n_x == n_y (n_z: see below) */
   double L[3];   /* box lengths along x, y, z, bohr; each > 0               */
   int n_orb;     /* number of occupied real orbitals, >= 1                   */
   int kernel;    /* hfx_kernel                                              */
@@ -84,7 +84,10 @@ typedef struct hfx_plan_t* hfx_plan;
 
 /*
  * Create a plan for n_sys systems at the given precision (hfx_precision).
- * Supported grids: n in {24, 64, 72, 80, 96, 108, 120, 128}.  `options` is a
+ * Supported grids: n x n x n with n in {24, 64, 72, 80, 96, 108, 120, 128},
+ * and the slab-cell grids n x n x nz with (n, nz) in {(24, 48), (64, 128)}
+ * (x and y transforms of length n, z transforms of length nz; layout
+ * [z][y][x]; the box may be orthorhombic in either case).  `options` is a
  * nullable "key=value;key=value" string: tiles=<k> caps the orbital tiles per
  * batch; maxws=<bytes> caps the workspace; variant=<name> picks a compiled
  * kernel configuration (see hfx_variants); streams=2 runs consecutive batches
@@ -105,7 +108,7 @@ typedef struct hfx_plan_t* hfx_plan;
  * (synchronous).  Errors: HFX_EINVAL for null out/sys, n_sys < 1, n <= 0,
  * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0, an unknown
  * option key or a malformed option value;
- * HFX_EUNSUPPORTED for a non-cubic or unsupported grid size; HFX_EDEVICE or
+ * HFX_EUNSUPPORTED for n_x != n_y or an unsupported grid; HFX_EDEVICE or
  * HFX_ENOMEM when device set-up fails.  *out is NULL on failure.
  */
 hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int precision,
@@ -305,7 +308,7 @@ hfx_status hfx_graph_launch(hfx_graph graph, void* stream);
 hfx_status hfx_graph_destroy(hfx_graph graph);
 
 /*
- * Names of the compiled kernel configurations for an n^3 grid at the given
+ * Names of the compiled kernel configurations for an n^3 (cubic) grid at the given
  * precision, ';'-separated, default first ("" if the size is unsupported).
  * A single-system plan selects one with the option "variant=<name>".
  * The returned string is thread-local and valid until the next call.

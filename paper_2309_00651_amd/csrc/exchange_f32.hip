@@ -49,6 +49,13 @@ using P108 = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, S
 using P108r = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
                             Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, false,
                             false>;
+// slab cells (n x n x nz): z transforms of length nz, planes of n x n
+using P24x48 = FusedPipeline<float, 24, 16, 8, Sched<4, 12>, Sched<12, 4>, 144, Sched<4, 6>,
+                             Sched<6, 4>, Sched<4, 6>, Sched<6, 4>, false, 256, 512, true, true,
+                             false, false, 48>;
+using P64x128 = FusedPipeline<float, 64, 16, 8, Sched<8, 16>, Sched<16, 8>, 256, Sched<8, 8>,
+                              Sched<8, 8>, Sched<8, 8>, Sched<8, 8>, false, 256, 1024, false, false,
+                              false, false, 128>;
 // persistent prefetching plane kernel (one plane per compute unit fits)
 using P128pp = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
                              Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, false,
@@ -90,6 +97,8 @@ const Variant* variants_f32(int* count) {
       P128::describe("f32-n128"),
       P128lp::describe("f32-n128-lp"),
       P128pp::describe("f32-n128-pp"),
+      P24x48::describe("f32-n24x48"),
+      P64x128::describe("f32-n64x128"),
   };
   *count = (int)(sizeof(v) / sizeof(v[0]));
   return v;

@@ -27,6 +27,13 @@ using P96q384 = FusedPipeline<double, 96, 16, 8, Sched<8, 12>, Sched<12, 8>, 384
                               Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
 using P96z8 = FusedPipeline<double, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
                             Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
+// slab cells (n x n x nz)
+using P24x48 = FusedPipeline<double, 24, 16, 8, Sched<4, 12>, Sched<12, 4>, 144, Sched<4, 6>,
+                             Sched<6, 4>, Sched<4, 6>, Sched<6, 4>, false, 384, 384, false, false,
+                             false, false, 48>;
+using P64x128 = FusedPipeline<double, 64, 16, 8, Sched<8, 16>, Sched<16, 8>, 512, Sched<8, 8>,
+                              Sched<8, 8>, Sched<8, 8>, Sched<8, 8>, false, 512, 512, false, false,
+                              false, false, 128>;
 // SplitPipeline<T, N, W, column threads, tile, z fwd, z inv, rows per wg,
 //               row threads, x fwd, x inv, y fwd, y inv>
 using P108 = SplitPipeline<double, 108, 16, 192, 8, Sched<12, 9>, Sched<9, 12>, 16, 192,
@@ -52,6 +59,8 @@ const Variant* variants_f64(int* count) {
       P108::describe("f64-n108"),
       P120::describe("f64-n120"),
       P128::describe("f64-n128"),
+      P24x48::describe("f64-n24x48"),
+      P64x128::describe("f64-n64x128"),
   };
   *count = (int)(sizeof(v) / sizeof(v[0]));
   return v;

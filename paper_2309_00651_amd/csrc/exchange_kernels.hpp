@@ -148,21 +148,22 @@ __device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const Til
 // HBM stores are never waited for (one in-order counter tracks loads and
 // stores, so a later load would wait for them).  Without PIL, psi_a is loaded
 // per orbital.
-template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL, bool SCR>
+// N: grid points along x and y; NZ: along z (slab cells: NZ != N).
+template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL, bool SCR, int NZ = N>
 __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
   constexpr int W2 = 2 * W;
-  using G = Geom<T, N, W2, NT, true, W2, 1>;
+  using G = Geom<T, NZ, W2, NT, true, W2, 1>;
   using L = LastStage<G, SZF>;
   using E = FFT<G, false, SZF>;
   constexpr int RL = SchedInfo<SZF>::last;
   constexpr int NXB = (N + W - 1) / W;
   constexpr int BR = N * NXB;
-  constexpr int P = N * W;
+  constexpr int P = NZ * W;
   constexpr int PT = (P + NT - 1) / NT;
-  constexpr long long NR = (long long)N * N * N;
-  constexpr int ZSL = (N / RL) * N * N;  // offset between legs of a last-stage butterfly
-  __shared__ cpx<T> lds[N * W2];
+  constexpr long long NR = (long long)NZ * N * N;
+  constexpr int ZSL = (NZ / RL) * N * N;  // offset between legs of a last-stage butterfly
+  __shared__ cpx<T> lds[NZ * W2];
   __shared__ TwEntry<T> twl[tw_slots<T, SZF>()];
   __shared__ T mul[TT * TT];  // pair-density means of the tile, [a][b]
   __shared__ T pil[PIL ? TT * PT * NT : 1];  // psi of the I block, [a][k][tid]
@@ -307,23 +308,23 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
 // (second register buffer), and the next orbital's psi and old K psi values
 // are loaded one step ahead.
 template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC, bool PJL, bool PF,
-          bool SCR>
+          bool SCR, int NZ = N>
 __global__ void __launch_bounds__(NT)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_inv_acc(PassArgs a) {
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
   constexpr int W2 = 2 * W;
   constexpr int QB = TT / 4;               // grid pairs per orbital a
-  using G = Geom<T, N, W2, NT, true, W2, 1>;
+  using G = Geom<T, NZ, W2, NT, true, W2, 1>;
   using F = FirstStage<G, SZI>;
   using E = FFT<G, true, SZI>;
   constexpr int RF = SchedInfo<SZI>::first;
   constexpr int NXB = (N + W - 1) / W;
   constexpr int BR = N * NXB;
-  constexpr int P = N * W;                 // brick points
+  constexpr int P = NZ * W;                // brick points
   constexpr int PT = (P + NT - 1) / NT;    // accumulation points per thread
-  constexpr long long NR = (long long)N * N * N;
-  constexpr int ZSF = (N / RF) * N * N;    // offset between legs of a first-stage butterfly
-  __shared__ cpx<T> lds[N * W2];
+  constexpr long long NR = (long long)NZ * N * N;
+  constexpr int ZSF = (NZ / RF) * N * N;   // offset between legs of a first-stage butterfly
+  __shared__ cpx<T> lds[NZ * W2];
   __shared__ double red[pow2_at_least<NT>()];
   __shared__ T pjl[PJL ? TT * PT * NT : 1];  // [b][k][tid]
   __shared__ TwEntry<T> twl[tw_slots<T, SZI>()];
@@ -601,7 +602,7 @@ constexpr int plane_waves_per_eu() {
 // plane.  The v(G) loads come first, so waiting for them never waits for the
 // prefetch (one in-order counter tracks the loads).
 template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, bool SW = false,
-          bool PP = false>
+          bool PP = false, int NZ = N>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<T, N, NT>())))
 k_plane_conv(PassArgs a) {
   static_assert(!SW || N % 8 == 0, "swizzle needs whole blocks of 8");
@@ -620,12 +621,12 @@ k_plane_conv(PassArgs a) {
   using LXI = LastStage<GX, SXI>;
   static_assert(SchedInfo<SYI>::first == SchedInfo<SYF>::last, "fused y schedules");
   static_assert(FYI::VALS == LY::VALS, "fused y register maps");
-  constexpr long long NR = (long long)N * N * N;
+  constexpr long long NR = (long long)NZ * N * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* plane = reinterpret_cast<cpx<T>*>(smem_raw);
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
-  const int total = a.n_active * N;  // planes of this launch, kz-major
+  const int total = a.n_active * NZ;  // planes of this launch, kz-major
   cpx<T>* __restrict__ gbase = static_cast<cpx<T>*>(a.grids);
 
   if (lg >= total) return;
@@ -851,7 +852,7 @@ template <typename T, int N, int W, int TT, class SZF, class SZI, int NTQ, class
           class SYF, class SYI, bool SW = false,
           int NTF = pencil_threads<T, N, W, true>(), int NTI = pencil_threads<T, N, W, false>(),
           bool PJL = pencil_prefetch<T, N, W>(), bool PF = pencil_prefetch<T, N, W>(),
-          bool PIL = false, bool PP = false>
+          bool PIL = false, bool PP = false, int NZ = N>
 struct FusedPipeline {
   static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
   // persistent plane kernel: one workgroup per plane slot of the device
@@ -870,39 +871,42 @@ struct FusedPipeline {
   }
   static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
     if (a.perm)
-      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true>), dim3(nb), dim3(NTF), 0, s, a);
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true, NZ>), dim3(nb), dim3(NTF), 0,
+                         s, a);
     else
-      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false>), dim3(nb), dim3(NTF), 0, s, a);
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false, NZ>), dim3(nb), dim3(NTF), 0,
+                         s, a);
   }
   static void plane(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP>), dim3(plane_grid(nb)),
-                       dim3(NTQ), lds, s, a);
+    hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ>),
+                       dim3(plane_grid(nb)), dim3(NTQ), lds, s, a);
   }
   static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
     if (a.perm)
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, true>), dim3(nb), dim3(NTI), 0,
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, true, NZ>), dim3(nb), dim3(NTI), 0,
                          s, a);
     else
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, false>), dim3(nb), dim3(NTI),
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, false, NZ>), dim3(nb), dim3(NTI),
                          0, s, a);
   }
   static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
     if (a.perm)
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, true>), dim3(nb), dim3(NTI), 0,
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, true, NZ>), dim3(nb), dim3(NTI), 0,
                          s, a);
     else
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, false>), dim3(nb), dim3(NTI),
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, false, NZ>), dim3(nb), dim3(NTI),
                          0, s, a);
   }
   static hipError_t prepare() {
     return hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP>),
+        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
   static Variant describe(const char* name) {
     Variant v{};
     v.name = name;
     v.n = N;
+    v.nz = NZ;
     v.prec = sizeof(T) == 8 ? 1 : 0;
     v.brick = W;
     v.tile = TT;
@@ -979,6 +983,7 @@ struct SplitPipeline {
     Variant v{};
     v.name = name;
     v.n = N;
+    v.nz = N;
     v.prec = sizeof(T) == 8 ? 1 : 0;
     v.brick = W;
     v.tile = TT;

@@ -125,12 +125,12 @@ struct hfx_graph_t {
 
 namespace {
 
-// First compiled variant for grid size n (the default), or the one named.
-const Variant* find_variant(int n, int prec, const std::string& name = "") {
+// First compiled variant for an n x n x nz grid (the default), or the one named.
+const Variant* find_variant(int n, int nz, int prec, const std::string& name = "") {
   int count = 0;
   const Variant* v = prec == HFX_FP64 ? variants_f64(&count) : variants_f32(&count);
   for (int i = 0; i < count; ++i)
-    if (v[i].n == n && (name.empty() || name == v[i].name)) return &v[i];
+    if (v[i].n == n && v[i].nz == nz && (name.empty() || name == v[i].name)) return &v[i];
   return nullptr;
 }
 
@@ -402,19 +402,20 @@ void build_screened_schedule(SystemPlan& sp, const std::vector<unsigned char>& k
 // v(G)/N_r on the FFT grid.  zero_dc: store 0 at G = 0 (float32 plans take the
 // G = 0 term out of the transforms, see run_exchange).
 template <typename T>
-std::vector<T> kernel_table(const hfx_system& s, int n, bool zero_dc, double scale) {
+std::vector<T> kernel_table(const hfx_system& s, bool zero_dc, double scale) {
   const double pi = 3.14159265358979323846;
   const double om = s.L[0] * s.L[1] * s.L[2];
-  const double nr = (double)n * n * n;
+  const int nx = s.n[0], ny = s.n[1], nz = s.n[2];
+  const double nr = (double)nx * ny * nz;
   const double rc = std::cbrt(3.0 * om / (4.0 * pi));
-  std::vector<T> out((size_t)n * n * n);
-  auto freq = [n](int k) { return k < (n + 1) / 2 ? k : k - n; };
-  for (int z = 0; z < n; ++z)
-    for (int y = 0; y < n; ++y)
-      for (int x = 0; x < n; ++x) {
-        const double gx = 2 * pi * freq(x) / s.L[0];
-        const double gy = 2 * pi * freq(y) / s.L[1];
-        const double gz = 2 * pi * freq(z) / s.L[2];
+  std::vector<T> out((size_t)nx * ny * nz);
+  auto freq = [](int k, int n) { return k < (n + 1) / 2 ? k : k - n; };
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const double gx = 2 * pi * freq(x, nx) / s.L[0];
+        const double gy = 2 * pi * freq(y, ny) / s.L[1];
+        const double gz = 2 * pi * freq(z, nz) / s.L[2];
         const double g2 = gx * gx + gy * gy + gz * gz;
         double v;
         if (s.kernel == HFX_KERNEL_TRUNCATED) {
@@ -428,7 +429,7 @@ std::vector<T> kernel_table(const hfx_system& s, int n, bool zero_dc, double sca
           const double w = s.param;
           v = g2 == 0.0 ? pi / (w * w) : -4 * pi * std::expm1(-g2 / (4 * w * w)) / g2;
         }
-        out[((size_t)z * n + y) * n + x] = T(scale * v / nr);
+        out[((size_t)z * ny + y) * nx + x] = T(scale * v / nr);
       }
   if (zero_dc) out[0] = T(0);
   return out;
@@ -474,8 +475,8 @@ hfx_status validate_system(const hfx_system& s, int idx) {
     return fail(HFX_EINVAL, "unknown kernel" + at);
   if (s.kernel == HFX_KERNEL_ERFC && !(s.param > 0.0 && std::isfinite(s.param)))
     return fail(HFX_EINVAL, "erfc kernel needs w > 0" + at);
-  if (s.n[0] != s.n[1] || s.n[1] != s.n[2])
-    return fail(HFX_EUNSUPPORTED, "only cubic grids n x n x n are supported" + at);
+  if (s.n[0] != s.n[1])
+    return fail(HFX_EUNSUPPORTED, "grids need n_x == n_y (n_z may differ: slab cells)" + at);
   return HFX_OK;
 }
 
@@ -594,11 +595,12 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   a.perm = sp.d_perm;
   a.n_orb = sp.sys.n_orb;
   const int br = bricks_per_tile(v);
-  const int n = v->n;
+  const int n = v->n, nz = v->nz;
   const int nxb = (n + v->brick - 1) / v->brick;
   const double nr = (double)sp.nr, ce = 2.0 * elem;  // complex element bytes
   // FFT flops per complex grid and axis pass: 5 N_r log2(N) (radix-2 count)
-  const double fft_axis = 5.0 * nr * std::log2((double)n);
+  const double fft_axis = 5.0 * nr * std::log2((double)n);      // x or y
+  const double fft_z = 5.0 * nr * std::log2((double)nz);
   // Two batch streams: batch k runs on stream k % 2 with grid buffer k % 2.
   // Its inv_acc waits for batch k-1's, so K psi receives its updates in the
   // serial order (identical results) while the transforms of one batch
@@ -644,11 +646,11 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
     {
       Bracket bk(plan, HFX_PASS_PAIR_FWD, bs);
       v->pair_fwd(a, b.n_tiles * br, bs);
-      bk.done(orbs * nr * elem + grids * nr * ce, grids * fft_axis);
+      bk.done(orbs * nr * elem + grids * nr * ce, grids * fft_z);
     }
     if (v->plane_mode == 0) {
       Bracket bk(plan, HFX_PASS_PLANE, bs);
-      v->plane(a, b.n_active * n, bs);
+      v->plane(a, b.n_active * nz, bs);
       bk.done(grids * nr * ce * 2.0, grids * fft_axis * 4.0);
     } else {
       const int rb = (n * n + v->rows_per_wg - 1) / v->rows_per_wg;
@@ -672,11 +674,11 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
     if (acc) {
       Bracket bk(plan, HFX_PASS_INV_ACC, bs);
       v->inv_acc(a, b.n_tiles * br, bs);
-      bk.done(grids * nr * ce + orbs * nr * elem * 3.0, grids * fft_axis);
+      bk.done(grids * nr * ce + orbs * nr * elem * 3.0, grids * fft_z);
     } else {
       Bracket bk(plan, HFX_PASS_INV_ENERGY, bs);
       v->inv_energy(a, b.n_tiles * br, bs);
-      bk.done(grids * nr * ce + orbs * nr * elem, grids * fft_axis);
+      bk.done(grids * nr * ce + orbs * nr * elem, grids * fft_z);
     }
     if (two) HIP_TRY(hipEventRecord(sp.ev_acc[q], bs));
   }
@@ -895,7 +897,7 @@ const char* hfx_variants(int n, int precision) {
   int count = 0;
   const Variant* v = precision == HFX_FP64 ? variants_f64(&count) : variants_f32(&count);
   for (int i = 0; i < count; ++i)
-    if (v[i].n == n) {
+    if (v[i].n == n && v[i].nz == n) {  // cubic grids
       if (!out.empty()) out += ";";
       out += v[i].name;
     }
@@ -914,8 +916,9 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   for (int i = 0; i < n_sys; ++i) {
     hfx_status s = validate_system(sys[i], i);
     if (s != HFX_OK) return s;
-    if (!find_variant(sys[i].n[0], precision))
-      return fail(HFX_EUNSUPPORTED, "grid size " + std::to_string(sys[i].n[0]) +
+    if (!find_variant(sys[i].n[0], sys[i].n[2], precision))
+      return fail(HFX_EUNSUPPORTED, "grid " + std::to_string(sys[i].n[0]) + "^2 x " +
+                                        std::to_string(sys[i].n[2]) +
                                         " is not supported (system " + std::to_string(i) +
                                         ")");
   }
@@ -957,7 +960,7 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   const std::string vname = parse_option_str(options, "variant");
   if (!vname.empty() && n_sys > 1)
     return fail(HFX_EINVAL, "variant= applies to single-system plans only");
-  if (!vname.empty() && !find_variant(sys[0].n[0], precision, vname))
+  if (!vname.empty() && !find_variant(sys[0].n[0], sys[0].n[2], precision, vname))
     return fail(HFX_EINVAL, "unknown variant '" + vname + "' for this grid and precision");
   if (batch_streams != 1 && batch_streams != 2)
     return fail(HFX_EINVAL, "streams= must be 1 or 2");
@@ -975,9 +978,9 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   for (int i = 0; i < n_sys; ++i) {
     SystemPlan& sp = p->sys[i];
     sp.sys = sys[i];
-    sp.var = find_variant(sys[i].n[0], precision, vname);
+    sp.var = find_variant(sys[i].n[0], sys[i].n[2], precision, vname);
     sp.n = sys[i].n[0];
-    sp.nr = (long long)sp.n * sp.n * sp.n;
+    sp.nr = (long long)sp.n * sp.n * sys[i].n[2];
     sp.dv = sys[i].L[0] * sys[i].L[1] * sys[i].L[2] / (double)sp.nr;
     sp.shard = shard;
     sp.shards = shards;
@@ -1046,9 +1049,9 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     // the gradient alike
     sp.v0 = mix * kernel_g0(sp.sys);
     if (precision == HFX_FP64)
-      s = upload(kernel_table<double>(sp.sys, sp.n, false, mix), &sp.vtab);
+      s = upload(kernel_table<double>(sp.sys, false, mix), &sp.vtab);
     else
-      s = upload(kernel_table<float>(sp.sys, sp.n, true, mix), &sp.vtab);
+      s = upload(kernel_table<float>(sp.sys, true, mix), &sp.vtab);
     if (s != HFX_OK) return cleanup(s);
     const Variant* v = sp.var;
     const int* rs[6] = {v->zf, v->zi, v->xf, v->xi, v->yf, v->yi};
@@ -1320,6 +1323,7 @@ const char* hfx_plan_describe(hfx_plan plan, int system) {
     return o;
   };
   std::string d = std::string("variant=") + v->name + " n=" + std::to_string(v->n) +
+                  (v->nz != v->n ? " nz=" + std::to_string(v->nz) : std::string()) +
                   " tile=" + std::to_string(v->tile) + " brick=" + std::to_string(v->brick) +
                   " z=" + sched(v->zf, v->nzf) + "/" + sched(v->zi, v->nzi) +
                   " x=" + sched(v->xf, v->nxf) + "/" + sched(v->xi, v->nxi) +

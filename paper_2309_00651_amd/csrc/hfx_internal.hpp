@@ -55,7 +55,8 @@ typedef void (*launch_fn)(const PassArgs&, int nblocks, hipStream_t);
 // precision: radix schedules, launch shapes and the launchers.
 struct Variant {
   const char* name;
-  int n;           // grid points per axis
+  int n;           // grid points along x and y
+  int nz;          // grid points along z (n for cubic grids)
   int prec;        // 0 float32, 1 float64
   int brick;       // pencil width W (x values per workgroup)
   int tile;        // orbital tile T

@@ -123,15 +123,21 @@ def _stream():
 
 @dataclass(frozen=True)
 class SystemSpec:
-    n: int
+    n: object          # grid points per axis (cubic), or (nx, ny, nz) with nx == ny
     box: tuple
     n_orb: int
     kernel: int = TRUNCATED
     param: float = 0.0
 
+    @property
+    def shape_xyz(self):
+        return tuple(int(x) for x in self.n) if isinstance(self.n, (tuple, list)) \
+            else (int(self.n),) * 3
+
     def to_c(self):
         s = System()
-        s.n[0] = s.n[1] = s.n[2] = int(self.n)
+        for k, v in enumerate(self.shape_xyz):
+            s.n[k] = v
         for k in range(3):
             s.L[k] = float(self.box[k])
         s.n_orb = int(self.n_orb)
@@ -141,7 +147,8 @@ class SystemSpec:
 
     @property
     def nr(self):
-        return self.n ** 3
+        nx, ny, nz = self.shape_xyz
+        return nx * ny * nz
 
     @property
     def dv(self):
@@ -347,7 +354,8 @@ class Plan:
         out, off = [], 0
         for s in self.systems:
             k = s.n_orb * s.nr
-            out.append(flat.reshape(-1)[off:off + k].view(s.n_orb, s.n, s.n, s.n))
+            nx, ny, nz = s.shape_xyz
+            out.append(flat.reshape(-1)[off:off + k].view(s.n_orb, nz, ny, nx))
             off += k
         return out
 

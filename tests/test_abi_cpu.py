@@ -73,13 +73,20 @@ def test_plan_validation(lib, spec, code, msg):
     assert st == code and msg in err and not h.value
 
 
-def test_non_cubic_grid_unsupported(lib):
+def test_unsupported_grid_shapes(lib):
+    """n_x != n_y, and an n x n x n_z slab grid without a compiled variant,
+    are rejected before any device call."""
     s = GOOD.to_c()
     s.n[2] = 32
     arr = (hfx.System * 1)(s)
     h = ctypes.c_void_p()
     assert lib.hfx_plan_create(ctypes.byref(h), arr, 1, 0, None) == 2
-    assert "cubic" in lib.hfx_last_error().decode()
+    assert "not supported" in lib.hfx_last_error().decode()
+    s = GOOD.to_c()
+    s.n[1] = s.n[0] + 8
+    arr = (hfx.System * 1)(s)
+    assert lib.hfx_plan_create(ctypes.byref(h), arr, 1, 0, None) == 2
+    assert "n_x == n_y" in lib.hfx_last_error().decode()
 
 
 def test_bad_precision_and_counts(lib):

@@ -121,3 +121,41 @@ def test_mixing_fraction(prec):
     assert np.max(np.abs(m.view(n_orb, n_orb).cpu().numpy() - m_ref)) <= \
         np.sqrt(L ** 3) * k_bar + 1e-12
     assert np.max(np.abs(grad.cpu().numpy() - 2 * dv * a * ref["kpsi"])) <= 2 * dv * k_bar
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=IDS)
+@pytest.mark.parametrize("nxy,nz,box,kernel,param,family,n_orb", [
+    (24, 48, (10.0, 10.0, 20.0), hfx.TRUNCATED, 0.0, "pw", 9),
+    (64, 128, (15.7, 15.7, 31.3), hfx.ERFC, 0.106, "g", 12),
+])
+def test_slab_grid(prec, nxy, nz, box, kernel, param, family, n_orb):
+    """Slab cells: an n x n x nz grid (z transforms of length nz) on an
+    elongated box; K psi, E_x, the exchange matrix and the gradient against
+    the oracle on the same grid."""
+    print(f"case slab {nxy}x{nxy}x{nz} box={box} prec={prec}", flush=True)
+    shape = (nz, nxy, nxy)
+    if family == "pw":
+        psi = generate.random_pw(shape, box, n_orb, 5.0, seed=4700 + nz)
+    else:
+        psi = generate.gaussians(shape, box, n_orb, 20.0, seed=4700 + nz)[0]
+    vg = oracle.coulomb_kernel(shape, box, kernel, param)
+    ref = oracle.exchange(psi, box, vg, workers=4)
+    dv = box[0] * box[1] * box[2] / psi[0].size
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec((nxy, nxy, nz), box, n_orb, kernel, param), prec, device=dev)
+    pt = torch.from_numpy(psi).to(dev)
+    kpsi, ex = plan.apply_exchange(pt)
+    m = plan.exchange_matrix(pt, kpsi)
+    grad = plan.exchange_gradient(pt)
+    torch.cuda.synchronize()
+    e_bar, k_bar = bars(prec, ref["kpsi"])
+    rel = abs(float(ex[0]) - ref["ex"]) / abs(ref["ex"])
+    k = kpsi.double().cpu().numpy()
+    dk = np.max(np.abs(k - ref["kpsi"]))
+    print(f"  rel dE {rel:.2e} max dK {dk:.2e} {plan.describe()}", flush=True)
+    assert rel <= e_bar and dk <= k_bar
+    m_ref = oracle.exchange_matrix(psi, ref["kpsi"], dv)
+    omega = box[0] * box[1] * box[2]
+    assert np.max(np.abs(m.view(n_orb, n_orb).cpu().numpy() - m_ref)) <= \
+        np.sqrt(omega) * k_bar + 1e-12
+    assert np.max(np.abs(grad.cpu().numpy() - 2 * dv * ref["kpsi"])) <= 2 * dv * k_bar
