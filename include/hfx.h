@@ -98,7 +98,13 @@ typedef struct hfx_plan_t* hfx_plan;
  * r % R == g, one of R virtual groups of the pair list (the way the pairs
  * would be dealt over R GPUs): K psi, E_x, M and the gradient are then that
  * group's partial sums, which add up over g = 0..R-1 to the full result (the
- * G = 0 energy of the pair means is added by group 0); mix=<a>, 0 < a <= 1,
+ * G = 0 energy of the pair means is added by group 0); rows=<R>, R in
+ * {8, 16, 24, 32}, sets the rows of a tile pair (R orbitals x the 8-orbital
+ * column tile): more rows read psi and update K psi of the column tile once
+ * per R pairs instead of once per 8 (default 32 for systems of at least 256
+ * orbitals, else 16; clamped to 8 for variants that stage the row orbitals
+ * in LDS; screened schedules use 8 x 8 tiles; results agree to rounding, not
+ * bitwise, across R); mix=<a>, 0 < a <= 1,
  * is a hybrid functional's exact-exchange fraction: the kernel is scaled by a,
  * so E_x, K psi, M, the gradient and the ACE operator are a times the full
  * exchange (default 1).  Open-shell systems are two systems of one plan, the

@@ -1,8 +1,8 @@
 """Autotuner for libhfx plans.
 
 Times every compiled kernel configuration for a system's grid size
-(``hfx.variants``) crossed with a few orbital-tile batch sizes, on the
-caller's orbitals, with HIP events around ``apply_exchange``; the fastest
+(``hfx.variants``) crossed with a few orbital-tile batch sizes and rows per
+tile pair (those that fit the orbital count), on the caller's orbitals, with HIP events around ``apply_exchange``; the fastest
 candidate wins, and among candidates within ``tie`` of the fastest the first
 in a fixed candidate order is taken, so re-runs agree.  Results are cached in
 a JSON file keyed by GPU architecture, grid, orbital count, precision and a
@@ -19,6 +19,7 @@ import torch
 from . import hfx
 
 TILE_CHOICES = (4, 8, 16)
+ROW_CHOICES = (8, 16, 32)
 
 
 def _build_id():
@@ -35,10 +36,14 @@ def cache_key(spec, precision):
 
 
 def candidates(spec, precision):
+    # rows beyond the orbital count (rounded up to a column tile) repeat the
+    # schedule of the largest row count that fits
+    rows = [r for r in ROW_CHOICES if r == ROW_CHOICES[0] or r <= -(-spec.n_orb // 8) * 8]
     out = []
     for v in hfx.variants(spec.n, precision):
         for t in TILE_CHOICES:
-            out.append(f"variant={v};tiles={t}")
+            for r in rows:
+                out.append(f"variant={v};tiles={t};rows={r}")
     return out
 
 

@@ -77,12 +77,13 @@ __device__ __forceinline__ int orb_at(const PassArgs& a, int p) {
   return p;
 }
 
-// Whether pair (a, b) of a tile is evaluated: inside the blocks, a <= b on a
-// diagonal tile, and, in screened plans, kept by the tile's mask (8-orbital
-// tiles).  Unscreened plans compile without the mask tests.
+// Whether pair (a, b) of a tile is evaluated: inside the blocks, i <= j on a
+// tile inside one diagonal block (row a is orbital i0 + a, column b is
+// orbital j0 + b = i0 + joff + b), and, in screened plans, kept by the tile's
+// mask (8-orbital tiles).  Unscreened plans compile without the mask tests.
 template <int TT, bool SCR>
 __device__ __forceinline__ bool pair_live(const TileDesc& td, int ia, int b) {
-  if (b >= td.nJ || (td.diag && b < ia)) return false;
+  if (b >= td.nJ || (td.diag && b + td.joff < ia)) return false;
   if constexpr (SCR && TT == 8) return (td.keep >> (8 * ia + b)) & 1ull;
   return true;
 }
@@ -121,13 +122,13 @@ __device__ __forceinline__ int next_live_row(unsigned rows, int ia, int nI) {
   return ia + 1;
 }
 
-// scale * (pair-density mean) for the TT x TT pairs of a tile, [a][b], zero
-// outside the tile or without means (float64 plans): staged in LDS so that
-// the loops below issue no global loads besides their own data.
+// scale * (pair-density mean) for the kMaxRows x TT pairs of a tile, [a][b],
+// zero outside the tile or without means (float64 plans): staged in LDS so
+// that the loops below issue no global loads besides their own data.
 template <typename T, int TT, int NT, bool SCR>
 __device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const TileDesc& td,
                                             double scale, int tid) {
-  for (int q = tid; q < TT * TT; q += NT) {
+  for (int q = tid; q < kMaxRows * TT; q += NT) {
     const int ia = q / TT, b = q - ia * TT;
     dst[q] = (a.mean && ia < td.nI && b < td.nJ)
                  ? (T)(scale * a.mean[(long long)orb_at<SCR>(a, td.i0 + ia) * a.n_orb +
@@ -165,7 +166,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   constexpr int ZSL = (NZ / RL) * N * N;  // offset between legs of a last-stage butterfly
   __shared__ cpx<T> lds[NZ * W2];
   __shared__ TwEntry<T> twl[tw_slots<T, SZF>()];
-  __shared__ T mul[TT * TT];  // pair-density means of the tile, [a][b]
+  __shared__ T mul[kMaxRows * TT];  // pair-density means of the tile, [a][b]
   __shared__ T pil[PIL ? TT * PT * NT : 1];  // psi of the I block, [a][k][tid]
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
@@ -328,7 +329,7 @@ __global__ void __launch_bounds__(NT)
   __shared__ double red[pow2_at_least<NT>()];
   __shared__ T pjl[PJL ? TT * PT * NT : 1];  // [b][k][tid]
   __shared__ TwEntry<T> twl[tw_slots<T, SZI>()];
-  __shared__ T dcl[TT * TT];  // v(0) * pair-density mean, [a][b]
+  __shared__ T dcl[kMaxRows * TT];  // v(0) * pair-density mean, [a][b]
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   const int t = lg / BR, br = lg - t * BR;
@@ -470,7 +471,7 @@ __global__ void __launch_bounds__(NT)
       // weight of e_ab in sum_{i,j} e_ij: 2 for a != b, 1 for a == b, 0 for
       // pairs not evaluated
       if (!pair_live<TT, SCR>(td, ia, b)) return;
-      const int w = (td.diag && b == ia) ? 1 : 2;
+      const int w = (td.diag && b + td.joff == ia) ? 1 : 2;
       // G = 0 part of v_ab when the mean was taken out of the transform;
       // its energy v0 * Omega * mu_ab^2 is added in float64 at the reduction
       const T dc = dcl[ia * TT + b];
@@ -910,6 +911,7 @@ struct FusedPipeline {
     v.prec = sizeof(T) == 8 ? 1 : 0;
     v.brick = W;
     v.tile = TT;
+    v.max_rows = PIL ? TT : kMaxRows;
     v.nt_fwd = NTF;
     v.nt_acc = NTI;
     v.nt_plane = NTQ;
@@ -987,6 +989,7 @@ struct SplitPipeline {
     v.prec = sizeof(T) == 8 ? 1 : 0;
     v.brick = W;
     v.tile = TT;
+    v.max_rows = PIL ? TT : kMaxRows;
     v.nt_fwd = NTF;
     v.nt_acc = NTI;
     v.nt_plane = NTQ;

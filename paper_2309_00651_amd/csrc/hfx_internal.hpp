@@ -11,18 +11,25 @@ namespace hfx {
 
 // One orbital tile: pairs (a, b) with a in [i0, i0+nI) and b in [j0, j0+nJ).
 // Off-diagonal tiles (diag == 0, disjoint blocks) take every (a, b); diagonal
-// tiles (the same block twice) take a <= b.  Packed pair-grid slot of
+// tiles (J inside I's block) take a <= b.  Packed pair-grid slot of
 // (a - i0, b - j0) is slot0 + (a - i0) * (tile / 2) + (b - j0) / 2: the two
 // pairs (a, 2p) and (a, 2p+1) share one complex grid (real and imaginary part).
-// One tile pair of orbital blocks: positions i0..i0+nI-1 (I) and j0..j0+nJ-1
-// (J) in the plan's orbital order (see PassArgs::perm); diag when I == J (pairs
-// a <= b only); slot0 = first pair-grid slot.  keep: bit 8 a + b set when the
-// pair (position a of I, position b of J) is evaluated (all set unless the
-// pairs are screened; only 8-orbital tiles are screened).
+// One tile pair: rows i0..i0+nI-1 (I, up to kMaxRows) and columns
+// j0..j0+nJ-1 (J, one tile of `tile` orbitals) in the plan's orbital order
+// (see PassArgs::perm).  diag when both lie in one diagonal block of the
+// schedule: J starts joff = j0 - i0 rows into I and only pairs i <= j are
+// evaluated (row a, column b with a <= b + joff).  slot0 = first pair-grid
+// slot.  keep: bit 8 a + b set when the pair (position a of I, position b of
+// J) is evaluated (all set unless the pairs are screened; only 8 x 8 tiles
+// are screened).
 struct TileDesc {
-  int i0, nI, j0, nJ, diag, slot0;
+  int i0, nI, j0, nJ, diag, joff, slot0;
   unsigned long long keep;
 };
+
+// Most rows a tile may have: the pass kernels stage kMaxRows x tile pair
+// means in LDS.
+constexpr int kMaxRows = 32;
 
 // Arguments of one exchange pass over one batch of tiles of one system.
 struct PassArgs {
@@ -59,7 +66,8 @@ struct Variant {
   int nz;          // grid points along z (n for cubic grids)
   int prec;        // 0 float32, 1 float64
   int brick;       // pencil width W (x values per workgroup)
-  int tile;        // orbital tile T
+  int tile;        // orbital tile T (columns of a tile pair)
+  int max_rows;    // most rows per tile pair (T when psi of I is staged in LDS)
   int nt_fwd;      // threads per pair_fwd workgroup
   int nt_acc;      // threads per inv_acc workgroup
   int nt_plane;    // threads per plane workgroup (plane_mode 1: per row workgroup)
