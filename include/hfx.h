@@ -103,8 +103,9 @@ typedef struct hfx_plan_t* hfx_plan;
  * column tile): more rows read psi and update K psi of the column tile once
  * per R pairs instead of once per 8 (default 32 for systems of at least 256
  * orbitals, else 16; clamped to 8 for variants that stage the row orbitals
- * in LDS; screened schedules use 8 x 8 tiles; results agree to rounding, not
- * bitwise, across R); mix=<a>, 0 < a <= 1,
+ * in LDS; screened schedules use the same tile pairs with masks of the kept
+ * pairs; results agree to rounding, not bitwise, across R); mix=<a>,
+ * 0 < a <= 1,
  * is a hybrid functional's exact-exchange fraction: the kernel is scaled by a,
  * so E_x, K psi, M, the gradient and the ACE operator are a times the full
  * exchange (default 1).  Open-shell systems are two systems of one plan, the

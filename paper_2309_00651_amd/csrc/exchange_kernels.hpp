@@ -80,11 +80,12 @@ __device__ __forceinline__ int orb_at(const PassArgs& a, int p) {
 // Whether pair (a, b) of a tile is evaluated: inside the blocks, i <= j on a
 // tile inside one diagonal block (row a is orbital i0 + a, column b is
 // orbital j0 + b = i0 + joff + b), and, in screened plans, kept by the tile's
-// mask (8-orbital tiles).  Unscreened plans compile without the mask tests.
+// mask (8-orbital column tiles).  Unscreened plans compile without the mask
+// tests.
 template <int TT, bool SCR>
 __device__ __forceinline__ bool pair_live(const TileDesc& td, int ia, int b) {
   if (b >= td.nJ || (td.diag && b + td.joff < ia)) return false;
-  if constexpr (SCR && TT == 8) return (td.keep >> (8 * ia + b)) & 1ull;
+  if constexpr (SCR && TT == 8) return (keep_word(td, ia >> 3) >> (8 * (ia & 7) + b)) & 1ull;
   return true;
 }
 
@@ -96,7 +97,8 @@ __device__ __forceinline__ unsigned live_rows(const TileDesc& td) {
   if constexpr (SCR && TT == 8) {
     unsigned r = 0;
 #pragma unroll
-    for (int a = 0; a < 8; ++a) r |= (((td.keep >> (8 * a)) & 0xffull) != 0 ? 1u : 0u) << a;
+    for (int a = 0; a < kMaxRows; ++a)
+      r |= (((keep_word(td, a >> 3) >> (8 * (a & 7))) & 0xffull) != 0 ? 1u : 0u) << a;
     return r;
   }
   return ~0u;
@@ -104,7 +106,7 @@ __device__ __forceinline__ unsigned live_rows(const TileDesc& td) {
 template <int TT, bool SCR>
 __device__ __forceinline__ unsigned live_cols(const TileDesc& td) {
   if constexpr (SCR && TT == 8) {
-    unsigned long long k = td.keep;
+    unsigned long long k = td.keep0 | td.keep1 | td.keep2 | td.keep3;
     k |= k >> 32;
     k |= k >> 16;
     k |= k >> 8;

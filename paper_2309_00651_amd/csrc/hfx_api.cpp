@@ -279,7 +279,7 @@ void build_schedule(SystemPlan& sp, long long tiles_cap) {
         td.diag = bp.first == bp.second ? 1 : 0;
         td.joff = td.diag ? td.j0 - td.i0 : 0;
         if (td.diag) td.nI = std::min(td.nI, td.joff + td.nJ);
-        td.keep = ~0ull;
+        td.keep0 = td.keep1 = td.keep2 = td.keep3 = ~0ull;
         group.push_back(td);
       }
       for (size_t s0 = 0; s0 < group.size(); s0 += tpb) {
@@ -347,46 +347,71 @@ std::vector<int> cluster_order(int n, int tile, const std::vector<double>& a,
   return order;
 }
 
-// Schedule of a screened plan: 8 x 8 tile pairs of the reordered orbitals
-// that keep at least one pair, packed greedily (first fit, in (I, J) order)
-// into batches with disjoint orbital blocks, as many per batch as the
-// unscreened plan's pair-grid slots hold (so the workspace still fits).
+// Bit of pair (row a, column b) in a tile's keep mask.
+bool keep_bit(const TileDesc& td, int a, int b) {
+  return (keep_word(td, a >> 3) >> (8 * (a & 7) + b)) & 1ull;
+}
+
+// Schedule of a screened plan: the tile pairs of the unscreened schedule's
+// shape (R rows x 8 columns over the reordered orbitals, i <= j inside a
+// diagonal block) that keep at least one pair, each with the mask of its kept
+// pairs, packed greedily (first fit, in (I, J, q) order) into batches whose
+// tile pairs touch disjoint orbitals, as many per batch as the unscreened
+// plan's pair-grid slots hold (so the workspace still fits).
 void build_screened_schedule(SystemPlan& sp, const std::vector<unsigned char>& keep,
                              const std::vector<int>& perm) {
   const Variant* v = sp.var;
-  const int T = v->tile, n = sp.sys.n_orb;
-  const int nb = (n + T - 1) / T;
+  const int T = v->tile, R = sp.rows, n = sp.sys.n_orb;
+  const int nb = (n + R - 1) / R, nc = (n + T - 1) / T;
   const int br = bricks_per_tile(v);
-  const int tpb = std::max(1, sp.slots_per_batch / (T * (T / 2)));
+  const int tpb = std::max(1, sp.slots_per_batch / (R * (T / 2)));
   sp.tiles_per_batch = tpb;
-  struct TP {
-    int bi, bj;
-    unsigned long long mask;
-  };
-  std::vector<TP> tps;
+  std::vector<TileDesc> tps;
   for (int bi = 0; bi < nb; ++bi)
-    for (int bj = bi; bj < nb; ++bj) {
-      unsigned long long mask = 0;
-      for (int a = 0; a < T; ++a)
-        for (int b = 0; b < T; ++b) {
-          const int pa = bi * T + a, pb = bj * T + b;
-          if (pa >= n || pb >= n || (bi == bj && b < a)) continue;
-          if (keep[(size_t)perm[pa] * n + perm[pb]]) mask |= 1ull << (8 * a + b);
-        }
-      if (mask) tps.push_back({bi, bj, mask});
-    }
-  std::vector<std::vector<TP>> batches;
+    for (int bj = bi; bj < nb; ++bj)
+      for (int q = 0; q < R / T; ++q) {
+        TileDesc td{};
+        td.i0 = bi * R;
+        td.j0 = bj * R + q * T;
+        if (td.j0 >= n) continue;
+        td.nJ = std::min(T, n - td.j0);
+        td.nI = std::min(R, n - td.i0);
+        td.diag = bi == bj ? 1 : 0;
+        td.joff = td.diag ? td.j0 - td.i0 : 0;
+        if (td.diag) td.nI = std::min(td.nI, td.joff + td.nJ);
+        bool any = false;
+        for (int a = 0; a < td.nI; ++a)
+          for (int b = 0; b < td.nJ; ++b) {
+            if (td.diag && b + td.joff < a) continue;
+            if (keep[(size_t)perm[td.i0 + a] * n + perm[td.j0 + b]]) {
+              unsigned long long* w[4] = {&td.keep0, &td.keep1, &td.keep2, &td.keep3};
+              *w[a >> 3] |= 1ull << (8 * (a & 7) + b);
+              any = true;
+            }
+          }
+        if (any) tps.push_back(td);
+      }
+  // first fit; a tile pair occupies the T-orbital column tiles of its rows
+  // and its column tile
+  std::vector<std::vector<TileDesc>> batches;
   std::vector<std::vector<char>> used;
-  for (const TP& t : tps) {
+  for (const TileDesc& t : tps) {
+    const int c0 = t.i0 / T, c1 = (t.i0 + t.nI - 1) / T, cj = t.j0 / T;
+    auto fits = [&](const std::vector<char>& u) {
+      for (int c = c0; c <= c1; ++c)
+        if (u[c]) return false;
+      return !u[cj];
+    };
     size_t k = 0;
     for (; k < batches.size(); ++k)
-      if ((int)batches[k].size() < tpb && !used[k][t.bi] && !used[k][t.bj]) break;
+      if ((int)batches[k].size() < tpb && fits(used[k])) break;
     if (k == batches.size()) {
       batches.emplace_back();
-      used.emplace_back(nb, 0);
+      used.emplace_back(nc, 0);
     }
     batches[k].push_back(t);
-    used[k][t.bi] = used[k][t.bj] = 1;
+    for (int c = c0; c <= c1; ++c) used[k][c] = 1;
+    used[k][cj] = 1;
   }
   sp.tiles.clear();
   sp.active.clear();
@@ -399,23 +424,13 @@ void build_screened_schedule(SystemPlan& sp, const std::vector<unsigned char>& k
     b.active_off = (int)sp.active.size();
     b.part_base = part;
     for (size_t q = 0; q < batches[k].size(); ++q) {
-      const TP& t = batches[k][q];
-      TileDesc td{};
-      td.i0 = t.bi * T;
-      td.nI = std::min(T, n - td.i0);
-      td.j0 = t.bj * T;
-      td.nJ = std::min(T, n - td.j0);
-      td.diag = t.bi == t.bj ? 1 : 0;
-      td.joff = 0;
-      td.slot0 = (int)q * T * (T / 2);
-      td.keep = t.mask;
-      auto live = [&](int a, int bb) {
-        return bb < td.nJ && !(td.diag && bb < a) && ((t.mask >> (8 * a + bb)) & 1ull);
-      };
+      TileDesc td = batches[k][q];
+      td.slot0 = (int)q * R * (T / 2);
       for (int ia = 0; ia < td.nI; ++ia)
-        for (int bp = 0; bp < T / 2; ++bp)
-          if (live(ia, 2 * bp) || live(ia, 2 * bp + 1))
-            sp.active.push_back(td.slot0 + ia * (T / 2) + bp);
+        for (int g = 0; g < T / 2; ++g)
+          if ((2 * g < td.nJ && keep_bit(td, ia, 2 * g)) ||
+              (2 * g + 1 < td.nJ && keep_bit(td, ia, 2 * g + 1)))
+            sp.active.push_back(td.slot0 + ia * (T / 2) + g);
       sp.tiles.push_back(td);
     }
     b.n_tiles = (int)sp.tiles.size() - b.tile_off;
@@ -656,15 +671,16 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
       const TileDesc& td = sp.tiles[b.tile_off + t];
       if (sp.d_keep) {
         // screened: only rows and columns with an evaluated pair are touched
-        unsigned rows = 0, cols = 0;
-        for (int r = 0; r < 8; ++r)
-          for (int c = 0; c < 8; ++c)
-            if ((td.keep >> (8 * r + c)) & 1ull) {
-              rows |= 1u << r;
-              cols |= 1u << c;
+        // (in a diagonal tile, column b is row joff + b)
+        unsigned long long rows = 0, cols = 0;
+        for (int r = 0; r < td.nI; ++r)
+          for (int c = 0; c < td.nJ; ++c)
+            if (keep_bit(td, r, c)) {
+              rows |= 1ull << r;
+              cols |= 1ull << (td.diag ? td.joff + c : c);
             }
-        orbs += td.diag ? __builtin_popcount(rows | cols)
-                        : __builtin_popcount(rows) + __builtin_popcount(cols);
+        orbs += td.diag ? __builtin_popcountll(rows | cols)
+                        : __builtin_popcountll(rows) + __builtin_popcountll(cols);
       } else {
         orbs += td.diag ? td.nI : td.nI + td.nJ;  // J lies inside I's rows
       }
@@ -1371,7 +1387,7 @@ const char* hfx_plan_describe(hfx_plan plan, int system) {
                   std::to_string(v->plane_mode == 0 ? v->nt_plane : v->nt_cols) + "/" +
                   std::to_string(v->nt_acc) + " plane=" +
                   (v->plane_mode == 0 ? "fused" : "split") +
-                  " rows=" + std::to_string(sp.d_keep ? v->tile : sp.rows) +
+                  " rows=" + std::to_string(sp.rows) +
                   " tiles_per_batch=" + std::to_string(sp.tiles_per_batch) +
                   " batches=" + std::to_string(sp.batches.size()) +
                   " streams=" + std::to_string(sp.nstreams) +
@@ -1403,12 +1419,11 @@ hfx_status hfx_schedule_info(hfx_plan plan, int system, long long* info) {
   if (system < 0 || system >= (int)plan->sys.size()) return fail(HFX_EINVAL, "no such system");
   const SystemPlan& sp = plan->sys[system];
   long long pairs = 0;
-  const bool masked = sp.d_keep != nullptr;  // screened schedules: 8 x 8 tiles with masks
+  const bool masked = sp.d_keep != nullptr;  // screened schedules carry pair masks
   for (const TileDesc& td : sp.tiles)
     for (int a = 0; a < td.nI; ++a)
       for (int b = 0; b < td.nJ; ++b)
-        if (!(td.diag && b + td.joff < a) && (!masked || ((td.keep >> (8 * a + b)) & 1ull)))
-          ++pairs;
+        if (!(td.diag && b + td.joff < a) && (!masked || keep_bit(td, a, b))) ++pairs;
   info[0] = (long long)sp.batches.size();
   info[1] = (long long)sp.tiles.size();
   info[2] = (long long)sp.active.size();

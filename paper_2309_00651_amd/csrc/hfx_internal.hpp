@@ -14,22 +14,34 @@ namespace hfx {
 // tiles (J inside I's block) take a <= b.  Packed pair-grid slot of
 // (a - i0, b - j0) is slot0 + (a - i0) * (tile / 2) + (b - j0) / 2: the two
 // pairs (a, 2p) and (a, 2p+1) share one complex grid (real and imaginary part).
+// Most rows a tile pair may have: the pass kernels stage kMaxRows x tile pair
+// means in LDS.
+constexpr int kMaxRows = 32;
+
 // One tile pair: rows i0..i0+nI-1 (I, up to kMaxRows) and columns
 // j0..j0+nJ-1 (J, one tile of `tile` orbitals) in the plan's orbital order
 // (see PassArgs::perm).  diag when both lie in one diagonal block of the
 // schedule: J starts joff = j0 - i0 rows into I and only pairs i <= j are
 // evaluated (row a, column b with a <= b + joff).  slot0 = first pair-grid
-// slot.  keep: bit 8 a + b set when the pair (position a of I, position b of
-// J) is evaluated (all set unless the pairs are screened; only 8 x 8 tiles
-// are screened).
+// slot.  keep0..keep3: bit 8 (a % 8) + b of word a / 8 set when the pair
+// (row a, column b) is evaluated (all set unless the pairs are screened;
+// screening needs 8-orbital column tiles).  Named words, not an array: a
+// kernel's copy of the descriptor then stays in registers.
 struct TileDesc {
   int i0, nI, j0, nJ, diag, joff, slot0;
-  unsigned long long keep;
+  unsigned long long keep0, keep1, keep2, keep3;
 };
+static_assert(kMaxRows == 32, "four 64-bit mask words");
 
-// Most rows a tile may have: the pass kernels stage kMaxRows x tile pair
-// means in LDS.
-constexpr int kMaxRows = 32;
+// Mask word w (rows 8 w .. 8 w + 7) of a tile pair, combined from values
+// (a select between the fields' addresses would put the descriptor in memory).
+__host__ __device__ inline unsigned long long keep_word(const TileDesc& td, int w) {
+  const unsigned long long m0 = 0ull - (unsigned long long)(w == 0);
+  const unsigned long long m1 = 0ull - (unsigned long long)(w == 1);
+  const unsigned long long m2 = 0ull - (unsigned long long)(w == 2);
+  const unsigned long long m3 = 0ull - (unsigned long long)(w == 3);
+  return (td.keep0 & m0) | (td.keep1 & m1) | (td.keep2 & m2) | (td.keep3 & m3);
+}
 
 // Arguments of one exchange pass over one batch of tiles of one system.
 struct PassArgs {

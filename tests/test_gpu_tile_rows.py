@@ -151,9 +151,11 @@ def test_rows_clamped_where_psi_i_is_staged():
 
 
 def test_rows_plan_screening_round_trip():
-    """Screening a rows plan switches to 8 x 8 tiles: K psi and E_x of the
-    kept pairs match the oracle's screened exchange; rho_cut = 0 restores the
-    rows schedule (equal to the plan's first result bit for bit)."""
+    """Screening a rows plan keeps its R x 8 tile pairs, now with masks of the
+    kept pairs: K psi and E_x of the kept pairs match the oracle's screened
+    exchange, and equal those of a screened 8-row plan to rounding; rho_cut =
+    0 restores the unscreened schedule (equal to the plan's first result bit
+    for bit)."""
     psi, _ = reference(37, 5500)
     dev = _dev()
     spec = hfx.SystemSpec(N, BOX, 37)
@@ -174,9 +176,15 @@ def test_rows_plan_screening_round_trip():
     kept = p16.screen(pt, rho_cut)
     print(f"  rho_cut {rho_cut:.4f} kept {kept}", flush=True)
     assert kept == [int(np.triu(keep).sum())] and 0 < kept[0] < 37 * 38 // 2
-    assert "rows=8" in p16.describe() and "screened=yes" in p16.describe()
+    assert "rows=16" in p16.describe() and "screened=yes" in p16.describe()
+    assert p16.schedule_info()[3] == kept[0]
     ks, es = p16.apply_exchange(pt)
+    p8 = hfx.Plan(spec, hfx.FP32, options="rows=8", device=dev)
+    assert p8.screen(pt, rho_cut) == kept
+    k8, e8 = p8.apply_exchange(pt)
     torch.cuda.synchronize()
+    assert abs(float(es[0]) - float(e8[0])) <= 1e-12 * abs(float(e8[0]))
+    assert float(torch.max(torch.abs(ks - k8))) <= 1e-6
     ref = oracle.exchange(psi, BOX, oracle.coulomb_kernel((N,) * 3, BOX, hfx.TRUNCATED, 0.0),
                           keep=keep, workers=4)
     assert abs(float(es[0]) - ref["ex"]) <= 1e-7 * abs(ref["ex"])
