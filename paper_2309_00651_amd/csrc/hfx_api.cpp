@@ -1,13 +1,15 @@
 // C ABI of the exact-exchange library: plan construction, argument
 // validation, workspace layout and the launch sequence of each entry point.
 //
-// Pair work is scheduled in orbital tiles of T x T pairs (T = variant tile).
-// Blocks of T orbitals meet in round-robin rounds (circle method), so the
-// tiles of one round share no orbital; a batch is a slice of one round, and
-// its three pipeline passes run back to back on the caller's stream.  This
-// makes K psi accumulation race-free and its order fixed (the pair loop of
-// Eq. (vx) split over tiles, in the spirit of the paper's task groups, which
-// also divide the pair list and sum the partial operators).
+// Pair work is scheduled in tile pairs of R rows x T columns (T = variant
+// tile, R = rows per tile pair, a multiple of T).  Blocks of R orbitals meet
+// in round-robin rounds (circle method); a block pair is cut into R / T tile
+// pairs, one per column tile, and the tile pairs of one round with the same
+// column tile share no orbital.  A batch is a slice of such a set, and its
+// three pipeline passes run back to back on the caller's stream.  This makes
+// K psi accumulation race-free and its order fixed (the pair loop of Eq. (vx)
+// split over tiles, in the spirit of the paper's task groups, which also
+// divide the pair list and sum the partial operators).
 #include "../../include/hfx.h"
 
 #include <hip/hip_runtime.h>
@@ -244,7 +246,7 @@ int bricks_per_tile(const Variant* v) {
 // different batches, so no two workgroups of a launch update one orbital's
 // K psi.  Inside a diagonal block only pairs i <= j are evaluated and rows
 // below the tile's last column are dropped.  With R = T this is the plain
-// T x T tiling.  Rows amortise the J side (psi_J and K psi_J traffic) over R
+// T x T tiling.  Rows spread the J side (psi_J and K psi_J traffic) over R
 // pairs per column instead of T.
 void build_schedule(SystemPlan& sp, long long tiles_cap) {
   // (rounds outside this plan's virtual group are skipped below)
