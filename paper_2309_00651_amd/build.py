@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhfx.so")
-SOURCES = ["hfx_api.cpp", "exchange_common.hip", "exchange_f32.hip", "exchange_f64.hip",
+SOURCES = ["hfx_api.cpp", "schedule.cpp", "exchange_common.hip", "exchange_f32.hip", "exchange_f64.hip",
            "gemm.hip", "ortho.hip", "ace.hip", "scdm.hip"]
 ARCH = "gfx950"
 # packed float32 instructions stay off (see the design notes on v_pk_* ops)
