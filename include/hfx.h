@@ -254,8 +254,9 @@ hfx_status hfx_schedule_info(hfx_plan plan, int system, long long* info);
 /*
  * One-line description of a system's kernel configuration and schedule:
  * variant name, grid, tile and brick sizes, radix schedules (forward/inverse
- * per axis), threads per workgroup (pair_fwd/plane/inv_acc), tiles per batch,
- * batches, batch streams and whether the pairs are screened.  The text is
+ * per axis), threads per workgroup (pair_fwd/plane/inv_acc), rows per tile
+ * pair, tiles per batch, batches, batch streams and whether the pairs are
+ * screened.  The text is
  * owned by the plan and valid until the next call of this function on the
  * plan or its destruction.  NULL (and HFX_EINVAL in hfx_last_error) for a null
  * plan or an index out of range.
