@@ -159,3 +159,39 @@ def test_slab_grid(prec, nxy, nz, box, kernel, param, family, n_orb):
     assert np.max(np.abs(m.view(n_orb, n_orb).cpu().numpy() - m_ref)) <= \
         np.sqrt(omega) * k_bar + 1e-12
     assert np.max(np.abs(grad.cpu().numpy() - 2 * dv * ref["kpsi"])) <= 2 * dv * k_bar
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=IDS)
+@pytest.mark.parametrize("rows", [8, 32])
+def test_slab_grid_screened_rows(prec, rows):
+    """s-MTACE screening on a slab grid (24 x 24 x 48, localised Gaussians),
+    with 8- and 32-row tile pairs: the screened K psi and E_x against the
+    oracle's sums over the same kept pairs."""
+    nxy, nz, box, n_orb = 24, 48, (10.0, 10.0, 20.0), 40
+    shape = (nz, nxy, nxy)
+    print(f"case slab screened rows={rows} prec={prec}", flush=True)
+    psi = generate.gaussians(shape, box, n_orb, 5.0, seed=4800)[0]
+    dv = box[0] * box[1] * box[2] / psi[0].size
+    a = oracle.pair_overlap_abs(psi, dv)
+    vals = np.sort(a[np.triu_indices(n_orb, 1)])[::-1]
+    mid = len(vals) // 3
+    k = max(range(mid - 100, mid + 100), key=lambda i: (vals[i - 1] - vals[i]) / vals[i - 1])
+    assert (vals[k - 1] - vals[k]) / vals[k - 1] > 1e-6
+    rho_cut = 0.5 * (vals[k - 1] + vals[k])
+    keep = oracle.screen_pairs(psi, dv, rho_cut)
+    vg = oracle.coulomb_kernel(shape, box, hfx.ERFC, 0.3)
+    ref = oracle.exchange(psi, box, vg, keep=keep, workers=4)
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec((nxy, nxy, nz), box, n_orb, hfx.ERFC, 0.3), prec,
+                    options=f"rows={rows}", device=dev)
+    pt = torch.from_numpy(psi).to(dev)
+    kept = plan.screen(pt, rho_cut)
+    assert kept == [int(np.triu(keep).sum())] and kept[0] < n_orb * (n_orb + 1) // 2
+    assert plan.schedule_info()[3] == kept[0]
+    kpsi, ex = plan.apply_exchange(pt)
+    torch.cuda.synchronize()
+    e_bar, k_bar = bars(prec, ref["kpsi"])
+    rel = abs(float(ex[0]) - ref["ex"]) / abs(ref["ex"])
+    dk = np.max(np.abs(kpsi.double().cpu().numpy() - ref["kpsi"]))
+    print(f"  rho_cut {rho_cut:.4f} kept {kept[0]} rel dE {rel:.2e} max dK {dk:.2e}", flush=True)
+    assert rel <= e_bar and dk <= k_bar
