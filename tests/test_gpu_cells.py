@@ -195,3 +195,28 @@ def test_slab_grid_screened_rows(prec, rows):
     dk = np.max(np.abs(kpsi.double().cpu().numpy() - ref["kpsi"]))
     print(f"  rho_cut {rho_cut:.4f} kept {kept[0]} rel dE {rel:.2e} max dK {dk:.2e}", flush=True)
     assert rel <= e_bar and dk <= k_bar
+
+
+def test_mixing_fraction_with_screening():
+    """mix=0.25 on a screened plan: a quarter of the oracle's screened sums."""
+    a_mix, n, L, n_orb = 0.25, 24, 10.0, 30
+    shape, box = (n, n, n), (L, L, L)
+    psi = generate.gaussians(shape, box, n_orb, 5.0, seed=4901)[0]
+    dv = L ** 3 / n ** 3
+    a = oracle.pair_overlap_abs(psi, dv)
+    vals = np.sort(a[np.triu_indices(n_orb, 1)])[::-1]
+    mid = len(vals) // 2
+    k = max(range(mid - 80, mid + 80), key=lambda i: (vals[i - 1] - vals[i]) / vals[i - 1])
+    assert (vals[k - 1] - vals[k]) / vals[k - 1] > 1e-6
+    rho_cut = 0.5 * (vals[k - 1] + vals[k])
+    keep = oracle.screen_pairs(psi, dv, rho_cut)
+    ref = oracle.exchange(psi, box, oracle.coulomb_kernel(shape, box, hfx.TRUNCATED, 0.0),
+                          keep=keep)
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec(n, box, n_orb), hfx.FP32, options="mix=0.25", device=dev)
+    pt = torch.from_numpy(psi).to(dev)
+    assert plan.screen(pt, rho_cut) == [int(np.triu(keep).sum())]
+    kpsi, ex = plan.apply_exchange(pt)
+    torch.cuda.synchronize()
+    assert abs(float(ex[0]) - a_mix * ref["ex"]) <= 1e-7 * abs(a_mix * ref["ex"])
+    assert np.max(np.abs(kpsi.double().cpu().numpy() - a_mix * ref["kpsi"])) <= 1e-5 * a_mix

@@ -120,3 +120,30 @@ def test_graph_step_matches_eager_step():
         assert torch.equal(kb, ka), rep
         assert torch.equal(eb, ea) and torch.equal(mb, ma), rep
     g.close()
+
+
+@pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
+def test_batched_plan_with_different_row_tiles(prec):
+    """Systems of 260 and 21 orbitals take 32- and 16-row tile pairs by
+    default; in one plan each gives its single-system result bit for bit."""
+    dev = _dev()
+    L = 10.0
+    psis = [generate.random_pw((24,) * 3, (L,) * 3, no, 5.0, seed=900 + no) for no in (260, 21)]
+    specs = [hfx.SystemSpec(24, (L,) * 3, no) for no in (260, 21)]
+    plan = hfx.Plan(specs, prec, device=dev)
+    assert "rows=32" in plan.describe(0) and "rows=16" in plan.describe(1)
+    flat = torch.from_numpy(np.concatenate([p.reshape(-1) for p in psis])).to(dev)
+    kpsi, ex = plan.apply_exchange(flat)
+    torch.cuda.synchronize()
+    for i, (spec, p) in enumerate(zip(specs, psis)):
+        single = hfx.Plan(spec, prec, device=dev)
+        pt = torch.from_numpy(p).to(dev)
+        k1, e1 = single.apply_exchange(pt)
+        torch.cuda.synchronize()
+        assert torch.equal(plan.split(kpsi)[i], k1)
+        assert float(ex[i]) == float(e1[0])
+    # the 21-orbital system against the oracle (the 260-orbital loop is long on the CPU)
+    vg = oracle.coulomb_kernel((24,) * 3, (L,) * 3, hfx.TRUNCATED, 0.0)
+    ref = oracle.exchange(psis[1], (L,) * 3, vg)
+    tol = 1e-7 if prec == hfx.FP32 else 1e-12
+    assert abs(float(ex[1]) - ref["ex"]) <= tol * abs(ref["ex"])
