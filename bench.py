@@ -139,7 +139,7 @@ def bench_batched6(args):
     g.close()
     del plan
     log("batched6: six single-system plans in turn")
-    singles = [hfx.Plan(sp, hfx.FP32, device=dev) for sp in specs]
+    singles = [hfx.Plan(sp, hfx.FP32, options=args.options, device=dev) for sp in specs]
     views, off = [], 0
     for s in systems:
         k = s.n_orb * s.n ** 3
@@ -180,6 +180,9 @@ def main():
                     help="skip the s-MTACE screening timings (profiled runs of the step)")
     ap.add_argument("--options", default=None, help="float32 plan options, e.g. 'tiles=2'")
     ap.add_argument("--fp64-options", default=None, help="float64 plan options")
+    ap.add_argument("--no-band-limit", action="store_true",
+                    help="do not tell the plans the workload's orbital cutoff (ecut=); the "
+                         "passes then also transform the kz planes beyond the pair band")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (5 times): the "
                          "reference dispatch for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE")
@@ -202,6 +205,21 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 4 * n, "copies": 5}), flush=True)
         return
+
+    # The synthetic orbitals are band-limited by construction ((1/2)|G|^2 <=
+    # ecut of the workload), so the plans are told the cutoff (plan option
+    # ecut=) unless --no-band-limit: kz planes beyond the pair densities' band
+    # are then skipped (exact up to rounding; parity tests cover both forms).
+    from workloads import configs as _cfg
+    cuts = {s.ecut for s in (_cfg.BATCHED6 if args.workload == "batched6"
+                             else [_cfg.ALL[args.workload]])}
+    args.default_options = args.options is None and args.fp64_options is None
+    if not args.no_band_limit and len(cuts) == 1:
+        band = f"ecut={cuts.pop():g}"
+        args.options = band if args.options is None else f"{band};{args.options}"
+        args.fp64_options = band if args.fp64_options is None else f"{band};{args.fp64_options}"
+    else:
+        args.default_options = False
 
     if args.workload == "batched6":
         bench_batched6(args)
@@ -363,8 +381,8 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / MFMA_FP32_PEAK_TFLOPS, "traffic": None}
     else:
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        # counters were taken with the default plan options
-        tr = traffic_from_profiles(dname, system.name) if not args.options else None
+        # counters were taken with the default plan options (the workload's cutoff)
+        tr = traffic_from_profiles(dname, system.name) if args.default_options else None
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": tr}
     roof["kernel"] = dname

@@ -104,8 +104,14 @@ typedef struct hfx_plan_t* hfx_plan;
  * per R pairs instead of once per 8 (default 32 for systems of at least 256
  * orbitals, else 16; clamped to 8 for variants that stage the row orbitals
  * in LDS; screened schedules use the same tile pairs with masks of the kept
- * pairs; results agree to rounding, not bitwise, across R); mix=<a>,
- * 0 < a <= 1,
+ * pairs; results agree to rounding, not bitwise, across R); ecut=<Ha>
+ * declares that every orbital lies in the plane-wave sphere (1/2)|G|^2 <=
+ * ecut (true of plane-wave orbitals of that cutoff, and kept by linear
+ * combinations such as orthonormalisation): pair densities then vanish on the
+ * kz planes with |kz| > 2 floor(sqrt(2 ecut) L_z / 2 pi), which the passes
+ * skip (results agree with the full transform to rounding; orbitals outside
+ * the sphere give wrong results, which the library cannot detect; no effect
+ * on the split plane path of float64 grids from 108 on); mix=<a>, 0 < a <= 1,
  * is a hybrid functional's exact-exchange fraction: the kernel is scaled by a,
  * so E_x, K psi, M, the gradient and the ACE operator are a times the full
  * exchange (default 1).  Open-shell systems are two systems of one plan, the

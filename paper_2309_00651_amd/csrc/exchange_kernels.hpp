@@ -193,6 +193,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   }
   int offL[L::PER], gL[L::PER];
   bool vL[L::PER];
+  unsigned kzL[L::PER];  // bit r: leg r (frequency j + r NZ / RL) lies on a kept kz plane
 #pragma unroll
   for (int i = 0; i < L::PER; ++i) {
     int m = 0, j = 0;
@@ -201,6 +202,9 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
     const int mx = m - gL[i] * W;
     vL[i] = L::valid(tid, i) && (x0 + mx) < N;
     offL[i] = vL[i] ? (j * N + y) * N + x0 + mx : 0;
+    kzL[i] = 0;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) kzL[i] |= (kz_kept(j + r * (NZ / RL), NZ, a.kz_max) ? 1u : 0u) << r;
   }
 
   // psi of the J block (registers) and, with PIL, of the I block (LDS),
@@ -286,7 +290,8 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
         if (vL[i] && use) {
           cpx<T>* g = grids + (long long)(slot0 + gL[i]) * NR;
 #pragma unroll
-          for (int r = 0; r < RL; ++r) g[offL[i] + r * ZSL] = out[i * RL + r];
+          for (int r = 0; r < RL; ++r)
+            if ((kzL[i] >> r) & 1u) g[offL[i] + r * ZSL] = out[i * RL + r];
         }
       }
     });
@@ -310,8 +315,10 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
 // one grid pair is transformed the loads of the next one are in flight
 // (second register buffer), and the next orbital's psi and old K psi values
 // are loaded one step ahead.
+// KZ: band-limited plans (PassArgs::kz_max < NZ / 2) skip the loads of the
+// pruned kz planes; other plans compile without the plane tests.
 template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC, bool PJL, bool PF,
-          bool SCR, int NZ = N>
+          bool SCR, int NZ = N, bool KZ = false>
 __global__ void __launch_bounds__(NT)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_inv_acc(PassArgs a) {
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
@@ -347,6 +354,7 @@ __global__ void __launch_bounds__(NT)
 
   int offF[F::PER], gF[F::PER];
   bool vF[F::PER];
+  unsigned kzF[F::PER];  // bit r: leg r (frequency j + r NZ / RF) lies on a kept kz plane
 #pragma unroll
   for (int i = 0; i < F::PER; ++i) {
     int m = 0, j = 0;
@@ -355,6 +363,12 @@ __global__ void __launch_bounds__(NT)
     const int mx = m - gF[i] * W;
     vF[i] = F::valid(tid, i) && (x0 + mx) < N;
     offF[i] = vF[i] ? (j * N + y) * N + x0 + mx : 0;
+    kzF[i] = ~0u;
+    if constexpr (KZ) {
+      kzF[i] = 0;
+#pragma unroll
+      for (int r = 0; r < RF; ++r) kzF[i] |= (kz_kept(j + r * (NZ / RF), NZ, a.kz_max) ? 1u : 0u) << r;
+    }
   }
   int offA[PT], ldsA[PT];
   bool vA[PT];
@@ -414,14 +428,15 @@ __global__ void __launch_bounds__(NT)
     u0 = pair_live<TT, SCR>(td, ia, b0) || pair_live<TT, SCR>(td, ia, b0 + 1);
     u1 = pair_live<TT, SCR>(td, ia, b0 + 2) || pair_live<TT, SCR>(td, ia, b0 + 3);
   };
-  // Loads below are issued unconditionally and their values used as loaded:
-  // masked-off lanes read a valid dummy address (data written earlier in the
-  // batch: finite).  With no branches or selects after them, the compiler
-  // counts the loads in flight and waits only for the ones needed.  Dummy
-  // values are harmless: a grid of an unused pair is transformed but its
-  // potentials are never used, and at points outside the grid psi_b = 0 (set
-  // at the tile load), so energies and K psi_a get exact zeros there, while
-  // K psi_b is not stored there.
+  // Loads below are issued unconditionally: masked-off lanes read a valid
+  // dummy address (data written earlier in the batch: finite), and legs on
+  // pruned kz planes (never written) read the dummy address too and take
+  // zero.  With no branches after them, the compiler counts the loads in
+  // flight and waits only for the ones needed.  Dummy values are harmless: a
+  // grid of an unused pair is transformed but its potentials are never used,
+  // and at points outside the grid psi_b = 0 (set at the tile load), so
+  // energies and K psi_a get exact zeros there, while K psi_b is not stored
+  // there.
   auto load_pair = [&](int ia, int bq, cpx<T>* v) {
     bool u0, u1;
     uses(ia, bq, u0, u1);
@@ -429,10 +444,19 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
     for (int i = 0; i < F::PER; ++i) {
       const bool ok = vF[i] && (gF[i] == 0 ? u0 : u1);
-      const cpx<T>* g = ok ? grids + (long long)(slot0 + gF[i]) * NR + offF[i]
-                           : grids + (long long)td.slot0 * NR;
+      const cpx<T>* dummy = grids + (long long)td.slot0 * NR;
+      const cpx<T>* g = ok ? grids + (long long)(slot0 + gF[i]) * NR + offF[i] : dummy;
+      if constexpr (KZ) {
 #pragma unroll
-      for (int r = 0; r < RF; ++r) v[i * RF + r] = g[ok ? r * ZSF : 0];
+        for (int r = 0; r < RF; ++r) {
+          const bool kept = (kzF[i] >> r) & 1u;
+          const cpx<T> val = *(ok && kept ? g + r * ZSF : dummy);
+          v[i * RF + r] = kept ? val : cpx<T>{T(0), T(0)};
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < RF; ++r) v[i * RF + r] = g[ok ? r * ZSF : 0];
+      }
     }
   };
   // psi and old K psi of orbital a at the thread's points (offA = 0 off the grid)
@@ -629,7 +653,7 @@ k_plane_conv(PassArgs a) {
   cpx<T>* plane = reinterpret_cast<cpx<T>*>(smem_raw);
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
-  const int total = a.n_active * NZ;  // planes of this launch, kz-major
+  const int total = a.n_active * kz_planes(NZ, a.kz_max);  // planes of this launch, kz-major
   cpx<T>* __restrict__ gbase = static_cast<cpx<T>*>(a.grids);
 
   if (lg >= total) return;
@@ -640,7 +664,8 @@ k_plane_conv(PassArgs a) {
   stage_twiddles<T, SYI, NT>(twyi, a.tw_yi, tid);
   stage_twiddles<T, SXI, NT>(twxi, a.tw_xi, tid);
   auto plane_base = [&](int L) {
-    const int kz = L / a.n_active, ai = L - kz * a.n_active;
+    const int c = L / a.n_active, ai = L - c * a.n_active;
+    const int kz = kz_of_plane(c, NZ, a.kz_max);
     return gbase + (long long)a.active[ai] * NR + (long long)kz * N * N;
   };
   // x-forward stage-0 inputs straight from HBM (rows, x contiguous)
@@ -660,7 +685,8 @@ k_plane_conv(PassArgs a) {
   load_rows(plane_base(L), v);
   while (true) {
     cpx<T>* __restrict__ base = plane_base(L);
-    const T* __restrict__ vt = static_cast<const T*>(a.vtab) + (long long)(L / a.n_active) * N * N;
+    const T* __restrict__ vt =
+        static_cast<const T*>(a.vtab) + (long long)kz_of_plane(L / a.n_active, NZ, a.kz_max) * N * N;
     {
       cpx<T> o[LXF::VALS];
       EXF::reg2reg(v, plane, twxf, tid, o);
@@ -884,22 +910,29 @@ struct FusedPipeline {
     hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ>),
                        dim3(plane_grid(nb)), dim3(NTQ), lds, s, a);
   }
-  static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
-    if (a.perm)
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, true, NZ>), dim3(nb), dim3(NTI), 0,
-                         s, a);
-    else
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, false, NZ>), dim3(nb), dim3(NTI),
-                         0, s, a);
+  // screened (perm) and band-limited (kz_max < NZ / 2) plans take their own
+  // instantiations
+  template <bool ACC>
+  static void inv_pass(const PassArgs& a, int nb, hipStream_t s) {
+    const bool kz = a.kz_max < NZ / 2;
+    if (a.perm) {
+      if (kz)
+        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, true, NZ, true>), dim3(nb),
+                           dim3(NTI), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, true, NZ, false>), dim3(nb),
+                           dim3(NTI), 0, s, a);
+    } else {
+      if (kz)
+        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, false, NZ, true>), dim3(nb),
+                           dim3(NTI), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, false, NZ, false>), dim3(nb),
+                           dim3(NTI), 0, s, a);
+    }
   }
-  static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
-    if (a.perm)
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, true, NZ>), dim3(nb), dim3(NTI), 0,
-                         s, a);
-    else
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, false, NZ>), dim3(nb), dim3(NTI),
-                         0, s, a);
-  }
+  static void inv_acc(const PassArgs& a, int nb, hipStream_t s) { inv_pass<true>(a, nb, s); }
+  static void inv_energy(const PassArgs& a, int nb, hipStream_t s) { inv_pass<false>(a, nb, s); }
   static hipError_t prepare() {
     return hipFuncSetAttribute(
         reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ>),

@@ -58,6 +58,9 @@ struct SystemPlan {
   long long nr = 0;
   double dv = 0.0;
   int rows = 8;  // rows per tile pair (a multiple of the variant's tile)
+  // band limit: pair densities vanish on kz planes |kz| > kz_max (>= nz / 2:
+  // no plane is skipped)
+  int kz_max = 1 << 30;
   int tiles_per_batch = 1;
   int slots_per_batch = 0;
   std::vector<TileDesc> tiles;
@@ -151,6 +154,20 @@ std::string parse_option_str(const char* opts, const char* key) {
   return "";
 }
 
+// Whether an item "key=..." is present (its value may be empty).
+bool has_option(const char* opts, const char* key) {
+  if (!opts) return false;
+  const std::string s(opts), k = std::string(key) + "=";
+  size_t p = 0;
+  while (p < s.size()) {
+    size_t e = s.find(';', p);
+    if (e == std::string::npos) e = s.size();
+    if (s.compare(p, k.size(), k) == 0) return true;
+    p = e + 1;
+  }
+  return false;
+}
+
 // Integer option: def when absent; false when present but not a whole
 // non-negative decimal number.
 bool parse_option(const char* opts, const char* key, long long def, long long* out) {
@@ -169,7 +186,8 @@ bool parse_option(const char* opts, const char* key, long long def, long long* o
 // Every key of the option string is one of the known ones.
 bool options_known(const char* opts, std::string* bad) {
   if (!opts) return true;
-  static const char* known[] = {"tiles", "maxws", "variant", "streams", "shard", "mix", "rows"};
+  static const char* known[] = {"tiles", "maxws", "variant", "streams", "shard", "mix", "rows",
+                                "ecut"};
   const std::string s(opts);
   size_t p = 0;
   while (p < s.size()) {
@@ -422,8 +440,11 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   a.v0 = sp.v0;
   a.perm = sp.d_perm;
   a.n_orb = sp.sys.n_orb;
+  a.kz_max = sp.kz_max;
   const int br = bricks_per_tile(v);
   const int n = v->n, nz = v->nz;
+  // share of the grid on kept kz planes (pair-grid traffic of the passes)
+  const double kzf = (double)kz_planes(nz, sp.kz_max) / nz;
   const int nxb = (n + v->brick - 1) / v->brick;
   const double nr = (double)sp.nr, ce = 2.0 * elem;  // complex element bytes
   // FFT flops per complex grid and axis pass: 5 N_r log2(N) (radix-2 count)
@@ -475,12 +496,12 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
     {
       Bracket bk(plan, HFX_PASS_PAIR_FWD, bs);
       v->pair_fwd(a, b.n_tiles * br, bs);
-      bk.done(orbs * nr * elem + grids * nr * ce, grids * fft_z);
+      bk.done(orbs * nr * elem + grids * nr * ce * kzf, grids * fft_z);
     }
     if (v->plane_mode == 0) {
       Bracket bk(plan, HFX_PASS_PLANE, bs);
-      v->plane(a, b.n_active * nz, bs);
-      bk.done(grids * nr * ce * 2.0, grids * fft_axis * 4.0);
+      v->plane(a, b.n_active * kz_planes(nz, sp.kz_max), bs);
+      bk.done(grids * nr * ce * 2.0 * kzf, grids * fft_axis * 4.0 * kzf);
     } else {
       const int rb = (n * n + v->rows_per_wg - 1) / v->rows_per_wg;
       {
@@ -503,11 +524,11 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
     if (acc) {
       Bracket bk(plan, HFX_PASS_INV_ACC, bs);
       v->inv_acc(a, b.n_tiles * br, bs);
-      bk.done(grids * nr * ce + orbs * nr * elem * 3.0, grids * fft_z);
+      bk.done(grids * nr * ce * kzf + orbs * nr * elem * 3.0, grids * fft_z);
     } else {
       Bracket bk(plan, HFX_PASS_INV_ENERGY, bs);
       v->inv_energy(a, b.n_tiles * br, bs);
-      bk.done(grids * nr * ce + orbs * nr * elem, grids * fft_z);
+      bk.done(grids * nr * ce * kzf + orbs * nr * elem, grids * fft_z);
     }
     if (two) HIP_TRY(hipEventRecord(sp.ev_acc[q], bs));
   }
@@ -783,11 +804,25 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   double mix = 1.0;
   {
     const std::string mv = parse_option_str(options, "mix");
+    if (mv.empty() && has_option(options, "mix"))
+      return fail(HFX_EINVAL, "mix=<a> needs 0 < a <= 1");
     if (!mv.empty()) {
       char* end = nullptr;
       mix = std::strtod(mv.c_str(), &end);
       if (end == mv.c_str() || *end != '\0' || !(mix > 0.0 && mix <= 1.0))
         return fail(HFX_EINVAL, "mix=<a> needs 0 < a <= 1");
+    }
+  }
+  double ecut = 0.0;
+  {
+    const std::string ev = parse_option_str(options, "ecut");
+    if (ev.empty() && has_option(options, "ecut"))
+      return fail(HFX_EINVAL, "ecut=<Ha> needs a positive cutoff");
+    if (!ev.empty()) {
+      char* end = nullptr;
+      ecut = std::strtod(ev.c_str(), &end);
+      if (end == ev.c_str() || *end != '\0' || !(ecut > 0.0 && ecut < 1e6))
+        return fail(HFX_EINVAL, "ecut=<Ha> needs a positive cutoff");
     }
   }
   const std::string vname = parse_option_str(options, "variant");
@@ -827,6 +862,12 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
       sp.rows = std::max(t, r / t * t);
     }
     schedule_all_pairs(sp, tiles_cap);
+    if (ecut > 0.0 && sp.var->plane_mode == 0) {
+      // orbitals with (1/2)|G|^2 <= ecut have |m_z| <= G_cut L_z / (2 pi); pair
+      // densities then |kz| <= 2 of that (the split plane path keeps every plane)
+      const double mz = std::sqrt(2.0 * ecut) * sys[i].L[2] / (2.0 * 3.14159265358979323846);
+      sp.kz_max = 2 * (int)std::floor(mz + 1e-9);
+    }
     sp.psi_off = psi_off;
     sp.m_off = m_off;
     sp.orb_off = orb_off;
@@ -1174,6 +1215,8 @@ const char* hfx_plan_describe(hfx_plan plan, int system) {
                   std::to_string(v->nt_acc) + " plane=" +
                   (v->plane_mode == 0 ? "fused" : "split") +
                   " rows=" + std::to_string(sp.rows) +
+                  (sp.kz_max < v->nz / 2 ? " kz_max=" + std::to_string(sp.kz_max)
+                                          : std::string()) +
                   " tiles_per_batch=" + std::to_string(sp.tiles_per_batch) +
                   " batches=" + std::to_string(sp.batches.size()) +
                   " streams=" + std::to_string(sp.nstreams) +

@@ -66,7 +66,25 @@ struct PassArgs {
   int n_orb;
   int n_tiles;
   int n_active;
+  // Band-limited orbitals: pair densities vanish on the kz planes with
+  // |kz| > kz_max, which are then neither stored, transformed nor loaded
+  // (read as zeros).  kz_max >= NZ / 2: every plane is kept.
+  int kz_max;
 };
+
+// Whether z frequency index k (0 <= k < nz) lies on a kept plane.
+__host__ __device__ inline bool kz_kept(int k, int nz, int kz_max) {
+  return (k <= nz - k ? k : nz - k) <= kz_max;
+}
+// Number of kept kz planes, and the frequency index of compact plane c
+// (0 <= c < kz_planes): 0 .. kz_max, then nz - kz_max .. nz - 1.  Written
+// without 2 kz_max, which overflows for the "keep all" value.
+__host__ __device__ inline int kz_planes(int nz, int kz_max) {
+  return kz_max >= nz / 2 ? nz : 2 * kz_max + 1;
+}
+__host__ __device__ inline int kz_of_plane(int c, int nz, int kz_max) {
+  return (kz_max >= nz / 2 || c <= kz_max) ? c : nz - (2 * kz_max + 1 - c);
+}
 
 typedef void (*launch_fn)(const PassArgs&, int nblocks, hipStream_t);
 

@@ -9,7 +9,9 @@
 //   * the tile pairs of a batch touch disjoint orbitals (race-free K psi);
 //   * tile pair shapes within the shape (nI <= rows, nJ <= tile, joff), slots
 //     inside the batch buffer, `active` = exactly the slots with a live pair;
-//   * batch offsets, tile counts and energy partials consistent.
+//   * batch offsets, tile counts and energy partials consistent;
+//   * the kept kz planes of band-limited plans: compact plane index <-> kept
+//     frequency one to one, for every cutoff including "keep all".
 // Prints ALL OK and exits 0 when every check holds.
 #include <algorithm>
 #include <cstdio>
@@ -204,7 +206,33 @@ static void check_screened() {
           }
 }
 
+// Pruned kz planes (band-limited orbitals): the compact plane index maps
+// one to one onto the kept frequencies, for every cutoff including the
+// "keep all" value the plans use by default.
+static void check_kz_planes() {
+  for (int nz : {24, 48, 64, 72, 80, 96, 108, 120, 128})
+    for (int kz_max : {0, 1, 5, nz / 2 - 1, nz / 2, nz / 2 + 1, nz, 1 << 30}) {
+      if (kz_max < 0) continue;
+      const int np = kz_planes(nz, kz_max);
+      int kept = 0;
+      for (int k = 0; k < nz; ++k) kept += kz_kept(k, nz, kz_max) ? 1 : 0;
+      CHECK(np > 0 && np <= nz && np == kept, "kz nz=%d kz_max=%d planes %d kept %d", nz, kz_max,
+            np, kept);
+      std::vector<int> seen(nz, 0);
+      for (int c = 0; c < np; ++c) {
+        const int k = kz_of_plane(c, nz, kz_max);
+        CHECK(k >= 0 && k < nz && kz_kept(k, nz, kz_max), "kz nz=%d kz_max=%d plane %d -> %d", nz,
+              kz_max, c, k);
+        if (k >= 0 && k < nz) ++seen[k];
+      }
+      for (int k = 0; k < nz; ++k)
+        CHECK(seen[k] == (kz_kept(k, nz, kz_max) ? 1 : 0), "kz nz=%d kz_max=%d k=%d seen %d", nz,
+              kz_max, k, seen[k]);
+    }
+}
+
 int main() {
+  check_kz_planes();
   check_rounds();
   check_unscreened();
   check_screened();

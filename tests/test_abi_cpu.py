@@ -132,7 +132,8 @@ def test_status_strings(lib):
                                   b"mix=0.25x", b"mix=nan", b"tiles=abc", b"tiles=-2",
                                   b"tiles=", b"maxws=1e9", b"streams=", b"tilez=3",
                                   b"tiles", b"tiles=2;bogus=1", b"rows=12", b"rows=40",
-                                  b"rows=-8", b"rows=abc", b"rows="])
+                                  b"rows=-8", b"rows=abc", b"rows=", b"ecut=0", b"ecut=-5",
+                                  b"ecut=abc", b"ecut=nan", b"ecut=", b"ecut=5Ha", b"mix="])
 def test_bad_plan_options_rejected_before_device(lib, opts):
     st, h, err = _create(lib, [GOOD], opts=opts)
     assert st == 1 and not h.value and err
