@@ -315,10 +315,14 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
 // one grid pair is transformed the loads of the next one are in flight
 // (second register buffer), and the next orbital's psi and old K psi values
 // are loaded one step ahead.
-// KZ: band-limited plans (PassArgs::kz_max < NZ / 2) skip the loads of the
-// pruned kz planes; other plans compile without the plane tests.
+// KZ: band-limited plans (PassArgs::kz_max < NZ / 2) do not load the pruned
+// kz planes; other plans (KZ = 0) compile without the plane tests.  KZ = 1
+// (most planes kept): pruned legs load zeros from the plan's zero block, so
+// every load stays unconditional; KZ = 2 (many planes pruned): pruned legs are
+// not loaded at all (the compiler branches around them, and whole waves skip
+// the legs of fully pruned frequency blocks).
 template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC, bool PJL, bool PF,
-          bool SCR, int NZ = N, bool KZ = false>
+          bool SCR, int NZ = N, int KZ = 0>
 __global__ void __launch_bounds__(NT)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_inv_acc(PassArgs a) {
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
@@ -364,7 +368,7 @@ __global__ void __launch_bounds__(NT)
     vF[i] = F::valid(tid, i) && (x0 + mx) < N;
     offF[i] = vF[i] ? (j * N + y) * N + x0 + mx : 0;
     kzF[i] = ~0u;
-    if constexpr (KZ) {
+    if constexpr (KZ != 0) {
       kzF[i] = 0;
 #pragma unroll
       for (int r = 0; r < RF; ++r) kzF[i] |= (kz_kept(j + r * (NZ / RF), NZ, a.kz_max) ? 1u : 0u) << r;
@@ -430,9 +434,9 @@ __global__ void __launch_bounds__(NT)
   };
   // Loads below are issued unconditionally: masked-off lanes read a valid
   // dummy address (data written earlier in the batch: finite), and legs on
-  // pruned kz planes (never written) read the dummy address too and take
-  // zero.  With no branches after them, the compiler counts the loads in
-  // flight and waits only for the ones needed.  Dummy values are harmless: a
+  // pruned kz planes (never written) read zeros from the plan's zero block.
+  // With no branches after them, the compiler counts the loads in flight and
+  // waits only for the ones needed.  Dummy values are harmless: a
   // grid of an unused pair is transformed but its potentials are never used,
   // and at points outside the grid psi_b = 0 (set at the tile load), so
   // energies and K psi_a get exact zeros there, while K psi_b is not stored
@@ -446,7 +450,19 @@ __global__ void __launch_bounds__(NT)
       const bool ok = vF[i] && (gF[i] == 0 ? u0 : u1);
       const cpx<T>* dummy = grids + (long long)td.slot0 * NR;
       const cpx<T>* g = ok ? grids + (long long)(slot0 + gF[i]) * NR + offF[i] : dummy;
-      if constexpr (KZ) {
+      if constexpr (KZ == 1) {
+        // a leg on a pruned plane loads from the plan's zero block (this
+        // thread's own element): every load is issued and its value used as
+        // loaded (no branch, no select)
+        static_assert(NT * sizeof(cpx<T>) <= kZeroBytes, "zero block per thread");
+        const cpx<T>* zero = static_cast<const cpx<T>*>(a.zero) + tid;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+          const bool kept = (kzF[i] >> r) & 1u;
+          v[i * RF + r] = *(kept ? g + (ok ? r * ZSF : 0) : zero);
+        }
+      } else if constexpr (KZ == 2) {
+        // the value of a pruned leg is discarded, so its load is skipped
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
           const bool kept = (kzF[i] >> r) & 1u;
@@ -912,24 +928,34 @@ struct FusedPipeline {
   }
   // screened (perm) and band-limited (kz_max < NZ / 2) plans take their own
   // instantiations
+  template <bool ACC, bool SCR>
+  static void inv_launch(const PassArgs& a, int nb, hipStream_t s) {
+    // band-limited plans: float32 takes zero-block loads while at least 3/4
+    // of the planes are kept and skipped loads below that; float64 (one
+    // workgroup per compute unit, registers tight) always skips (measured at
+    // 93 of 96 planes and at 29..57 of 64..120)
+    const int kept = kz_planes(NZ, a.kz_max);
+    if (kept == NZ) {
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 0>), dim3(nb),
+                         dim3(NTI), 0, s, a);
+      return;
+    }
+    if constexpr (sizeof(T) == 4) {
+      if (4 * kept >= 3 * NZ) {
+        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 1>), dim3(nb),
+                           dim3(NTI), 0, s, a);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 2>), dim3(nb),
+                       dim3(NTI), 0, s, a);
+  }
   template <bool ACC>
   static void inv_pass(const PassArgs& a, int nb, hipStream_t s) {
-    const bool kz = a.kz_max < NZ / 2;
-    if (a.perm) {
-      if (kz)
-        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, true, NZ, true>), dim3(nb),
-                           dim3(NTI), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, true, NZ, false>), dim3(nb),
-                           dim3(NTI), 0, s, a);
-    } else {
-      if (kz)
-        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, false, NZ, true>), dim3(nb),
-                           dim3(NTI), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, false, NZ, false>), dim3(nb),
-                           dim3(NTI), 0, s, a);
-    }
+    if (a.perm)
+      inv_launch<ACC, true>(a, nb, s);
+    else
+      inv_launch<ACC, false>(a, nb, s);
   }
   static void inv_acc(const PassArgs& a, int nb, hipStream_t s) { inv_pass<true>(a, nb, s); }
   static void inv_energy(const PassArgs& a, int nb, hipStream_t s) { inv_pass<false>(a, nb, s); }

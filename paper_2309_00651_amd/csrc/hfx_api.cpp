@@ -72,6 +72,7 @@ struct SystemPlan {
   void* tw[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   TileDesc* d_tiles = nullptr;
   int* d_active = nullptr;
+  void* d_zero = nullptr;  // kZeroBytes of zeros: what pruned kz planes read as (band-limited plans)
   // offsets inside the caller's workspace
   size_t off_psi32 = 0, off_grids = 0, off_partials = 0, off_gemm = 0, off_ortho = 0;
   size_t off_grad = 0;  // float32 K psi staging of the gradient (float32 plans)
@@ -331,6 +332,8 @@ void free_system(SystemPlan& sp) {
   for (auto& p : sp.tw)
     if (p) (void)hipFree(p);
   if (sp.d_tiles) (void)hipFree(sp.d_tiles);
+  if (sp.d_zero) (void)hipFree(sp.d_zero);
+  sp.d_zero = nullptr;
   if (sp.d_active) (void)hipFree(sp.d_active);
   if (sp.d_perm) (void)hipFree(sp.d_perm);
   if (sp.d_keep) (void)hipFree(sp.d_keep);
@@ -441,6 +444,7 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
   a.perm = sp.d_perm;
   a.n_orb = sp.sys.n_orb;
   a.kz_max = sp.kz_max;
+  a.zero = sp.d_zero;
   const int br = bricks_per_tile(v);
   const int n = v->n, nz = v->nz;
   // share of the grid on kept kz planes (pair-grid traffic of the passes)
@@ -949,6 +953,8 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     s = upload(sp.active, &d);
     if (s != HFX_OK) return cleanup(s);
     sp.d_active = static_cast<int*>(d);
+    s = upload(std::vector<double>(kZeroBytes / 8, 0.0), &sp.d_zero);
+    if (s != HFX_OK) return cleanup(s);
     if (sp.nstreams == 2) {
       if (hipStreamCreateWithFlags(&sp.bstream, hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&sp.ev_fork, hipEventDisableTiming) != hipSuccess ||

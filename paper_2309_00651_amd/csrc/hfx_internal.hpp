@@ -70,7 +70,12 @@ struct PassArgs {
   // |kz| > kz_max, which are then neither stored, transformed nor loaded
   // (read as zeros).  kz_max >= NZ / 2: every plane is kept.
   int kz_max;
+  const void* zero;  // kZeroBytes of zeros (device): the pruned planes' loads read these
 };
+
+// Zero block of band-limited plans: one 16-byte element per thread of a
+// workgroup, so that pruned loads spread over many cache lines.
+constexpr int kZeroBytes = 1024 * 16;
 
 // Whether z frequency index k (0 <= k < nz) lies on a kept plane.
 __host__ __device__ inline bool kz_kept(int k, int nz, int kz_max) {
