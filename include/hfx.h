@@ -110,8 +110,8 @@ typedef struct hfx_plan_t* hfx_plan;
  * combinations such as orthonormalisation): pair densities then vanish on the
  * kz planes with |kz| > 2 floor(sqrt(2 ecut) L_z / 2 pi), which the passes
  * skip (results agree with the full transform to rounding; orbitals outside
- * the sphere give wrong results, which the library cannot detect; no effect
- * on the split plane path of float64 grids from 108 on); mix=<a>, 0 < a <= 1,
+ * the sphere give wrong results, which the library cannot detect); mix=<a>,
+ * 0 < a <= 1,
  * is a hybrid functional's exact-exchange fraction: the kernel is scaled by a,
  * so E_x, K psi, M, the gradient and the ACE operator are a times the full
  * exchange (default 1).  Open-shell systems are two systems of one plan, the

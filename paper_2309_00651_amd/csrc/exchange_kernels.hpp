@@ -760,7 +760,9 @@ __global__ void __launch_bounds__(NT) k_rows(PassArgs a) {
   using F = FirstStage<G, SX>;
   using L = LastStage<G, SX>;
   constexpr long long NR = (long long)N * N * N;
-  constexpr int RB = (N * N + RW - 1) / RW;  // row blocks per grid
+  // rows (z, y) of the kept kz planes, numbered compactly; row blocks per grid
+  const int nrows = kz_planes(N, a.kz_max) * N;
+  const int RB = (nrows + RW - 1) / RW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   const int tid = threadIdx.x;
@@ -769,6 +771,11 @@ __global__ void __launch_bounds__(NT) k_rows(PassArgs a) {
   const int slot = a.active[ai];
   cpx<T>* __restrict__ base = static_cast<cpx<T>*>(a.grids) + (long long)slot * NR;
   const long long row0 = (long long)rb * RW;
+  // grid row of compact row c (c < nrows)
+  auto grid_row = [&](long long c) {
+    const int zc = (int)(c / N);
+    return (long long)kz_of_plane(zc, N, a.kz_max) * N + (c - (long long)zc * N);
+  };
   __shared__ TwEntry<T> twl[tw_slots<T, SX>()];
   stage_twiddles<T, SX, NT>(twl, INV ? a.tw_xi : a.tw_xf, tid);  // visible after the first barrier
   const TwEntry<T>* tw = twl;
@@ -778,11 +785,12 @@ __global__ void __launch_bounds__(NT) k_rows(PassArgs a) {
     if (!F::valid(tid, i)) continue;
     int m, j;
     F::mj(tid, i, m, j);
-    const bool rv = row0 + m < (long long)N * N;
+    const bool rv = row0 + m < nrows;
+    const long long gr = rv ? grid_row(row0 + m) : 0;
 #pragma unroll
     for (int r = 0; r < SchedInfo<SX>::first; ++r)
       v[i * SchedInfo<SX>::first + r] =
-          rv ? base[(row0 + m) * N + F::in_pos(j, r)] : cpx<T>{T(0), T(0)};
+          rv ? base[gr * N + F::in_pos(j, r)] : cpx<T>{T(0), T(0)};
   }
   cpx<T> o[L::VALS];
   E::reg2reg(v, lds, tw, tid, o);
@@ -791,10 +799,11 @@ __global__ void __launch_bounds__(NT) k_rows(PassArgs a) {
     if (!L::valid(tid, i)) continue;
     int m, j;
     L::mj(tid, i, m, j);
-    if (row0 + m >= (long long)N * N) continue;
+    if (row0 + m >= nrows) continue;
+    const long long gr = grid_row(row0 + m);
 #pragma unroll
     for (int r = 0; r < SchedInfo<SX>::last; ++r)
-      base[(row0 + m) * N + L::in_pos(j, r)] = o[i * SchedInfo<SX>::last + r];
+      base[gr * N + L::in_pos(j, r)] = o[i * SchedInfo<SX>::last + r];
   }
 }
 
@@ -817,9 +826,10 @@ __global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
   stage_twiddles<T, SYF, NT>(twf, a.tw_yf, tid);  // visible after the first barrier
   stage_twiddles<T, SYI, NT>(twi, a.tw_yi, tid);
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
-  const int per_grid = N * NXB;
+  const int per_grid = kz_planes(N, a.kz_max) * NXB;  // kept planes x column blocks
   const int ai = lg / per_grid, rem = lg - ai * per_grid;
-  const int z = rem / NXB, x0 = (rem - z * NXB) * W;
+  const int zc = rem / NXB, x0 = (rem - zc * NXB) * W;
+  const int z = kz_of_plane(zc, N, a.kz_max);
   const int slot = a.active[ai];
   cpx<T>* __restrict__ base = static_cast<cpx<T>*>(a.grids) + (long long)slot * NR + (long long)z * N * N;
   const T* __restrict__ vt = static_cast<const T*>(a.vtab) + (long long)z * N * N;
@@ -1018,21 +1028,28 @@ struct SplitPipeline {
   static void cols_conv(const PassArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_cols_conv<T, N, W, NTC, SYF, SYI>), dim3(nb), dim3(NTC), 0, s, a);
   }
+  // screened (perm) and band-limited (kz_max < N / 2: pruned loads skipped)
+  // plans take their own instantiations
+  template <bool ACC, bool SCR>
+  static void inv_launch(const PassArgs& a, int nb, hipStream_t s) {
+    if (kz_planes(N, a.kz_max) == N)
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, N, 0>), dim3(nb),
+                         dim3(NTI), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, N, 2>), dim3(nb),
+                         dim3(NTI), 0, s, a);
+  }
   static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
     if (a.perm)
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, true>), dim3(nb), dim3(NTI), 0,
-                         s, a);
+      inv_launch<true, true>(a, nb, s);
     else
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, true, PJL, PF, false>), dim3(nb), dim3(NTI),
-                         0, s, a);
+      inv_launch<true, false>(a, nb, s);
   }
   static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
     if (a.perm)
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, true>), dim3(nb), dim3(NTI), 0,
-                         s, a);
+      inv_launch<false, true>(a, nb, s);
     else
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, false, PJL, PF, false>), dim3(nb), dim3(NTI),
-                         0, s, a);
+      inv_launch<false, false>(a, nb, s);
   }
   static hipError_t prepare() {
     hipError_t e = hipFuncSetAttribute(

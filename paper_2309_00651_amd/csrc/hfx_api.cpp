@@ -507,21 +507,22 @@ hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* 
       v->plane(a, b.n_active * kz_planes(nz, sp.kz_max), bs);
       bk.done(grids * nr * ce * 2.0 * kzf, grids * fft_axis * 4.0 * kzf);
     } else {
-      const int rb = (n * n + v->rows_per_wg - 1) / v->rows_per_wg;
+      // rows and planes of the kept kz planes only
+      const int rb = (kz_planes(nz, sp.kz_max) * n + v->rows_per_wg - 1) / v->rows_per_wg;
       {
         Bracket bk(plan, HFX_PASS_ROWS_FWD, bs);
         v->rows_fwd(a, b.n_active * rb, bs);
-        bk.done(grids * nr * ce * 2.0, grids * fft_axis);
+        bk.done(grids * nr * ce * 2.0 * kzf, grids * fft_axis * kzf);
       }
       {
         Bracket bk(plan, HFX_PASS_COLS_CONV, bs);
-        v->cols_conv(a, b.n_active * n * nxb, bs);
-        bk.done(grids * nr * ce * 2.0, grids * fft_axis * 2.0);
+        v->cols_conv(a, b.n_active * kz_planes(nz, sp.kz_max) * nxb, bs);
+        bk.done(grids * nr * ce * 2.0 * kzf, grids * fft_axis * 2.0 * kzf);
       }
       {
         Bracket bk(plan, HFX_PASS_ROWS_INV, bs);
         v->rows_inv(a, b.n_active * rb, bs);
-        bk.done(grids * nr * ce * 2.0, grids * fft_axis);
+        bk.done(grids * nr * ce * 2.0 * kzf, grids * fft_axis * kzf);
       }
     }
     if (two && k > 0) HIP_TRY(hipStreamWaitEvent(bs, sp.ev_acc[q ^ 1], 0));
@@ -866,9 +867,9 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
       sp.rows = std::max(t, r / t * t);
     }
     schedule_all_pairs(sp, tiles_cap);
-    if (ecut > 0.0 && sp.var->plane_mode == 0) {
+    if (ecut > 0.0) {
       // orbitals with (1/2)|G|^2 <= ecut have |m_z| <= G_cut L_z / (2 pi); pair
-      // densities then |kz| <= 2 of that (the split plane path keeps every plane)
+      // densities then |kz| <= 2 of that
       const double mz = std::sqrt(2.0 * ecut) * sys[i].L[2] / (2.0 * 3.14159265358979323846);
       sp.kz_max = 2 * (int)std::floor(mz + 1e-9);
     }

@@ -3,8 +3,9 @@
 Orbitals with plane-wave components only in (1/2)|G|^2 <= ecut have pair
 densities with |kz| <= kz_max = 2 floor(sqrt(2 ecut) L_z / 2 pi); the passes
 then skip the kz planes beyond (not stored, transformed or loaded).  The
-oracle transforms the whole grid.  Covered: pruned planes on a cubic and a
-slab grid, both precisions, E_x, K psi, M, the energy-only path and the
+oracle transforms the whole grid.  Covered: pruned planes on cubic grids
+(the fused plane kernel, and at 108^3 in float64 the split rows + columns
+path) and a slab grid, both precisions, E_x, K psi, M, the energy-only path and the
 gradient; a screened plan; and a cutoff above the grid's reach, which must
 give the unpruned result bit for bit.  Bars as in the parity tests.
 """
@@ -45,6 +46,7 @@ def kz_max(ecut, lz):
 @pytest.mark.parametrize("n,nz,box,n_orb", [
     (64, 64, (15.7, 15.7, 15.7), 13),
     (24, 48, (10.0, 10.0, 20.0), 11),
+    (108, 108, (26.4, 26.4, 26.4), 3),   # float64: the split (rows + columns) plane path
 ])
 def test_band_limited_planes_skipped(prec, n, nz, box, n_orb):
     ecut = 5.0
