@@ -143,6 +143,9 @@ def pair_energy(psi_i, psi_j, vg, dv):
     return dv * float(np.sum(rho * pair_potential(rho, vg)))
 
 
+_FORKED = {}  # inputs of a forked pool, inherited by its workers (not pickled)
+
+
 def _rows_worker(args):
     psi, vg, dv, rows, want_kpsi, keep = args
     n_orb = psi.shape[0]
@@ -163,6 +166,11 @@ def _rows_worker(args):
                 if j != i:
                     kpsi[j] -= vij * psi[i]
     return kpsi, e
+
+
+def _forked_rows(rows):
+    f = _FORKED
+    return _rows_worker((f["psi"], f["vg"], f["dv"], rows, f["want_kpsi"], f["keep"]))
 
 
 def exchange(psi, box, vg, want_kpsi=True, workers=1, keep=None):
@@ -189,10 +197,15 @@ def exchange(psi, box, vg, want_kpsi=True, workers=1, keep=None):
         import multiprocessing as mp
         # Balance rows: row i has n_orb - i pairs; deal them round-robin.
         chunks = [list(range(w, n_orb, workers)) for w in range(workers)]
-        ctx = mp.get_context("fork")
-        with ctx.Pool(workers) as pool:
-            parts = pool.map(_rows_worker,
-                             [(psi, vg, dv, c, want_kpsi, keep) for c in chunks])
+        # The workers inherit the inputs through fork (copy-on-write) instead
+        # of receiving pickled copies, so a multi-GB Psi is held once.
+        _FORKED.update(psi=psi, vg=vg, dv=dv, want_kpsi=want_kpsi, keep=keep)
+        try:
+            ctx = mp.get_context("fork")
+            with ctx.Pool(workers) as pool:
+                parts = pool.map(_forked_rows, chunks)
+        finally:
+            _FORKED.clear()
         kpsi = np.zeros_like(psi) if want_kpsi else None
         e = np.zeros((n_orb, n_orb))
         for kp, ep in parts:          # fixed summation order
