@@ -149,15 +149,30 @@ hfx_status hfx_apply_exchange(hfx_plan plan, const double* psi, void* kpsi, doub
                               void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Exchange matrix M = dV Psi^T (K Psi), M_kl = <psi_k | K psi_l>, as float64
- * row-major n_orb x n_orb blocks per system.  kpsi is the output of
- * hfx_apply_exchange for the same plan and psi (precision of the plan).
- * FP32 plans: psi is split into float32 hi + lo parts, both multiplied with
- * the float32 K psi on FP32 MFMA, float64 accumulation across k-blocks.
- * FP64 plans: float64 MFMA.
+ * Exchange matrix M = dV Psi^T (K Psi), M_kl = <psi_k | K psi_l> (the matrix
+ * whose Cholesky factor -M = L L^T builds the ACE operator, Eq. (vx_ace)),
+ * as float64 row-major n_orb x n_orb blocks per system, and optionally E_x.
+ * K psi is formed first (as by hfx_apply_exchange) in the workspace, which
+ * holds n_orb x n^3 values of the plan's precision for it.  ex: nullable,
+ * n_sys float64.  FP32 plans: psi is split into float32 hi + lo parts
+ * (hi = fl32(psi), lo = fl32(psi - hi)), both multiplied with the float32
+ * K psi on FP32 MFMA, each float32 accumulator folded into float64 every 32
+ * grid points.  FP64 plans: float64 MFMA.  Errors as hfx_apply_exchange, and
+ * HFX_EINVAL for a null m.
  */
-hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, const void* kpsi, double* m,
-                               void* ws, size_t ws_bytes, void* stream);
+hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, double* m, double* ex, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/*
+ * The same contraction M = dV Psi^T (K Psi) from a K psi the caller already
+ * holds (the output of hfx_apply_exchange for the same plan and psi, in the
+ * plan's precision: float32 or float64 [n_orb][n^3] per system), so that an
+ * SCF step that needs both K psi and M forms K psi once.  kpsi may be any
+ * array of that layout and precision: the call is then a plain contraction.
+ * HFX_EINVAL for null psi, kpsi or m.
+ */
+hfx_status hfx_exchange_matrix_kpsi(hfx_plan plan, const double* psi, const void* kpsi, double* m,
+                                    void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Gradient of E_x: grad = 2 dV * gscale[s] * (K psi) for every system s, as
@@ -224,7 +239,9 @@ hfx_status hfx_ace_apply(hfx_plan plan, const double* p, const double* phi, doub
  * kept (host, one entry per system, may be NULL) receives the number of
  * kept unordered pairs a <= b.  The call waits for `stream` and returns
  * after the new schedule is uploaded (host-synchronous).  Graphs captured
- * earlier keep the schedule they were captured with.  HFX_EINVAL: null plan
+ * earlier keep the schedule they were captured with: while any graph of the
+ * plan is alive, the replaced device tables are kept (not freed) and are
+ * released when the plan's last graph is destroyed, or with the plan.  HFX_EINVAL: null plan
  * or psi, a non-finite rho_cut, or a call during graph capture; HFX_ENOMEM:
  * short workspace.
  */
@@ -311,7 +328,9 @@ hfx_status hfx_profile_read(hfx_plan plan, double* ms_host, double* bytes_host,
  * (hfx_orthonormalize of psi in place, hfx_apply_exchange, then
  * hfx_exchange_matrix; ex nullable).  Capture runs on a plan-owned stream and
  * launches nothing; the plan must outlive its graphs.  Systems of a batched
- * plan become parallel branches of one graph.
+ * plan become parallel branches of one graph.  hfx_graph_destroy synchronises
+ * the device when it releases schedule tables that hfx_screen replaced while
+ * graphs were alive (see hfx_screen).
  */
 typedef struct hfx_graph_t* hfx_graph;
 typedef enum { HFX_GRAPH_ENERGY = 0, HFX_GRAPH_APPLY = 1, HFX_GRAPH_STEP = 2 } hfx_graph_op;

@@ -75,7 +75,9 @@ struct SystemPlan {
   void* d_zero = nullptr;  // kZeroBytes of zeros: what pruned kz planes read as (band-limited plans)
   // offsets inside the caller's workspace
   size_t off_psi32 = 0, off_grids = 0, off_partials = 0, off_gemm = 0, off_ortho = 0;
-  size_t off_grad = 0;  // float32 K psi staging of the gradient (float32 plans)
+  // K psi staging of the gradient (float32 plans) and of hfx_exchange_matrix
+  // (both precisions): n_orb x N_r values of the working precision
+  size_t off_kpsi = 0;
   size_t off_mean = 0;  // float32 plans: pair-density means (n_orb x n_orb float64)
   double v0 = 0.0;      // v(G = 0)
   size_t ws_end = 0;
@@ -122,6 +124,12 @@ struct hfx_plan_t {
   hipEvent_t fork = nullptr;
   hipStream_t cap = nullptr;
   std::string desc;  // hfx_plan_describe's text
+  // Graphs bake the device addresses of the schedule tables into their
+  // kernel arguments.  While any graph of the plan is alive, tables that
+  // hfx_screen replaces are kept here instead of freed, and released when
+  // the last graph is destroyed (or with the plan).
+  int live_graphs = 0;
+  std::vector<void*> retired;
 };
 
 struct hfx_graph_t {
@@ -572,7 +580,7 @@ hfx_status enq_apply(hfx_plan plan, SystemPlan& sp, const double* psi, void* kps
 hfx_status enq_gradient(hfx_plan plan, SystemPlan& sp, const double* psi, const double* gscale,
                         double* grad, char* ws, hipStream_t st) {
   double* g = grad + sp.psi_off;
-  void* kp = plan->prec == HFX_FP64 ? static_cast<void*>(g) : static_cast<void*>(ws + sp.off_grad);
+  void* kp = plan->prec == HFX_FP64 ? static_cast<void*>(g) : static_cast<void*>(ws + sp.off_kpsi);
   hfx_status s = run_exchange(plan, sp, psi + sp.psi_off, kp, nullptr, ws, st, true);
   if (s != HFX_OK) return s;
   Bracket bk(plan, HFX_PASS_SCALE, st);
@@ -583,11 +591,12 @@ hfx_status enq_gradient(hfx_plan plan, SystemPlan& sp, const double* psi, const 
   return HFX_OK;
 }
 
-hfx_status enq_matrix(hfx_plan plan, SystemPlan& sp, const double* psi, const void* kpsi,
-                      double* m, char* ws, hipStream_t st) {
+// M of one system from its own K psi block kp (not a concatenated buffer).
+hfx_status enq_matrix_sys(hfx_plan plan, SystemPlan& sp, const double* psi, const void* kp_sys,
+                          double* m, char* ws, hipStream_t st) {
   const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
   double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
-  const char* kp = static_cast<const char*>(kpsi) + (size_t)sp.psi_off * elem;
+  const char* kp = static_cast<const char*>(kp_sys);
   const double nn = (double)sp.sys.n_orb, npts = (double)sp.nr;
   Bracket bk(plan, HFX_PASS_CONTRACT, st);
   if (plan->prec == HFX_FP32)
@@ -600,6 +609,22 @@ hfx_status enq_matrix(hfx_plan plan, SystemPlan& sp, const double* psi, const vo
   bk.done(nn * npts * (8.0 + elem), 2.0 * nn * nn * npts * (plan->prec == HFX_FP32 ? 2.0 : 1.0));
   HIP_TRY(hipGetLastError());
   return HFX_OK;
+}
+
+hfx_status enq_matrix(hfx_plan plan, SystemPlan& sp, const double* psi, const void* kpsi,
+                      double* m, char* ws, hipStream_t st) {
+  const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
+  return enq_matrix_sys(plan, sp, psi, static_cast<const char*>(kpsi) + (size_t)sp.psi_off * elem,
+                        m, ws, st);
+}
+
+// K psi into the workspace, then M from it (and E_x when ex is given).
+hfx_status enq_matrix_full(hfx_plan plan, SystemPlan& sp, const double* psi, double* m,
+                           double* ex, char* ws, hipStream_t st) {
+  void* kp = ws + sp.off_kpsi;
+  hfx_status r = run_exchange(plan, sp, psi + sp.psi_off, kp, ex, ws, st, true);
+  if (r != HFX_OK) return r;
+  return enq_matrix_sys(plan, sp, psi, kp, m, ws, st);
 }
 
 // ACE projectors: L = chol(-M), X = L^(-1), P = X W (Eq. (vx_ace)).
@@ -896,8 +921,8 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     }
     sp.off_gemm = off;
     off = align_up(off + gemm_partial_bytes(sys[i].n_orb, sp.nr));
-    sp.off_grad = off;
-    if (precision == HFX_FP32) off = align_up(off + (size_t)sys[i].n_orb * sp.nr * 4);
+    sp.off_kpsi = off;
+    off = align_up(off + (size_t)sys[i].n_orb * sp.nr * elem);
     sp.off_mean = off;
     if (precision == HFX_FP32) off = align_up(off + (size_t)sys[i].n_orb * sys[i].n_orb * 8);
     sp.off_ortho = off;
@@ -1030,6 +1055,7 @@ hfx_status hfx_plan_destroy(hfx_plan plan) {
   for (auto& ev : plan->join) (void)hipEventDestroy(ev);
   if (plan->fork) (void)hipEventDestroy(plan->fork);
   if (plan->cap) (void)hipStreamDestroy(plan->cap);
+  for (void* q : plan->retired) (void)hipFree(q);
   for (auto& sp : plan->sys) free_system(sp);
   delete plan;
   if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("pending device error: ") + hipGetErrorString(e));
@@ -1075,8 +1101,19 @@ hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double*
   });
 }
 
-hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, const void* kpsi, double* m,
+hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, double* m, double* ex,
                                void* ws, size_t ws_bytes, void* stream) {
+  hfx_status s = check_call(plan, psi, ws, ws_bytes);
+  if (s != HFX_OK) return s;
+  if (!m) return fail(HFX_EINVAL, "null m");
+  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
+    return enq_matrix_full(plan, plan->sys[i], psi, m, ex ? ex + i : nullptr,
+                           static_cast<char*>(ws), st);
+  });
+}
+
+hfx_status hfx_exchange_matrix_kpsi(hfx_plan plan, const double* psi, const void* kpsi, double* m,
+                                    void* ws, size_t ws_bytes, void* stream) {
   hfx_status s = check_call(plan, psi, ws, ws_bytes);
   if (s != HFX_OK) return s;
   if (!kpsi) return fail(HFX_EINVAL, "null kpsi");
@@ -1182,9 +1219,15 @@ hfx_status hfx_screen(hfx_plan plan, const double* psi, double rho_cut, long lon
         if (q) (void)hipFree(q);
       return s;
     }
-    // the stream is idle (synchronised above): the old tables can go
-    for (void* q : {(void*)sp.d_tiles, (void*)sp.d_active, (void*)sp.d_perm, (void*)sp.d_keep})
-      if (q) (void)hipFree(q);
+    // The stream is idle (synchronised above).  Graphs captured earlier
+    // still read the old tables: retire them while any graph is alive.
+    for (void* q : {(void*)sp.d_tiles, (void*)sp.d_active, (void*)sp.d_perm, (void*)sp.d_keep}) {
+      if (!q) continue;
+      if (plan->live_graphs > 0)
+        plan->retired.push_back(q);
+      else
+        (void)hipFree(q);
+    }
     sp.tiles = std::move(ns.tiles);
     sp.active = std::move(ns.active);
     sp.batches = std::move(ns.batches);
@@ -1312,6 +1355,7 @@ hfx_status hfx_graph_create(hfx_plan plan, int op, double* psi, void* kpsi, doub
     delete g;
     return fail(HFX_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   }
+  ++plan->live_graphs;
   *out = g;
   return HFX_OK;
 }
@@ -1327,7 +1371,16 @@ hfx_status hfx_graph_destroy(hfx_graph g) {
   hipError_t e = hipSuccess;
   if (g->exec) e = hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
+  hfx_plan plan = g->plan;
   delete g;
+  if (plan && --plan->live_graphs == 0 && !plan->retired.empty()) {
+    // the last graph that could read the retired tables is gone; a replay
+    // still in flight may read them, so wait for the device first
+    const hipError_t w = hipDeviceSynchronize();
+    if (e == hipSuccess) e = w;
+    for (void* q : plan->retired) (void)hipFree(q);
+    plan->retired.clear();
+  }
   if (e != hipSuccess) return fail(HFX_EDEVICE, std::string("hipGraphExecDestroy: ") + hipGetErrorString(e));
   return HFX_OK;
 }

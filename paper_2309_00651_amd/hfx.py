@@ -75,6 +75,7 @@ def load_library(path=None):
     lib.hfx_exchange_energy.argtypes = [vp, vp, vp, vp, sz, vp]
     lib.hfx_apply_exchange.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.hfx_exchange_matrix.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.hfx_exchange_matrix_kpsi.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.hfx_orthonormalize.argtypes = [vp, vp, i, vp, sz, vp]
     lib.hfx_exchange_gradient.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.hfx_profile_enable.argtypes = [vp, i]
@@ -98,7 +99,7 @@ def load_library(path=None):
     lib.hfx_last_error.restype = ctypes.c_char_p
     for name in ("hfx_plan_create", "hfx_plan_destroy", "hfx_workspace_size",
                  "hfx_exchange_energy", "hfx_apply_exchange", "hfx_exchange_matrix",
-                 "hfx_orthonormalize", "hfx_exchange_gradient", "hfx_profile_enable",
+                 "hfx_exchange_matrix_kpsi", "hfx_orthonormalize", "hfx_exchange_gradient", "hfx_profile_enable",
                  "hfx_profile_read", "hfx_graph_create", "hfx_graph_launch",
                  "hfx_graph_destroy", "hfx_ace_build", "hfx_ace_apply", "hfx_screen", "hfx_scdm",
                  "hfx_schedule_info"):
@@ -230,16 +231,26 @@ class Plan:
                                        _ptr(ws), self.ws_bytes, _stream()))
         return kpsi, ex
 
-    def exchange_matrix(self, psi, kpsi, m=None):
+    def exchange_matrix(self, psi, kpsi=None, m=None, ex=None):
+        """M = dV Psi^T (K Psi) (float64, systems' n_orb^2 blocks concatenated).
+
+        Without ``kpsi`` the library forms K psi itself (hfx_exchange_matrix,
+        which also writes E_x into ``ex`` when given); with ``kpsi`` (from
+        apply_exchange of this plan) only the contraction runs
+        (hfx_exchange_matrix_kpsi)."""
         self._check_psi(psi)
-        if kpsi.dtype != self.kpsi_dtype or kpsi.numel() != psi.numel():
-            raise ValueError("kpsi must come from apply_exchange of this plan")
         if m is None:
             m = torch.empty(sum(s.n_orb ** 2 for s in self.systems), dtype=torch.float64,
                             device=self.device)
         ws = self.workspace()
-        _check(_lib.hfx_exchange_matrix(self._h, _ptr(psi), _ptr(kpsi), _ptr(m), _ptr(ws),
-                                        self.ws_bytes, _stream()))
+        if kpsi is None:
+            _check(_lib.hfx_exchange_matrix(self._h, _ptr(psi), _ptr(m), _ptr(ex), _ptr(ws),
+                                            self.ws_bytes, _stream()))
+            return m
+        if kpsi.dtype != self.kpsi_dtype or kpsi.numel() != psi.numel():
+            raise ValueError("kpsi must come from apply_exchange of this plan")
+        _check(_lib.hfx_exchange_matrix_kpsi(self._h, _ptr(psi), _ptr(kpsi), _ptr(m), _ptr(ws),
+                                             self.ws_bytes, _stream()))
         return m
 
     def exchange_gradient(self, psi, gscale=None, grad=None):

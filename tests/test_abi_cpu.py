@@ -29,7 +29,7 @@ def test_header_declares_entry_points():
     syms = declared_symbols()
     for s in ("hfx_plan_create", "hfx_plan_destroy", "hfx_workspace_size",
               "hfx_exchange_energy", "hfx_apply_exchange", "hfx_exchange_matrix",
-              "hfx_exchange_gradient", "hfx_orthonormalize", "hfx_ace_build",
+              "hfx_exchange_matrix_kpsi", "hfx_exchange_gradient", "hfx_orthonormalize", "hfx_ace_build",
               "hfx_ace_apply", "hfx_screen", "hfx_scdm", "hfx_schedule_info", "hfx_plan_describe",
               "hfx_status_string",
               "hfx_last_error"):
@@ -111,7 +111,8 @@ def test_null_plan_calls(lib):
     assert lib.hfx_workspace_size(vp(0), ctypes.byref(ctypes.c_size_t())) == 1
     assert lib.hfx_exchange_energy(vp(0), vp(8), vp(8), vp(256), 0, vp(0)) == 1
     assert lib.hfx_apply_exchange(vp(0), vp(8), vp(8), vp(0), vp(256), 0, vp(0)) == 1
-    assert lib.hfx_exchange_matrix(vp(0), vp(8), vp(8), vp(8), vp(256), 0, vp(0)) == 1
+    assert lib.hfx_exchange_matrix(vp(0), vp(8), vp(8), vp(0), vp(256), 0, vp(0)) == 1
+    assert lib.hfx_exchange_matrix_kpsi(vp(0), vp(8), vp(8), vp(8), vp(256), 0, vp(0)) == 1
     assert lib.hfx_exchange_gradient(vp(0), vp(8), vp(0), vp(8), vp(256), 0, vp(0)) == 1
     assert lib.hfx_orthonormalize(vp(0), vp(8), 0, vp(256), 0, vp(0)) == 1
     assert lib.hfx_ace_build(vp(0), vp(8), vp(8), vp(8), vp(256), 0, vp(0)) == 1

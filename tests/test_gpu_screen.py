@@ -209,6 +209,44 @@ def test_screened_graph_replays_match_eager():
     g.close()
 
 
+def test_graph_captured_before_screening_keeps_its_schedule():
+    """A graph captured before hfx_screen keeps replaying the unscreened
+    schedule: the tables the screening replaces stay alive while the graph
+    does.  Every replay equals the eager unscreened call made before the
+    screening, bitwise, with screened eager calls in between; a second
+    screening (tables replaced twice) and the graph's destruction follow."""
+    psi, rho, _, _ = case(64, 9101, 0.3)
+    dev = _dev()
+    pt = torch.from_numpy(psi).to(dev)
+    plan = plan_for(64, hfx.FP32)
+    k_all, e_all = plan.apply_exchange(pt)
+    torch.cuda.synchronize()
+    k = torch.empty_like(k_all)
+    e = torch.empty_like(e_all)
+    g = plan.graph(hfx.GRAPH_APPLY, pt, kpsi=k, ex=e)
+    plan.screen(pt, rho)
+    k_scr, e_scr = plan.apply_exchange(pt)
+    torch.cuda.synchronize()
+    assert not torch.equal(e_scr, e_all)
+    for rep in range(3):
+        k.fill_(float("nan"))
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(k, k_all) and torch.equal(e, e_all), rep
+        k2, e2 = plan.apply_exchange(pt)        # eager screened work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(k2, k_scr) and torch.equal(e2, e_scr), rep
+        if rep == 1:
+            plan.screen(pt, rho)                 # replace the tables once more
+    g.close()
+    k3, e3 = plan.apply_exchange(pt)
+    plan.screen(pt, 0.0)                         # back to all pairs, no graph alive
+    k4, e4 = plan.apply_exchange(pt)
+    torch.cuda.synchronize()
+    assert torch.equal(k3, k_scr) and torch.equal(e3, e_scr)
+    assert torch.equal(k4, k_all) and torch.equal(e4, e_all)
+
+
 def test_screened_open_shell_plan():
     """hfx_screen on a two-system plan screens each system on its own
     orbitals and reports one kept count per system."""
