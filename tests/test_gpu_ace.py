@@ -5,6 +5,8 @@ P = W L^(-T) from the GPU's own W = K psi and M, and V^ACE phi = -sum_k P_k
 V^ACE psi_j = K psi_j on the GPU's K psi; V^ACE on random functions against
 the oracle; multi-system plans equal to single-system ones bit for bit.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -94,3 +96,49 @@ def test_ace_multi_system_plan_equals_single_plans():
         torch.cuda.synchronize()
         assert torch.equal(plan.split(p)[i], p1.view_as(plan.split(p)[i]))
         assert torch.equal(plan.split(out)[i], o1.view_as(plan.split(out)[i]))
+
+
+GOLDEN_ACE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "water96_ace_oracle.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN_ACE),
+                    reason="water96 ACE reference not written")
+@pytest.mark.parametrize("prec", [hfx.FP32, hfx.FP64], ids=["fp32", "fp64"])
+def test_ace_fullsize_water96(prec):
+    """ACE at the benchmarked size (96^3, 256 Loewdin orbitals, erfc kernel):
+    eight 32-blocks of the blocked Cholesky of -M, seven trailing updates.
+    The oracle's P = L^(-1) W (from its own float64 K psi and M) at seeded
+    points of six rows spread over the blocks, and L's diagonal through
+    <P_k|psi_k> = -L_kk.  Bars: float64 1e-10 of max|P|; float32 1e-5 of
+    max|P| (W carries the float32 K psi error, ~1e-7 relative, amplified by
+    at most cond(L) = sqrt(cond(-M)), which the test prints)."""
+    import json
+
+    from workloads import configs
+    with open(GOLDEN_ACE) as f:
+        g = json.load(f)
+    s = configs.WATER96
+    assert (g["n"], g["n_orb"], g["seed"], g["kernel"]) == (s.n, s.n_orb, s.seed, s.kernel)
+    dev = _dev()
+    print(f"case ace water96 prec={prec}", flush=True)
+    psi = torch.from_numpy(s.orbitals()).to(dev)
+    plan = hfx.Plan(hfx.SystemSpec(s.n, s.box, s.n_orb, s.kernel, s.param), prec, device=dev)
+    plan.orthonormalize(psi)
+    kpsi, _ = plan.apply_exchange(psi)
+    m = plan.exchange_matrix(psi, kpsi)
+    p = plan.ace_build(kpsi, m)
+    dv = s.L ** 3 / s.n ** 3
+    pf = p.view(s.n_orb, -1)
+    l_diag = (-dv * torch.sum(pf * psi.view(s.n_orb, -1), dim=1)).cpu().numpy()
+    torch.cuda.synchronize()
+    ev = np.linalg.eigvalsh(-m.view(s.n_orb, s.n_orb).cpu().numpy())
+    got = np.array([float(pf[o, q]) for o, q, _ in g["samples"]])
+    want = np.array([v for _, _, v in g["samples"]])
+    dp = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    dl = float(np.max(np.abs(l_diag - np.array(g["l_diag"])) / np.array(g["l_diag"])))
+    print(f"  cond(-M) {ev[-1] / ev[0]:.2e}  rel dP(samples) {dp:.2e}  rel dL_kk {dl:.2e}",
+          flush=True)
+    assert np.all(np.isfinite(got))
+    assert dp <= (1e-10 if prec == hfx.FP64 else 1e-5)
+    assert dl <= (1e-10 if prec == hfx.FP64 else 1e-5)

@@ -181,3 +181,20 @@ def test_scdm_mutation_transposed_columns_is_caught(monkeypatch):
     _patch(monkeypatch, "scdm", mut_scdm_transposed_columns)
     with pytest.raises(AssertionError):
         pins.test_scdm_orthonormal_same_span_and_rotation_invariant()
+
+
+def mut_scdm_gram_schmidt(psi, dv):
+    """The right pivots and columns, orthonormalised by Gram-Schmidt
+    (Cholesky) instead of Loewdin."""
+    a = psi.reshape(psi.shape[0], -1)
+    piv, _ = _orig_pivots(psi)
+    xi = (a[:, piv].T @ a).reshape(psi.shape)
+    return ho.cholesky_orthonormalize(xi, dv), piv
+
+
+def test_scdm_mutation_gram_schmidt_is_caught(monkeypatch):
+    _patch(monkeypatch, "scdm", mut_scdm_gram_schmidt)
+    # the other SCDM pins hold for any orthonormalisation of the same span
+    pins.test_scdm_orthonormal_same_span_and_rotation_invariant()
+    with pytest.raises(AssertionError):
+        pins.test_scdm_final_step_is_loewdin()

@@ -518,6 +518,25 @@ def test_scdm_orthonormal_same_span_and_rotation_invariant():
     assert np.max(np.abs(phi_u - phi)) <= 1e-11 * np.max(np.abs(phi))
 
 
+def test_scdm_final_step_is_loewdin():
+    """Loewdin's characterisation, independent of how the orthonormalisation
+    is computed: among all orthonormal Phi = T Xi spanning the density-matrix
+    columns Xi, the symmetric (Loewdin) one has T = S^(-1/2) symmetric
+    positive definite, i.e. the overlaps C = <phi_k|xi_l> = (T S)_kl =
+    S^(1/2) are symmetric positive definite with C C = S = <xi_k|xi_l>.
+    Gram-Schmidt or Cholesky would give a triangular C instead."""
+    psi, dv = _scdm_case("g", 32, 10, 5)
+    phi, piv = oracle.scdm(psi, dv)
+    a = psi.reshape(10, -1)
+    xi = a[:, piv].T @ a                 # xi_k(r) = sum_i psi_i(c_k) psi_i(r)
+    f = phi.reshape(10, -1)
+    c = dv * f @ xi.T
+    s = dv * xi @ xi.T
+    assert np.max(np.abs(c - c.T)) <= 1e-12 * np.max(np.abs(c))
+    assert np.linalg.eigvalsh(0.5 * (c + c.T)).min() > 0.0
+    assert np.max(np.abs(c @ c - s)) <= 1e-11 * np.max(np.abs(s))
+
+
 def test_scdm_relocalises_mixed_gaussians():
     """Localised Gaussians mixed by a random rotation are delocalised; the
     SCDM functions of the mixture are localised again (inverse participation

@@ -27,7 +27,7 @@ import os
 import numpy as np
 import scipy.fft as sfft
 
-__all__ = ["random_pw", "gaussians", "ifft_real"]
+__all__ = ["random_pw", "gaussians", "white_noise", "ifft_real", "fd_direction"]
 
 
 def _int_freqs(n):
@@ -107,3 +107,22 @@ def gaussians(shape, box, n_orb, ecut, seed, s_lo=1.2, s_hi=1.8):
         coef[~inside] = 0.0
         out[o] = ifft_real(coef)
     return _normalise(out, dv), centres, widths
+
+
+def white_noise(shape, box, n_orb, seed):
+    """Full-spectrum real orbitals: independent N(0, 1) values at every grid
+    point, scaled to unit norm.  Not band-limited: their pair densities fill
+    every frequency of the grid, the Nyquist planes included, unlike the two
+    families above."""
+    rng = np.random.default_rng(seed)
+    dv = box[0] * box[1] * box[2] / float(np.prod(shape))
+    return _normalise(rng.standard_normal(size=(n_orb,) + tuple(shape)), dv)
+
+
+def fd_direction(shape, dv, seed, k):
+    """Direction k of a seeded set of perturbations D[orb, z, y, x] for finite
+    differences: independent N(0, 1) values (numpy PCG64 stream seed + k),
+    scaled to dV sum D^2 = 1.  ``shape`` includes the orbital axis."""
+    rng = np.random.default_rng(seed + k)
+    d = rng.standard_normal(size=tuple(shape))
+    return d / math.sqrt(dv * float(np.sum(d * d)))
