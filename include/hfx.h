@@ -117,7 +117,14 @@ typedef struct hfx_plan_t* hfx_plan;
  * exchange (default 1).  Open-shell systems are two systems of one plan, the
  * spin-up and the spin-down orbitals on the same box: pairs never mix spins,
  * and the total exchange energy is the sum of the two E_x.  The environment
- * variable HFX_MAX_WORKSPACE_BYTES also caps the workspace.  Uploads the plan's tables
+ * variable HFX_MAX_WORKSPACE_BYTES also caps the workspace.  variant=, tiles=
+ * and rows= take either one value for every system or a ','-separated list
+ * with one value per system (variant names are checked against each
+ * system's grid).  tune_cache=<path> (or the environment variable
+ * HFX_AUTOTUNE_CACHE) names a cache written by hfx_autotune: each system
+ * whose key is found there takes the cached variant, tiles and rows for
+ * whatever the options leave open (hfx_plan_describe reports tuned=yes);
+ * a missing file or key leaves the defaults.  Uploads the plan's tables
  * (synchronous).  Errors: HFX_EINVAL for null out/sys, n_sys < 1, n <= 0,
  * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0, an unknown
  * option key or a malformed option value;
@@ -343,10 +350,41 @@ hfx_status hfx_graph_destroy(hfx_graph graph);
 /*
  * Names of the compiled kernel configurations for an n^3 (cubic) grid at the given
  * precision, ';'-separated, default first ("" if the size is unsupported).
- * A single-system plan selects one with the option "variant=<name>".
+ * A plan selects one with the option "variant=<name>" (a list for batches).
  * The returned string is thread-local and valid until the next call.
  */
 const char* hfx_variants(int n, int precision);
+
+/*
+ * Autotuner (host-synchronous; allocates device memory for its trial runs).
+ * For each of the n_sys systems (described as for hfx_plan_create, orbitals
+ * psi concatenated in that order, float64 device data as the compute calls
+ * take), times hfx_apply_exchange of single-system plans over the compiled
+ * kernel configurations of the system's grid (hfx_variants) crossed with the
+ * batch size (tiles=0, the default, and tiles=4) and the rows per tile pair
+ * (8, 16, 32 up to the orbital count), reps timed calls after one warm-up,
+ * with HIP events on `stream` (the fastest of the reps counts).  The fastest
+ * wins, except that among candidates within 5 % of it the first in a fixed
+ * order is taken (the plan defaults first), which keeps the choice stable
+ * against run-to-run timing spread.  `options`
+ * (nullable) is added to every candidate plan, e.g. "ecut=20", and may not
+ * name variant, tiles, rows or tune_cache.  cache_path (nullable): a text
+ * file of earlier choices, one line "<key> <options> <ms>" per system key
+ * (device architecture, grid, orbital count, precision, kz band of ecut and
+ * the identity of the compiled kernel sources); systems found there are not
+ * timed again and new choices are added.  chosen_host (nullable, host,
+ * chosen_bytes long) receives the choice as plan options with one value per
+ * system, "variant=a,b;tiles=x,y;rows=p,q", which hfx_plan_create accepts;
+ * plans created with option tune_cache=<path> (or with the environment
+ * variable HFX_AUTOTUNE_CACHE set) take each system's cached choice for
+ * whatever their own options leave open.  Errors: HFX_EINVAL for null sys or
+ * psi, n_sys < 1, a bad precision, an option the tuner sets itself, a short
+ * chosen_host or an unwritable cache; HFX_EUNSUPPORTED for a grid without a
+ * compiled configuration; otherwise the status of a failing trial plan.
+ */
+hfx_status hfx_autotune(const hfx_system* sys, int n_sys, int precision, const char* options,
+                        const double* psi, int reps, const char* cache_path, char* chosen_host,
+                        size_t chosen_bytes, void* stream);
 
 /* Static description of a status code. */
 const char* hfx_status_string(hfx_status s);

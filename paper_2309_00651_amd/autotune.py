@@ -1,96 +1,54 @@
-"""Autotuner for libhfx plans.
+"""Autotuner binding: argument marshalling for the library's hfx_autotune.
 
-Times every compiled kernel configuration for a system's grid size
-(``hfx.variants``) crossed with a few orbital-tile batch sizes and rows per
-tile pair (those that fit the orbital count), on the caller's orbitals, with HIP events around ``apply_exchange``; the fastest
-candidate wins, and among candidates within ``tie`` of the fastest the first
-in a fixed candidate order is taken, so re-runs agree.  Results are cached in
-a JSON file keyed by GPU architecture, grid, orbital count, precision and a
-hash of the library binary.
+The tuner itself is native (``csrc/autotune.cpp``): for each system it times
+the compiled kernel configurations of the system's grid crossed with batch
+sizes and rows per tile pair on the caller's orbitals, keeps the fastest
+(ties within 5 % go to the earliest candidate, the plan defaults first), and
+records the choice in a text cache keyed by device architecture, grid,
+orbital count, precision, kz band and the identity of the kernel sources.
+Plans created with ``tune_cache=<path>`` pick the cached choices up.
 """
 from __future__ import annotations
 
-import hashlib
-import json
-import os
+import ctypes
 
 import torch
 
 from . import hfx
 
-TILE_CHOICES = (4, 8, 16)
-ROW_CHOICES = (8, 16, 32)
+
+def tune(specs, precision, psi, cache_path=None, reps=2, options=None):
+    """Per-system plan options chosen by the tuner, e.g.
+    ``"variant=f32-n96;tiles=0;rows=32"`` (lists for several systems).
+
+    ``psi``: the systems' float64 orbitals concatenated on the GPU; ``options``:
+    options every trial plan gets (e.g. ``"ecut=20"``); ``cache_path``: the
+    text cache to read and extend."""
+    lib = hfx.load_library()
+    if isinstance(specs, hfx.SystemSpec):
+        specs = [specs]
+    specs = list(specs)
+    if psi.dtype != torch.float64 or not psi.is_cuda or not psi.is_contiguous():
+        raise ValueError("psi must be a contiguous float64 CUDA tensor")
+    if psi.numel() != sum(s.n_orb * s.nr for s in specs):
+        raise ValueError("psi does not hold the systems' orbitals")
+    arr = (hfx.System * len(specs))(*[s.to_c() for s in specs])
+    out = ctypes.create_string_buffer(64 * len(specs) + 64)
+    with torch.cuda.device(psi.device):
+        hfx._check(lib.hfx_autotune(arr, len(specs), int(precision),
+                                    options.encode() if options else None,
+                                    ctypes.c_void_p(psi.data_ptr()), int(reps),
+                                    cache_path.encode() if cache_path else None, out,
+                                    len(out), hfx._stream()))
+    return out.value.decode()
 
 
-def _build_id():
-    h = hashlib.sha1()
-    with open(hfx.LIB_PATH, "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
-
-
-def cache_key(spec, precision):
-    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-    return (f"{arch}|n={spec.n}|n_orb={spec.n_orb}|kernel={spec.kernel}|"
-            f"prec={precision}|build={_build_id()}")
-
-
-def candidates(spec, precision):
-    # rows beyond the orbital count (rounded up to a column tile) repeat the
-    # schedule of the largest row count that fits
-    rows = [r for r in ROW_CHOICES if r == ROW_CHOICES[0] or r <= -(-spec.n_orb // 8) * 8]
+def cached_lines(cache_path):
+    """The cache's records as (key, options, ms) tuples."""
     out = []
-    for v in hfx.variants(spec.n, precision):
-        for t in TILE_CHOICES:
-            for r in rows:
-                out.append(f"variant={v};tiles={t};rows={r}")
-    return out
-
-
-def time_candidate(spec, precision, psi, options, reps=2):
-    plan = hfx.Plan(spec, precision, options=options, device=psi.device)
-    kpsi = torch.empty(psi.shape, dtype=plan.kpsi_dtype, device=psi.device)
-    ex = torch.empty(1, dtype=torch.float64, device=psi.device)
-    plan.apply_exchange(psi, kpsi=kpsi, ex=ex)      # warm-up
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(reps):
-        plan.apply_exchange(psi, kpsi=kpsi, ex=ex)
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / reps
-    plan.close()
-    return ms
-
-
-def tune(spec, precision, psi, cache_path=None, reps=2, tie=0.02, log=None):
-    """Return the best options string for this system (and store it in the cache)."""
-    key = cache_key(spec, precision)
-    cache = {}
-    if cache_path and os.path.exists(cache_path):
-        with open(cache_path) as f:
-            cache = json.load(f)
-        if key in cache:
-            return cache[key]["options"]
-    timings = {}
-    for opt in candidates(spec, precision):
-        timings[opt] = time_candidate(spec, precision, psi, opt, reps)
-        if log:
-            log(f"{opt}: {timings[opt]:.2f} ms")
-    best_ms = min(timings.values())
-    best = next(o for o in timings if timings[o] <= best_ms * (1 + tie))
-    if cache_path:
-        cache[key] = {"options": best, "ms": timings[best], "timings": timings}
-        with open(cache_path, "w") as f:
-            json.dump(cache, f, indent=1, sort_keys=True)
-    return best
-
-
-def cached_options(spec, precision, cache_path):
-    """Options stored for this system, or None."""
-    if not cache_path or not os.path.exists(cache_path):
-        return None
     with open(cache_path) as f:
-        cache = json.load(f)
-    rec = cache.get(cache_key(spec, precision))
-    return rec["options"] if rec else None
+        for line in f:
+            parts = line.split()
+            if len(parts) == 3:
+                out.append((parts[0], parts[1], float(parts[2])))
+    return out

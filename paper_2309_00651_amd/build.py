@@ -16,8 +16,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhfx.so")
-SOURCES = ["hfx_api.cpp", "schedule.cpp", "exchange_common.hip", "exchange_f32.hip", "exchange_f64.hip",
-           "gemm.hip", "ortho.hip", "ace.hip", "scdm.hip"]
+SOURCES = ["hfx_api.cpp", "autotune.cpp", "schedule.cpp", "exchange_common.hip",
+           "exchange_f32.hip", "exchange_f64.hip", "gemm.hip", "ortho.hip", "ace.hip", "scdm.hip"]
+# Sources whose content decides the speed of a kernel configuration: their
+# hash is the build identity in tune-cache keys (a cached choice is used only
+# by a library built from the same kernels and schedules).
+TUNED_SOURCES = ["fft.hpp", "exchange_kernels.hpp", "exchange_f32.hip", "exchange_f64.hip",
+                 "hfx_internal.hpp", "schedule.cpp", "schedule.hpp"]
 ARCH = "gfx950"
 # packed float32 instructions stay off (see the design notes on v_pk_* ops)
 FLAGS = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC",
@@ -32,9 +37,19 @@ def hipcc():
     raise RuntimeError("hipcc not found: the HIP toolchain is required to build libhfx")
 
 
+def sources_id():
+    import hashlib
+    h = hashlib.sha1()
+    for name in TUNED_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *FLAGS, f'-DHFX_SOURCES_ID="{sources_id()}"', "-x", "hip", "-c",
+           os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

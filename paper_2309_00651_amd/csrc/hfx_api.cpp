@@ -25,23 +25,39 @@
 
 #include "hfx_internal.hpp"
 #include "schedule.hpp"
+#include "tune.hpp"
 #include "twiddle.hpp"
 
 using namespace hfx;
 
-namespace {
-
 // Rows per tile pair when the plan options name none: 32 from 256 orbitals
 // on, else 16 (measured on one MI355X over 64-512 orbitals and 64^3-128^3
 // grids: never slower than 8 rows, within 2.5 % of the best choice).
-int default_rows(int n_orb) { return n_orb >= 256 ? 32 : 16; }
+int hfx::default_rows(int n_orb) { return n_orb >= 256 ? 32 : 16; }
+
+namespace {
 
 thread_local std::string g_last_error;
 
 hfx_status fail(hfx_status s, const std::string& msg) {
   g_last_error = msg;
+  hfx::log_line(std::string(hfx_status_string(s)) + ": " + msg);
   return s;
 }
+
+}  // namespace
+
+void hfx::set_error(const std::string& msg) { g_last_error = msg; }
+
+void hfx::log_line(const std::string& msg) {
+  static const bool on = [] {
+    const char* e = std::getenv("HFX_LOG");
+    return e && *e && std::strcmp(e, "0") != 0;
+  }();
+  if (on) std::fprintf(stderr, "[hfx] %s\n", msg.c_str());
+}
+
+namespace {
 
 #define HIP_TRY(expr)                                                              \
   do {                                                                             \
@@ -98,6 +114,7 @@ struct SystemPlan {
   // offsets inside concatenated user buffers
   long long psi_off = 0, m_off = 0;
   long long orb_off = 0;  // first orbital of this system (per-orbital arrays)
+  bool tuned = false;     // kernel configuration taken from the tune cache
 };
 
 }  // namespace
@@ -196,7 +213,7 @@ bool parse_option(const char* opts, const char* key, long long def, long long* o
 bool options_known(const char* opts, std::string* bad) {
   if (!opts) return true;
   static const char* known[] = {"tiles", "maxws", "variant", "streams", "shard", "mix", "rows",
-                                "ecut"};
+                                "ecut", "tune_cache"};
   const std::string s(opts);
   size_t p = 0;
   while (p < s.size()) {
@@ -216,6 +233,38 @@ bool options_known(const char* opts, std::string* bad) {
       return false;
     }
   }
+  return true;
+}
+
+// Value of a per-system option for system i: "key=v" applies to every
+// system, "key=v0,v1,..." gives one value per system (exactly n_sys of them).
+// Empty when the key is absent; false when a list has the wrong length.
+bool per_system_value(const std::string& v, int i, int n_sys, std::string* out) {
+  out->clear();
+  if (v.find(',') == std::string::npos) {
+    *out = v;
+    return true;
+  }
+  std::vector<std::string> items;
+  size_t p = 0;
+  while (true) {
+    const size_t e = v.find(',', p);
+    items.push_back(v.substr(p, e == std::string::npos ? std::string::npos : e - p));
+    if (e == std::string::npos) break;
+    p = e + 1;
+  }
+  if ((int)items.size() != n_sys) return false;
+  *out = items[i];
+  return true;
+}
+
+// Whole non-negative decimal number.
+bool parse_count(const std::string& v, long long* out) {
+  char* end = nullptr;
+  errno = 0;
+  const long long x = std::strtoll(v.c_str(), &end, 10);
+  if (v.empty() || end == v.c_str() || *end != '\0' || errno != 0 || x < 0) return false;
+  *out = x;
   return true;
 }
 
@@ -807,17 +856,11 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     if (!options_known(options, &bad))
       return fail(HFX_EINVAL, "unknown plan option '" + bad + "'");
   }
-  long long tiles_cap = 0, ws_cap = 0, batch_streams = 1;
-  if (!parse_option(options, "tiles", 0, &tiles_cap))
-    return fail(HFX_EINVAL, "tiles= takes a non-negative integer");
+  long long ws_cap = 0, batch_streams = 1;
   if (!parse_option(options, "maxws", 0, &ws_cap))
     return fail(HFX_EINVAL, "maxws= takes a non-negative integer (bytes)");
   if (!parse_option(options, "streams", 1, &batch_streams))
     return fail(HFX_EINVAL, "streams= must be 1 or 2");
-  long long rows_opt = 0;
-  if (!parse_option(options, "rows", 0, &rows_opt) ||
-      (rows_opt != 0 && (rows_opt % 8 != 0 || rows_opt > kMaxRows)))
-    return fail(HFX_EINVAL, "rows= takes 8, 16, 24 or 32");
   int shard = 0, shards = 1;
   {
     const std::string sv = parse_option_str(options, "shard");
@@ -855,11 +898,65 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
         return fail(HFX_EINVAL, "ecut=<Ha> needs a positive cutoff");
     }
   }
-  const std::string vname = parse_option_str(options, "variant");
-  if (!vname.empty() && n_sys > 1)
-    return fail(HFX_EINVAL, "variant= applies to single-system plans only");
-  if (!vname.empty() && !find_variant(sys[0].n[0], sys[0].n[2], precision, vname))
-    return fail(HFX_EINVAL, "unknown variant '" + vname + "' for this grid and precision");
+  // Per-system kernel configuration: variant=, tiles= and rows= take one
+  // value for every system or a ','-separated list with one per system;
+  // systems that name none take the tune cache's choice, else the defaults.
+  std::vector<std::string> vnames(n_sys);
+  std::vector<long long> tiles_v(n_sys, 0), rows_v(n_sys, 0);
+  std::vector<char> tuned(n_sys, 0);
+  {
+    const std::string vv = parse_option_str(options, "variant");
+    const std::string tv = parse_option_str(options, "tiles");
+    const std::string rv = parse_option_str(options, "rows");
+    if (tv.empty() && has_option(options, "tiles"))
+      return fail(HFX_EINVAL, "tiles= takes a non-negative integer");
+    if (rv.empty() && has_option(options, "rows"))
+      return fail(HFX_EINVAL, "rows= takes 8, 16, 24 or 32");
+    std::string tc = parse_option_str(options, "tune_cache");
+    if (tc.empty() && has_option(options, "tune_cache"))
+      return fail(HFX_EINVAL, "tune_cache= needs a file path");
+    if (tc.empty())
+      if (const char* env = std::getenv("HFX_AUTOTUNE_CACHE")) tc = env;
+    double ecut_k = 0.0;
+    {
+      const std::string ev = parse_option_str(options, "ecut");
+      if (!ev.empty()) ecut_k = std::strtod(ev.c_str(), nullptr);
+    }
+    for (int i = 0; i < n_sys; ++i) {
+      std::string x;
+      if (!per_system_value(vv, i, n_sys, &x))
+        return fail(HFX_EINVAL, "variant= list needs one name per system");
+      vnames[i] = x;
+      if (!per_system_value(tv, i, n_sys, &x) || (!x.empty() && !parse_count(x, &tiles_v[i])))
+        return fail(HFX_EINVAL, "tiles= takes a non-negative integer (or one per system)");
+      if (!per_system_value(rv, i, n_sys, &x) || (!x.empty() && !parse_count(x, &rows_v[i])) ||
+          (rows_v[i] != 0 && (rows_v[i] % 8 != 0 || rows_v[i] > kMaxRows)))
+        return fail(HFX_EINVAL, "rows= takes 8, 16, 24 or 32 (or one per system)");
+      if (!tc.empty()) {
+        std::string topt;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        const std::string key =
+            tune_key(sys[i], precision, kz_max_for(ecut_k, sys[i].L[2]), device_arch(dev));
+        if (tune_lookup(tc, key, &topt)) {
+          // explicit options win over the cache
+          const std::string cv = parse_option_str(topt.c_str(), "variant");
+          const std::string ct = parse_option_str(topt.c_str(), "tiles");
+          const std::string cr = parse_option_str(topt.c_str(), "rows");
+          long long t = 0, r = 0;
+          if (vnames[i].empty() && !cv.empty() &&
+              find_variant(sys[i].n[0], sys[i].n[2], precision, cv))
+            vnames[i] = cv;
+          if (tv.empty() && parse_count(ct, &t)) tiles_v[i] = t;
+          if (rv.empty() && parse_count(cr, &r) && r % 8 == 0 && r <= kMaxRows) rows_v[i] = r;
+          tuned[i] = 1;
+        }
+      }
+      if (!vnames[i].empty() && !find_variant(sys[i].n[0], sys[i].n[2], precision, vnames[i]))
+        return fail(HFX_EINVAL, "unknown variant '" + vnames[i] + "' for the grid of system " +
+                                    std::to_string(i));
+    }
+  }
   if (batch_streams != 1 && batch_streams != 2)
     return fail(HFX_EINVAL, "streams= must be 1 or 2");
   if (const char* env = std::getenv("HFX_MAX_WORKSPACE_BYTES")) {
@@ -876,28 +973,24 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   for (int i = 0; i < n_sys; ++i) {
     SystemPlan& sp = p->sys[i];
     sp.sys = sys[i];
-    sp.var = find_variant(sys[i].n[0], sys[i].n[2], precision, vname);
+    sp.var = find_variant(sys[i].n[0], sys[i].n[2], precision, vnames[i]);
+    sp.tuned = tuned[i] != 0;
     sp.n = sys[i].n[0];
     sp.nr = (long long)sp.n * sp.n * sys[i].n[2];
     sp.dv = sys[i].L[0] * sys[i].L[1] * sys[i].L[2] / (double)sp.nr;
     sp.shard = shard;
     sp.shards = shards;
-    sp.tiles_cap = tiles_cap;
+    sp.tiles_cap = tiles_v[i];
     {
       // rows per tile pair: a multiple of the tile, at most what the variant
       // allows (rows= is clamped per system)
       const int t = sp.var->tile;
-      int r = rows_opt > 0 ? (int)rows_opt : default_rows(sp.sys.n_orb);
+      int r = rows_v[i] > 0 ? (int)rows_v[i] : default_rows(sp.sys.n_orb);
       r = std::min(r, sp.var->max_rows);
       sp.rows = std::max(t, r / t * t);
     }
-    schedule_all_pairs(sp, tiles_cap);
-    if (ecut > 0.0) {
-      // orbitals with (1/2)|G|^2 <= ecut have |m_z| <= G_cut L_z / (2 pi); pair
-      // densities then |kz| <= 2 of that
-      const double mz = std::sqrt(2.0 * ecut) * sys[i].L[2] / (2.0 * 3.14159265358979323846);
-      sp.kz_max = 2 * (int)std::floor(mz + 1e-9);
-    }
+    schedule_all_pairs(sp, sp.tiles_cap);
+    sp.kz_max = kz_max_for(ecut, sys[i].L[2]);
     sp.psi_off = psi_off;
     sp.m_off = m_off;
     sp.orb_off = orb_off;
@@ -1004,6 +1097,9 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     }
   }
   *out = p;
+  for (int i = 0; i < n_sys; ++i)
+    log_line("plan system " + std::to_string(i) + ": " + hfx_plan_describe(p, i) +
+             " workspace=" + std::to_string(p->ws_bytes));
   return HFX_OK;
 }
 
@@ -1270,7 +1366,8 @@ const char* hfx_plan_describe(hfx_plan plan, int system) {
                   " tiles_per_batch=" + std::to_string(sp.tiles_per_batch) +
                   " batches=" + std::to_string(sp.batches.size()) +
                   " streams=" + std::to_string(sp.nstreams) +
-                  " screened=" + (sp.d_keep ? "yes" : "no");
+                  " screened=" + (sp.d_keep ? "yes" : "no") +
+                  " tuned=" + (sp.tuned ? "yes" : "no");
   plan->desc = d;
   return plan->desc.c_str();
 }

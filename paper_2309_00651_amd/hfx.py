@@ -88,6 +88,8 @@ def load_library(path=None):
     lib.hfx_schedule_info.argtypes = [vp, i, ctypes.POINTER(ctypes.c_longlong)]
     lib.hfx_plan_describe.argtypes = [vp, i]
     lib.hfx_plan_describe.restype = ctypes.c_char_p
+    lib.hfx_autotune.argtypes = [ctypes.POINTER(System), i, i, ctypes.c_char_p, vp, i,
+                                 ctypes.c_char_p, ctypes.c_char_p, sz, vp]
     lib.hfx_graph_create.argtypes = [vp, i, vp, vp, vp, vp, vp, sz, ctypes.POINTER(vp)]
     lib.hfx_graph_launch.argtypes = [vp, vp]
     lib.hfx_graph_destroy.argtypes = [vp]
@@ -102,7 +104,7 @@ def load_library(path=None):
                  "hfx_exchange_matrix_kpsi", "hfx_orthonormalize", "hfx_exchange_gradient", "hfx_profile_enable",
                  "hfx_profile_read", "hfx_graph_create", "hfx_graph_launch",
                  "hfx_graph_destroy", "hfx_ace_build", "hfx_ace_apply", "hfx_screen", "hfx_scdm",
-                 "hfx_schedule_info"):
+                 "hfx_schedule_info", "hfx_autotune"):
         getattr(lib, name).restype = i
     if path is None:
         _lib = lib

@@ -134,7 +134,21 @@ def test_status_strings(lib):
                                   b"tiles=", b"maxws=1e9", b"streams=", b"tilez=3",
                                   b"tiles", b"tiles=2;bogus=1", b"rows=12", b"rows=40",
                                   b"rows=-8", b"rows=abc", b"rows=", b"ecut=0", b"ecut=-5",
-                                  b"ecut=abc", b"ecut=nan", b"ecut=", b"ecut=5Ha", b"mix="])
+                                  b"ecut=abc", b"ecut=nan", b"ecut=", b"ecut=5Ha", b"mix=",
+                                  b"tune_cache=", b"rows=8,16", b"tiles=1,2", b"variant=a,b",
+                                  b"variant=nope"])
 def test_bad_plan_options_rejected_before_device(lib, opts):
     st, h, err = _create(lib, [GOOD], opts=opts)
     assert st == 1 and not h.value and err
+
+
+def test_autotune_argument_errors_before_device(lib):
+    vp = ctypes.c_void_p
+    arr = (hfx.System * 1)(GOOD.to_c())
+    buf = ctypes.create_string_buffer(64)
+    assert lib.hfx_autotune(None, 1, 0, None, vp(8), 1, None, buf, 64, vp(0)) == 1
+    assert lib.hfx_autotune(arr, 0, 0, None, vp(8), 1, None, buf, 64, vp(0)) == 1
+    assert lib.hfx_autotune(arr, 1, 0, None, vp(0), 1, None, buf, 64, vp(0)) == 1
+    assert lib.hfx_autotune(arr, 1, 7, None, vp(8), 1, None, buf, 64, vp(0)) == 1
+    assert lib.hfx_autotune(arr, 1, 0, b"rows=8", vp(8), 1, None, buf, 64, vp(0)) == 1
+    assert "chooses" in lib.hfx_last_error().decode()
