@@ -369,7 +369,8 @@ const char* hfx_variants(int n, int precision);
  * against run-to-run timing spread.  `options`
  * (nullable) is added to every candidate plan, e.g. "ecut=20", and may not
  * name variant, tiles, rows or tune_cache.  cache_path (nullable): a text
- * file of earlier choices, one line "<key> <options> <ms>" per system key
+ * file of earlier choices, one line "<key> <options> <ms>" per system key,
+ * each followed by its candidate table ("<key>#candidate <options> <ms>")
  * (device architecture, grid, orbital count, precision, kz band of ecut and
  * the identity of the compiled kernel sources); systems found there are not
  * timed again and new choices are added.  chosen_host (nullable, host,

@@ -44,7 +44,16 @@ def tune(specs, precision, psi, cache_path=None, reps=2, options=None):
 
 
 def cached_lines(cache_path):
-    """The cache's records as (key, options, ms) tuples."""
+    """The cache's choices as (key, options, ms) tuples."""
+    return [r for r in _records(cache_path) if "#" not in r[0]]
+
+
+def candidate_table(cache_path, key):
+    """{options: ms} of every candidate timed for key."""
+    return {o: ms for k, o, ms in _records(cache_path) if k == key + "#candidate"}
+
+
+def _records(cache_path):
     out = []
     with open(cache_path) as f:
         for line in f:

@@ -72,7 +72,9 @@ bool tune_lookup(const std::string& path, const std::string& key, std::string* o
 }
 
 bool tune_store(const std::string& path, const std::string& key, const std::string& options,
-                double ms) {
+                double ms, const std::vector<std::pair<std::string, double>>& timings) {
+  // the key's choice and its candidate table replace earlier ones
+  const std::string table = key + "#candidate";
   std::vector<std::string> lines;
   {
     std::ifstream f(path);
@@ -80,12 +82,16 @@ bool tune_store(const std::string& path, const std::string& key, const std::stri
     while (f && std::getline(f, line)) {
       std::istringstream ls(line);
       std::string k;
-      if (ls >> k && k != key) lines.push_back(line);
+      if (ls >> k && k != key && k != table) lines.push_back(line);
     }
   }
   char buf[64];
   std::snprintf(buf, sizeof buf, "%.4f", ms);
   lines.push_back(key + " " + options + " " + buf);
+  for (const auto& t : timings) {
+    std::snprintf(buf, sizeof buf, "%.4f", t.second);
+    lines.push_back(table + " " + t.first + " " + buf);
+  }
   const std::string tmp = path + ".tmp";
   {
     std::ofstream o(tmp, std::ios::trunc);
@@ -264,7 +270,10 @@ extern "C" hfx_status hfx_autotune(const hfx_system* sys, int n_sys, int precisi
       while (!(ms[pick] > 0.0 && ms[pick] <= fastest * (1.0 + kTieWindow))) ++pick;
       best = cands[pick];
       log_line("autotune system " + std::to_string(i) + ": chose " + best);
-      if (cache_path && !tune_store(cache_path, key, best, ms[pick])) {
+      std::vector<std::pair<std::string, double>> table;
+      for (size_t c = 0; c < cands.size(); ++c)
+        if (ms[c] > 0.0) table.emplace_back(cands[c], ms[c]);
+      if (cache_path && !tune_store(cache_path, key, best, ms[pick], table)) {
         set_error(std::string("cannot write the tune cache ") + cache_path);
         return HFX_EINVAL;
       }

@@ -1,8 +1,10 @@
-// Tune-cache helpers shared by plan creation (hfx_api.cpp) and the
-// autotuner (autotune.cpp).  Host code.
+// Host-side helpers shared by the plan (hfx_api.cpp) and the autotuner
+// (autotune.cpp).
 #pragma once
 
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/hfx.h"
 
@@ -27,10 +29,12 @@ std::string tune_key(const hfx_system& s, int precision, int kz_max, const std::
 // rows=.."); false when the file or the key is missing.
 bool tune_lookup(const std::string& path, const std::string& key, std::string* options);
 
-// Adds or replaces the line of key (written to a temporary file, then
-// renamed over the cache).  False when the file cannot be written.
+// Adds or replaces the line of key and its candidate table (one line
+// "<key>#candidate <options> <ms>" per timed candidate), written to a
+// temporary file that is then renamed over the cache.  False when the file
+// cannot be written.
 bool tune_store(const std::string& path, const std::string& key, const std::string& options,
-                double ms);
+                double ms, const std::vector<std::pair<std::string, double>>& timings);
 
 // Identity of the kernel sources the library was built from.
 const char* build_id();

@@ -4,9 +4,10 @@
   float64 oracle to the parity bars (Eqs. (HFX), (vx)), and
   hfx_plan_describe reports the cached configuration (tuned=yes).
 * The choice is cached (one line per system, keyed with the kernel-source
-  identity), a re-run with the cache returns it without timing, and a
-  re-run without the cache (fresh timings) picks the same configuration:
-  the 5 % tie rule makes the choice stable against timing noise.
+  identity, with the table of every candidate's time), a re-run with the
+  cache returns it without timing, and a re-run without the cache (fresh
+  timings) picks the same configuration or, when candidates sit at the edge
+  of the 5 % tie window, one that is equally fast in both runs' tables.
 * A two-system plan takes a different cached configuration per system
   (per-system options), and its results equal single-system plans with the
   same explicit options, bitwise.
@@ -49,10 +50,21 @@ def test_tuned_plan_matches_oracle_and_choice_is_stable(tmp_path):
     assert _parse(best)["variant"] in hfx.variants(N, hfx.FP32)
     # cached: same answer
     assert autotune.tune(spec, hfx.FP32, psi, cache_path=cache, options="ecut=20") == best
-    # fresh timings, no cache: same choice
-    again = autotune.tune(spec, hfx.FP32, psi, reps=3, options="ecut=20")
+    # fresh timings (a new cache): the same choice, or, when two candidates
+    # sit at the edge of the tie window, one that both runs time within the
+    # window plus the run-to-run spread (3 %) of the other
+    cache2 = str(tmp_path / "tune2.txt")
+    again = autotune.tune(spec, hfx.FP32, psi, cache_path=cache2, reps=3, options="ecut=20")
+    t1 = autotune.candidate_table(cache, recs[0][0])
+    t2 = autotune.candidate_table(cache2, recs[0][0])
     print(f"  tuned {best}; re-tuned without the cache {again}", flush=True)
-    assert again == best
+    for t in (t1, t2):
+        print("   ", " ".join(f"{o.split(';', 1)[0][8:]}/{o.split(';', 1)[1]}={ms:.3f}"
+                              for o, ms in t.items()), flush=True)
+    assert len(t1) == len(t2) > 1
+    if again != best:
+        for t in (t1, t2):
+            assert abs(t[again] - t[best]) <= 0.08 * min(t[again], t[best])
     plan = hfx.Plan(spec, hfx.FP32, options=f"ecut=20;tune_cache={cache}", device=dev)
     d = plan.describe()
     print(f"  {d}", flush=True)
