@@ -182,6 +182,27 @@ hfx_status hfx_exchange_matrix_kpsi(hfx_plan plan, const double* psi, const void
                                     void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * hfx_apply_exchange without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same launch sequence and results
+ * (K psi = V_X psi and optionally E_x, bitwise equal to hfx_apply_exchange's)
+ * with the workspace in a file-scope device array of the library, 256 MiB on
+ * every GPU the library runs on, held until the process ends.  The call
+ * allocates nothing and creates no event (profiling is skipped); the first
+ * call on a device looks the array's address up.  The plan's device must be
+ * current.  Every call on one GPU shares that GPU's array: calls that overlap
+ * on the device (from several host threads, or on streams not ordered with
+ * each other) race and give wrong results; ordered calls are safe, since no
+ * state is kept between calls (nothing in the array needs to start at zero).
+ * Errors: HFX_EINVAL for null plan, psi or kpsi, or another device current;
+ * HFX_ENOMEM when the plan's energy and K psi calls need more than 256 MiB
+ * of workspace (plans with fewer tile pairs per batch, tiles=, need less);
+ * HFX_EDEVICE when the array's address cannot be looked up.
+ */
+hfx_status hfx_apply_exchange_noalloc(hfx_plan plan, const double* psi, void* kpsi, double* ex,
+                                      void* stream);
+
+/*
  * Gradient of E_x: grad = 2 dV * gscale[s] * (K psi) for every system s, as
  * float64 [n_orb][n^3] (overwritten).  The pair potentials are recomputed
  * (nothing is kept from an earlier energy call).  gscale: nullable device

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhfx.so")
 SOURCES = ["hfx_api.cpp", "autotune.cpp", "schedule.cpp", "exchange_common.hip",
-           "exchange_f32.hip", "exchange_f64.hip", "gemm.hip", "ortho.hip", "ace.hip", "scdm.hip"]
+           "exchange_f32.hip", "exchange_f64.hip", "gemm.hip", "ortho.hip", "ace.hip", "scdm.hip",
+           "noalloc.hip"]
 # Sources whose content decides the speed of a kernel configuration: their
 # hash is the build identity in tune-cache keys (a cached choice is used only
 # by a library built from the same kernels and schedules).

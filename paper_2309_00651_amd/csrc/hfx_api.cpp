@@ -96,7 +96,6 @@ struct SystemPlan {
   size_t off_kpsi = 0;
   size_t off_mean = 0;  // float32 plans: pair-density means (n_orb x n_orb float64)
   double v0 = 0.0;      // v(G = 0)
-  size_t ws_end = 0;
   // batch streams: 2 = consecutive batches alternate between the call's
   // stream and an owned stream, each with its own pair-grid buffer
   int nstreams = 1;
@@ -129,9 +128,11 @@ struct hfx_plan_t {
   int prec = 0;
   std::vector<SystemPlan> sys;
   size_t ws_bytes = 0;
+  size_t apply_bytes = 0;  // leading workspace bytes the energy and K psi calls use
   int device = 0;
   bool prof = false;
   bool capturing = false;
+  bool quiet = false;  // no profiling events (a call that must not create any)
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   // multi-system plans: one side stream per system (default priority) and
@@ -414,12 +415,12 @@ struct Bracket {
   hipStream_t st;
   hipEvent_t start = nullptr;
   Bracket(hfx_plan p, int ps, hipStream_t s) : plan(p), pass(ps), st(s) {
-    if (!plan->prof || plan->capturing) return;
+    if (!plan->prof || plan->capturing || plan->quiet) return;
     start = take_event(plan);
     if (start) (void)hipEventRecord(start, st);
   }
   void done(double bytes, double flops) {
-    if (!plan->prof || plan->capturing || !start) return;
+    if (!plan->prof || plan->capturing || plan->quiet || !start) return;
     hipEvent_t stop = take_event(plan);
     if (!stop) return;
     (void)hipEventRecord(stop, st);
@@ -1014,14 +1015,19 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     }
     sp.off_gemm = off;
     off = align_up(off + gemm_partial_bytes(sys[i].n_orb, sp.nr));
-    sp.off_kpsi = off;
-    off = align_up(off + (size_t)sys[i].n_orb * sp.nr * elem);
     sp.off_mean = off;
     if (precision == HFX_FP32) off = align_up(off + (size_t)sys[i].n_orb * sys[i].n_orb * 8);
+  }
+  // Everything the energy and K psi calls use comes first (all systems);
+  // the regions only the other calls use follow.
+  p->apply_bytes = off;
+  for (int i = 0; i < n_sys; ++i) {
+    SystemPlan& sp = p->sys[i];
+    sp.off_kpsi = off;
+    off = align_up(off + (size_t)sys[i].n_orb * sp.nr * elem);
     sp.off_ortho = off;
     off = align_up(off + (size_t)6 * sys[i].n_orb * sys[i].n_orb * 8 + 64);
     off = align_up(off + (size_t)sys[i].n_orb * std::min<long long>(sp.nr, 32768) * 8);
-    sp.ws_end = off;
   }
   p->ws_bytes = off;
   if (ws_cap > 0 && (long long)p->ws_bytes > ws_cap) {
@@ -1185,6 +1191,27 @@ hfx_status hfx_apply_exchange(hfx_plan plan, const double* psi, void* kpsi, doub
                      st);
   });
 }
+
+}  // extern "C"
+
+size_t hfx::apply_workspace_bytes(hfx_plan plan) { return plan->apply_bytes; }
+
+int hfx::plan_device(hfx_plan plan) { return plan->device; }
+
+hfx_status hfx::apply_into(hfx_plan plan, const double* psi, void* kpsi, double* ex, void* ws,
+                           void* stream) {
+  // the caller checked the arguments and that ws holds apply_workspace_bytes
+  plan->quiet = true;
+  const hfx_status s =
+      dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
+        return enq_apply(plan, plan->sys[i], psi, kpsi, ex ? ex + i : nullptr,
+                         static_cast<char*>(ws), st);
+      });
+  plan->quiet = false;
+  return s;
+}
+
+extern "C" {
 
 hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double* gscale,
                                  double* grad, void* ws, size_t ws_bytes, void* stream) {

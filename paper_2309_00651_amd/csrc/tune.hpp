@@ -1,5 +1,5 @@
-// Host-side helpers shared by the plan (hfx_api.cpp) and the autotuner
-// (autotune.cpp).
+// Host-side helpers shared by the plan (hfx_api.cpp), the autotuner
+// (autotune.cpp) and the entry point that allocates nothing (noalloc.hip).
 #pragma once
 
 #include <string>
@@ -44,6 +44,14 @@ int default_rows(int n_orb);
 
 // Sets the thread-local text hfx_last_error() returns (hfx_api.cpp).
 void set_error(const std::string& msg);
+
+// Leading workspace bytes the energy and K psi calls of a plan use, the
+// plan's device, and hfx_apply_exchange's launch sequence on a workspace of
+// that size with no profiling events (hfx_api.cpp).
+size_t apply_workspace_bytes(hfx_plan plan);
+int plan_device(hfx_plan plan);
+hfx_status apply_into(hfx_plan plan, const double* psi, void* kpsi, double* ex, void* ws,
+                      void* stream);
 
 // One line "[hfx] msg" on stderr when the environment variable HFX_LOG is set
 // to a non-empty value other than "0" (hfx_api.cpp).
