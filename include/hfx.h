@@ -110,7 +110,14 @@ typedef struct hfx_plan_t* hfx_plan;
  * combinations such as orthonormalisation): pair densities then vanish on the
  * kz planes with |kz| > 2 floor(sqrt(2 ecut) L_z / 2 pi), which the passes
  * skip (results agree with the full transform to rounding; orbitals outside
- * the sphere give wrong results, which the library cannot detect); mix=<a>,
+ * the sphere give wrong results, which check=1 detects); check=1 (or the
+ * environment variable HFX_CHECK_INPUTS=1) makes the energy, K psi, matrix
+ * and gradient calls check psi first and return HFX_EINVAL, launching
+ * nothing else, when an orbital holds a non-finite value or, in a plan with
+ * ecut=, has more than 1e-12 of its power beyond the z band |m_z| <=
+ * floor(sqrt(2 ecut) L_z / 2 pi) that the skipped planes rely on (a direct
+ * z transform of every orbital column in float64; the call then waits for
+ * its stream; skipped under graph capture); mix=<a>,
  * 0 < a <= 1,
  * is a hybrid functional's exact-exchange fraction: the kernel is scaled by a,
  * so E_x, K psi, M, the gradient and the ACE operator are a times the full

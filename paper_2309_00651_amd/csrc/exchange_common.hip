@@ -1,6 +1,7 @@
 // Elementwise helpers of the exchange pipeline: float64 -> float32 staging
 // of the orbitals, zero fill (a kernel rather than a memset, so the calls stay
-// graph-capture friendly), and the fixed-order float64 energy reduction.
+// graph-capture friendly), the fixed-order float64 energy reduction, and the
+// optional input check (non-finite values, z band of the orbitals).
 #include <hip/hip_runtime.h>
 
 #include "hfx_internal.hpp"
@@ -86,6 +87,78 @@ __global__ void __launch_bounds__(256) k_mask(double* __restrict__ m,
                                              const unsigned char* __restrict__ keep, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n && !keep[i]) m[i] = 0.0;
+}
+
+// Input check of one x-chunk of one (orbital, y) row: the number of
+// non-finite values, sum psi^2, and, when m_max >= 0, the power of the z
+// spectrum beyond |m_z| <= m_max, sum over those k of |sum_z psi(z)
+// e^(-2 pi i k z / nz)|^2 (nz times its share of sum psi^2, by Parseval).
+// Direct DFT of the pruned frequencies from a column block in LDS: a check,
+// not a hot path.  One 64-thread workgroup: 32 x columns, two halves
+// splitting z rows and frequencies; a fixed-order wavefront sum.
+constexpr int kCheckXC = 32, kCheckNZ = 128;
+__global__ void __launch_bounds__(64) k_check_orbitals(const double* __restrict__ psi, int nx,
+                                                      int ny, int nz, int m_max,
+                                                      double* __restrict__ part) {
+  __shared__ double col[kCheckNZ][kCheckXC + 1];
+  __shared__ double twc[kCheckNZ], tws[kCheckNZ];
+  const int xcs = (nx + kCheckXC - 1) / kCheckXC;
+  const long long b = blockIdx.x;
+  const int xc = (int)(b % xcs);
+  const int y = (int)((b / xcs) % ny);
+  const long long o = b / ((long long)xcs * ny);
+  const int t = threadIdx.x, c = t & (kCheckXC - 1), h = t >> 5;
+  const int x = xc * kCheckXC + c;
+  const bool valid = x < nx;
+  double tot = 0.0, bad = 0.0, oob = 0.0;
+  for (int z = h; z < nz; z += 2) {
+    const double v = valid ? psi[((o * nz + z) * ny + y) * (long long)nx + x] : 0.0;
+    col[z][c] = v;
+    tot += v * v;
+    bad += isfinite(v) ? 0.0 : 1.0;
+  }
+  for (int k = t; k < nz; k += 64) {
+    double sn, cs;
+    sincospi(-2.0 * k / nz, &sn, &cs);
+    twc[k] = cs;
+    tws[k] = sn;
+  }
+  __syncthreads();
+  if (m_max >= 0 && valid) {
+    for (int k = m_max + 1 + h; k <= nz - 1 - m_max; k += 2) {
+      double re = 0.0, im = 0.0;
+      int idx = 0;  // k z mod nz
+      for (int z = 0; z < nz; ++z) {
+        re += col[z][c] * twc[idx];
+        im += col[z][c] * tws[idx];
+        idx += k;
+        if (idx >= nz) idx -= nz;
+      }
+      oob += re * re + im * im;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    tot += __shfl_xor(tot, off);
+    bad += __shfl_xor(bad, off);
+    oob += __shfl_xor(oob, off);
+  }
+  if (t == 0) {
+    part[3 * b] = bad;
+    part[3 * b + 1] = tot;
+    part[3 * b + 2] = oob;
+  }
+}
+
+long long check_partials(int n_orb, int nx, int ny) {
+  return (long long)n_orb * ny * ((nx + kCheckXC - 1) / kCheckXC);
+}
+
+bool launch_check_orbitals(const double* psi, int n_orb, int nx, int ny, int nz, int m_max,
+                           double* part, hipStream_t s) {
+  if (nz > kCheckNZ) return false;
+  hipLaunchKernelGGL(k_check_orbitals, dim3((unsigned)check_partials(n_orb, nx, ny)), dim3(64),
+                     0, s, psi, nx, ny, nz, m_max, part);
+  return true;
 }
 
 static int grid_for(size_t work) {

@@ -133,6 +133,7 @@ struct hfx_plan_t {
   bool prof = false;
   bool capturing = false;
   bool quiet = false;  // no profiling events (a call that must not create any)
+  bool check = false;  // check the orbitals before each exchange call (option check=1)
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   // multi-system plans: one side stream per system (default priority) and
@@ -214,7 +215,7 @@ bool parse_option(const char* opts, const char* key, long long def, long long* o
 bool options_known(const char* opts, std::string* bad) {
   if (!opts) return true;
   static const char* known[] = {"tiles", "maxws", "variant", "streams", "shard", "mix", "rows",
-                                "ecut", "tune_cache"};
+                                "ecut", "tune_cache", "check"};
   const std::string s(opts);
   size_t p = 0;
   while (p < s.size()) {
@@ -448,6 +449,55 @@ hfx_status check_call(hfx_plan plan, const void* psi, void* ws, size_t ws_bytes)
                                 " bytes, got " + std::to_string(ws_bytes));
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
     return fail(HFX_EINVAL, "workspace must be 256-byte aligned");
+  return HFX_OK;
+}
+
+// Largest share of an orbital's z power beyond the plan's orbital band that
+// the input check accepts: such content would change E_x by about this
+// relative amount where the band-limited passes skip planes.
+constexpr double kBandTolerance = 1e-12;
+
+// Input check (option check=1): every orbital finite, and, for band-limited
+// plans, inside the z band |m_z| <= kz_max / 2 that the skipped kz planes
+// rely on.  Host-synchronous (waits for `st`); skipped under graph capture.
+hfx_status check_inputs(hfx_plan plan, const double* psi, char* ws, hipStream_t st) {
+  if (!plan->check || plan->capturing) return HFX_OK;
+  for (size_t i = 0; i < plan->sys.size(); ++i) {
+    const SystemPlan& sp = plan->sys[i];
+    const int nx = sp.sys.n[0], ny = sp.sys.n[1], nz = sp.sys.n[2];
+    const int m_max = sp.kz_max < nz / 2 ? sp.kz_max / 2 : -1;
+    double* part = reinterpret_cast<double*>(ws + sp.off_ortho);
+    const long long np = check_partials(sp.sys.n_orb, nx, ny);
+    if (!launch_check_orbitals(psi + sp.psi_off, sp.sys.n_orb, nx, ny, nz, m_max, part, st))
+      return fail(HFX_EUNSUPPORTED, "input check supports z lengths up to 128");
+    HIP_TRY(hipGetLastError());
+    std::vector<double> h((size_t)np * 3);
+    HIP_TRY(hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const long long per_orb = np / sp.sys.n_orb;
+    for (int o = 0; o < sp.sys.n_orb; ++o) {
+      double bad = 0.0, tot = 0.0, oob = 0.0;
+      for (long long k = 0; k < per_orb; ++k) {
+        const double* q = &h[(size_t)(o * per_orb + k) * 3];
+        bad += q[0];
+        tot += q[1];
+        oob += q[2];
+      }
+      const std::string at = "system " + std::to_string(i) + ", orbital " + std::to_string(o);
+      if (bad > 0.0 || !std::isfinite(tot))
+        return fail(HFX_EINVAL, "input check: " + at + " holds " +
+                                    std::to_string((long long)bad) + " non-finite values");
+      // Parseval: sum_k |psi~_k|^2 = nz sum_z psi(z)^2
+      const double frac = tot > 0.0 ? oob / (nz * tot) : 0.0;
+      if (m_max >= 0 && !(frac <= kBandTolerance)) {
+        char buf[64];
+        std::snprintf(buf, sizeof buf, "%.3e", frac);
+        return fail(HFX_EINVAL, "input check: " + at + " has " + buf +
+                                    " of its power beyond |m_z| <= " + std::to_string(m_max) +
+                                    ": the plan's ecut does not hold for these orbitals");
+      }
+    }
+  }
   return HFX_OK;
 }
 
@@ -862,6 +912,12 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     return fail(HFX_EINVAL, "maxws= takes a non-negative integer (bytes)");
   if (!parse_option(options, "streams", 1, &batch_streams))
     return fail(HFX_EINVAL, "streams= must be 1 or 2");
+  long long check_opt = 0;
+  if (!parse_option(options, "check", 0, &check_opt) || check_opt > 1)
+    return fail(HFX_EINVAL, "check= takes 0 or 1");
+  if (!has_option(options, "check"))
+    if (const char* env = std::getenv("HFX_CHECK_INPUTS"))
+      check_opt = (*env && std::strcmp(env, "0") != 0) ? 1 : 0;
   int shard = 0, shards = 1;
   {
     const std::string sv = parse_option_str(options, "shard");
@@ -967,6 +1023,7 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
 
   hfx_plan p = new hfx_plan_t();
   p->prec = precision;
+  p->check = check_opt == 1;
   p->sys.resize(n_sys);
   size_t off = 0;
   long long psi_off = 0, m_off = 0, orb_off = 0;
@@ -1176,6 +1233,8 @@ hfx_status hfx_exchange_energy(hfx_plan plan, const double* psi, double* ex, voi
   hfx_status s = check_call(plan, psi, ws, ws_bytes);
   if (s != HFX_OK) return s;
   if (!ex) return fail(HFX_EINVAL, "null ex");
+  s = check_inputs(plan, psi, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  if (s != HFX_OK) return s;
   return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
     return enq_energy(plan, plan->sys[i], psi, ex + i, static_cast<char*>(ws), st);
   });
@@ -1186,6 +1245,8 @@ hfx_status hfx_apply_exchange(hfx_plan plan, const double* psi, void* kpsi, doub
   hfx_status s = check_call(plan, psi, ws, ws_bytes);
   if (s != HFX_OK) return s;
   if (!kpsi) return fail(HFX_EINVAL, "null kpsi");
+  s = check_inputs(plan, psi, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  if (s != HFX_OK) return s;
   return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
     return enq_apply(plan, plan->sys[i], psi, kpsi, ex ? ex + i : nullptr, static_cast<char*>(ws),
                      st);
@@ -1218,6 +1279,8 @@ hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double*
   hfx_status s = check_call(plan, psi, ws, ws_bytes);
   if (s != HFX_OK) return s;
   if (!grad) return fail(HFX_EINVAL, "null grad");
+  s = check_inputs(plan, psi, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  if (s != HFX_OK) return s;
   return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
     return enq_gradient(plan, plan->sys[i], psi, gscale ? gscale + i : nullptr, grad,
                         static_cast<char*>(ws), st);
@@ -1229,6 +1292,8 @@ hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, double* m, doub
   hfx_status s = check_call(plan, psi, ws, ws_bytes);
   if (s != HFX_OK) return s;
   if (!m) return fail(HFX_EINVAL, "null m");
+  s = check_inputs(plan, psi, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  if (s != HFX_OK) return s;
   return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
     return enq_matrix_full(plan, plan->sys[i], psi, m, ex ? ex + i : nullptr,
                            static_cast<char*>(ws), st);

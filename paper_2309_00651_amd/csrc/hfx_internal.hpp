@@ -139,6 +139,14 @@ void launch_scale_to_f64(const void* src, int src_is_f64, double* dst, size_t n,
 void launch_energy_reduce(const double* partials, long long n, double scale, const double* mean,
                           int n_orb, double dc_scale, double* out, hipStream_t s);
 
+// Input check (exchange_common.hip): per (orbital, y row, 32-column chunk)
+// three doubles: non-finite count, sum psi^2, power of the z spectrum beyond
+// |m_z| <= m_max (m_max < 0: not computed).  check_partials() triples of
+// output; false (nothing launched) for nz above 128.
+long long check_partials(int n_orb, int nx, int ny);
+bool launch_check_orbitals(const double* psi, int n_orb, int nx, int ny, int nz, int m_max,
+                           double* part, hipStream_t s);
+
 // Dense products (gemm.hip); `partial` holds gemm_partial_bytes(n_orb, nr).
 // C[k][l] = alpha * sum_r A[k][r] B[l][r], A float64 split into hi + lo
 // float32 parts, B float32, float32 MFMA with float64 accumulation across

@@ -136,7 +136,7 @@ def test_status_strings(lib):
                                   b"rows=-8", b"rows=abc", b"rows=", b"ecut=0", b"ecut=-5",
                                   b"ecut=abc", b"ecut=nan", b"ecut=", b"ecut=5Ha", b"mix=",
                                   b"tune_cache=", b"rows=8,16", b"tiles=1,2", b"variant=a,b",
-                                  b"variant=nope"])
+                                  b"variant=nope", b"check=2", b"check=x", b"check="])
 def test_bad_plan_options_rejected_before_device(lib, opts):
     st, h, err = _create(lib, [GOOD], opts=opts)
     assert st == 1 and not h.value and err
