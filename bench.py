@@ -95,11 +95,66 @@ def cpu_baseline(system, psi, seconds_target=10.0):
                       f"workload, float64, scipy FFT, {cores} worker processes, {dt:.1f} s"}
 
 
-def bench_batched6(args):
-    """Six systems of different grids in one plan: K psi + E_x for all of them,
-    (a) replayed from a captured hipGraph, (b) launched eagerly from the same
-    plan (systems on forked streams), (c) six single-system plans in turn."""
-    import numpy as np
+TUNE_CACHE = os.path.join(ROOT, "paper_2309_00651_amd", "tune", "mi355x.txt")
+
+
+def _passes(prof, steps):
+    """Per-pass time per step and rate of the method's bytes (the library's
+    algorithmic tally: each operand read or written once, pair grids on the
+    kept kz planes only)."""
+    return {k: {"ms_per_step": v["ms"] / steps,
+                "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None,
+                "frac_of_hbm_peak": (v["bytes"] / (v["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                if v["ms"] > 0 else None}
+            for k, v in prof.items()}
+
+
+PAIR_PASSES = ("pair_fwd", "plane", "inv_acc", "rows_fwd", "cols_conv", "rows_inv")
+
+
+def _pipeline_frac(prof):
+    ms = sum(prof[k]["ms"] for k in PAIR_PASSES if k in prof)
+    by = sum(prof[k]["bytes"] for k in PAIR_PASSES if k in prof)
+    return (by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if ms > 0 else None
+
+
+def _event_times(fn, steps, warmup):
+    """Per-call times (ms) from HIP events on the current stream, after
+    warm-up calls."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for k in range(steps):
+        fn()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    return [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+
+
+def _median(xs):
+    xs = sorted(xs)
+    n = len(xs)
+    return xs[n // 2] if n % 2 else 0.5 * (xs[n // 2 - 1] + xs[n // 2])
+
+
+def _golden_ex(name):
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_full_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)["ex"]
+
+
+def measure_batched6(steps, warmup, options, tune_cache, singles=True):
+    """Six systems of different grids in one plan: K psi + E_x for all of
+    them, (a) replayed from a captured hipGraph, (b) launched eagerly from the
+    same plan (systems on forked streams), (c) six single-system plans in
+    turn.  Per-system kernel configurations come from the tune cache (plan
+    option tune_cache=); the per-pass rates are those of one profiled eager
+    call."""
     import torch
 
     from paper_2309_00651_amd import hfx
@@ -109,60 +164,117 @@ def bench_batched6(args):
     dev = torch.device("cuda:0")
     specs = [hfx.SystemSpec(s.n, s.box, s.n_orb, s.kernel, s.param) for s in systems]
     n_pairs = sum(s.n_pairs for s in systems)
-    log(f"generating batched6: {len(systems)} systems, {n_pairs} pairs")
-    parts = []
-    for s in systems:
-        parts.append(torch.from_numpy(s.orbitals().reshape(-1)).to(dev))
-    psi = torch.cat(parts)
-    del parts
-    plan = hfx.Plan(specs, hfx.FP32, options=args.options, device=dev)
+    log(f"batched6: generating {len(systems)} systems, {n_pairs} pairs")
+    psi = torch.cat([torch.from_numpy(s.orbitals().reshape(-1)) for s in systems]).to(dev)
+    opts = options
+    if tune_cache and os.path.exists(tune_cache):
+        opts = f"{options};tune_cache={tune_cache}" if options else f"tune_cache={tune_cache}"
+    plan = hfx.Plan(specs, hfx.FP32, options=opts, device=dev)
     kpsi = torch.empty(psi.shape, dtype=torch.float32, device=dev)
     ex = torch.empty(len(systems), dtype=torch.float64, device=dev)
-
-    def timed(fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps * 1e3
-
     log("batched6: graph replay")
     g = plan.graph(hfx.GRAPH_APPLY, psi, kpsi, ex)
-    ms_graph = timed(g.launch, args.steps, args.warmup)
-    ex_graph = ex.clone()
+    t_graph = _event_times(g.launch, steps, warmup)
+    ex_graph = [float(x) for x in ex.cpu()]
     log("batched6: eager multi-system plan")
-    ms_eager = timed(lambda: plan.apply_exchange(psi, kpsi=kpsi, ex=ex), args.steps, args.warmup)
-    assert torch.equal(ex, ex_graph), "graph replay and eager launch disagree"
+    t_eager = _event_times(lambda: plan.apply_exchange(psi, kpsi=kpsi, ex=ex), steps, 1)
+    assert [float(x) for x in ex.cpu()] == ex_graph, "graph replay and eager launch disagree"
     g.close()
+    plan.profile(True)
+    plan.apply_exchange(psi, kpsi=kpsi, ex=ex)
+    prof = plan.profile_read()
+    plan.profile(False)
+    describe = [plan.describe(i) for i in range(len(systems))]
     del plan
-    log("batched6: six single-system plans in turn")
-    singles = [hfx.Plan(sp, hfx.FP32, options=args.options, device=dev) for sp in specs]
-    views, off = [], 0
-    for s in systems:
-        k = s.n_orb * s.n ** 3
-        views.append((psi[off:off + k], kpsi[off:off + k]))
-        off += k
+    ms_graph = _median(t_graph)
+    out = {"pairs": n_pairs, "ms_graph_replay_median": ms_graph,
+           "ms_graph_replay_mean": sum(t_graph) / len(t_graph),
+           "ms_eager_one_plan_median": _median(t_eager),
+           "pairs_per_s": n_pairs / (ms_graph * 1e-3), "steps": steps,
+           "passes": _passes(prof, 1), "pair_pipeline_hbm_frac_eager": _pipeline_frac(prof),
+           "kernel_configs": describe, "plan_options": opts, "ex": ex_graph}
+    gold = [_golden_ex(s.name) for s in systems]
+    if all(x is not None for x in gold):
+        out["rel_dEx_vs_oracle_max"] = max(abs(a - b) / abs(b) for a, b in zip(ex_graph, gold))
+    if singles:
+        log("batched6: six single-system plans in turn")
+        plans = [hfx.Plan(sp, hfx.FP32, options=opts, device=dev) for sp in specs]
+        views, off = [], 0
+        for s in systems:
+            k = s.n_orb * s.n ** 3
+            views.append((psi[off:off + k], kpsi[off:off + k]))
+            off += k
 
-    def seq():
-        for pl, (pv, kv) in zip(singles, views):
-            pl.apply_exchange(pv, kpsi=kv)
-    ms_seq = timed(seq, args.steps, args.warmup)
+        def seq():
+            for pl, (pv, kv) in zip(plans, views):
+                pl.apply_exchange(pv, kpsi=kv)
+        t_seq = _event_times(seq, max(2, steps // 2), 1)
+        out["ms_six_single_plans_median"] = _median(t_seq)
+        out["batch_gain_vs_single_plans"] = _median(t_seq) / ms_graph
+        del plans
+    del psi, kpsi
+    torch.cuda.empty_cache()
+    return out
+
+
+def measure_large128(steps, warmup, options, fp64_steps):
+    """The 128^3 / 512-orbital box: K psi + E_x of all 131,328 pairs on the
+    raw generated orbitals (the input of the stored full-loop reference), in
+    float32 and float64, with per-pass rates from a profiled call."""
+    import torch
+
+    from paper_2309_00651_amd import hfx
+    from workloads import configs
+
+    s = configs.LARGE128
+    dev = torch.device("cuda:0")
+    log(f"large128: generating {s.n_orb} orbitals on {s.n}^3")
+    psi = torch.from_numpy(s.orbitals()).to(dev)
+    spec = hfx.SystemSpec(s.n, s.box, s.n_orb, s.kernel, s.param)
+    out = {"pairs": s.n_pairs}
+    gold = _golden_ex(s.name)
+    for prec, tag, n_steps in ((hfx.FP32, "fp32", steps), (hfx.FP64, "fp64", fp64_steps)):
+        if n_steps <= 0:
+            continue
+        plan = hfx.Plan(spec, prec, options=options, device=dev)
+        kpsi = torch.empty(psi.shape, dtype=plan.kpsi_dtype, device=dev)
+        ex = torch.empty(1, dtype=torch.float64, device=dev)
+        log(f"large128 {tag}: {warmup} warm-up + {n_steps} timed calls")
+        t = _event_times(lambda: plan.apply_exchange(psi, kpsi=kpsi, ex=ex), n_steps, warmup)
+        plan.profile(True)
+        plan.apply_exchange(psi, kpsi=kpsi, ex=ex)
+        prof = plan.profile_read()
+        plan.profile(False)
+        e = float(ex[0])
+        out[tag] = {"ms_median": _median(t), "ms_mean": sum(t) / len(t), "calls": n_steps,
+                    "pairs_per_s": s.n_pairs / (_median(t) * 1e-3), "passes": _passes(prof, 1),
+                    "pair_pipeline_hbm_frac": _pipeline_frac(prof), "ex": e,
+                    "kernel_config": plan.describe()}
+        if gold is not None:
+            out[tag]["rel_dEx_vs_oracle"] = abs(e - gold) / abs(gold)
+        del plan, kpsi
+        torch.cuda.empty_cache()
+    if "fp32" in out and "fp64" in out:
+        out["fp32_speedup_vs_fp64"] = out["fp64"]["ms_median"] / out["fp32"]["ms_median"]
+    del psi
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batched6(args):
+    """--workload batched6: the six-system batch as its own JSON line."""
+    r = measure_batched6(args.steps, args.warmup, args.options, args.tune_cache)
     line = {
         "metric": "pair-exchange evals/s, six systems of different grids in one batch",
-        "value": n_pairs / (ms_graph * 1e-3), "unit": "pair-exchange evals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
+        "value": r["pairs_per_s"], "unit": "pair-exchange evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_graph_replay_mean"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched6: grids 64^3..120^3 at spacing 23.5/96 bohr, 64..384 "
                                "random plane-wave orbitals (5 Ha), truncated Coulomb; step = "
                                "K psi + E_x for all six systems",
-                   "pairs": n_pairs, "plan_options": args.options},
-        "extra": {"ms_graph_replay": ms_graph, "ms_eager_one_plan": ms_eager,
-                  "ms_six_single_plans": ms_seq,
-                  "ex": [float(x) for x in ex_graph.cpu()]},
+                   "pairs": r["pairs"], "plan_options": r["plan_options"]},
+        "extra": r,
     }
     print(json.dumps(line), flush=True)
 
@@ -183,6 +295,10 @@ def main():
     ap.add_argument("--no-band-limit", action="store_true",
                     help="do not tell the plans the workload's orbital cutoff (ecut=); the "
                          "passes then also transform the kz planes beyond the pair band")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="tune cache of the batched plan's per-system configurations")
+    ap.add_argument("--no-extra-workloads", action="store_true",
+                    help="skip the six-system batch and the 128^3 box after the main workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (5 times): the "
                          "reference dispatch for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE")
@@ -254,19 +370,22 @@ def main():
         torch.cuda.synchronize()
         if profile:
             plan.profile(True)
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        # one event between consecutive steps: the mean over the timed
+        # region and the median of the steps come from the same record
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
-        start.record()
-        for _ in range(steps):
+        ev[0].record()
+        for k in range(steps):
             step()
-        stop.record()
+            ev[k + 1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        ev_ms = start.elapsed_time(stop)
+        per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+        ev_ms = ev[0].elapsed_time(ev[steps])
         prof = plan.profile_read() if profile else None
         plan.profile(False)
-        out = dict(ms=ev_ms / steps, wall_ms=1e3 * wall / steps, prof=prof, ex=float(ex[0]),
-                   m=m, kpsi=kpsi, psi=p, describe=plan.describe())
+        out = dict(ms=ev_ms / steps, ms_median=_median(per_step), wall_ms=1e3 * wall / steps,
+                   prof=prof, ex=float(ex[0]), m=m, kpsi=kpsi, psi=p, describe=plan.describe())
         return out, plan
 
     def time_ace(plan, r, reps=3):
@@ -430,6 +549,24 @@ def main():
                       "fp32_speedup_vs_fp64": r64["ms"] / ms,
                       "rel_dEx_fp32_vs_fp64": abs(r32["ex"] - r64["ex"]) / abs(r64["ex"])})
         del r64
+    extra["ms_per_step_median_fp32"] = r32["ms_median"]
+    extra["timing"] = ("HIP events between consecutive steps on the launching stream; "
+                       "ms_per_step is the mean over the timed steps, the median is reported "
+                       "beside it; per-pass times come from event brackets around every launch")
+    del plan32
+    torch.cuda.empty_cache()
+    if not args.no_extra_workloads:
+        band5 = None if args.no_band_limit else "ecut=5"
+        band20 = None if args.no_band_limit else "ecut=20"
+        extra["batched6"] = measure_batched6(5, 1, band5, args.tune_cache)
+        b6 = extra["batched6"]
+        log(f"batched6: graph replay {b6['ms_graph_replay_median']:.1f} ms "
+            f"({b6['pairs_per_s']:.0f} pairs/s), six single plans "
+            f"{b6.get('ms_six_single_plans_median', float('nan')):.1f} ms")
+        extra["large128"] = measure_large128(3, 1, band20, 0 if args.no_fp64 else 2)
+        l1 = extra["large128"]
+        log(f"large128: fp32 {l1['fp32']['ms_median']:.1f} ms "
+            f"({l1['fp32']['pairs_per_s']:.0f} pairs/s)")
     golden = os.path.join(ROOT, "tests", "golden", f"{system.name}_oracle.json")
     if os.path.exists(golden):
         with open(golden) as f:
