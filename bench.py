@@ -592,9 +592,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{system.name}: L={system.L} bohr, {system.n}^3 grid, "
-                               f"{system.n_orb} localised Gaussian orbitals ({system.ecut:g} Ha), "
-                               f"erfc w={system.param}; step = orthonormalise + K psi (all "
-                               f"{n_pairs} pairs) + E_x + exchange matrix",
+                               f"{system.n_orb} "
+                               + ("localised Gaussian" if system.family == "gaussians"
+                                  else "random plane-wave")
+                               + f" orbitals ({system.ecut:g} Ha), "
+                               + (f"erfc w={system.param}" if system.kernel == 1
+                                  else "truncated Coulomb")
+                               + f"; step = orthonormalise + K psi (all {n_pairs} pairs) + "
+                               "E_x + exchange matrix",
                    "n": system.n, "n_orb": system.n_orb, "pairs": n_pairs,
                    "precision": "fp32 FFT/kernel, fp64 orthonormalisation and sums",
                    "plan_options": args.options, "fp64_plan_options": args.fp64_options},

@@ -153,7 +153,10 @@ __device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const Til
 // per orbital.
 // N: grid points along x and y; NZ: along z (slab cells: NZ != N).
 template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL, bool SCR, int NZ = N>
-__global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
+__global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
+  int sys_ = 0;
+  const int lg_ = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
+  const PassArgs& a = grp.a[sys_];
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
   constexpr int W2 = 2 * W;
   using G = Geom<T, NZ, W2, NT, true, W2, 1>;
@@ -171,7 +174,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
   __shared__ T mul[kMaxRows * TT];  // pair-density means of the tile, [a][b]
   __shared__ T pil[PIL ? TT * PT * NT : 1];  // psi of the I block, [a][k][tid]
   const int tid = threadIdx.x;
-  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int lg = lg_;
   const int t = lg / BR, br = lg - t * BR;
   const int y = br / NXB, x0 = (br - y * NXB) * W;
   const TileDesc td = a.tiles[t];
@@ -324,7 +327,10 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassArgs a) {
 template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC, bool PJL, bool PF,
           bool SCR, int NZ = N, int KZ = 0>
 __global__ void __launch_bounds__(NT)
-    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_inv_acc(PassArgs a) {
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_inv_acc(PassGroup grp) {
+  int sys_ = 0;
+  const int lg_ = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
+  const PassArgs& a = grp.a[sys_];
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
   constexpr int W2 = 2 * W;
   constexpr int QB = TT / 4;               // grid pairs per orbital a
@@ -344,7 +350,7 @@ __global__ void __launch_bounds__(NT)
   __shared__ TwEntry<T> twl[tw_slots<T, SZI>()];
   __shared__ T dcl[kMaxRows * TT];  // v(0) * pair-density mean, [a][b]
   const int tid = threadIdx.x;
-  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int lg = lg_;
   const int t = lg / BR, br = lg - t * BR;
   const int y = br / NXB, x0 = (br - y * NXB) * W;
   const TileDesc td = a.tiles[t];
@@ -647,7 +653,10 @@ constexpr int plane_waves_per_eu() {
 template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, bool SW = false,
           bool PP = false, int NZ = N>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<T, N, NT>())))
-k_plane_conv(PassArgs a) {
+k_plane_conv(PassGroup grp) {
+  int sys_ = 0;
+  const int lg_ = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
+  const PassArgs& a = grp.a[sys_];
   static_assert(!SW || N % 8 == 0, "swizzle needs whole blocks of 8");
   constexpr int P = N + 1;
   using GX = Geom<T, N, N, NT, false, 1, P, SW ? 1 : 0>;  // rows: sequence m = y, element n = x
@@ -668,7 +677,7 @@ k_plane_conv(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* plane = reinterpret_cast<cpx<T>*>(smem_raw);
   const int tid = threadIdx.x;
-  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int lg = lg_;
   const int total = a.n_active * kz_planes(NZ, a.kz_max);  // planes of this launch, kz-major
   cpx<T>* __restrict__ gbase = static_cast<cpx<T>*>(a.grids);
 
@@ -753,7 +762,10 @@ k_plane_conv(PassArgs a) {
 // Split plane pass for grids whose plane does not fit in LDS:
 // (a) FFT along x of RW consecutive rows, (b) y columns with the multiply.
 template <typename T, int N, int RW, int NT, class SX, bool INV>
-__global__ void __launch_bounds__(NT) k_rows(PassArgs a) {
+__global__ void __launch_bounds__(NT) k_rows(PassGroup grp) {
+  int sys_ = 0;
+  const int lg_ = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
+  const PassArgs& a = grp.a[sys_];
   constexpr int P = N + 1;
   using G = Geom<T, N, RW, NT, false, 1, P>;
   using E = FFT<G, INV, SX>;
@@ -766,7 +778,7 @@ __global__ void __launch_bounds__(NT) k_rows(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   const int tid = threadIdx.x;
-  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int lg = lg_;
   const int ai = lg / RB, rb = lg - ai * RB;
   const int slot = a.active[ai];
   cpx<T>* __restrict__ base = static_cast<cpx<T>*>(a.grids) + (long long)slot * NR;
@@ -808,7 +820,10 @@ __global__ void __launch_bounds__(NT) k_rows(PassArgs a) {
 }
 
 template <typename T, int N, int W, int NT, class SYF, class SYI>
-__global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
+__global__ void __launch_bounds__(NT) k_cols_conv(PassGroup grp) {
+  int sys_ = 0;
+  const int lg_ = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
+  const PassArgs& a = grp.a[sys_];
   using G = Geom<T, N, W, NT, true, W, 1>;
   using EF = FFT<G, false, SYF>;
   using EI = FFT<G, true, SYI>;
@@ -825,7 +840,7 @@ __global__ void __launch_bounds__(NT) k_cols_conv(PassArgs a) {
   const int tid = threadIdx.x;
   stage_twiddles<T, SYF, NT>(twf, a.tw_yf, tid);  // visible after the first barrier
   stage_twiddles<T, SYI, NT>(twi, a.tw_yi, tid);
-  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int lg = lg_;
   const int per_grid = kz_planes(N, a.kz_max) * NXB;  // kept planes x column blocks
   const int ai = lg / per_grid, rem = lg - ai * per_grid;
   const int zc = rem / NXB, x0 = (rem - zc * NXB) * W;
@@ -924,51 +939,51 @@ struct FusedPipeline {
     }();
     return planes < slots ? planes : slots;
   }
-  static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    if (a.perm)
+  static void pair_fwd(const PassGroup& g, int nb, hipStream_t s) {
+    if (g.a[0].perm)
       hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true, NZ>), dim3(nb), dim3(NTF), 0,
-                         s, a);
+                         s, g);
     else
       hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false, NZ>), dim3(nb), dim3(NTF), 0,
-                         s, a);
+                         s, g);
   }
-  static void plane(const PassArgs& a, int nb, hipStream_t s) {
+  static void plane(const PassGroup& g, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ>),
-                       dim3(plane_grid(nb)), dim3(NTQ), lds, s, a);
+                       dim3(plane_grid(nb)), dim3(NTQ), lds, s, g);
   }
   // screened (perm) and band-limited (kz_max < NZ / 2) plans take their own
   // instantiations
   template <bool ACC, bool SCR>
-  static void inv_launch(const PassArgs& a, int nb, hipStream_t s) {
+  static void inv_launch(const PassGroup& g, int nb, hipStream_t s) {
     // band-limited plans: float32 takes zero-block loads while at least 3/4
     // of the planes are kept and skipped loads below that; float64 (one
     // workgroup per compute unit, registers tight) always skips (measured at
     // 93 of 96 planes and at 29..57 of 64..120)
-    const int kept = kz_planes(NZ, a.kz_max);
+    const int kept = kz_planes(NZ, g.a[0].kz_max);
     if (kept == NZ) {
       hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 0>), dim3(nb),
-                         dim3(NTI), 0, s, a);
+                         dim3(NTI), 0, s, g);
       return;
     }
     if constexpr (sizeof(T) == 4) {
       if (4 * kept >= 3 * NZ) {
         hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 1>), dim3(nb),
-                           dim3(NTI), 0, s, a);
+                           dim3(NTI), 0, s, g);
         return;
       }
     }
     hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 2>), dim3(nb),
-                       dim3(NTI), 0, s, a);
+                       dim3(NTI), 0, s, g);
   }
   template <bool ACC>
-  static void inv_pass(const PassArgs& a, int nb, hipStream_t s) {
-    if (a.perm)
-      inv_launch<ACC, true>(a, nb, s);
+  static void inv_pass(const PassGroup& g, int nb, hipStream_t s) {
+    if (g.a[0].perm)
+      inv_launch<ACC, true>(g, nb, s);
     else
-      inv_launch<ACC, false>(a, nb, s);
+      inv_launch<ACC, false>(g, nb, s);
   }
-  static void inv_acc(const PassArgs& a, int nb, hipStream_t s) { inv_pass<true>(a, nb, s); }
-  static void inv_energy(const PassArgs& a, int nb, hipStream_t s) { inv_pass<false>(a, nb, s); }
+  static void inv_acc(const PassGroup& g, int nb, hipStream_t s) { inv_pass<true>(g, nb, s); }
+  static void inv_energy(const PassGroup& g, int nb, hipStream_t s) { inv_pass<false>(g, nb, s); }
   static hipError_t prepare() {
     return hipFuncSetAttribute(
         reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ>),
@@ -989,6 +1004,7 @@ struct FusedPipeline {
     v.nt_cols = 0;
     v.plane_mode = 0;
     v.rows_per_wg = 0;
+    v.persistent = PP;
     fill_radices(v.zf, v.nzf, SZF{});
     fill_radices(v.zi, v.nzi, SZI{});
     fill_radices(v.xf, v.nxf, SXF{});
@@ -1013,43 +1029,43 @@ template <typename T, int N, int W, int NTC, int TT, class SZF, class SZI, int R
           bool PJL = false, bool PF = false, bool PIL = false>
 struct SplitPipeline {
   static constexpr size_t lds = (size_t)RW * (N + 1) * sizeof(cpx<T>);
-  static void pair_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    if (a.perm)
-      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true>), dim3(nb), dim3(NTF), 0, s, a);
+  static void pair_fwd(const PassGroup& g, int nb, hipStream_t s) {
+    if (g.a[0].perm)
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true>), dim3(nb), dim3(NTF), 0, s, g);
     else
-      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false>), dim3(nb), dim3(NTF), 0, s, a);
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false>), dim3(nb), dim3(NTF), 0, s, g);
   }
-  static void rows_fwd(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXF, false>), dim3(nb), dim3(NTQ), lds, s, a);
+  static void rows_fwd(const PassGroup& g, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXF, false>), dim3(nb), dim3(NTQ), lds, s, g);
   }
-  static void rows_inv(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXI, true>), dim3(nb), dim3(NTQ), lds, s, a);
+  static void rows_inv(const PassGroup& g, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_rows<T, N, RW, NTQ, SXI, true>), dim3(nb), dim3(NTQ), lds, s, g);
   }
-  static void cols_conv(const PassArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_cols_conv<T, N, W, NTC, SYF, SYI>), dim3(nb), dim3(NTC), 0, s, a);
+  static void cols_conv(const PassGroup& g, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_cols_conv<T, N, W, NTC, SYF, SYI>), dim3(nb), dim3(NTC), 0, s, g);
   }
   // screened (perm) and band-limited (kz_max < N / 2: pruned loads skipped)
   // plans take their own instantiations
   template <bool ACC, bool SCR>
-  static void inv_launch(const PassArgs& a, int nb, hipStream_t s) {
-    if (kz_planes(N, a.kz_max) == N)
+  static void inv_launch(const PassGroup& g, int nb, hipStream_t s) {
+    if (kz_planes(N, g.a[0].kz_max) == N)
       hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, N, 0>), dim3(nb),
-                         dim3(NTI), 0, s, a);
+                         dim3(NTI), 0, s, g);
     else
       hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, N, 2>), dim3(nb),
-                         dim3(NTI), 0, s, a);
+                         dim3(NTI), 0, s, g);
   }
-  static void inv_acc(const PassArgs& a, int nb, hipStream_t s) {
-    if (a.perm)
-      inv_launch<true, true>(a, nb, s);
+  static void inv_acc(const PassGroup& g, int nb, hipStream_t s) {
+    if (g.a[0].perm)
+      inv_launch<true, true>(g, nb, s);
     else
-      inv_launch<true, false>(a, nb, s);
+      inv_launch<true, false>(g, nb, s);
   }
-  static void inv_energy(const PassArgs& a, int nb, hipStream_t s) {
-    if (a.perm)
-      inv_launch<false, true>(a, nb, s);
+  static void inv_energy(const PassGroup& g, int nb, hipStream_t s) {
+    if (g.a[0].perm)
+      inv_launch<false, true>(g, nb, s);
     else
-      inv_launch<false, false>(a, nb, s);
+      inv_launch<false, false>(g, nb, s);
   }
   static hipError_t prepare() {
     hipError_t e = hipFuncSetAttribute(

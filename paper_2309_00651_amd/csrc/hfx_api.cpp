@@ -134,6 +134,7 @@ struct hfx_plan_t {
   bool capturing = false;
   bool quiet = false;  // no profiling events (a call that must not create any)
   bool check = false;  // check the orbitals before each exchange call (option check=1)
+  bool group = true;   // systems of one size class share launches (option group=0: not)
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   // multi-system plans: one side stream per system (default priority) and
@@ -215,7 +216,7 @@ bool parse_option(const char* opts, const char* key, long long def, long long* o
 bool options_known(const char* opts, std::string* bad) {
   if (!opts) return true;
   static const char* known[] = {"tiles", "maxws", "variant", "streams", "shard", "mix", "rows",
-                                "ecut", "tune_cache", "check"};
+                                "ecut", "tune_cache", "check", "group"};
   const std::string s(opts);
   size_t p = 0;
   while (p < s.size()) {
@@ -501,192 +502,286 @@ hfx_status check_inputs(hfx_plan plan, const double* psi, char* ws, hipStream_t 
   return HFX_OK;
 }
 
-// Runs the pair pipeline of one system.  acc: accumulate K psi into kpsi.
-hfx_status run_exchange(hfx_plan plan, SystemPlan& sp, const double* psi, void* kpsi, double* ex,
-                        char* ws, hipStream_t st, bool acc) {
-  const Variant* v = sp.var;
+// One system's share of an exchange call: its orbitals (the system's own
+// block), K psi destination (its own block; null for the energy only) and
+// energy output (nullable).
+struct SysCall {
+  SystemPlan* sp;
+  const double* psi;
+  void* kpsi;
+  double* ex;
+};
+
+// Runs the pair pipeline of the systems of one size class (same kernel
+// configuration and band, all screened or none) on stream st.  Each system's
+// batches run in order; batch t of every system in the class shares one
+// launch per pass (a PassGroup: the systems' workgroup ranges side by side),
+// so a class of several systems launches each pass once per batch step
+// instead of once per system.  Results equal those of separate launches bit
+// for bit (every workgroup does the same work).  acc: accumulate K psi.
+hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* ws,
+                        hipStream_t st, bool acc) {
+  const Variant* v = calls[0].sp->var;
   const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
-  const void* psi_w = psi;
-  const double orb_pts = (double)sp.sys.n_orb * (double)sp.nr;
-  if (plan->prec == HFX_FP32) {
-    float* p32 = reinterpret_cast<float*>(ws + sp.off_psi32);
-    Bracket br(plan, HFX_PASS_STAGE, st);
-    launch_cast_f64_f32(psi, p32, (size_t)sp.sys.n_orb * sp.nr, st);
-    br.done(orb_pts * 12.0, 0.0);
-    psi_w = p32;
+  const int nc = (int)calls.size();
+  std::vector<PassArgs> args(nc);
+  size_t max_batches = 0;
+  for (int c = 0; c < nc; ++c) {
+    SystemPlan& sp = *calls[c].sp;
+    const double* psi = calls[c].psi;
+    const void* psi_w = psi;
+    const double orb_pts = (double)sp.sys.n_orb * (double)sp.nr;
+    if (plan->prec == HFX_FP32) {
+      float* p32 = reinterpret_cast<float*>(ws + sp.off_psi32);
+      Bracket br(plan, HFX_PASS_STAGE, st);
+      launch_cast_f64_f32(psi, p32, (size_t)sp.sys.n_orb * sp.nr, st);
+      br.done(orb_pts * 12.0, 0.0);
+      psi_w = p32;
+    }
+    // float32 plans: exact pair-density means mu_ab = (1/N_r) sum_r psi_a psi_b
+    // (float64 MFMA).  Transforming rho_ab - mu_ab keeps the large G = 0
+    // coefficient out of the float32 FFTs; v(0) mu_ab is added back to the
+    // potentials and v(0) Omega mu_ab^2 to the energy in float64.
+    const double* mean = nullptr;
+    if (plan->prec == HFX_FP32) {
+      double* mu = reinterpret_cast<double*>(ws + sp.off_mean);
+      double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
+      Bracket br(plan, HFX_PASS_CONTRACT, st);
+      launch_xtx_f64(psi, psi, sp.sys.n_orb, sp.nr, 1.0 / (double)sp.nr, part, mu, st);
+      // screened pairs contribute no G = 0 energy either
+      if (sp.d_keep) launch_mask(mu, sp.d_keep, (size_t)sp.sys.n_orb * sp.sys.n_orb, st);
+      br.done(orb_pts * 8.0, 2.0 * (double)sp.sys.n_orb * orb_pts);
+      mean = mu;
+    }
+    if (acc) {
+      Bracket br(plan, HFX_PASS_ZERO, st);
+      launch_zero(calls[c].kpsi, (size_t)sp.sys.n_orb * sp.nr * elem, st);
+      br.done(orb_pts * elem, 0.0);
+    }
+    PassArgs& a = args[c];
+    a = PassArgs{};
+    a.psi = psi_w;
+    a.kpsi = calls[c].kpsi;
+    a.vtab = sp.vtab;
+    a.tw_zf = sp.tw[0];
+    a.tw_zi = sp.tw[1];
+    a.tw_xf = sp.tw[2];
+    a.tw_xi = sp.tw[3];
+    a.tw_yf = sp.tw[4];
+    a.tw_yi = sp.tw[5];
+    a.partials = reinterpret_cast<double*>(ws + sp.off_partials);
+    a.mean = mean;
+    a.v0 = sp.v0;
+    a.perm = sp.d_perm;
+    a.n_orb = sp.sys.n_orb;
+    a.kz_max = sp.kz_max;
+    a.zero = sp.d_zero;
+    max_batches = std::max(max_batches, sp.batches.size());
   }
-  // float32 plans: exact pair-density means mu_ab = (1/N_r) sum_r psi_a psi_b
-  // (float64 MFMA).  Transforming rho_ab - mu_ab keeps the large G = 0
-  // coefficient out of the float32 FFTs; v(0) mu_ab is added back to the
-  // potentials and v(0) Omega mu_ab^2 to the energy in float64.
-  const double* mean = nullptr;
-  if (plan->prec == HFX_FP32) {
-    double* mu = reinterpret_cast<double*>(ws + sp.off_mean);
-    double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
-    Bracket br(plan, HFX_PASS_CONTRACT, st);
-    launch_xtx_f64(psi, psi, sp.sys.n_orb, sp.nr, 1.0 / (double)sp.nr, part, mu, st);
-    // screened pairs contribute no G = 0 energy either
-    if (sp.d_keep) launch_mask(mu, sp.d_keep, (size_t)sp.sys.n_orb * sp.sys.n_orb, st);
-    br.done(orb_pts * 8.0, 2.0 * (double)sp.sys.n_orb * orb_pts);
-    mean = mu;
-  }
-  if (acc) {
-    Bracket br(plan, HFX_PASS_ZERO, st);
-    launch_zero(kpsi, (size_t)sp.sys.n_orb * sp.nr * elem, st);
-    br.done(orb_pts * elem, 0.0);
-  }
-  double* partials = reinterpret_cast<double*>(ws + sp.off_partials);
-  PassArgs a{};
-  a.psi = psi_w;
-  a.kpsi = kpsi;
-  a.vtab = sp.vtab;
-  a.tw_zf = sp.tw[0];
-  a.tw_zi = sp.tw[1];
-  a.tw_xf = sp.tw[2];
-  a.tw_xi = sp.tw[3];
-  a.tw_yf = sp.tw[4];
-  a.tw_yi = sp.tw[5];
-  a.partials = partials;
-  a.mean = mean;
-  a.v0 = sp.v0;
-  a.perm = sp.d_perm;
-  a.n_orb = sp.sys.n_orb;
-  a.kz_max = sp.kz_max;
-  a.zero = sp.d_zero;
   const int br = bricks_per_tile(v);
   const int n = v->n, nz = v->nz;
-  // share of the grid on kept kz planes (pair-grid traffic of the passes)
-  const double kzf = (double)kz_planes(nz, sp.kz_max) / nz;
   const int nxb = (n + v->brick - 1) / v->brick;
-  const double nr = (double)sp.nr, ce = 2.0 * elem;  // complex element bytes
-  // FFT flops per complex grid and axis pass: 5 N_r log2(N) (radix-2 count)
-  const double fft_axis = 5.0 * nr * std::log2((double)n);      // x or y
-  const double fft_z = 5.0 * nr * std::log2((double)nz);
-  // Two batch streams: batch k runs on stream k % 2 with grid buffer k % 2.
-  // Its inv_acc waits for batch k-1's, so K psi receives its updates in the
-  // serial order (identical results) while the transforms of one batch
-  // overlap the other batch's passes.  Consecutive batches of one tile round
-  // touch disjoint orbitals anyway; across rounds the wait is needed.
-  // Graph capture keeps the batches on the one stream (the two-stream form
-  // is not captured): a captured graph equals that of a streams=1 plan.
-  const bool two = sp.nstreams == 2 && sp.batches.size() > 1 && !plan->capturing;
+  const double ce = 2.0 * elem;  // complex element bytes
+  // Two batch streams (single-system classes only): batch k runs on stream
+  // k % 2 with grid buffer k % 2.  Its inv_acc waits for batch k-1's, so K
+  // psi receives its updates in the serial order (identical results) while
+  // the transforms of one batch overlap the other batch's passes.
+  // Consecutive batches of one tile round touch disjoint orbitals anyway;
+  // across rounds the wait is needed.  Graph capture keeps the batches on
+  // the one stream (the two-stream form is not captured): a captured graph
+  // equals that of a streams=1 plan.
+  SystemPlan& sp0 = *calls[0].sp;
+  const bool two = nc == 1 && sp0.nstreams == 2 && sp0.batches.size() > 1 && !plan->capturing;
   if (two) {
-    HIP_TRY(hipEventRecord(sp.ev_fork, st));
-    HIP_TRY(hipStreamWaitEvent(sp.bstream, sp.ev_fork, 0));
+    HIP_TRY(hipEventRecord(sp0.ev_fork, st));
+    HIP_TRY(hipStreamWaitEvent(sp0.bstream, sp0.ev_fork, 0));
   }
-  char* grids0 = ws + sp.off_grids;
-  for (size_t k = 0; k < sp.batches.size(); ++k) {
-    const Batch& b = sp.batches[k];
+  for (size_t k = 0; k < max_batches; ++k) {
     const int q = two ? (int)(k & 1) : 0;
-    const hipStream_t bs = q ? sp.bstream : st;
-    a.grids = grids0 + (size_t)q * sp.grid_bytes;
-    a.tiles = sp.d_tiles + b.tile_off;
-    a.active = sp.d_active + b.active_off;
-    a.n_tiles = b.n_tiles;
-    a.n_active = b.n_active;
-    a.part_base = b.part_base;
-    double orbs = 0.0;  // orbital rows a batch reads (each tile's blocks once)
-    for (int t = 0; t < b.n_tiles; ++t) {
-      const TileDesc& td = sp.tiles[b.tile_off + t];
-      if (sp.d_keep) {
-        // screened: only rows and columns with an evaluated pair are touched
-        // (in a diagonal tile, column b is row joff + b)
-        unsigned long long rows = 0, cols = 0;
-        for (int r = 0; r < td.nI; ++r)
-          for (int c = 0; c < td.nJ; ++c)
-            if (keep_bit(td, r, c)) {
-              rows |= 1ull << r;
-              cols |= 1ull << (td.diag ? td.joff + c : c);
-            }
-        orbs += td.diag ? __builtin_popcountll(rows | cols)
-                        : __builtin_popcountll(rows) + __builtin_popcountll(cols);
-      } else {
-        orbs += td.diag ? td.nI : td.nI + td.nJ;  // J lies inside I's rows
+    const hipStream_t bs = q ? sp0.bstream : st;
+    // the systems with a batch k, their workgroups per pass, and the
+    // algorithmic bytes and flops of each pass over them
+    PassGroup g{};
+    std::vector<int> who;
+    double by_fwd = 0, fl_fwd = 0, by_pl = 0, fl_pl = 0, by_row = 0, fl_row = 0, by_col = 0,
+           fl_col = 0, by_inv = 0, fl_inv = 0;
+    std::vector<int> nb_fwd, nb_pl, nb_row, nb_col, nb_inv;
+    for (int c = 0; c < nc; ++c) {
+      SystemPlan& sp = *calls[c].sp;
+      if (k >= sp.batches.size()) continue;
+      const Batch& b = sp.batches[k];
+      PassArgs a = args[c];
+      a.grids = ws + sp.off_grids + (size_t)q * sp.grid_bytes;
+      a.tiles = sp.d_tiles + b.tile_off;
+      a.active = sp.d_active + b.active_off;
+      a.n_tiles = b.n_tiles;
+      a.n_active = b.n_active;
+      a.part_base = b.part_base;
+      g.a[(int)who.size()] = a;
+      who.push_back(c);
+      const double nr = (double)sp.nr;
+      // share of the grid on kept kz planes (pair-grid traffic of the passes)
+      const double kzf = (double)kz_planes(nz, sp.kz_max) / nz;
+      // FFT flops per complex grid and axis pass: 5 N_r log2(N) (radix-2 count)
+      const double fft_axis = 5.0 * nr * std::log2((double)n);  // x or y
+      const double fft_z = 5.0 * nr * std::log2((double)nz);
+      double orbs = 0.0;  // orbital rows a batch reads (each tile's blocks once)
+      for (int t = 0; t < b.n_tiles; ++t) {
+        const TileDesc& td = sp.tiles[b.tile_off + t];
+        if (sp.d_keep) {
+          // screened: only rows and columns with an evaluated pair are touched
+          // (in a diagonal tile, column b is row joff + b)
+          unsigned long long rows = 0, cols = 0;
+          for (int r = 0; r < td.nI; ++r)
+            for (int cc = 0; cc < td.nJ; ++cc)
+              if (keep_bit(td, r, cc)) {
+                rows |= 1ull << r;
+                cols |= 1ull << (td.diag ? td.joff + cc : cc);
+              }
+          orbs += td.diag ? __builtin_popcountll(rows | cols)
+                          : __builtin_popcountll(rows) + __builtin_popcountll(cols);
+        } else {
+          orbs += td.diag ? td.nI : td.nI + td.nJ;  // J lies inside I's rows
+        }
       }
+      const double grids = (double)b.n_active;
+      const int kp = kz_planes(nz, sp.kz_max);
+      nb_fwd.push_back(b.n_tiles * br);
+      by_fwd += orbs * nr * elem + grids * nr * ce * kzf;
+      fl_fwd += grids * fft_z;
+      nb_pl.push_back(b.n_active * kp);
+      by_pl += grids * nr * ce * 2.0 * kzf;
+      fl_pl += grids * fft_axis * 4.0 * kzf;
+      nb_row.push_back(b.n_active * ((kp * n + v->rows_per_wg - 1) / std::max(v->rows_per_wg, 1)));
+      by_row += grids * nr * ce * 2.0 * kzf;
+      fl_row += grids * fft_axis * kzf;
+      nb_col.push_back(b.n_active * kp * nxb);
+      by_col += grids * nr * ce * 2.0 * kzf;
+      fl_col += grids * fft_axis * 2.0 * kzf;
+      nb_inv.push_back(b.n_tiles * br);
+      by_inv += grids * nr * ce * kzf + orbs * nr * elem * (acc ? 3.0 : 1.0);
+      fl_inv += grids * fft_z;
     }
-    const double grids = (double)b.n_active;
-    {
-      Bracket bk(plan, HFX_PASS_PAIR_FWD, bs);
-      v->pair_fwd(a, b.n_tiles * br, bs);
-      bk.done(orbs * nr * elem + grids * nr * ce * kzf, grids * fft_z);
-    }
+    g.count = (int)who.size();
+    auto launch = [&](launch_fn fn, const std::vector<int>& nbs, int pass, double bytes,
+                      double flops) {
+      int total = 0;
+      for (int i = 0; i < g.count; ++i) {
+        g.start[i] = total;
+        total += nbs[i];
+      }
+      g.start[g.count] = total;
+      Bracket bk(plan, pass, bs);
+      fn(g, total, bs);
+      bk.done(bytes, flops);
+    };
+    launch(v->pair_fwd, nb_fwd, HFX_PASS_PAIR_FWD, by_fwd, fl_fwd);
     if (v->plane_mode == 0) {
-      Bracket bk(plan, HFX_PASS_PLANE, bs);
-      v->plane(a, b.n_active * kz_planes(nz, sp.kz_max), bs);
-      bk.done(grids * nr * ce * 2.0 * kzf, grids * fft_axis * 4.0 * kzf);
+      launch(v->plane, nb_pl, HFX_PASS_PLANE, by_pl, fl_pl);
     } else {
       // rows and planes of the kept kz planes only
-      const int rb = (kz_planes(nz, sp.kz_max) * n + v->rows_per_wg - 1) / v->rows_per_wg;
-      {
-        Bracket bk(plan, HFX_PASS_ROWS_FWD, bs);
-        v->rows_fwd(a, b.n_active * rb, bs);
-        bk.done(grids * nr * ce * 2.0 * kzf, grids * fft_axis * kzf);
-      }
-      {
-        Bracket bk(plan, HFX_PASS_COLS_CONV, bs);
-        v->cols_conv(a, b.n_active * kz_planes(nz, sp.kz_max) * nxb, bs);
-        bk.done(grids * nr * ce * 2.0 * kzf, grids * fft_axis * 2.0 * kzf);
-      }
-      {
-        Bracket bk(plan, HFX_PASS_ROWS_INV, bs);
-        v->rows_inv(a, b.n_active * rb, bs);
-        bk.done(grids * nr * ce * 2.0 * kzf, grids * fft_axis * kzf);
-      }
+      launch(v->rows_fwd, nb_row, HFX_PASS_ROWS_FWD, by_row, fl_row);
+      launch(v->cols_conv, nb_col, HFX_PASS_COLS_CONV, by_col, fl_col);
+      launch(v->rows_inv, nb_row, HFX_PASS_ROWS_INV, by_row, fl_row);
     }
-    if (two && k > 0) HIP_TRY(hipStreamWaitEvent(bs, sp.ev_acc[q ^ 1], 0));
-    if (acc) {
-      Bracket bk(plan, HFX_PASS_INV_ACC, bs);
-      v->inv_acc(a, b.n_tiles * br, bs);
-      bk.done(grids * nr * ce * kzf + orbs * nr * elem * 3.0, grids * fft_z);
-    } else {
-      Bracket bk(plan, HFX_PASS_INV_ENERGY, bs);
-      v->inv_energy(a, b.n_tiles * br, bs);
-      bk.done(grids * nr * ce * kzf + orbs * nr * elem, grids * fft_z);
-    }
-    if (two) HIP_TRY(hipEventRecord(sp.ev_acc[q], bs));
+    if (two && k > 0) HIP_TRY(hipStreamWaitEvent(bs, sp0.ev_acc[q ^ 1], 0));
+    if (acc)
+      launch(v->inv_acc, nb_inv, HFX_PASS_INV_ACC, by_inv, fl_inv);
+    else
+      launch(v->inv_energy, nb_inv, HFX_PASS_INV_ENERGY, by_inv, fl_inv);
+    if (two) HIP_TRY(hipEventRecord(sp0.ev_acc[q], bs));
   }
   if (two) {
-    HIP_TRY(hipEventRecord(sp.ev_join, sp.bstream));
-    HIP_TRY(hipStreamWaitEvent(st, sp.ev_join, 0));
+    HIP_TRY(hipEventRecord(sp0.ev_join, sp0.bstream));
+    HIP_TRY(hipStreamWaitEvent(st, sp0.ev_join, 0));
   }
-  if (ex) {
+  for (int c = 0; c < nc; ++c) {
+    if (!calls[c].ex) continue;
+    SystemPlan& sp = *calls[c].sp;
     Bracket bk(plan, HFX_PASS_ENERGY_REDUCE, st);
     const double om = sp.dv * (double)sp.nr;
     // the G = 0 energy of the means is not pair work: added by group 0 only
     const bool dc = sp.shard == 0;
-    launch_energy_reduce(partials, sp.n_partials, -0.5 * sp.dv, dc ? mean : nullptr,
-                         sp.sys.n_orb, dc ? -0.5 * om * sp.v0 : 0.0, ex, st);
+    launch_energy_reduce(args[c].partials, sp.n_partials, -0.5 * sp.dv,
+                         dc ? args[c].mean : nullptr, sp.sys.n_orb,
+                         dc ? -0.5 * om * sp.v0 : 0.0, calls[c].ex, st);
     bk.done((double)sp.n_partials * 8.0, 0.0);
   }
   HIP_TRY(hipGetLastError());
   return HFX_OK;
 }
 
+// The size classes of a plan's systems for the exchange calls: systems with
+// the same kernel configuration, band and screening state share launches
+// (at most kMaxGroup per class); a system with two batch streams, or a plan
+// created with group=0, is a class of its own.  Classes keep the plan order
+// of their first system.
+std::vector<std::vector<int>> size_classes(hfx_plan plan) {
+  std::vector<std::vector<int>> out;
+  for (int i = 0; i < (int)plan->sys.size(); ++i) {
+    const SystemPlan& sp = plan->sys[i];
+    bool placed = false;
+    if (plan->group && sp.nstreams == 1 && !sp.var->persistent)
+      for (auto& c : out) {
+        const SystemPlan& f = plan->sys[c[0]];
+        if ((int)c.size() < kMaxGroup && f.var == sp.var && f.kz_max == sp.kz_max &&
+            (f.d_keep != nullptr) == (sp.d_keep != nullptr) && f.nstreams == 1) {
+          c.push_back(i);
+          placed = true;
+          break;
+        }
+      }
+    if (!placed) out.push_back({i});
+  }
+  return out;
+}
+
 // ---------------------------------------------------------------------------
 // Per-system launch sequences of each entry point.
 
-hfx_status enq_energy(hfx_plan plan, SystemPlan& sp, const double* psi, double* ex, char* ws,
-                      hipStream_t st) {
-  return run_exchange(plan, sp, psi + sp.psi_off, nullptr, ex, ws, st, false);
+// Exchange calls of one size class (cls: system indices).  psi, kpsi, grad
+// and ex are the call's concatenated buffers.
+hfx_status enq_energy(hfx_plan plan, const std::vector<int>& cls, const double* psi, double* ex,
+                      char* ws, hipStream_t st) {
+  std::vector<SysCall> calls;
+  for (int i : cls) {
+    SystemPlan& sp = plan->sys[i];
+    calls.push_back({&sp, psi + sp.psi_off, nullptr, ex + i});
+  }
+  return run_exchange(plan, calls, ws, st, false);
 }
 
-hfx_status enq_apply(hfx_plan plan, SystemPlan& sp, const double* psi, void* kpsi, double* ex,
-                     char* ws, hipStream_t st) {
+hfx_status enq_apply(hfx_plan plan, const std::vector<int>& cls, const double* psi, void* kpsi,
+                     double* ex, char* ws, hipStream_t st) {
   const size_t elem = plan->prec == HFX_FP64 ? 8 : 4;
-  void* kp = static_cast<char*>(kpsi) + (size_t)sp.psi_off * elem;
-  return run_exchange(plan, sp, psi + sp.psi_off, kp, ex, ws, st, true);
+  std::vector<SysCall> calls;
+  for (int i : cls) {
+    SystemPlan& sp = plan->sys[i];
+    calls.push_back({&sp, psi + sp.psi_off, static_cast<char*>(kpsi) + (size_t)sp.psi_off * elem,
+                     ex ? ex + i : nullptr});
+  }
+  return run_exchange(plan, calls, ws, st, true);
 }
 
-hfx_status enq_gradient(hfx_plan plan, SystemPlan& sp, const double* psi, const double* gscale,
-                        double* grad, char* ws, hipStream_t st) {
-  double* g = grad + sp.psi_off;
-  void* kp = plan->prec == HFX_FP64 ? static_cast<void*>(g) : static_cast<void*>(ws + sp.off_kpsi);
-  hfx_status s = run_exchange(plan, sp, psi + sp.psi_off, kp, nullptr, ws, st, true);
+hfx_status enq_gradient(hfx_plan plan, const std::vector<int>& cls, const double* psi,
+                        const double* gscale, double* grad, char* ws, hipStream_t st) {
+  std::vector<SysCall> calls;
+  for (int i : cls) {
+    SystemPlan& sp = plan->sys[i];
+    double* g = grad + sp.psi_off;
+    void* kp = plan->prec == HFX_FP64 ? static_cast<void*>(g) : static_cast<void*>(ws + sp.off_kpsi);
+    calls.push_back({&sp, psi + sp.psi_off, kp, nullptr});
+  }
+  hfx_status s = run_exchange(plan, calls, ws, st, true);
   if (s != HFX_OK) return s;
-  Bracket bk(plan, HFX_PASS_SCALE, st);
-  launch_scale_to_f64(kp, plan->prec == HFX_FP64, g, (size_t)sp.sys.n_orb * sp.nr, 2.0 * sp.dv,
-                      gscale, st);
-  bk.done((double)sp.sys.n_orb * sp.nr * (plan->prec == HFX_FP64 ? 16.0 : 12.0), 0.0);
+  for (size_t c = 0; c < cls.size(); ++c) {
+    SystemPlan& sp = *calls[c].sp;
+    Bracket bk(plan, HFX_PASS_SCALE, st);
+    launch_scale_to_f64(calls[c].kpsi, plan->prec == HFX_FP64, grad + sp.psi_off,
+                        (size_t)sp.sys.n_orb * sp.nr, 2.0 * sp.dv,
+                        gscale ? gscale + cls[c] : nullptr, st);
+    bk.done((double)sp.sys.n_orb * sp.nr * (plan->prec == HFX_FP64 ? 16.0 : 12.0), 0.0);
+  }
   HIP_TRY(hipGetLastError());
   return HFX_OK;
 }
@@ -719,12 +814,17 @@ hfx_status enq_matrix(hfx_plan plan, SystemPlan& sp, const double* psi, const vo
 }
 
 // K psi into the workspace, then M from it (and E_x when ex is given).
-hfx_status enq_matrix_full(hfx_plan plan, SystemPlan& sp, const double* psi, double* m,
-                           double* ex, char* ws, hipStream_t st) {
-  void* kp = ws + sp.off_kpsi;
-  hfx_status r = run_exchange(plan, sp, psi + sp.psi_off, kp, ex, ws, st, true);
-  if (r != HFX_OK) return r;
-  return enq_matrix_sys(plan, sp, psi, kp, m, ws, st);
+hfx_status enq_matrix_full(hfx_plan plan, const std::vector<int>& cls, const double* psi,
+                           double* m, double* ex, char* ws, hipStream_t st) {
+  std::vector<SysCall> calls;
+  for (int i : cls) {
+    SystemPlan& sp = plan->sys[i];
+    calls.push_back({&sp, psi + sp.psi_off, ws + sp.off_kpsi, ex ? ex + i : nullptr});
+  }
+  hfx_status r = run_exchange(plan, calls, ws, st, true);
+  for (size_t c = 0; c < calls.size() && r == HFX_OK; ++c)
+    r = enq_matrix_sys(plan, *calls[c].sp, psi, calls[c].kpsi, m, ws, st);
+  return r;
 }
 
 // ACE projectors: L = chol(-M), X = L^(-1), P = X W (Eq. (vx_ace)).
@@ -854,6 +954,25 @@ hfx_status dispatch(hfx_plan plan, hipStream_t user, F&& fn) {
   return HFX_OK;
 }
 
+// Runs fn(class, stream) for every size class of the plan's systems (see
+// size_classes): one class on the caller's stream, several forked onto the
+// side streams of their first systems and joined back like dispatch().
+template <class F>
+hfx_status dispatch_classes(hfx_plan plan, hipStream_t user, F&& fn) {
+  const std::vector<std::vector<int>> classes = size_classes(plan);
+  if (classes.size() == 1) return fn(classes[0], user);
+  HIP_TRY(hipEventRecord(plan->fork, user));
+  for (const auto& cls : classes) {
+    const int i = cls[0];
+    HIP_TRY(hipStreamWaitEvent(plan->side[i], plan->fork, 0));
+    hfx_status s = fn(cls, plan->side[i]);
+    if (s != HFX_OK) return s;
+    HIP_TRY(hipEventRecord(plan->join[i], plan->side[i]));
+    HIP_TRY(hipStreamWaitEvent(user, plan->join[i], 0));
+  }
+  return HFX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -912,6 +1031,9 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     return fail(HFX_EINVAL, "maxws= takes a non-negative integer (bytes)");
   if (!parse_option(options, "streams", 1, &batch_streams))
     return fail(HFX_EINVAL, "streams= must be 1 or 2");
+  long long group_opt = 1;
+  if (!parse_option(options, "group", 1, &group_opt) || group_opt > 1)
+    return fail(HFX_EINVAL, "group= takes 0 or 1");
   long long check_opt = 0;
   if (!parse_option(options, "check", 0, &check_opt) || check_opt > 1)
     return fail(HFX_EINVAL, "check= takes 0 or 1");
@@ -1024,6 +1146,7 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   hfx_plan p = new hfx_plan_t();
   p->prec = precision;
   p->check = check_opt == 1;
+  p->group = group_opt == 1;
   p->sys.resize(n_sys);
   size_t off = 0;
   long long psi_off = 0, m_off = 0, orb_off = 0;
@@ -1235,9 +1358,10 @@ hfx_status hfx_exchange_energy(hfx_plan plan, const double* psi, double* ex, voi
   if (!ex) return fail(HFX_EINVAL, "null ex");
   s = check_inputs(plan, psi, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
   if (s != HFX_OK) return s;
-  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
-    return enq_energy(plan, plan->sys[i], psi, ex + i, static_cast<char*>(ws), st);
-  });
+  return dispatch_classes(plan, static_cast<hipStream_t>(stream),
+                          [&](const std::vector<int>& cls, hipStream_t st) {
+                            return enq_energy(plan, cls, psi, ex, static_cast<char*>(ws), st);
+                          });
 }
 
 hfx_status hfx_apply_exchange(hfx_plan plan, const double* psi, void* kpsi, double* ex,
@@ -1247,10 +1371,10 @@ hfx_status hfx_apply_exchange(hfx_plan plan, const double* psi, void* kpsi, doub
   if (!kpsi) return fail(HFX_EINVAL, "null kpsi");
   s = check_inputs(plan, psi, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
   if (s != HFX_OK) return s;
-  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
-    return enq_apply(plan, plan->sys[i], psi, kpsi, ex ? ex + i : nullptr, static_cast<char*>(ws),
-                     st);
-  });
+  return dispatch_classes(plan, static_cast<hipStream_t>(stream),
+                          [&](const std::vector<int>& cls, hipStream_t st) {
+                            return enq_apply(plan, cls, psi, kpsi, ex, static_cast<char*>(ws), st);
+                          });
 }
 
 }  // extern "C"
@@ -1263,10 +1387,9 @@ hfx_status hfx::apply_into(hfx_plan plan, const double* psi, void* kpsi, double*
                            void* stream) {
   // the caller checked the arguments and that ws holds apply_workspace_bytes
   plan->quiet = true;
-  const hfx_status s =
-      dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
-        return enq_apply(plan, plan->sys[i], psi, kpsi, ex ? ex + i : nullptr,
-                         static_cast<char*>(ws), st);
+  const hfx_status s = dispatch_classes(
+      plan, static_cast<hipStream_t>(stream), [&](const std::vector<int>& cls, hipStream_t st) {
+        return enq_apply(plan, cls, psi, kpsi, ex, static_cast<char*>(ws), st);
       });
   plan->quiet = false;
   return s;
@@ -1281,10 +1404,11 @@ hfx_status hfx_exchange_gradient(hfx_plan plan, const double* psi, const double*
   if (!grad) return fail(HFX_EINVAL, "null grad");
   s = check_inputs(plan, psi, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
   if (s != HFX_OK) return s;
-  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
-    return enq_gradient(plan, plan->sys[i], psi, gscale ? gscale + i : nullptr, grad,
-                        static_cast<char*>(ws), st);
-  });
+  return dispatch_classes(plan, static_cast<hipStream_t>(stream),
+                          [&](const std::vector<int>& cls, hipStream_t st) {
+                            return enq_gradient(plan, cls, psi, gscale, grad,
+                                                static_cast<char*>(ws), st);
+                          });
 }
 
 hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, double* m, double* ex,
@@ -1294,10 +1418,11 @@ hfx_status hfx_exchange_matrix(hfx_plan plan, const double* psi, double* m, doub
   if (!m) return fail(HFX_EINVAL, "null m");
   s = check_inputs(plan, psi, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
   if (s != HFX_OK) return s;
-  return dispatch(plan, static_cast<hipStream_t>(stream), [&](size_t i, hipStream_t st) {
-    return enq_matrix_full(plan, plan->sys[i], psi, m, ex ? ex + i : nullptr,
-                           static_cast<char*>(ws), st);
-  });
+  return dispatch_classes(plan, static_cast<hipStream_t>(stream),
+                          [&](const std::vector<int>& cls, hipStream_t st) {
+                            return enq_matrix_full(plan, cls, psi, m, ex,
+                                                   static_cast<char*>(ws), st);
+                          });
 }
 
 hfx_status hfx_exchange_matrix_kpsi(hfx_plan plan, const double* psi, const void* kpsi, double* m,
@@ -1460,6 +1585,14 @@ const char* hfx_plan_describe(hfx_plan plan, int system) {
                   " streams=" + std::to_string(sp.nstreams) +
                   " screened=" + (sp.d_keep ? "yes" : "no") +
                   " tuned=" + (sp.tuned ? "yes" : "no");
+  {
+    // the size class: systems that share the pass launches of exchange calls
+    const std::vector<std::vector<int>> cls = size_classes(plan);
+    for (size_t c = 0; c < cls.size(); ++c)
+      for (int i : cls[c])
+        if (i == system)
+          d += " class=" + std::to_string(c) + "/" + std::to_string(cls[c].size());
+  }
   plan->desc = d;
   return plan->desc.c_str();
 }
@@ -1521,13 +1654,16 @@ hfx_status hfx_graph_create(hfx_plan plan, int op, double* psi, void* kpsi, doub
     return fail(HFX_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
   }
   char* w = static_cast<char*>(ws);
-  s = dispatch(plan, plan->cap, [&](size_t i, hipStream_t st) {
-    SystemPlan& sp = plan->sys[i];
+  s = dispatch_classes(plan, plan->cap, [&](const std::vector<int>& cls, hipStream_t st) {
     hfx_status r = HFX_OK;
-    if (op == HFX_GRAPH_ENERGY) return enq_energy(plan, sp, psi, ex + i, w, st);
-    if (op == HFX_GRAPH_STEP) r = enq_ortho(plan, sp, psi, HFX_ORTHO_LOWDIN, w, st);
-    if (r == HFX_OK) r = enq_apply(plan, sp, psi, kpsi, ex ? ex + i : nullptr, w, st);
-    if (r == HFX_OK && op == HFX_GRAPH_STEP) r = enq_matrix(plan, sp, psi, kpsi, m, w, st);
+    if (op == HFX_GRAPH_ENERGY) return enq_energy(plan, cls, psi, ex, w, st);
+    if (op == HFX_GRAPH_STEP)
+      for (int i : cls)
+        if (r == HFX_OK) r = enq_ortho(plan, plan->sys[i], psi, HFX_ORTHO_LOWDIN, w, st);
+    if (r == HFX_OK) r = enq_apply(plan, cls, psi, kpsi, ex, w, st);
+    if (op == HFX_GRAPH_STEP)
+      for (int i : cls)
+        if (r == HFX_OK) r = enq_matrix(plan, plan->sys[i], psi, kpsi, m, w, st);
     return r;
   });
   e = hipStreamEndCapture(plan->cap, &g->graph);

@@ -91,7 +91,29 @@ __host__ __device__ inline int kz_of_plane(int c, int nz, int kz_max) {
   return (kz_max >= nz / 2 || c <= kz_max) ? c : nz - (2 * kz_max + 1 - c);
 }
 
-typedef void (*launch_fn)(const PassArgs&, int nblocks, hipStream_t);
+// One launch of a pass over the current batches of up to kMaxGroup systems
+// that share a kernel configuration (a size class): system s owns the
+// logical workgroups [start[s], start[s + 1]) and reads its own PassArgs.
+// Single-system launches are groups of one.  Passed by value as the kernel
+// argument (about 1.3 KB), so a launch needs no device-side table upload
+// and can be captured in a graph as is.
+constexpr int kMaxGroup = 8;
+struct PassGroup {
+  PassArgs a[kMaxGroup];
+  int start[kMaxGroup + 1];
+  int count;
+  // system of logical workgroup L (in s) and L's index inside that system
+  __device__ __forceinline__ int locate(int L, int& s) const {
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxGroup; ++i)
+      if (i < count && L >= start[i]) k = i;
+    s = k;
+    return L - start[k];
+  }
+};
+
+typedef void (*launch_fn)(const PassGroup&, int nblocks, hipStream_t);
 
 // One compiled configuration of the exchange pipeline for a grid size and
 // precision: radix schedules, launch shapes and the launchers.
@@ -109,6 +131,7 @@ struct Variant {
   int nt_cols;     // plane_mode 1: threads per column workgroup
   int plane_mode;  // 0: fused xy plane in LDS; 1: x rows + y columns passes
   int rows_per_wg; // plane_mode 1: rows per row-FFT workgroup
+  bool persistent; // plane kernel loops over planes (grid of resident workgroups only)
   int zf[4], nzf, zi[4], nzi;  // z radix schedules (forward, inverse)
   int xf[4], nxf, xi[4], nxi;  // x
   int yf[4], nyf, yi[4], nyi;  // y
