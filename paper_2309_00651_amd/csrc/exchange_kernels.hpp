@@ -650,17 +650,24 @@ constexpr int plane_waves_per_eu() {
 // they are in flight during that transform and the stores of the current
 // plane.  The v(G) loads come first, so waiting for them never waits for the
 // prefetch (one in-order counter tracks the loads).
+// QB > 0 (band-limited plans whose pair densities vanish for |kx| > QB):
+// the forward x transform stores zeros in the columns beyond the band and
+// the y transforms, the multiply and the inverse y transforms run on the
+// 2 QB + 1 columns of the band only (a band geometry of the engine); the
+// inverse x transforms read the zeros.
 template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, bool SW = false,
-          bool PP = false, int NZ = N>
+          bool PP = false, int NZ = N, int QB = 0>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<T, N, NT>())))
 k_plane_conv(PassGroup grp) {
   int sys_ = 0;
   const int lg_ = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
   const PassArgs& a = grp.a[sys_];
   static_assert(!SW || N % 8 == 0, "swizzle needs whole blocks of 8");
+  static_assert(QB == 0 || (!SW && 2 * QB + 1 < N), "band columns: no swizzle, inside the row");
   constexpr int P = N + 1;
   using GX = Geom<T, N, N, NT, false, 1, P, SW ? 1 : 0>;  // rows: sequence m = y, element n = x
-  using GY = Geom<T, N, N, NT, true, P, 1, SW ? 2 : 0>;   // columns: sequence m = x, element n = y
+  // columns: sequence m = x (or the m-th column of the band), element n = y
+  using GY = Geom<T, N, QB ? 2 * QB + 1 : N, NT, true, P, 1, SW ? 2 : (QB ? 3 : 0)>;
   using EXF = FFT<GX, false, SXF>;
   using EXI = FFT<GX, true, SXI>;
   using EYF = FFT<GY, false, SYF>;
@@ -715,7 +722,23 @@ k_plane_conv(PassGroup grp) {
     {
       cpx<T> o[LXF::VALS];
       EXF::reg2reg(v, plane, twxf, tid, o);
-      EXF::store_last(o, plane, tid);
+      if constexpr (QB == 0) {
+        EXF::store_last(o, plane, tid);
+      } else {
+        // columns beyond the band hold rounding noise only: store zeros
+#pragma unroll
+        for (int i = 0; i < LXF::PER; ++i) {
+          if (!LXF::valid(tid, i)) continue;
+          int m, j;
+          LXF::mj(tid, i, m, j);
+#pragma unroll
+          for (int r = 0; r < SchedInfo<SXF>::last; ++r) {
+            const int x = LXF::out_pos(j, r);
+            const bool in = x <= QB || x >= N - QB;
+            plane[GX::idx(m, x)] = in ? o[i * SchedInfo<SXF>::last + r] : cpx<T>{T(0), T(0)};
+          }
+        }
+      }
     }
     __syncthreads();
     // y forward, multiply by v(G)/N_r, y inverse (hand-over in registers)
@@ -728,7 +751,7 @@ k_plane_conv(PassGroup grp) {
       LY::mj(tid, i, m, j);
 #pragma unroll
       for (int r = 0; r < SchedInfo<SYF>::last; ++r) {
-        const T f = vt[LY::in_pos(j, r) * N + m];
+        const T f = vt[LY::in_pos(j, r) * N + (QB ? GY::band_col(m) : m)];
         oy[i * SchedInfo<SYF>::last + r] = cscale(oy[i * SchedInfo<SYF>::last + r], f);
       }
     }
@@ -925,6 +948,11 @@ template <typename T, int N, int W, int TT, class SZF, class SZI, int NTQ, class
           bool PIL = false, bool PP = false, int NZ = N>
 struct FusedPipeline {
   static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
+  // band of the plane kernel's column-pruned instantiation (float32 cubic
+  // grids from 64 up to 120, plain layouts): |kx| <= N / 4, the band of
+  // orbitals at half the grid's plane-wave reach (a twofold oversampled grid)
+  static constexpr int QB = (sizeof(T) == 4 && NZ == N && N >= 64 && N <= 120 && !SW && !PP)
+                                ? N / 4 : 0;
   // persistent plane kernel: one workgroup per plane slot of the device
   static int plane_grid(int planes) {
     if (!PP) return planes;
@@ -948,6 +976,15 @@ struct FusedPipeline {
                          s, g);
   }
   static void plane(const PassGroup& g, int nb, hipStream_t s) {
+    if constexpr (QB > 0) {
+      bool band = true;
+      for (int i = 0; i < g.count; ++i) band = band && g.a[i].kx_max <= QB;
+      if (band) {
+        hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB>),
+                           dim3(plane_grid(nb)), dim3(NTQ), lds, s, g);
+        return;
+      }
+    }
     hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ>),
                        dim3(plane_grid(nb)), dim3(NTQ), lds, s, g);
   }
@@ -985,8 +1022,12 @@ struct FusedPipeline {
   static void inv_acc(const PassGroup& g, int nb, hipStream_t s) { inv_pass<true>(g, nb, s); }
   static void inv_energy(const PassGroup& g, int nb, hipStream_t s) { inv_pass<false>(g, nb, s); }
   static hipError_t prepare() {
-    return hipFuncSetAttribute(
+    hipError_t e = hipFuncSetAttribute(
         reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess || QB == 0) return e;
+    return hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
   static Variant describe(const char* name) {

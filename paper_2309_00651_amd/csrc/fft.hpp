@@ -270,6 +270,9 @@ template <bool INV, typename T> struct DFT<16, INV, T> : DFTPQ<4, 4, INV, T> {};
 //     y*P + (x ^ ((x >> 3) & 7)), an XOR inside each block of 8 along x that
 //     spreads the stride-8 first-stage writes of the row transforms over the
 //     banks without extra LDS (needs N % 8 == 0).
+//   3 a band of columns of an N x N plane: M = 2Q + 1 sequences m are the
+//     columns x = 0..Q and N-Q..N-1 (m > Q maps to x = m + N - M); element n
+//     of column m at n*ES + x (TS = 1).
 template <typename T_, int N_, int M_, int NT_, bool MFAST_, int ES_, int TS_, int SWZ_ = 0>
 struct Geom {
   using T = T_;
@@ -280,11 +283,15 @@ struct Geom {
   static constexpr int ES = ES_;   // LDS stride between elements of a sequence
   static constexpr int TS = TS_;   // LDS stride between sequences
   static constexpr int SWZ = SWZ_;
+  // column of sequence m in a band geometry (SWZ == 3)
+  HFX_HD static int band_col(int m) { return m <= (M - 1) / 2 ? m : m + N - M; }
   HFX_HD static int idx(int m, int n) {
     if constexpr (SWZ == 1) {
       return m * TS + (n ^ ((n >> 3) & 7));
     } else if constexpr (SWZ == 2) {
       return n * ES + (m ^ ((m >> 3) & 7));
+    } else if constexpr (SWZ == 3) {
+      return n * ES + band_col(m);
     } else {
       return m * TS + n * ES;
     }

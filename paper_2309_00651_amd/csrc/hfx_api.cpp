@@ -77,6 +77,7 @@ struct SystemPlan {
   // band limit: pair densities vanish on kz planes |kz| > kz_max (>= nz / 2:
   // no plane is skipped)
   int kz_max = 1 << 30;
+  int kx_max = 1 << 30;  // the same along x (from L_x)
   int tiles_per_batch = 1;
   int slots_per_batch = 0;
   std::vector<TileDesc> tiles;
@@ -575,6 +576,7 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
     a.perm = sp.d_perm;
     a.n_orb = sp.sys.n_orb;
     a.kz_max = sp.kz_max;
+    a.kx_max = sp.kx_max;
     a.zero = sp.d_zero;
     max_batches = std::max(max_batches, sp.batches.size());
   }
@@ -1172,6 +1174,7 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     }
     schedule_all_pairs(sp, sp.tiles_cap);
     sp.kz_max = kz_max_for(ecut, sys[i].L[2]);
+    sp.kx_max = kz_max_for(ecut, sys[i].L[0]);
     sp.psi_off = psi_off;
     sp.m_off = m_off;
     sp.orb_off = orb_off;

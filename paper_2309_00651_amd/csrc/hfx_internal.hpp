@@ -71,6 +71,10 @@ struct PassArgs {
   // (read as zeros).  kz_max >= NZ / 2: every plane is kept.
   int kz_max;
   const void* zero;  // kZeroBytes of zeros (device): the pruned planes' loads read these
+  // Band-limited orbitals: pair densities also vanish for |kx| > kx_max, so
+  // the plane pass may skip the y transforms of those columns (kx_max >=
+  // N / 2: every column is kept).
+  int kx_max;
 };
 
 // Zero block of band-limited plans: one 16-byte element per thread of a
