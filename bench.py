@@ -180,18 +180,25 @@ def measure_batched6(steps, warmup, options, tune_cache, singles=True):
     t_eager = _event_times(lambda: plan.apply_exchange(psi, kpsi=kpsi, ex=ex), steps, 1)
     assert [float(x) for x in ex.cpu()] == ex_graph, "graph replay and eager launch disagree"
     g.close()
+    # the batch's algorithmic bytes (the library's tally: pair grids on the
+    # kept kz planes only) over the graph replay's time
     plan.profile(True)
     plan.apply_exchange(psi, kpsi=kpsi, ex=ex)
-    prof = plan.profile_read()
+    prof_all = plan.profile_read()
     plan.profile(False)
     describe = [plan.describe(i) for i in range(len(systems))]
     del plan
     ms_graph = _median(t_graph)
+    bytes_all = sum(v["bytes"] for v in prof_all.values())
+    bytes_pipe = sum(prof_all[k]["bytes"] for k in PAIR_PASSES if k in prof_all)
     out = {"pairs": n_pairs, "ms_graph_replay_median": ms_graph,
            "ms_graph_replay_mean": sum(t_graph) / len(t_graph),
            "ms_eager_one_plan_median": _median(t_eager),
            "pairs_per_s": n_pairs / (ms_graph * 1e-3), "steps": steps,
-           "passes": _passes(prof, 1), "pair_pipeline_hbm_frac_eager": _pipeline_frac(prof),
+           "algorithmic_GB_per_call": bytes_all / 1e9,
+           "hbm_frac_of_graph_replay": bytes_all / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "pair_pipeline_bytes_frac_of_graph_replay":
+               bytes_pipe / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "kernel_configs": describe, "plan_options": opts, "ex": ex_graph}
     gold = [_golden_ex(s.name) for s in systems]
     if all(x is not None for x in gold):
@@ -211,8 +218,78 @@ def measure_batched6(steps, warmup, options, tune_cache, singles=True):
         t_seq = _event_times(seq, max(2, steps // 2), 1)
         out["ms_six_single_plans_median"] = _median(t_seq)
         out["batch_gain_vs_single_plans"] = _median(t_seq) / ms_graph
+        # per-pass rates of the kernels, each system's plan profiled alone (in
+        # the batched plan the systems' launches overlap, which stretches every
+        # event-timed launch)
+        per = {}
+        for sname, pl, (pv, kv) in zip([s.name for s in systems], plans, views):
+            pl.profile(True)
+            pl.apply_exchange(pv, kpsi=kv)
+            pr = pl.profile_read()
+            pl.profile(False)
+            per[sname] = {k: v for k, v in _passes(pr, 1).items() if k in PAIR_PASSES}
+            per[sname]["pair_pipeline_hbm_frac"] = _pipeline_frac(pr)
+        out["passes_per_system"] = per
         del plans
     del psi, kpsi
+    torch.cuda.empty_cache()
+    return out
+
+
+def measure_size_classes(steps, warmup):
+    """Sixteen small systems on one grid with uneven orbital counts (24^3,
+    L = 10 bohr, 8..23 random plane-wave orbitals, 5 Ha, truncated Coulomb):
+    K psi + E_x of all of them per call, replayed from a graph, (a) with size
+    classes (the default here: two classes of eight systems, each batch step
+    one launch per pass), (b) with group=0 (sixteen forked launch sequences),
+    (c) sixteen single plans in turn.  All three give the same results bit
+    for bit."""
+    import numpy as np
+    import torch
+
+    from paper_2309_00651_amd import hfx
+    from workloads import generate
+
+    dev = torch.device("cuda:0")
+    n, L = 24, 10.0
+    counts = list(range(8, 24))
+    psis = [generate.random_pw((n,) * 3, (L,) * 3, no, 5.0, 20231300 + no) for no in counts]
+    specs = [hfx.SystemSpec(n, (L,) * 3, no) for no in counts]
+    flat = torch.from_numpy(np.concatenate([p.reshape(-1) for p in psis])).to(dev)
+    n_pairs = sum(no * (no + 1) // 2 for no in counts)
+    out = {"systems": len(counts), "grid": n, "orbitals": counts, "pairs": n_pairs}
+    ex_ref = None
+    for tag, opt in (("classes", "ecut=5"), ("group0", "ecut=5;group=0")):
+        plan = hfx.Plan(specs, hfx.FP32, options=opt, device=dev)
+        kpsi = torch.empty(flat.shape, dtype=torch.float32, device=dev)
+        ex = torch.empty(len(counts), dtype=torch.float64, device=dev)
+        g = plan.graph(hfx.GRAPH_APPLY, flat, kpsi, ex)
+        t = _event_times(g.launch, steps, warmup)
+        e = [float(x) for x in ex.cpu()]
+        if ex_ref is None:
+            ex_ref = e
+        assert e == ex_ref, "grouped and per-system launches disagree"
+        out[f"ms_graph_{tag}"] = _median(t)
+        out[f"classes_{tag}"] = sorted({plan.describe(i).split("class=")[1]
+                                        for i in range(len(counts))})
+        g.close()
+        del plan, kpsi
+    plans = [hfx.Plan(sp, hfx.FP32, options="ecut=5", device=dev) for sp in specs]
+    views, off = [], 0
+    kp = torch.empty(flat.shape, dtype=torch.float32, device=dev)
+    for no in counts:
+        k = no * n ** 3
+        views.append((flat[off:off + k], kp[off:off + k]))
+        off += k
+
+    def seq():
+        for pl, (pv, kv) in zip(plans, views):
+            pl.apply_exchange(pv, kpsi=kv)
+    out["ms_single_plans"] = _median(_event_times(seq, steps, warmup))
+    out["pairs_per_s_classes"] = n_pairs / (out["ms_graph_classes"] * 1e-3)
+    out["gain_vs_group0"] = out["ms_graph_group0"] / out["ms_graph_classes"]
+    out["gain_vs_single_plans"] = out["ms_single_plans"] / out["ms_graph_classes"]
+    del plans, flat, kp
     torch.cuda.empty_cache()
     return out
 
@@ -563,6 +640,10 @@ def main():
         log(f"batched6: graph replay {b6['ms_graph_replay_median']:.1f} ms "
             f"({b6['pairs_per_s']:.0f} pairs/s), six single plans "
             f"{b6.get('ms_six_single_plans_median', float('nan')):.1f} ms")
+        extra["size_classes"] = measure_size_classes(5, 2)
+        sc = extra["size_classes"]
+        log(f"size classes: {sc['ms_graph_classes']:.2f} ms (group=0 {sc['ms_graph_group0']:.2f}"
+            f", single plans {sc['ms_single_plans']:.2f})")
         extra["large128"] = measure_large128(3, 1, band20, 0 if args.no_fp64 else 2)
         l1 = extra["large128"]
         log(f"large128: fp32 {l1['fp32']['ms_median']:.1f} ms "

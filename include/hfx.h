@@ -131,7 +131,14 @@ typedef struct hfx_plan_t* hfx_plan;
  * HFX_AUTOTUNE_CACHE) names a cache written by hfx_autotune: each system
  * whose key is found there takes the cached variant, tiles and rows for
  * whatever the options leave open (hfx_plan_describe reports tuned=yes);
- * a missing file or key leaves the defaults.  Uploads the plan's tables
+ * a missing file or key leaves the defaults.  Size classes: the energy, K psi,
+ * matrix and gradient calls run systems with the same compiled configuration,
+ * kz band and screening state (up to eight) as one class whose batch steps
+ * share one launch per pass, with one staging, pair-mean and zero-fill
+ * launch for the class; other classes run on forked streams.  By default only
+ * systems whose own pass launches are small (fewer than 512 workgroups) are
+ * grouped; group=1 groups every system it can, group=0 none (results are the
+ * same bit for bit; hfx_plan_describe reports class=<k>/<size>).  Uploads the plan's tables
  * (synchronous).  Errors: HFX_EINVAL for null out/sys, n_sys < 1, n <= 0,
  * L <= 0, n_orb < 1, unknown kernel or precision, erfc w <= 0, an unknown
  * option key or a malformed option value;

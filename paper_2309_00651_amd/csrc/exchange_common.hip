@@ -161,6 +161,93 @@ bool launch_check_orbitals(const double* psi, int n_orb, int nx, int ny, int nz,
   return true;
 }
 
+// Grouped forms for the systems of a size class: segment s (count <=
+// kMaxGroup) owns the workgroups [start[s], start[s + 1]) and walks its own
+// range with a grid stride of its own workgroups.
+struct SegGroup {
+  const void* src[kMaxGroup];
+  void* dst[kMaxGroup];
+  size_t n[kMaxGroup];
+  int start[kMaxGroup + 1];
+  int count;
+};
+__device__ __forceinline__ int seg_locate(const SegGroup& g, int b, int& s) {
+  int k = 0;
+#pragma unroll
+  for (int i = 1; i < kMaxGroup; ++i)
+    if (i < g.count && b >= g.start[i]) k = i;
+  s = k;
+  return b - g.start[k];
+}
+
+__global__ void __launch_bounds__(256) k_cast_group(SegGroup g) {
+  int s = 0;
+  const int b = seg_locate(g, (int)blockIdx.x, s);
+  const double* __restrict__ in = static_cast<const double*>(g.src[s]);
+  float* __restrict__ out = static_cast<float*>(g.dst[s]);
+  const size_t n = g.n[s];
+  const size_t stride = (size_t)(g.start[s + 1] - g.start[s]) * blockDim.x * 2;
+  for (size_t i = ((size_t)b * blockDim.x + threadIdx.x) * 2; i < n; i += stride) {
+    if (i + 1 < n) {
+      const double2 v = *reinterpret_cast<const double2*>(in + i);
+      *reinterpret_cast<float2*>(out + i) = make_float2((float)v.x, (float)v.y);
+    } else {
+      out[i] = (float)in[i];
+    }
+  }
+}
+
+// byte ranges; n counts bytes
+__global__ void __launch_bounds__(256) k_zero_group(SegGroup g) {
+  int s = 0;
+  const int b = seg_locate(g, (int)blockIdx.x, s);
+  unsigned char* p = static_cast<unsigned char*>(g.dst[s]);
+  const size_t bytes = g.n[s];
+  const size_t stride = (size_t)(g.start[s + 1] - g.start[s]) * blockDim.x;
+  const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
+  const size_t head = addr % 16 ? (16 - addr % 16 < bytes ? 16 - addr % 16 : bytes) : 0;
+  const size_t n16 = (bytes - head) / 16;
+  uint4* body = reinterpret_cast<uint4*>(p + head);
+  for (size_t i = (size_t)b * blockDim.x + threadIdx.x; i < n16; i += stride)
+    body[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (b == 0) {
+    for (size_t i = threadIdx.x; i < head; i += blockDim.x) p[i] = 0;
+    for (size_t i = head + n16 * 16 + threadIdx.x; i < bytes; i += blockDim.x) p[i] = 0;
+  }
+}
+
+static int grid_for(size_t work);
+
+void launch_cast_group(const double* const* in, float* const* out, const size_t* n, int count,
+                       hipStream_t s) {
+  SegGroup g{};
+  g.count = count;
+  int blocks = 0;
+  for (int i = 0; i < count; ++i) {
+    g.src[i] = in[i];
+    g.dst[i] = out[i];
+    g.n[i] = n[i];
+    g.start[i] = blocks;
+    blocks += grid_for((n[i] + 1) / 2);
+  }
+  g.start[count] = blocks;
+  hipLaunchKernelGGL(k_cast_group, dim3(blocks), dim3(256), 0, s, g);
+}
+
+void launch_zero_group(void* const* p, const size_t* bytes, int count, hipStream_t s) {
+  SegGroup g{};
+  g.count = count;
+  int blocks = 0;
+  for (int i = 0; i < count; ++i) {
+    g.dst[i] = p[i];
+    g.n[i] = bytes[i];
+    g.start[i] = blocks;
+    blocks += grid_for(bytes[i] / 16 > 0 ? bytes[i] / 16 : 1);
+  }
+  g.start[count] = blocks;
+  hipLaunchKernelGGL(k_zero_group, dim3(blocks), dim3(256), 0, s, g);
+}
+
 static int grid_for(size_t work) {
   const size_t b = (work + 255) / 256;
   return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);

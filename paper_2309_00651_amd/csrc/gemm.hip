@@ -97,11 +97,50 @@ GemmShape gemm_shape(int n, long long nr, bool sym) {
 //   result, 4 values i = 0..3:  f32: D[4 (l / 16) + i][l % 16]
 //                               f64: D[(l / 16) + 4 i][l % 16]
 // (both checked on gfx950 against a host product).
+// One product of a launch: C = alpha A B^T over nr points, its chunking and
+// tiles (gemm_shape), partials and output.  A launch carries up to
+// kMaxGroup of them (a GramGroup, by value as the kernel argument); product s
+// owns the logical workgroups [start[s], start[s + 1]) of the product kernel
+// and [rstart[s], rstart[s + 1]) of the reduction.  Each product keeps its
+// own chunking, so its result is the same whether launched alone or with
+// others.
+struct GramJob {
+  const double* a;
+  const void* b;
+  double* part;
+  double* c;
+  double alpha;
+  long long nr, chunk_len;
+  int n, n_chunks, tiles_m, tiles_n, n_tiles, sym;
+};
+struct GramGroup {
+  GramJob j[kMaxGroup];
+  int start[kMaxGroup + 1];
+  int rstart[kMaxGroup + 1];
+  int count;
+};
+__device__ __forceinline__ int gram_locate(const int* start, int count, int L, int& s) {
+  int k = 0;
+#pragma unroll
+  for (int i = 1; i < kMaxGroup; ++i)
+    if (i < count && L >= start[i]) k = i;
+  s = k;
+  return L - start[k];
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_gram(const double* __restrict__ a, const void* __restrict__ bv, int n, long long nr,
-       long long chunk_len, int n_chunks, int tiles_m, int tiles_n, int n_tiles, int sym,
-       double* __restrict__ part) {
+k_gram(GramGroup grp) {
+  int js = 0;
+  const int L = gram_locate(grp.start, grp.count, xcd_order(blockIdx.x, gridDim.x), js);
+  const GramJob& J = grp.j[js];
+  const double* __restrict__ a = J.a;
+  const void* __restrict__ bv = J.b;
+  const int n = J.n, n_chunks = J.n_chunks, tiles_m = J.tiles_m, tiles_n = J.tiles_n;
+  const int n_tiles = J.n_tiles, sym = J.sym;
+  const long long nr = J.nr, chunk_len = J.chunk_len;
+  double* __restrict__ part = J.part;
+  (void)n_chunks;
   using C = Cfg<MODE>;
   constexpr int TM = C::TM, TN = C::TN, BM = C::BM, BN = C::BN;
   constexpr bool SPLIT = MODE == 1;
@@ -112,7 +151,6 @@ k_gram(const double* __restrict__ a, const void* __restrict__ bv, int n, long lo
   __shared__ float as_lo[SPLIT ? 2 : 1][SPLIT ? TM : 1][KB + 1];
   __shared__ BT bs[2][TN][KB + 1];
 
-  const int L = xcd_order(blockIdx.x, gridDim.x);
   const int tile = L % n_tiles, c = L / n_tiles;
   int ti, tj;
   tile_coords(tile, tiles_m, tiles_n, sym != 0, ti, tj);
@@ -295,12 +333,18 @@ k_gram(const double* __restrict__ a, const void* __restrict__ bv, int n, long lo
 // C[i][j] = alpha * sum_c part[tile(i, j)][c][i % TM][j % TN] in a fixed
 // order over c; symmetric products read (j, i) below the diagonal.
 template <int MODE>
-__global__ void __launch_bounds__(256) k_gram_reduce(const double* __restrict__ part, int n,
-                                                     int n_chunks, int tiles_m, int tiles_n,
-                                                     int sym, double alpha,
-                                                     double* __restrict__ cmat) {
+__global__ void __launch_bounds__(256) k_gram_reduce(GramGroup grp) {
+  int js = 0;
+  const int blk = gram_locate(grp.rstart, grp.count, (int)blockIdx.x, js);
+  const GramJob& J = grp.j[js];
+  const double* __restrict__ part = J.part;
+  const int n = J.n, n_chunks = J.n_chunks, tiles_m = J.tiles_m, tiles_n = J.tiles_n;
+  const int sym = J.sym;
+  const double alpha = J.alpha;
+  double* __restrict__ cmat = J.c;
+  (void)tiles_m;
   using C = Cfg<MODE>;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long idx = (long long)blk * blockDim.x + threadIdx.x;
   if (idx >= (long long)n * n) return;
   int i = (int)(idx / n), j = (int)(idx % n);
   if (sym && i > j) {
@@ -325,15 +369,51 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double* __restrict__ 
 }
 
 template <int MODE>
+static GramJob gram_job(const double* a, const void* b, int n, long long nr, double alpha,
+                        bool sym, double* part, double* c) {
+  const GemmShape g = gemm_shape<MODE>(n, nr, sym);
+  GramJob j{};
+  j.a = a;
+  j.b = b;
+  j.part = part;
+  j.c = c;
+  j.alpha = alpha;
+  j.nr = nr;
+  j.chunk_len = g.chunk_len;
+  j.n = n;
+  j.n_chunks = g.n_chunks;
+  j.tiles_m = g.tiles_m;
+  j.tiles_n = g.tiles_n;
+  j.n_tiles = g.n_tiles;
+  j.sym = sym ? 1 : 0;
+  return j;
+}
+
+// The products of jobs[0..count) in one launch of the product kernel and
+// one of the reduction.
+template <int MODE>
+static void launch_gram_group(const GramJob* jobs, int count, hipStream_t s) {
+  GramGroup g{};
+  g.count = count;
+  int blocks = 0, rblocks = 0;
+  for (int i = 0; i < count; ++i) {
+    g.j[i] = jobs[i];
+    g.start[i] = blocks;
+    g.rstart[i] = rblocks;
+    blocks += jobs[i].n_tiles * jobs[i].n_chunks;
+    rblocks += (int)(((long long)jobs[i].n * jobs[i].n + 255) / 256);
+  }
+  g.start[count] = blocks;
+  g.rstart[count] = rblocks;
+  hipLaunchKernelGGL(k_gram<MODE>, dim3((unsigned)blocks), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_gram_reduce<MODE>, dim3((unsigned)rblocks), dim3(256), 0, s, g);
+}
+
+template <int MODE>
 static void launch_gram(const double* a, const void* b, int n, long long nr, double alpha,
                         bool sym, double* part, double* c, hipStream_t s) {
-  const GemmShape g = gemm_shape<MODE>(n, nr, sym);
-  hipLaunchKernelGGL(k_gram<MODE>, dim3((unsigned)(g.n_tiles * g.n_chunks)), dim3(256), 0, s, a,
-                     b, n, nr, g.chunk_len, g.n_chunks, g.tiles_m, g.tiles_n, g.n_tiles,
-                     sym ? 1 : 0, part);
-  const long long total = (long long)n * n;
-  hipLaunchKernelGGL(k_gram_reduce<MODE>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     part, n, g.n_chunks, g.tiles_m, g.tiles_n, sym ? 1 : 0, alpha, c);
+  const GramJob j = gram_job<MODE>(a, b, n, nr, alpha, sym, part, c);
+  launch_gram_group<MODE>(&j, 1, s);
 }
 
 size_t gemm_partial_bytes(int n_orb, long long nr) {
@@ -361,6 +441,15 @@ void launch_xtx_f64(const double* a, const double* b, int n, long long nr, doubl
 void launch_xtx_abs(const double* a, int n, long long nr, double alpha, double* part, double* c,
                     hipStream_t s) {
   launch_gram<2>(a, a, n, nr, alpha, true, part, c, s);
+}
+
+void launch_gram_self_group(const double* const* a, const int* n, const long long* nr,
+                            const double* alpha, double* const* part, double* const* c,
+                            int count, hipStream_t s) {
+  GramJob jobs[kMaxGroup];
+  for (int i = 0; i < count; ++i)
+    jobs[i] = gram_job<0>(a[i], a[i], n[i], nr[i], alpha[i], true, part[i], c[i]);
+  launch_gram_group<0>(jobs, count, s);
 }
 
 }  // namespace hfx

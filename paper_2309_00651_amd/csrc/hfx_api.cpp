@@ -135,7 +135,9 @@ struct hfx_plan_t {
   bool capturing = false;
   bool quiet = false;  // no profiling events (a call that must not create any)
   bool check = false;  // check the orbitals before each exchange call (option check=1)
-  bool group = true;   // systems of one size class share launches (option group=0: not)
+  // systems of one size class share launches: 1 always, 0 never, -1 (the
+  // default) for systems whose own launches are small (see size_classes)
+  int group = -1;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   // multi-system plans: one side stream per system (default priority) and
@@ -527,12 +529,70 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
   const int nc = (int)calls.size();
   std::vector<PassArgs> args(nc);
   size_t max_batches = 0;
+  // A class of several systems stages, takes the pair means of and zeroes
+  // all its members in one launch each (per-system launches on one stream
+  // would serialise many small launches); results are those of the
+  // per-system launches bit for bit.
+  const bool joint = nc > 1;
+  if (joint) {
+    double orbs = 0.0, mean_flops = 0.0;
+    for (const SysCall& c : calls) {
+      orbs += (double)c.sp->sys.n_orb * (double)c.sp->nr;
+      mean_flops += 2.0 * (double)c.sp->sys.n_orb * c.sp->sys.n_orb * (double)c.sp->nr;
+    }
+    if (plan->prec == HFX_FP32) {
+      std::vector<const double*> in(nc);
+      std::vector<float*> out(nc);
+      std::vector<size_t> cnt(nc);
+      std::vector<int> nn(nc);
+      std::vector<long long> nrr(nc);
+      std::vector<double> alpha(nc);
+      std::vector<double*> part(nc), mu(nc);
+      for (int c = 0; c < nc; ++c) {
+        SystemPlan& sp = *calls[c].sp;
+        in[c] = calls[c].psi;
+        out[c] = reinterpret_cast<float*>(ws + sp.off_psi32);
+        cnt[c] = (size_t)sp.sys.n_orb * sp.nr;
+        nn[c] = sp.sys.n_orb;
+        nrr[c] = sp.nr;
+        alpha[c] = 1.0 / (double)sp.nr;
+        part[c] = reinterpret_cast<double*>(ws + sp.off_gemm);
+        mu[c] = reinterpret_cast<double*>(ws + sp.off_mean);
+      }
+      {
+        Bracket br(plan, HFX_PASS_STAGE, st);
+        launch_cast_group(in.data(), out.data(), cnt.data(), nc, st);
+        br.done(orbs * 12.0, 0.0);
+      }
+      Bracket br(plan, HFX_PASS_CONTRACT, st);
+      launch_gram_self_group(in.data(), nn.data(), nrr.data(), alpha.data(), part.data(),
+                             mu.data(), nc, st);
+      for (int c = 0; c < nc; ++c)
+        if (calls[c].sp->d_keep)
+          launch_mask(mu[c], calls[c].sp->d_keep,
+                      (size_t)calls[c].sp->sys.n_orb * calls[c].sp->sys.n_orb, st);
+      br.done(orbs * 8.0, mean_flops);
+    }
+    if (acc) {
+      std::vector<void*> dst(nc);
+      std::vector<size_t> bytes(nc);
+      for (int c = 0; c < nc; ++c) {
+        dst[c] = calls[c].kpsi;
+        bytes[c] = (size_t)calls[c].sp->sys.n_orb * calls[c].sp->nr * elem;
+      }
+      Bracket br(plan, HFX_PASS_ZERO, st);
+      launch_zero_group(dst.data(), bytes.data(), nc, st);
+      br.done(orbs * elem, 0.0);
+    }
+  }
   for (int c = 0; c < nc; ++c) {
     SystemPlan& sp = *calls[c].sp;
     const double* psi = calls[c].psi;
     const void* psi_w = psi;
     const double orb_pts = (double)sp.sys.n_orb * (double)sp.nr;
-    if (plan->prec == HFX_FP32) {
+    if (joint) {
+      psi_w = plan->prec == HFX_FP32 ? static_cast<const void*>(ws + sp.off_psi32) : psi;
+    } else if (plan->prec == HFX_FP32) {
       float* p32 = reinterpret_cast<float*>(ws + sp.off_psi32);
       Bracket br(plan, HFX_PASS_STAGE, st);
       launch_cast_f64_f32(psi, p32, (size_t)sp.sys.n_orb * sp.nr, st);
@@ -544,7 +604,9 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
     // coefficient out of the float32 FFTs; v(0) mu_ab is added back to the
     // potentials and v(0) Omega mu_ab^2 to the energy in float64.
     const double* mean = nullptr;
-    if (plan->prec == HFX_FP32) {
+    if (joint) {
+      if (plan->prec == HFX_FP32) mean = reinterpret_cast<double*>(ws + sp.off_mean);
+    } else if (plan->prec == HFX_FP32) {
       double* mu = reinterpret_cast<double*>(ws + sp.off_mean);
       double* part = reinterpret_cast<double*>(ws + sp.off_gemm);
       Bracket br(plan, HFX_PASS_CONTRACT, st);
@@ -554,7 +616,7 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
       br.done(orb_pts * 8.0, 2.0 * (double)sp.sys.n_orb * orb_pts);
       mean = mu;
     }
-    if (acc) {
+    if (acc && !joint) {
       Bracket br(plan, HFX_PASS_ZERO, st);
       launch_zero(calls[c].kpsi, (size_t)sp.sys.n_orb * sp.nr * elem, st);
       br.done(orb_pts * elem, 0.0);
@@ -713,21 +775,43 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
   return HFX_OK;
 }
 
+// Largest pair_fwd launch of a system's schedule, in workgroups.
+long long largest_launch(const SystemPlan& sp) {
+  long long m = 0;
+  for (const Batch& b : sp.batches) m = std::max<long long>(m, b.n_tiles);
+  return m * bricks_per_tile(sp.var);
+}
+
+// Systems whose pass launches stay below this many workgroups (two per
+// compute unit) join size classes by default: their own launches leave the
+// device partly idle and the per-launch costs dominate.  Larger systems do
+// better as separate launch sequences on forked streams, where different
+// passes of different systems overlap (measured on one MI355X: 16 systems
+// of 8-23 orbitals on 24^3, 0.70 ms shared against 1.26 ms forked; 8 of
+// 32 orbitals on 96^3, 15.7 against 15.2 ms).
+constexpr long long kGroupBelowWorkgroups = 512;
+
 // The size classes of a plan's systems for the exchange calls: systems with
 // the same kernel configuration, band and screening state share launches
-// (at most kMaxGroup per class); a system with two batch streams, or a plan
-// created with group=0, is a class of its own.  Classes keep the plan order
-// of their first system.
+// (at most kMaxGroup per class).  A system with two batch streams, one of a
+// plan created with group=0, or (by default) one whose own launches are
+// large, is a class of its own; group=1 groups every system it can.
+// Classes keep the plan order of their first system.
 std::vector<std::vector<int>> size_classes(hfx_plan plan) {
   std::vector<std::vector<int>> out;
   for (int i = 0; i < (int)plan->sys.size(); ++i) {
     const SystemPlan& sp = plan->sys[i];
     bool placed = false;
-    if (plan->group && sp.nstreams == 1 && !sp.var->persistent)
+    const bool groupable =
+        plan->group == 1 || (plan->group < 0 && largest_launch(sp) < kGroupBelowWorkgroups);
+    if (groupable && sp.nstreams == 1 && !sp.var->persistent)
       for (auto& c : out) {
         const SystemPlan& f = plan->sys[c[0]];
-        if ((int)c.size() < kMaxGroup && f.var == sp.var && f.kz_max == sp.kz_max &&
-            (f.d_keep != nullptr) == (sp.d_keep != nullptr) && f.nstreams == 1) {
+        const bool fg =
+            plan->group == 1 || (plan->group < 0 && largest_launch(f) < kGroupBelowWorkgroups);
+        if ((int)c.size() < kMaxGroup && fg && f.var == sp.var && f.kz_max == sp.kz_max &&
+            (f.d_keep != nullptr) == (sp.d_keep != nullptr) && f.nstreams == 1 &&
+            !f.var->persistent) {
           c.push_back(i);
           placed = true;
           break;
@@ -1033,8 +1117,9 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     return fail(HFX_EINVAL, "maxws= takes a non-negative integer (bytes)");
   if (!parse_option(options, "streams", 1, &batch_streams))
     return fail(HFX_EINVAL, "streams= must be 1 or 2");
-  long long group_opt = 1;
-  if (!parse_option(options, "group", 1, &group_opt) || group_opt > 1)
+  long long group_opt = -1;
+  if (has_option(options, "group") &&
+      (!parse_option(options, "group", -1, &group_opt) || group_opt > 1))
     return fail(HFX_EINVAL, "group= takes 0 or 1");
   long long check_opt = 0;
   if (!parse_option(options, "check", 0, &check_opt) || check_opt > 1)
@@ -1148,7 +1233,7 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
   hfx_plan p = new hfx_plan_t();
   p->prec = precision;
   p->check = check_opt == 1;
-  p->group = group_opt == 1;
+  p->group = (int)group_opt;
   p->sys.resize(n_sys);
   size_t off = 0;
   long long psi_off = 0, m_off = 0, orb_off = 0;
@@ -1222,6 +1307,9 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
 
   auto cleanup = [&](hfx_status s) {
     for (auto& sp : p->sys) free_system(sp);
+    for (auto& st : p->side) (void)hipStreamDestroy(st);
+    for (auto& ev : p->join) (void)hipEventDestroy(ev);
+    if (p->fork) (void)hipEventDestroy(p->fork);
     delete p;
     return s;
   };

@@ -166,6 +166,12 @@ void launch_scale_to_f64(const void* src, int src_is_f64, double* dst, size_t n,
 void launch_energy_reduce(const double* partials, long long n, double scale, const double* mean,
                           int n_orb, double dc_scale, double* out, hipStream_t s);
 
+// The same for the count <= kMaxGroup systems of a size class in one launch
+// each: out[i] <- in[i] (n[i] values), p[i] zeroed (bytes[i] bytes).
+void launch_cast_group(const double* const* in, float* const* out, const size_t* n, int count,
+                       hipStream_t s);
+void launch_zero_group(void* const* p, const size_t* bytes, int count, hipStream_t s);
+
 // Input check (exchange_common.hip): per (orbital, y row, 32-column chunk)
 // three doubles: non-finite count, sum psi^2, power of the z spectrum beyond
 // |m_z| <= m_max (m_max < 0: not computed).  check_partials() triples of
@@ -187,6 +193,12 @@ void launch_xtx_f64(const double* a, const double* b, int n_orb, long long nr, d
 void launch_xtx_abs(const double* a, int n_orb, long long nr, double alpha, double* partial,
                     double* c, hipStream_t s);
 size_t gemm_partial_bytes(int n_orb, long long nr);
+// C_i = alpha_i A_i A_i^T (float64 MFMA, symmetric) for count <= kMaxGroup
+// products in one launch of the product and one of the reduction; each
+// result equals launch_xtx_f64's for the same arguments bit for bit.
+void launch_gram_self_group(const double* const* a, const int* n, const long long* nr,
+                            const double* alpha, double* const* part, double* const* c,
+                            int count, hipStream_t s);
 
 // Orthonormalisation helpers (ortho.hip)
 hipError_t launch_inverse_sqrt(double* s, int n, double* work, int max_iter, hipStream_t st);

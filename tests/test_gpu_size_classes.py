@@ -1,7 +1,10 @@
 """Size classes of a batched plan: systems with the same kernel configuration
 (grid, precision), band and screening state share one launch per pass and
 batch step (a table of the systems' pass arguments in the launch), up to
-eight per class; other systems run as their own class on a forked stream.
+eight per class, with one staging, pair-mean and zero-fill launch for the
+class; other systems run as their own class on a forked stream.  By default
+only systems with small launches (below 512 workgroups) are grouped; group=1
+groups every system it can, group=0 none.
 
 Checked: the class layout that hfx_plan_describe reports; K psi, E_x, the
 gradient and M of a plan whose classes hold several systems, bitwise equal
@@ -48,12 +51,14 @@ def test_grouped_plan_equals_ungrouped_and_single_plans(prec):
     flat = torch.from_numpy(np.concatenate([p.reshape(-1) for p in psis])).to(dev)
     grouped = hfx.Plan(specs, prec, device=dev)
     plain = hfx.Plan(specs, prec, options="group=0", device=dev)
+    forced = hfx.Plan(specs, prec, options="group=1", device=dev)
+    assert "class=0/4" in forced.describe(0) and "class=1/1" in forced.describe(2)
     d = [grouped.describe(i) for i in range(len(specs))]
     print("\n".join(d), flush=True)
     assert all("class=0/4" in d[i] for i in (0, 1, 3, 4)) and "class=1/1" in d[2]
     assert all("/1" in plain.describe(i).split("class=")[1] for i in range(len(specs)))
     out = {}
-    for name, plan in (("grouped", grouped), ("plain", plain)):
+    for name, plan in (("grouped", grouped), ("plain", plain), ("forced", forced)):
         k, e = plan.apply_exchange(flat)
         m = plan.exchange_matrix(flat, k)
         g = plan.exchange_gradient(flat)
@@ -63,8 +68,8 @@ def test_grouped_plan_equals_ungrouped_and_single_plans(prec):
         plan.exchange_matrix(flat, m=m2, ex=e3)
         torch.cuda.synchronize()
         out[name] = (k.clone(), e.clone(), m.clone(), g.clone(), e2.clone(), m2, e3)
-    for a, b in zip(out["grouped"], out["plain"]):
-        assert torch.equal(a, b)
+    for a, b, c in zip(out["grouped"], out["plain"], out["forced"]):
+        assert torch.equal(a, b) and torch.equal(a, c)
     k, e, m, g, e2, m2, e3 = out["grouped"]
     assert torch.equal(e2, e) and torch.equal(e3, e) and torch.equal(m2, m)
     for i, (spec, psi) in enumerate(zip(specs, psis)):
@@ -122,7 +127,7 @@ def test_screened_class_equals_screened_single_plans():
     psis = [generate.gaussians((n,) * 3, box, no, 20.0, 320 + no)[0] for no in (24, 17)]
     specs = [hfx.SystemSpec(n, box, p.shape[0], hfx.ERFC, 0.106) for p in psis]
     flat = torch.from_numpy(np.concatenate([p.reshape(-1) for p in psis])).to(dev)
-    plan = hfx.Plan(specs, hfx.FP32, device=dev)
+    plan = hfx.Plan(specs, hfx.FP32, options="group=1", device=dev)
     kept = plan.screen(flat, 2.5e-2)
     assert "screened=yes" in plan.describe(0) and "class=0/2" in plan.describe(1)
     k, e = plan.apply_exchange(flat)
