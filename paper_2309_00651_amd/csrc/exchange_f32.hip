@@ -44,11 +44,48 @@ using P96sw = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, S
 using P96pi = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
                             Sched<12, 8>, Sched<8, 12>, Sched<12, 8>, false, 512, 512, true, true,
                             true>;
+// Grids whose fused plane fills a compute unit's LDS (108 to 128): one plane
+// workgroup per compute unit.  Defaults: flat-load prefetching accumulation
+// (inv_acc loads spread over all threads, staged in LDS), and at 108 and 120
+// the persistent plane kernel that prefetches the next plane (at 120 with
+// radix-15 first stages, which keep its registers within the budget).
+// Alternatives: the earlier defaults (-lp: psi J block in LDS + prefetch;
+// -r: registers, no prefetch), the persistent plane kernel at 128 (-pp,
+// slower there: measured 742 against 711 ms per K psi at 128^3 / 512
+// orbitals), and flat loads with the non-persistent plane (-fl).
 using P108 = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
-                           Sched<9, 12>, Sched<12, 9>, Sched<9, 12>>;
+                           Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, false, true,
+                           false, true, 108, true>;
+using P108lp = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
+                             Sched<9, 12>, Sched<12, 9>, Sched<9, 12>>;
 using P108r = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
                             Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, false,
                             false>;
+using P108fl = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
+                             Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, false, true,
+                             false, false, 108, true>;
+using P120 = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<15, 8>,
+                           Sched<8, 15>, Sched<15, 8>, Sched<8, 15>, false, 256, 1024, false, true,
+                           false, true, 120, true>;
+using P120r = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
+                            Sched<12, 10>, Sched<10, 12>, Sched<12, 10>>;
+using P120lp = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
+                             Sched<12, 10>, Sched<10, 12>, Sched<12, 10>, false, 256, 1024, true,
+                             true>;
+using P120fl = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
+                             Sched<12, 10>, Sched<10, 12>, Sched<12, 10>, false, 256, 1024, false,
+                             true, false, false, 120, true>;
+using P128 = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
+                           Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, false, true,
+                           false, false, 128, true>;
+using P128r = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
+                            Sched<16, 8>, Sched<8, 16>, Sched<16, 8>>;
+using P128lp = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
+                             Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, true,
+                             true>;
+using P128pp = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
+                             Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, false,
+                             false, false, true>;
 // slab cells (n x n x nz): z transforms of length nz, planes of n x n
 using P24x48 = FusedPipeline<float, 24, 16, 8, Sched<4, 12>, Sched<12, 4>, 144, Sched<4, 6>,
                              Sched<6, 4>, Sched<4, 6>, Sched<6, 4>, false, 256, 512, true, true,
@@ -56,20 +93,6 @@ using P24x48 = FusedPipeline<float, 24, 16, 8, Sched<4, 12>, Sched<12, 4>, 144, 
 using P64x128 = FusedPipeline<float, 64, 16, 8, Sched<8, 16>, Sched<16, 8>, 256, Sched<8, 8>,
                               Sched<8, 8>, Sched<8, 8>, Sched<8, 8>, false, 256, 1024, false, false,
                               false, false, 128>;
-// persistent prefetching plane kernel (one plane per compute unit fits)
-using P128pp = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
-                             Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, false,
-                             false, false, true>;
-using P120 = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
-                           Sched<12, 10>, Sched<10, 12>, Sched<12, 10>>;
-using P120lp = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
-                             Sched<12, 10>, Sched<10, 12>, Sched<12, 10>, false, 256, 1024, true,
-                             true>;
-using P128 = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
-                           Sched<16, 8>, Sched<8, 16>, Sched<16, 8>>;
-using P128lp = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
-                             Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, true,
-                             true>;
 }  // namespace
 
 const Variant* variants_f32(int* count) {
@@ -91,10 +114,15 @@ const Variant* variants_f32(int* count) {
       P96sw::describe("f32-n96-sw"),
       P96pi::describe("f32-n96-pi"),
       P108::describe("f32-n108"),
+      P108lp::describe("f32-n108-lp"),
       P108r::describe("f32-n108-r"),
+      P108fl::describe("f32-n108-fl"),
       P120::describe("f32-n120"),
+      P120r::describe("f32-n120-r"),
       P120lp::describe("f32-n120-lp"),
+      P120fl::describe("f32-n120-fl"),
       P128::describe("f32-n128"),
+      P128r::describe("f32-n128-r"),
       P128lp::describe("f32-n128-lp"),
       P128pp::describe("f32-n128-pp"),
       P24x48::describe("f32-n24x48"),

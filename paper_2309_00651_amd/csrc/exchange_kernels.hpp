@@ -324,8 +324,15 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
 // every load stays unconditional; KZ = 2 (many planes pruned): pruned legs are
 // not loaded at all (the compiler branches around them, and whole waves skip
 // the legs of fully pruned frequency blocks).
+// FL (flat loads, with PF): a grid pair's brick is loaded by all threads in
+// its natural [z][2W] order (neighbouring threads on neighbouring x), a few
+// elements each, and written to LDS before the transform, which then starts
+// from LDS.  The prefetch of the next grid pair then holds NZ * 2W / NT values
+// per thread instead of the first stage's legs, which for large radices sit
+// in a quarter of the threads (a radix-16 first stage over 32 columns of 128
+// points is 256 butterflies) and cost 16 complex registers each.
 template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC, bool PJL, bool PF,
-          bool SCR, int NZ = N, int KZ = 0>
+          bool SCR, int NZ = N, int KZ = 0, bool FL = false>
 __global__ void __launch_bounds__(NT)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_inv_acc(PassGroup grp) {
   int sys_ = 0;
@@ -389,6 +396,23 @@ __global__ void __launch_bounds__(NT)
     vA[k] = p < P && (x0 + m) < N;
     offA[k] = vA[k] ? (z * N + y) * N + x0 + m : 0;
     ldsA[k] = z * W2 + m;
+  }
+
+  // FL: element e = tid + k NT of the brick, e = z 2W + c (c: column of the
+  // grid pair, grid c / W, x = x0 + c mod W) -- the LDS index of the engine
+  constexpr int FE = NZ * W2;
+  constexpr int FLV = FL ? (FE + NT - 1) / NT : 1;
+  int offFL[FLV];
+  bool vFL[FLV], gFL[FLV], kzFL[FLV];
+#pragma unroll
+  for (int k = 0; k < FLV; ++k) {
+    const int e = tid + k * NT;
+    const int z = e / W2, c = e - (e / W2) * W2;
+    const int g = c / W, m = c - (c / W) * W;
+    vFL[k] = FL && e < FE && x0 + m < N;
+    gFL[k] = g != 0;
+    offFL[k] = vFL[k] ? (z * N + y) * N + x0 + m : 0;
+    kzFL[k] = KZ == 0 || kz_kept(z < NZ ? z : 0, NZ, a.kz_max);
   }
 
   T pjr[PJL ? 1 : TT][PT];
@@ -481,6 +505,27 @@ __global__ void __launch_bounds__(NT)
       }
     }
   };
+  // FL: the grid pair's brick in flat order (same dummy and zero-block rules)
+  auto load_flat = [&](int ia, int bq, cpx<T>* v) {
+    bool u0, u1;
+    uses(ia, bq, u0, u1);
+    const int slot0 = td.slot0 + ia * (TT / 2) + 2 * bq;
+    const cpx<T>* dummy = grids + (long long)td.slot0 * NR;
+#pragma unroll
+    for (int k = 0; k < FLV; ++k) {
+      const bool ok = vFL[k] && (gFL[k] ? u1 : u0);
+      const cpx<T>* g = ok ? grids + (long long)(slot0 + (gFL[k] ? 1 : 0)) * NR + offFL[k] : dummy;
+      if constexpr (KZ == 1) {
+        const cpx<T>* zero = static_cast<const cpx<T>*>(a.zero) + tid;
+        v[k] = *(kzFL[k] ? g : zero);
+      } else if constexpr (KZ == 2) {
+        const cpx<T> val = *(ok && kzFL[k] ? g : dummy);
+        v[k] = kzFL[k] ? val : cpx<T>{T(0), T(0)};
+      } else {
+        v[k] = *g;
+      }
+    }
+  };
   // psi and old K psi of orbital a at the thread's points (offA = 0 off the grid)
   auto load_orbital = [&](int ia, T* p, T* ko) {
     const int oa = orb_at<SCR>(a, td.i0 + ia);
@@ -500,7 +545,15 @@ __global__ void __launch_bounds__(NT)
     if (!use0 && !use1) return;
     {
       cpx<T> out[LastStage<G, SZI>::VALS];
-      E::reg2reg(v, lds, tw, tid, out);
+      if constexpr (FL) {
+#pragma unroll
+        for (int k = 0; k < FLV; ++k)
+          if (FE % NT == 0 || tid + k * NT < FE) lds[tid + k * NT] = v[k];
+        __syncthreads();
+        E::lds2reg(lds, tw, tid, out);
+      } else {
+        E::reg2reg(v, lds, tw, tid, out);
+      }
       E::store_last(out, lds, tid);
     }
     __syncthreads();
@@ -549,11 +602,16 @@ __global__ void __launch_bounds__(NT)
     }
   };
   if constexpr (PF) {
-    cpx<T> vc[F::VALS], vn[F::VALS];
+    constexpr int PV = FL ? FLV : F::VALS;
+    cpx<T> vc[PV], vn[PV];
+    auto load_next = [&](int ia, int bq, cpx<T>* v) {
+      if constexpr (FL) load_flat(ia, bq, v);
+      else load_pair(ia, bq, v);
+    };
     const int ia0 = next_live_row<SCR>(rows, -1, td.nI);
     if (ia0 < td.nI) {
       load_orbital(ia0, pa, kold);
-      load_pair(ia0, 0, vc);
+      load_next(ia0, 0, vc);
     }
     for (int ia = ia0; ia < td.nI;) {
       const int nx = next_live_row<SCR>(rows, ia, td.nI);
@@ -563,14 +621,14 @@ __global__ void __launch_bounds__(NT)
         constexpr int q = decltype(bq)::value;
         // next step's loads go out before this step's transform
         if constexpr (q + 1 < QB) {
-          load_pair(ia, q + 1, vn);
+          load_next(ia, q + 1, vn);
         } else if (nx < td.nI) {
           load_orbital(nx, pa_n, kold_n);
-          load_pair(nx, 0, vn);
+          load_next(nx, 0, vn);
         }
         process(bq, ia, vc);
 #pragma unroll
-        for (int e = 0; e < F::VALS; ++e) vc[e] = vn[e];
+        for (int e = 0; e < PV; ++e) vc[e] = vn[e];
       });
       store_orbital(ia);
 #pragma unroll
@@ -581,6 +639,7 @@ __global__ void __launch_bounds__(NT)
       ia = nx;
     }
   } else {
+    static_assert(!FL, "flat loads are a form of the prefetching loop");
     for (int ia = next_live_row<SCR>(rows, -1, td.nI); ia < td.nI;
          ia = next_live_row<SCR>(rows, ia, td.nI)) {
       load_orbital(ia, pa, kold);
@@ -643,13 +702,18 @@ constexpr int plane_waves_per_eu() {
   return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
+// The v(G) factors of a plane are loaded into registers when the plane starts
+// (after its rows), so the multiply between the y transforms never waits for
+// them: a load issued behind the barriers of the forward transforms would
+// stall every wave of the workgroup at once.
 // PP (persistent, prefetching): for planes that leave room for one plane per
 // compute unit, a workgroup per compute unit walks the planes of the launch
 // (L, L + grid, ...) with the twiddles staged once, and issues the HBM loads
-// of its next plane before the inverse x transform of the current one, so
-// they are in flight during that transform and the stores of the current
-// plane.  The v(G) loads come first, so waiting for them never waits for the
-// prefetch (one in-order counter tracks the loads).
+// of its next plane's rows as soon as the forward x transform of the current
+// one has consumed its input registers, so they are in flight during the y
+// transforms, the multiply and the inverse x transform.  The v(G) loads of a
+// plane are issued before that prefetch, so waiting for them never waits for
+// it (one in-order counter tracks the loads).
 // QB > 0 (band-limited plans whose pair densities vanish for |kx| > QB):
 // the forward x transform stores zeros in the columns beyond the band and
 // the y transforms, the multiply and the inverse y transforms run on the
@@ -701,36 +765,58 @@ k_plane_conv(PassGroup grp) {
     return gbase + (long long)a.active[ai] * NR + (long long)kz * N * N;
   };
   // x-forward stage-0 inputs straight from HBM (rows, x contiguous)
-  auto load_rows = [&](const cpx<T>* __restrict__ base, cpx<T>* v) {
+  auto load_rows = [&](const cpx<T>* __restrict__ base, cpx<T>* v, int t) {
 #pragma unroll
     for (int i = 0; i < FX::PER; ++i) {
-      if (!FX::valid(tid, i)) continue;
+      if (!FX::valid(t, i)) continue;
       int m, j;
-      FX::mj(tid, i, m, j);
+      FX::mj(t, i, m, j);
 #pragma unroll
       for (int r = 0; r < SchedInfo<SXF>::first; ++r)
         v[i * SchedInfo<SXF>::first + r] = base[m * N + FX::in_pos(j, r)];
     }
   };
-  cpx<T> v[FX::VALS];
-  int L = lg;
-  load_rows(plane_base(L), v);
-  while (true) {
-    cpx<T>* __restrict__ base = plane_base(L);
+  // v(G) / N_r at the thread's multiply points of plane L
+  auto load_v = [&](int L, T* f, int t) {
     const T* __restrict__ vt =
         static_cast<const T*>(a.vtab) + (long long)kz_of_plane(L / a.n_active, NZ, a.kz_max) * N * N;
+#pragma unroll
+    for (int i = 0; i < LY::PER; ++i) {
+      int m = 0, j = 0;
+      LY::mj(t, i, m, j);
+      const bool ok = LY::valid(t, i);
+#pragma unroll
+      for (int r = 0; r < SchedInfo<SYF>::last; ++r)
+        f[i * SchedInfo<SYF>::last + r] = vt[ok ? LY::in_pos(j, r) * N + (QB ? GY::band_col(m) : m) : 0];
+    }
+  };
+  cpx<T> v[FX::VALS];
+  T vf[LY::VALS];
+  int L = lg;
+  load_rows(plane_base(L), v, tid);
+  while (true) {
+    // persistent form: the thread index is made opaque once per plane, so the
+    // compiler recomputes the (cheap) LDS and HBM offsets instead of keeping
+    // every one of them live across the loop
+    int t = tid;
+    if constexpr (PP) asm volatile("" : "+v"(t));
+    cpx<T>* __restrict__ base = plane_base(L);
+    load_v(L, vf, t);
+    const int next = PP ? L + (int)gridDim.x : total;
     {
       cpx<T> o[LXF::VALS];
-      EXF::reg2reg(v, plane, twxf, tid, o);
+      EXF::reg2reg(v, plane, twxf, t, o);
+      // the row registers are free: the next plane's rows go out now
+      if (PP && next < total) load_rows(plane_base(next), v, t);
       if constexpr (QB == 0) {
-        EXF::store_last(o, plane, tid);
+        EXF::store_last(o, plane, t);
       } else {
         // columns beyond the band hold rounding noise only: store zeros
 #pragma unroll
         for (int i = 0; i < LXF::PER; ++i) {
-          if (!LXF::valid(tid, i)) continue;
+          if (!LXF::valid(t, i)) continue;
           int m, j;
-          LXF::mj(tid, i, m, j);
+          LXF::mj(t, i, m, j);
 #pragma unroll
           for (int r = 0; r < SchedInfo<SXF>::last; ++r) {
             const int x = LXF::out_pos(j, r);
@@ -743,34 +829,29 @@ k_plane_conv(PassGroup grp) {
     __syncthreads();
     // y forward, multiply by v(G)/N_r, y inverse (hand-over in registers)
     cpx<T> oy[LY::VALS];
-    EYF::lds2reg(plane, twyf, tid, oy);
+    EYF::lds2reg(plane, twyf, t, oy);
 #pragma unroll
     for (int i = 0; i < LY::PER; ++i) {
-      if (!LY::valid(tid, i)) continue;
-      int m, j;
-      LY::mj(tid, i, m, j);
+      if (!LY::valid(t, i)) continue;
 #pragma unroll
-      for (int r = 0; r < SchedInfo<SYF>::last; ++r) {
-        const T f = vt[LY::in_pos(j, r) * N + (QB ? GY::band_col(m) : m)];
-        oy[i * SchedInfo<SYF>::last + r] = cscale(oy[i * SchedInfo<SYF>::last + r], f);
-      }
+      for (int r = 0; r < SchedInfo<SYF>::last; ++r)
+        oy[i * SchedInfo<SYF>::last + r] =
+            cscale(oy[i * SchedInfo<SYF>::last + r], vf[i * SchedInfo<SYF>::last + r]);
     }
-    const int next = PP ? L + (int)gridDim.x : total;
     {
       cpx<T> o[LYI::VALS];
-      EYI::reg2reg(oy, plane, twyi, tid, o);
-      EYI::store_last(o, plane, tid);
+      EYI::reg2reg(oy, plane, twyi, t, o);
+      EYI::store_last(o, plane, t);
     }
     __syncthreads();
-    if (PP && next < total) load_rows(plane_base(next), v);
     // x inverse, results straight to HBM
     cpx<T> ox[LXI::VALS];
-    EXI::lds2reg(plane, twxi, tid, ox);
+    EXI::lds2reg(plane, twxi, t, ox);
 #pragma unroll
     for (int i = 0; i < LXI::PER; ++i) {
-      if (!LXI::valid(tid, i)) continue;
+      if (!LXI::valid(t, i)) continue;
       int m, j;
-      LXI::mj(tid, i, m, j);
+      LXI::mj(t, i, m, j);
 #pragma unroll
       for (int r = 0; r < SchedInfo<SXI>::last; ++r)
         base[m * N + LXI::in_pos(j, r)] = ox[i * SchedInfo<SXI>::last + r];
@@ -945,13 +1026,14 @@ template <typename T, int N, int W, int TT, class SZF, class SZI, int NTQ, class
           class SYF, class SYI, bool SW = false,
           int NTF = pencil_threads<T, N, W, true>(), int NTI = pencil_threads<T, N, W, false>(),
           bool PJL = pencil_prefetch<T, N, W>(), bool PF = pencil_prefetch<T, N, W>(),
-          bool PIL = false, bool PP = false, int NZ = N>
+          bool PIL = false, bool PP = false, int NZ = N, bool FLI = false>
 struct FusedPipeline {
+  static_assert(!FLI || PF, "flat loads are a form of the prefetching accumulation");
   static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
   // band of the plane kernel's column-pruned instantiation (float32 cubic
   // grids from 64 up to 120, plain layouts): |kx| <= N / 4, the band of
   // orbitals at half the grid's plane-wave reach (a twofold oversampled grid)
-  static constexpr int QB = (sizeof(T) == 4 && NZ == N && N >= 64 && N <= 120 && !SW && !PP)
+  static constexpr int QB = (sizeof(T) == 4 && NZ == N && N >= 64 && N <= 120 && !SW)
                                 ? N / 4 : 0;
   // persistent plane kernel: one workgroup per plane slot of the device
   static int plane_grid(int planes) {
@@ -998,18 +1080,18 @@ struct FusedPipeline {
     // 93 of 96 planes and at 29..57 of 64..120)
     const int kept = kz_planes(NZ, g.a[0].kz_max);
     if (kept == NZ) {
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 0>), dim3(nb),
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 0, FLI>), dim3(nb),
                          dim3(NTI), 0, s, g);
       return;
     }
     if constexpr (sizeof(T) == 4) {
       if (4 * kept >= 3 * NZ) {
-        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 1>), dim3(nb),
+        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 1, FLI>), dim3(nb),
                            dim3(NTI), 0, s, g);
         return;
       }
     }
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 2>), dim3(nb),
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 2, FLI>), dim3(nb),
                        dim3(NTI), 0, s, g);
   }
   template <bool ACC>

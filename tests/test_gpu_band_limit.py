@@ -132,3 +132,42 @@ def test_band_limited_screened_plan(n, L, n_orb, prec):
     print(f"  screened rel dE {rel:.2e} max dK {dk:.2e}", flush=True)
     e_bar, k_bar = bars(prec, ref["kpsi"])
     assert rel <= e_bar and dk <= k_bar
+
+
+_LARGE_REF = {}
+
+
+@pytest.mark.parametrize("n,L,ecut", [(108, 26.4, 5.0), (108, 26.4, 20.0), (120, 29.4, 5.0),
+                                      (120, 29.4, 20.0), (128, 29.6, 5.0), (128, 29.6, 20.0)])
+def test_band_limited_every_large_variant(n, L, ecut):
+    """Every float32 configuration of the grids whose plane fills the LDS
+    (108, 120, 128), band-limited: at 5 Ha about half the kz planes are kept
+    (pruned loads skipped, and band columns in the plane pass up to 120), at
+    20 Ha nearly all (pruned legs read the zero block).  Covers the
+    persistent plane kernels and the flat-load accumulation on pruned grids
+    against the oracle's full transform, with several rows per tile pair so
+    that the prefetching loop runs."""
+    n_orb = 6
+    shape, box = (n,) * 3, (L,) * 3
+    key = (n, ecut)
+    if key not in _LARGE_REF:
+        _LARGE_REF.clear()
+        psi = generate.random_pw(shape, box, n_orb, ecut, seed=7300 + n + int(ecut))
+        vg = oracle.coulomb_kernel(shape, box, hfx.TRUNCATED, 0.0)
+        _LARGE_REF[key] = (psi, oracle.exchange(psi, box, vg, workers=4))
+    psi, ref = _LARGE_REF[key]
+    dev = _dev()
+    pt = torch.from_numpy(psi).to(dev)
+    e_bar, k_bar = bars(hfx.FP32, ref["kpsi"])
+    for v in hfx.variants(n, hfx.FP32):
+        print(f"case ecut={ecut} grid {n}^3 variant={v}", flush=True)
+        plan = hfx.Plan(hfx.SystemSpec(n, box, n_orb), hfx.FP32, options=f"ecut={ecut};variant={v}",
+                        device=dev)
+        assert "kz_max" in plan.describe()
+        kpsi, ex = plan.apply_exchange(pt)
+        torch.cuda.synchronize()
+        rel = abs(float(ex[0]) - ref["ex"]) / abs(ref["ex"])
+        dk = np.max(np.abs(kpsi.double().cpu().numpy() - ref["kpsi"]))
+        print(f"  rel dE {rel:.2e} max dK {dk:.2e}", flush=True)
+        assert rel <= e_bar and dk <= k_bar
+        del plan
