@@ -139,6 +139,21 @@ __device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const Til
   }
 }
 
+// Radix schedules of the half-length forward z transform (length L = NZ / 2)
+// of band-limited plans; void where none is compiled.  At 60 the 12 x 5 split
+// keeps every thread of a 256-thread workgroup busy in both stages (4 x 15
+// leaves half of them idle in the radix-15 stage: 103.6 against 93.5 ms per
+// K psi pass at 120^3 / 384 orbitals; 5 x 12 97.7, 6 x 10 95.9).
+template <int L> struct HalfZ { using type = void; };
+template <> struct HalfZ<24> { using type = Sched<4, 6>; };
+template <> struct HalfZ<32> { using type = Sched<4, 8>; };
+template <> struct HalfZ<36> { using type = Sched<4, 9>; };
+template <> struct HalfZ<40> { using type = Sched<4, 10>; };
+template <> struct HalfZ<48> { using type = Sched<4, 12>; };
+template <> struct HalfZ<54> { using type = Sched<6, 9>; };
+template <> struct HalfZ<60> { using type = Sched<12, 5>; };
+template <> struct HalfZ<64> { using type = Sched<8, 8>; };
+
 // ---------------------------------------------------------------------------
 // Pass 1: pair product + forward z FFT on bricks.
 // Two pair grids are transformed together: LDS holds [z][2W] with the brick
@@ -152,25 +167,36 @@ __device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const Til
 // stores, so a later load would wait for them).  Without PIL, psi_a is loaded
 // per orbital.
 // N: grid points along x and y; NZ: along z (slab cells: NZ != N).
-template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL, bool SCR, int NZ = N>
+// HZ (band-limited plans with 2 kz_max + 1 <= NZ / 2): the pair densities,
+// whose z spectrum lies in |kz| <= kz_max, are sampled exactly by the even z
+// points, so the forward z transform runs at length NZ / 2 on those (half the
+// orbital reads and half the transform work).  For such data the half-length
+// sum over even points is half the full-length sum at every kept frequency;
+// the products are doubled (exact) and half-length frequency k maps to grid
+// plane k (k <= kz_max) or k + NZ / 2 (k >= NZ / 2 - kz_max).
+template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL, bool SCR, int NZ = N,
+          bool HZ = false, class SZH = typename HalfZ<NZ / 2>::type>
 __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   int sys_ = 0;
   const int lg_ = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
   const PassArgs& a = grp.a[sys_];
   static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
   constexpr int W2 = 2 * W;
-  using G = Geom<T, NZ, W2, NT, true, W2, 1>;
-  using L = LastStage<G, SZF>;
-  using E = FFT<G, false, SZF>;
-  constexpr int RL = SchedInfo<SZF>::last;
+  constexpr int ZL = HZ ? NZ / 2 : NZ;  // transform length
+  using SZ = std::conditional_t<HZ, SZH, SZF>;
+  using G = Geom<T, ZL, W2, NT, true, W2, 1>;
+  using L = LastStage<G, SZ>;
+  using E = FFT<G, false, SZ>;
+  constexpr int RL = SchedInfo<SZ>::last;
   constexpr int NXB = (N + W - 1) / W;
   constexpr int BR = N * NXB;
-  constexpr int P = NZ * W;
+  constexpr int P = ZL * W;
   constexpr int PT = (P + NT - 1) / NT;
   constexpr long long NR = (long long)NZ * N * N;
-  constexpr int ZSL = (NZ / RL) * N * N;  // offset between legs of a last-stage butterfly
-  __shared__ cpx<T> lds[NZ * W2];
-  __shared__ TwEntry<T> twl[tw_slots<T, SZF>()];
+  constexpr int ZSL = (ZL / RL) * N * N;  // offset between legs of a last-stage butterfly
+  constexpr int ZS = HZ ? 2 : 1;         // z stride of the product points
+  __shared__ cpx<T> lds[ZL * W2];
+  __shared__ TwEntry<T> twl[tw_slots<T, SZ>()];
   __shared__ T mul[kMaxRows * TT];  // pair-density means of the tile, [a][b]
   __shared__ T pil[PIL ? TT * PT * NT : 1];  // psi of the I block, [a][k][tid]
   const int tid = threadIdx.x;
@@ -179,7 +205,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   const int y = br / NXB, x0 = (br - y * NXB) * W;
   const TileDesc td = a.tiles[t];
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
-  stage_twiddles<T, SZF, NT>(twl, a.tw_zf, tid);
+  stage_twiddles<T, SZ, NT>(twl, HZ ? a.tw_zh : a.tw_zf, tid);
   stage_means<T, TT, NT, SCR>(mul, a, td, 1.0, tid);
   const TwEntry<T>* tw = twl;
   cpx<T>* __restrict__ grids = static_cast<cpx<T>*>(a.grids);
@@ -191,12 +217,13 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
     const int p = tid + k * NT;
     const int z = p / W, m = p - (p / W) * W;
     vA[k] = p < P && (x0 + m) < N;
-    offA[k] = vA[k] ? (z * N + y) * N + x0 + m : 0;
+    offA[k] = vA[k] ? (ZS * z * N + y) * N + x0 + m : 0;
     ldsA[k] = z * W2 + m;
   }
   int offL[L::PER], gL[L::PER];
   bool vL[L::PER];
-  unsigned kzL[L::PER];  // bit r: leg r (frequency j + r NZ / RL) lies on a kept kz plane
+  unsigned kzL[L::PER];  // bit r: leg r (frequency j + r ZL / RL) lies on a kept kz plane
+  unsigned hiL[L::PER];  // HZ, bit r: leg r is a negative frequency (grid plane + NZ / 2)
 #pragma unroll
   for (int i = 0; i < L::PER; ++i) {
     int m = 0, j = 0;
@@ -206,8 +233,13 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
     vL[i] = L::valid(tid, i) && (x0 + mx) < N;
     offL[i] = vL[i] ? (j * N + y) * N + x0 + mx : 0;
     kzL[i] = 0;
+    hiL[i] = 0;
 #pragma unroll
-    for (int r = 0; r < RL; ++r) kzL[i] |= (kz_kept(j + r * (NZ / RL), NZ, a.kz_max) ? 1u : 0u) << r;
+    for (int r = 0; r < RL; ++r) {
+      const int k = j + r * (ZL / RL);
+      kzL[i] |= (kz_kept(k, ZL, a.kz_max) ? 1u : 0u) << r;
+      if constexpr (HZ) hiL[i] |= (2 * k >= ZL ? 1u : 0u) << r;
+    }
   }
 
   // psi of the J block (registers) and, with PIL, of the I block (LDS),
@@ -271,8 +303,9 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
       for (int q = 0; q < 4; ++q) {
         mu[q] = mul[ia * TT + b0 + q];
         // pairs not evaluated (screened, or below the diagonal) transform as
-        // zeros, so they add no rounding to the pair sharing their grid
-        on[q] = pair_live<TT, SCR>(td, ia, b0 + q) ? T(1) : T(0);
+        // zeros, so they add no rounding to the pair sharing their grid; the
+        // half-length transform takes doubled products
+        on[q] = pair_live<TT, SCR>(td, ia, b0 + q) ? T(ZS) : T(0);
       }
 #pragma unroll
       for (int k = 0; k < PT; ++k)
@@ -294,7 +327,9 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
           cpx<T>* g = grids + (long long)(slot0 + gL[i]) * NR;
 #pragma unroll
           for (int r = 0; r < RL; ++r)
-            if ((kzL[i] >> r) & 1u) g[offL[i] + r * ZSL] = out[i * RL + r];
+            if ((kzL[i] >> r) & 1u)
+              g[offL[i] + r * ZSL + (((hiL[i] >> r) & 1u) ? (NZ / 2) * N * N : 0)] =
+                  out[i * RL + r];
         }
       }
     });
@@ -1026,7 +1061,8 @@ template <typename T, int N, int W, int TT, class SZF, class SZI, int NTQ, class
           class SYF, class SYI, bool SW = false,
           int NTF = pencil_threads<T, N, W, true>(), int NTI = pencil_threads<T, N, W, false>(),
           bool PJL = pencil_prefetch<T, N, W>(), bool PF = pencil_prefetch<T, N, W>(),
-          bool PIL = false, bool PP = false, int NZ = N, bool FLI = false>
+          bool PIL = false, bool PP = false, int NZ = N, bool FLI = false,
+          class SZH = typename HalfZ<NZ / 2>::type>
 struct FusedPipeline {
   static_assert(!FLI || PF, "flat loads are a form of the prefetching accumulation");
   static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
@@ -1049,13 +1085,27 @@ struct FusedPipeline {
     }();
     return planes < slots ? planes : slots;
   }
-  static void pair_fwd(const PassGroup& g, int nb, hipStream_t s) {
+  // half-length forward z for band-limited plans (float32)
+  static constexpr bool HZOK = sizeof(T) == 4 && NZ % 2 == 0 && !std::is_void_v<SZH>;
+  template <bool HZ>
+  static void fwd_launch(const PassGroup& g, int nb, hipStream_t s) {
     if (g.a[0].perm)
-      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true, NZ>), dim3(nb), dim3(NTF), 0,
-                         s, g);
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true, NZ, HZ, SZH>), dim3(nb),
+                         dim3(NTF), 0, s, g);
     else
-      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false, NZ>), dim3(nb), dim3(NTF), 0,
-                         s, g);
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false, NZ, HZ, SZH>), dim3(nb),
+                         dim3(NTF), 0, s, g);
+  }
+  static void pair_fwd(const PassGroup& g, int nb, hipStream_t s) {
+    if constexpr (HZOK) {
+      bool half = true;
+      for (int i = 0; i < g.count; ++i) half = half && g.a[i].kz_max <= (NZ / 2 - 1) / 2;
+      if (half) {
+        fwd_launch<true>(g, nb, s);
+        return;
+      }
+    }
+    fwd_launch<false>(g, nb, s);
   }
   static void plane(const PassGroup& g, int nb, hipStream_t s) {
     if constexpr (QB > 0) {
@@ -1134,6 +1184,8 @@ struct FusedPipeline {
     fill_radices(v.xi, v.nxi, SXI{});
     fill_radices(v.yf, v.nyf, SYF{});
     fill_radices(v.yi, v.nyi, SYI{});
+    v.nzh = 0;
+    if constexpr (HZOK) fill_radices(v.zh, v.nzh, SZH{});
     v.plane_lds = lds;
     v.pair_fwd = &pair_fwd;
     v.plane = &plane;

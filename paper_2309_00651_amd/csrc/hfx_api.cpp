@@ -86,7 +86,7 @@ struct SystemPlan {
   long long n_partials = 0;
   // device tables (owned)
   void* vtab = nullptr;
-  void* tw[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void* tw[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   TileDesc* d_tiles = nullptr;
   int* d_active = nullptr;
   void* d_zero = nullptr;  // kZeroBytes of zeros: what pruned kz planes read as (band-limited plans)
@@ -276,6 +276,13 @@ bool parse_count(const std::string& v, long long* out) {
 
 int bricks_per_tile(const Variant* v) {
   return v->n * ((v->n + v->brick - 1) / v->brick);
+}
+
+// Whether the forward z transform of pair_fwd runs at half length: pair
+// densities with |kz| <= kz_max are sampled exactly by the even z points when
+// 2 kz_max + 1 <= nz / 2 (the same test as the kernels' launchers).
+bool half_z(const Variant* v, int kz_max) {
+  return v->nzh > 0 && v->nz % 2 == 0 && kz_max <= (v->nz / 2 - 1) / 2;
 }
 
 ScheduleShape shape_of(const SystemPlan& sp) {
@@ -632,6 +639,7 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
     a.tw_xi = sp.tw[3];
     a.tw_yf = sp.tw[4];
     a.tw_yi = sp.tw[5];
+    a.tw_zh = sp.tw[6];
     a.partials = reinterpret_cast<double*>(ws + sp.off_partials);
     a.mean = mean;
     a.v0 = sp.v0;
@@ -711,7 +719,8 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
       const double grids = (double)b.n_active;
       const int kp = kz_planes(nz, sp.kz_max);
       nb_fwd.push_back(b.n_tiles * br);
-      by_fwd += orbs * nr * elem + grids * nr * ce * kzf;
+      // a half-length forward z transform reads the orbitals on even z only
+      by_fwd += orbs * nr * elem * (half_z(v, sp.kz_max) ? 0.5 : 1.0) + grids * nr * ce * kzf;
       fl_fwd += grids * fft_z;
       nb_pl.push_back(b.n_active * kp);
       by_pl += grids * nr * ce * 2.0 * kzf;
@@ -1342,6 +1351,10 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
       s = upload_twiddles(rs[k], cs[k], precision, &sp.tw[k]);
       if (s != HFX_OK) return cleanup(s);
     }
+    if (v->nzh > 0) {
+      s = upload_twiddles(v->zh, v->nzh, precision, &sp.tw[6]);
+      if (s != HFX_OK) return cleanup(s);
+    }
     void* d = nullptr;
     s = upload(sp.tiles, &d);
     if (s != HFX_OK) return cleanup(s);
@@ -1671,6 +1684,8 @@ const char* hfx_plan_describe(hfx_plan plan, int system) {
                   " rows=" + std::to_string(sp.rows) +
                   (sp.kz_max < v->nz / 2 ? " kz_max=" + std::to_string(sp.kz_max)
                                           : std::string()) +
+                  (half_z(v, sp.kz_max) ? " z_fwd=half(" + sched(v->zh, v->nzh) + ")"
+                                        : std::string()) +
                   " tiles_per_batch=" + std::to_string(sp.tiles_per_batch) +
                   " batches=" + std::to_string(sp.batches.size()) +
                   " streams=" + std::to_string(sp.nstreams) +

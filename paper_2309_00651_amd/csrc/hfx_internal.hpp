@@ -57,6 +57,7 @@ struct PassArgs {
   const void* tw_xi;
   const void* tw_yf;
   const void* tw_yi;
+  const void* tw_zh;      // forward z at half length (band-limited to a quarter of NZ), or null
   double* partials;       // per-workgroup energy partial sums
   long long part_base;    // first partial of this launch
   const double* mean;     // float32 plans: pair-density means mu_ab = (1/N_r) sum psi_a psi_b
@@ -137,6 +138,7 @@ struct Variant {
   int rows_per_wg; // plane_mode 1: rows per row-FFT workgroup
   bool persistent; // plane kernel loops over planes (grid of resident workgroups only)
   int zf[4], nzf, zi[4], nzi;  // z radix schedules (forward, inverse)
+  int zh[4], nzh;              // forward z at half length (nzh = 0: not compiled)
   int xf[4], nxf, xi[4], nxi;  // x
   int yf[4], nyf, yi[4], nyi;  // y
   size_t plane_lds;            // dynamic LDS bytes of the plane/row kernels
