@@ -46,38 +46,43 @@ using P96pi = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, S
                             true>;
 // Grids whose fused plane fills a compute unit's LDS (108 to 128): one plane
 // workgroup per compute unit.  Defaults: flat-load prefetching accumulation
-// (inv_acc loads spread over all threads, staged in LDS), and at 108 and 120
+// (inv_acc loads spread over all threads, staged in LDS) and, at 108 and 120,
 // the persistent plane kernel that prefetches the next plane (at 120 with
-// radix-15 first stages, which keep its registers within the budget).
-// Alternatives: the earlier defaults (-lp: psi J block in LDS + prefetch;
-// -r: registers, no prefetch), the persistent plane kernel at 128 (-pp,
-// slower there: measured 742 against 711 ms per K psi at 128^3 / 512
-// orbitals), and flat loads with the non-persistent plane (-fl).
+// radix-15 first stages, which keep its registers within the budget) and an
+// accumulation transform over the four grids of a tile row (psi J block in
+// LDS: the larger prefetch leaves no registers for it).  Measured per K psi
+// pass (ms, accumulation pass in brackets): 108^3 / 320 orbitals at 5 Ha
+// 245.5 [112.2] against 251.5 [118.4] with two grids per transform (-fl2);
+// 120^3 / 384 473.1 [214.5] against 483.0 [224.5]; at 128^3 / 512 four grids
+// per transform were slower (468 against 414), and so was the persistent
+// plane kernel (-pp: 742 against 711 for the plane pass).  Alternatives: the
+// earlier defaults (-lp: psi J block in LDS + prefetch; -r: registers, no
+// prefetch).
 using P108 = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
-                           Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, false, true,
-                           false, true, 108, true>;
+                           Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, true, true,
+                           false, true, 108, 4>;
+using P108fl2 = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
+                              Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, false,
+                              true, false, true, 108, 1>;
 using P108lp = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
                              Sched<9, 12>, Sched<12, 9>, Sched<9, 12>>;
 using P108r = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
                             Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, false,
                             false>;
-using P108fl = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
-                             Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, false, true,
-                             false, false, 108, true>;
 using P120 = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<15, 8>,
-                           Sched<8, 15>, Sched<15, 8>, Sched<8, 15>, false, 256, 1024, false, true,
-                           false, true, 120, true>;
+                           Sched<8, 15>, Sched<15, 8>, Sched<8, 15>, false, 256, 1024, true, true,
+                           false, true, 120, 4>;
+using P120fl2 = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<15, 8>,
+                              Sched<8, 15>, Sched<15, 8>, Sched<8, 15>, false, 256, 1024, false,
+                              true, false, true, 120, 1>;
 using P120r = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
                             Sched<12, 10>, Sched<10, 12>, Sched<12, 10>>;
 using P120lp = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
                              Sched<12, 10>, Sched<10, 12>, Sched<12, 10>, false, 256, 1024, true,
                              true>;
-using P120fl = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960, Sched<10, 12>,
-                             Sched<12, 10>, Sched<10, 12>, Sched<12, 10>, false, 256, 1024, false,
-                             true, false, false, 120, true>;
 using P128 = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
                            Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, false, true,
-                           false, false, 128, true>;
+                           false, false, 128, 1>;
 using P128r = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
                             Sched<16, 8>, Sched<8, 16>, Sched<16, 8>>;
 using P128lp = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
@@ -114,13 +119,13 @@ const Variant* variants_f32(int* count) {
       P96sw::describe("f32-n96-sw"),
       P96pi::describe("f32-n96-pi"),
       P108::describe("f32-n108"),
+      P108fl2::describe("f32-n108-fl2"),
       P108lp::describe("f32-n108-lp"),
       P108r::describe("f32-n108-r"),
-      P108fl::describe("f32-n108-fl"),
       P120::describe("f32-n120"),
+      P120fl2::describe("f32-n120-fl2"),
       P120r::describe("f32-n120-r"),
       P120lp::describe("f32-n120-lp"),
-      P120fl::describe("f32-n120-fl"),
       P128::describe("f32-n128"),
       P128r::describe("f32-n128-r"),
       P128lp::describe("f32-n128-lp"),

@@ -367,15 +367,16 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
 // in a quarter of the threads (a radix-16 first stage over 32 columns of 128
 // points is 256 butterflies) and cost 16 complex registers each.
 template <typename T, int N, int W, int NT, int TT, class SZI, bool ACC, bool PJL, bool PF,
-          bool SCR, int NZ = N, int KZ = 0, bool FL = false>
+          bool SCR, int NZ = N, int KZ = 0, bool FL = false, int NG = 2>
 __global__ void __launch_bounds__(NT)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_inv_acc(PassGroup grp) {
   int sys_ = 0;
   const int lg_ = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
   const PassArgs& a = grp.a[sys_];
-  static_assert(TT % 4 == 0, "tile must hold whole grid pairs");
-  constexpr int W2 = 2 * W;
-  constexpr int QB = TT / 4;               // grid pairs per orbital a
+  static_assert(TT % (2 * NG) == 0, "a row of the tile must hold whole transforms");
+  static_assert(NG == 2 || FL, "four grids per transform come with flat loads");
+  constexpr int W2 = NG * W;               // columns of one transform (NG grids)
+  constexpr int QB = TT / (2 * NG);        // transforms per orbital a
   using G = Geom<T, NZ, W2, NT, true, W2, 1>;
   using F = FirstStage<G, SZI>;
   using E = FFT<G, true, SZI>;
@@ -433,19 +434,19 @@ __global__ void __launch_bounds__(NT)
     ldsA[k] = z * W2 + m;
   }
 
-  // FL: element e = tid + k NT of the brick, e = z 2W + c (c: column of the
-  // grid pair, grid c / W, x = x0 + c mod W) -- the LDS index of the engine
+  // FL: element e = tid + k NT of the brick, e = z NG W + c (c: column of
+  // the transform, grid c / W, x = x0 + c mod W) -- the LDS index of the engine
   constexpr int FE = NZ * W2;
   constexpr int FLV = FL ? (FE + NT - 1) / NT : 1;
-  int offFL[FLV];
-  bool vFL[FLV], gFL[FLV], kzFL[FLV];
+  int offFL[FLV], gFL[FLV];
+  bool vFL[FLV], kzFL[FLV];
 #pragma unroll
   for (int k = 0; k < FLV; ++k) {
     const int e = tid + k * NT;
     const int z = e / W2, c = e - (e / W2) * W2;
     const int g = c / W, m = c - (c / W) * W;
     vFL[k] = FL && e < FE && x0 + m < N;
-    gFL[k] = g != 0;
+    gFL[k] = g;
     offFL[k] = vFL[k] ? (z * N + y) * N + x0 + m : 0;
     kzFL[k] = KZ == 0 || kz_kept(z < NZ ? z : 0, NZ, a.kz_max);
   }
@@ -491,11 +492,16 @@ __global__ void __launch_bounds__(NT)
   T pa[PT], acca[PT], kold[ACC ? PT : 1];
   T pa_n[PF ? PT : 1], kold_n[(PF && ACC) ? PT : 1];
 
-  // grid pair bq of orbital a carries pairs (a, 4bq .. 4bq + 3)
-  auto uses = [&](int ia, int bq, bool& u0, bool& u1) {
-    const int b0 = 4 * bq;
-    u0 = pair_live<TT, SCR>(td, ia, b0) || pair_live<TT, SCR>(td, ia, b0 + 1);
-    u1 = pair_live<TT, SCR>(td, ia, b0 + 2) || pair_live<TT, SCR>(td, ia, b0 + 3);
+  // transform bq of orbital a carries pairs (a, 2 NG bq .. 2 NG bq + 2 NG - 1);
+  // bit g of the mask: grid g (pairs b0 + 2g, b0 + 2g + 1) has an evaluated pair
+  auto uses = [&](int ia, int bq) {
+    const int b0 = 2 * NG * bq;
+    unsigned um = 0;
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+      um |= (pair_live<TT, SCR>(td, ia, b0 + 2 * g) || pair_live<TT, SCR>(td, ia, b0 + 2 * g + 1)
+                 ? 1u : 0u) << g;
+    return um;
   };
   // Loads below are issued unconditionally: masked-off lanes read a valid
   // dummy address (data written earlier in the batch: finite), and legs on
@@ -507,12 +513,11 @@ __global__ void __launch_bounds__(NT)
   // energies and K psi_a get exact zeros there, while K psi_b is not stored
   // there.
   auto load_pair = [&](int ia, int bq, cpx<T>* v) {
-    bool u0, u1;
-    uses(ia, bq, u0, u1);
-    const int slot0 = td.slot0 + ia * (TT / 2) + 2 * bq;
+    const unsigned um = uses(ia, bq);
+    const int slot0 = td.slot0 + ia * (TT / 2) + NG * bq;
 #pragma unroll
     for (int i = 0; i < F::PER; ++i) {
-      const bool ok = vF[i] && (gF[i] == 0 ? u0 : u1);
+      const bool ok = vF[i] && ((um >> gF[i]) & 1u);
       const cpx<T>* dummy = grids + (long long)td.slot0 * NR;
       const cpx<T>* g = ok ? grids + (long long)(slot0 + gF[i]) * NR + offF[i] : dummy;
       if constexpr (KZ == 1) {
@@ -542,14 +547,13 @@ __global__ void __launch_bounds__(NT)
   };
   // FL: the grid pair's brick in flat order (same dummy and zero-block rules)
   auto load_flat = [&](int ia, int bq, cpx<T>* v) {
-    bool u0, u1;
-    uses(ia, bq, u0, u1);
-    const int slot0 = td.slot0 + ia * (TT / 2) + 2 * bq;
+    const unsigned um = uses(ia, bq);
+    const int slot0 = td.slot0 + ia * (TT / 2) + NG * bq;
     const cpx<T>* dummy = grids + (long long)td.slot0 * NR;
 #pragma unroll
     for (int k = 0; k < FLV; ++k) {
-      const bool ok = vFL[k] && (gFL[k] ? u1 : u0);
-      const cpx<T>* g = ok ? grids + (long long)(slot0 + (gFL[k] ? 1 : 0)) * NR + offFL[k] : dummy;
+      const bool ok = vFL[k] && ((um >> gFL[k]) & 1u);
+      const cpx<T>* g = ok ? grids + (long long)(slot0 + gFL[k]) * NR + offFL[k] : dummy;
       if constexpr (KZ == 1) {
         const cpx<T>* zero = static_cast<const cpx<T>*>(a.zero) + tid;
         v[k] = *(kzFL[k] ? g : zero);
@@ -574,10 +578,9 @@ __global__ void __launch_bounds__(NT)
   };
   // inverse transform of the grid pair in v, then energies and K psi updates
   auto process = [&](auto bqc, int ia, cpx<T>* v) {
-    constexpr int b0 = 4 * decltype(bqc)::value;
-    bool use0, use1;
-    uses(ia, decltype(bqc)::value, use0, use1);
-    if (!use0 && !use1) return;
+    constexpr int b0 = 2 * NG * decltype(bqc)::value;
+    const unsigned um = uses(ia, decltype(bqc)::value);
+    if (!um) return;
     {
       cpx<T> out[LastStage<G, SZI>::VALS];
       if constexpr (FL) {
@@ -594,7 +597,7 @@ __global__ void __launch_bounds__(NT)
     __syncthreads();
     // one grid's potentials at a time (bounded registers)
     cpx<T> pot[PT];
-    static_for<0, 4>([&](auto q) {
+    static_for<0, 2 * NG>([&](auto q) {
       constexpr int gq = decltype(q)::value / 2, half = decltype(q)::value % 2;
       constexpr int b = b0 + decltype(q)::value;
       if constexpr (half == 0) {
@@ -603,7 +606,7 @@ __global__ void __launch_bounds__(NT)
           pot[k] = tid + k * NT < P ? lds[ldsA[k] + gq * W] : cpx<T>{T(0), T(0)};
       }
       if (b >= td.nJ) return;
-      if (!(gq == 0 ? use0 : use1)) return;
+      if (!((um >> gq) & 1u)) return;
       // weight of e_ab in sum_{i,j} e_ij: 2 for a != b, 1 for a == b, 0 for
       // pairs not evaluated
       if (!pair_live<TT, SCR>(td, ia, b)) return;
@@ -681,9 +684,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int k = 0; k < PT; ++k) acca[k] = T(0);
       static_for<0, QB>([&](auto bq) {
-        bool u0, u1;
-        uses(ia, decltype(bq)::value, u0, u1);
-        if (!u0 && !u1) return;
+        if (!uses(ia, decltype(bq)::value)) return;
         cpx<T> v[F::VALS];
         load_pair(ia, decltype(bq)::value, v);
         process(bq, ia, v);
@@ -1061,10 +1062,15 @@ template <typename T, int N, int W, int TT, class SZF, class SZI, int NTQ, class
           class SYF, class SYI, bool SW = false,
           int NTF = pencil_threads<T, N, W, true>(), int NTI = pencil_threads<T, N, W, false>(),
           bool PJL = pencil_prefetch<T, N, W>(), bool PF = pencil_prefetch<T, N, W>(),
-          bool PIL = false, bool PP = false, int NZ = N, bool FLI = false,
+          bool PIL = false, bool PP = false, int NZ = N, int FLI = 0,
           class SZH = typename HalfZ<NZ / 2>::type>
 struct FusedPipeline {
-  static_assert(!FLI || PF, "flat loads are a form of the prefetching accumulation");
+  // FLI: inv_acc flat loads (0: none; 1: two grids per transform; 4: the four
+  // grids of a tile row per transform)
+  static_assert(FLI == 0 || FLI == 1 || FLI == 4, "flat-load mode");
+  static_assert(FLI == 0 || PF, "flat loads are a form of the prefetching accumulation");
+  static constexpr bool FLB = FLI != 0;
+  static constexpr int NGI = FLI == 4 ? 4 : 2;
   static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
   // band of the plane kernel's column-pruned instantiation (float32 cubic
   // grids from 64 up to 120, plain layouts): |kx| <= N / 4, the band of
@@ -1130,18 +1136,18 @@ struct FusedPipeline {
     // 93 of 96 planes and at 29..57 of 64..120)
     const int kept = kz_planes(NZ, g.a[0].kz_max);
     if (kept == NZ) {
-      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 0, FLI>), dim3(nb),
+      hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 0, FLB, NGI>), dim3(nb),
                          dim3(NTI), 0, s, g);
       return;
     }
     if constexpr (sizeof(T) == 4) {
       if (4 * kept >= 3 * NZ) {
-        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 1, FLI>), dim3(nb),
+        hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 1, FLB, NGI>), dim3(nb),
                            dim3(NTI), 0, s, g);
         return;
       }
     }
-    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 2, FLI>), dim3(nb),
+    hipLaunchKernelGGL((k_inv_acc<T, N, W, NTI, TT, SZI, ACC, PJL, PF, SCR, NZ, 2, FLB, NGI>), dim3(nb),
                        dim3(NTI), 0, s, g);
   }
   template <bool ACC>
