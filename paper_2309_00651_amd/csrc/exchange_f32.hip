@@ -55,9 +55,15 @@ using P96pi = FusedPipeline<float, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, S
 // 245.5 [112.2] against 251.5 [118.4] with two grids per transform (-fl2);
 // 120^3 / 384 473.1 [214.5] against 483.0 [224.5]; at 128^3 / 512 four grids
 // per transform were slower (468 against 414), and so was the persistent
-// plane kernel (-pp: 742 against 711 for the plane pass).  Alternatives: the
-// earlier defaults (-lp: psi J block in LDS + prefetch; -r: registers, no
-// prefetch).
+// plane kernel (-pp: 742 against 711 for the plane pass); there the plane
+// pass takes the XOR-swizzled LDS layout (the radix-8 first row stage writes
+// with a stride of 8 elements, which otherwise conflicts on the LDS banks,
+// 31 % of the cycles) and grid-major plane order: 709 -> 616 ms per K psi
+// pass (swizzle alone 635; grid-major alone 693).  Alternatives: the earlier
+// defaults (-fl: unswizzled kz-major plane; -lp: psi J block in LDS +
+// prefetch; -r: registers, no prefetch), the persistent plane kernel (-pp)
+// and the plane held in registers with two workgroups per compute unit (-h2,
+// 702 ms: it spills 17 registers).
 using P108 = FusedPipeline<float, 108, 16, 8, Sched<12, 9>, Sched<9, 12>, 972, Sched<12, 9>,
                            Sched<9, 12>, Sched<12, 9>, Sched<9, 12>, false, 256, 1024, true, true,
                            false, true, 108, 4>;
@@ -81,8 +87,16 @@ using P120lp = FusedPipeline<float, 120, 16, 8, Sched<8, 15>, Sched<15, 8>, 960,
                              Sched<12, 10>, Sched<10, 12>, Sched<12, 10>, false, 256, 1024, true,
                              true>;
 using P128 = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
-                           Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, false, true,
-                           false, false, 128, 1>;
+                           Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, true, 256, 1024, false, true,
+                           false, false, 128, 1, HalfZ<64>::type, 1, true>;
+using P128fl = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
+                             Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, false, true,
+                             false, false, 128, 1>;
+// plane in registers with a half-plane LDS buffer: two plane workgroups of
+// 512 threads per compute unit (k_plane_h2)
+using P128h2 = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 512, Sched<8, 16>,
+                             Sched<16, 8>, Sched<8, 16>, Sched<16, 8>, false, 256, 1024, false, true,
+                             false, false, 128, 1, HalfZ<64>::type, 2>;
 using P128r = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
                             Sched<16, 8>, Sched<8, 16>, Sched<16, 8>>;
 using P128lp = FusedPipeline<float, 128, 16, 8, Sched<8, 16>, Sched<16, 8>, 1024, Sched<8, 16>,
@@ -127,9 +141,11 @@ const Variant* variants_f32(int* count) {
       P120r::describe("f32-n120-r"),
       P120lp::describe("f32-n120-lp"),
       P128::describe("f32-n128"),
+      P128fl::describe("f32-n128-fl"),
       P128r::describe("f32-n128-r"),
       P128lp::describe("f32-n128-lp"),
       P128pp::describe("f32-n128-pp"),
+      P128h2::describe("f32-n128-h2"),
       P24x48::describe("f32-n24x48"),
       P64x128::describe("f32-n64x128"),
   };

@@ -755,8 +755,12 @@ constexpr int plane_waves_per_eu() {
 // the y transforms, the multiply and the inverse y transforms run on the
 // 2 QB + 1 columns of the band only (a band geometry of the engine); the
 // inverse x transforms read the zeros.
+// GM (grid-major plane order): logical plane L is plane L mod kp of grid
+// L / kp (kp kept planes per grid), so workgroups running together stream
+// neighbouring planes of one grid; kz-major order (GM false) has them read the
+// same plane of many grids, whose addresses coincide modulo the grid size.
 template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, bool SW = false,
-          bool PP = false, int NZ = N, int QB = 0>
+          bool PP = false, int NZ = N, int QB = 0, bool GM = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<T, N, NT>())))
 k_plane_conv(PassGroup grp) {
   int sys_ = 0;
@@ -795,10 +799,13 @@ k_plane_conv(PassGroup grp) {
   stage_twiddles<T, SYF, NT>(twyf, a.tw_yf, tid);
   stage_twiddles<T, SYI, NT>(twyi, a.tw_yi, tid);
   stage_twiddles<T, SXI, NT>(twxi, a.tw_xi, tid);
+  const int kp_ = kz_planes(NZ, a.kz_max);
+  auto plane_kz = [&](int L) {
+    return kz_of_plane(GM ? L - (L / kp_) * kp_ : L / a.n_active, NZ, a.kz_max);
+  };
   auto plane_base = [&](int L) {
-    const int c = L / a.n_active, ai = L - c * a.n_active;
-    const int kz = kz_of_plane(c, NZ, a.kz_max);
-    return gbase + (long long)a.active[ai] * NR + (long long)kz * N * N;
+    const int ai = GM ? L / kp_ : L - (L / a.n_active) * a.n_active;
+    return gbase + (long long)a.active[ai] * NR + (long long)plane_kz(L) * N * N;
   };
   // x-forward stage-0 inputs straight from HBM (rows, x contiguous)
   auto load_rows = [&](const cpx<T>* __restrict__ base, cpx<T>* v, int t) {
@@ -815,7 +822,7 @@ k_plane_conv(PassGroup grp) {
   // v(G) / N_r at the thread's multiply points of plane L
   auto load_v = [&](int L, T* f, int t) {
     const T* __restrict__ vt =
-        static_cast<const T*>(a.vtab) + (long long)kz_of_plane(L / a.n_active, NZ, a.kz_max) * N * N;
+        static_cast<const T*>(a.vtab) + (long long)plane_kz(L) * N * N;
 #pragma unroll
     for (int i = 0; i < LY::PER; ++i) {
       int m = 0, j = 0;
@@ -896,6 +903,146 @@ k_plane_conv(PassGroup grp) {
     L = next;
     __syncthreads();  // this plane's LDS reads end before the next plane's writes
   }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2 for planes whose LDS copy would fill a compute unit (128^2 float32:
+// 132 KB of the 160 KB): the plane is held in registers between the
+// transforms and passes through a half-plane LDS buffer, so two workgroups
+// share a compute unit and overlap each other's loads, barriers and stores.
+//   x forward : two halves of N/2 rows, each transformed through the buffer
+//               [N/2][N + 1]; results stay in registers (the last stage's
+//               legs: leg r of butterfly j is column j + r N / R_last)
+//   y pass    : two halves of N/2 columns: the registers of the half are
+//               scattered to the buffer [N][N/2 + 1], forward y, multiply by
+//               v(G)/N_r, inverse y, gathered back into the same registers
+//   x inverse : two halves of rows, scattered at the x forward's positions,
+//               transformed from LDS and stored to HBM.
+template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, int NZ = N>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((2 * NT / 64 + 3) / 4)))
+k_plane_h2(PassGroup grp) {
+  int sys_ = 0;
+  const int lg = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
+  const PassArgs& a = grp.a[sys_];
+  constexpr int H = N / 2;
+  constexpr int PX = N + 1;  // row-half buffer [H][N + 1]
+  constexpr int PY = H + 1;  // column-half buffer [N][H + 1]
+  using GX = Geom<T, N, H, NT, false, 1, PX>;  // sequences m = rows of the half, n = x
+  using GY = Geom<T, N, H, NT, true, PY, 1>;   // sequences m = columns of the half, n = y
+  using EXF = FFT<GX, false, SXF>;
+  using EXI = FFT<GX, true, SXI>;
+  using EYF = FFT<GY, false, SYF>;
+  using EYI = FFT<GY, true, SYI>;
+  using FX = FirstStage<GX, SXF>;
+  using LXF = LastStage<GX, SXF>;
+  using LY = LastStage<GY, SYF>;
+  using LYI = LastStage<GY, SYI>;
+  using LXI = LastStage<GX, SXI>;
+  constexpr int RL = SchedInfo<SXF>::last;
+  static_assert(N % 2 == 0 && RL % 2 == 0, "halves of rows and columns");
+  static_assert(LXF::NBF == N / RL && LXF::NBF == SchedInfo<SXF>::last_span,
+                "last x stage: leg r of butterfly j is column j + r N / R");
+  static_assert(SchedInfo<SYI>::first == SchedInfo<SYF>::last, "fused y schedules");
+  static_assert(LYI::VALS > 0 && LY::VALS == FirstStage<GY, SYI>::VALS, "fused y register maps");
+  constexpr long long NR = (long long)NZ * N * N;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int total = a.n_active * kz_planes(NZ, a.kz_max);
+  if (lg >= total) return;
+  __shared__ TwEntry<T> twxf[tw_slots<T, SXF>()], twyf[tw_slots<T, SYF>()],
+      twyi[tw_slots<T, SYI>()], twxi[tw_slots<T, SXI>()];
+  stage_twiddles<T, SXF, NT>(twxf, a.tw_xf, tid);  // visible after the first barrier
+  stage_twiddles<T, SYF, NT>(twyf, a.tw_yf, tid);
+  stage_twiddles<T, SYI, NT>(twyi, a.tw_yi, tid);
+  stage_twiddles<T, SXI, NT>(twxi, a.tw_xi, tid);
+  const int c_ = lg / a.n_active, ai = lg - c_ * a.n_active;
+  const int kz = kz_of_plane(c_, NZ, a.kz_max);
+  cpx<T>* __restrict__ base = static_cast<cpx<T>*>(a.grids) + (long long)a.active[ai] * NR +
+                              (long long)kz * N * N;
+  const T* __restrict__ vt = static_cast<const T*>(a.vtab) + (long long)kz * N * N;
+
+  // the x-transformed plane: row half h, the last stage's legs
+  cpx<T> xr[2][LXF::VALS];
+  static_for<0, 2>([&](auto hc) {
+    constexpr int h = decltype(hc)::value;
+    cpx<T> v[FX::VALS];
+#pragma unroll
+    for (int i = 0; i < FX::PER; ++i) {
+      if (!FX::valid(tid, i)) continue;
+      int m, j;
+      FX::mj(tid, i, m, j);
+#pragma unroll
+      for (int r = 0; r < SchedInfo<SXF>::first; ++r)
+        v[i * SchedInfo<SXF>::first + r] = base[(h * H + m) * N + FX::in_pos(j, r)];
+    }
+    EXF::reg2reg(v, buf, twxf, tid, xr[h]);  // the buffer is free again on return
+  });
+  // y pass over two column halves
+  static_for<0, 2>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    static_for<0, 2>([&](auto hc) {
+      constexpr int h = decltype(hc)::value;
+#pragma unroll
+      for (int i = 0; i < LXF::PER; ++i) {
+        if (!LXF::valid(tid, i)) continue;
+        int m, j;
+        LXF::mj(tid, i, m, j);
+#pragma unroll
+        for (int r = c * RL / 2; r < (c + 1) * RL / 2; ++r)
+          buf[(h * H + m) * PY + LXF::out_pos(j, r) - c * H] = xr[h][i * RL + r];
+      }
+    });
+    __syncthreads();
+    cpx<T> oy[LY::VALS];
+    EYF::lds2reg(buf, twyf, tid, oy);
+#pragma unroll
+    for (int i = 0; i < LY::PER; ++i) {
+      if (!LY::valid(tid, i)) continue;
+      int m, j;
+      LY::mj(tid, i, m, j);
+#pragma unroll
+      for (int r = 0; r < SchedInfo<SYF>::last; ++r)
+        oy[i * SchedInfo<SYF>::last + r] =
+            cscale(oy[i * SchedInfo<SYF>::last + r], vt[LY::in_pos(j, r) * N + c * H + m]);
+    }
+    {
+      cpx<T> o[LYI::VALS];
+      EYI::reg2reg(oy, buf, twyi, tid, o);
+      EYI::store_last(o, buf, tid);
+    }
+    __syncthreads();
+    static_for<0, 2>([&](auto hc) {
+      constexpr int h = decltype(hc)::value;
+#pragma unroll
+      for (int i = 0; i < LXF::PER; ++i) {
+        if (!LXF::valid(tid, i)) continue;
+        int m, j;
+        LXF::mj(tid, i, m, j);
+#pragma unroll
+        for (int r = c * RL / 2; r < (c + 1) * RL / 2; ++r)
+          xr[h][i * RL + r] = buf[(h * H + m) * PY + LXF::out_pos(j, r) - c * H];
+      }
+    });
+    __syncthreads();  // the buffer is rewritten next
+  });
+  // x inverse over two row halves, results straight to HBM
+  static_for<0, 2>([&](auto hc) {
+    constexpr int h = decltype(hc)::value;
+    EXF::store_last(xr[h], buf, tid);
+    __syncthreads();
+    cpx<T> ox[LXI::VALS];
+    EXI::lds2reg(buf, twxi, tid, ox);  // ends with a barrier after its last LDS read
+#pragma unroll
+    for (int i = 0; i < LXI::PER; ++i) {
+      if (!LXI::valid(tid, i)) continue;
+      int m, j;
+      LXI::mj(tid, i, m, j);
+#pragma unroll
+      for (int r = 0; r < SchedInfo<SXI>::last; ++r)
+        base[(h * H + m) * N + LXI::in_pos(j, r)] = ox[i * SchedInfo<SXI>::last + r];
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1063,15 +1210,22 @@ template <typename T, int N, int W, int TT, class SZF, class SZI, int NTQ, class
           int NTF = pencil_threads<T, N, W, true>(), int NTI = pencil_threads<T, N, W, false>(),
           bool PJL = pencil_prefetch<T, N, W>(), bool PF = pencil_prefetch<T, N, W>(),
           bool PIL = false, bool PP = false, int NZ = N, int FLI = 0,
-          class SZH = typename HalfZ<NZ / 2>::type>
+          class SZH = typename HalfZ<NZ / 2>::type, int PM = 1, bool GMP = false>
 struct FusedPipeline {
+  // PM: plane kernel (1: the plane in LDS, k_plane_conv; 2: the plane in
+  // registers with a half-plane LDS buffer, two workgroups per compute unit,
+  // k_plane_h2)
+  static_assert(PM == 1 || (PM == 2 && !PP && !SW && NZ == N), "plane kernel mode");
   // FLI: inv_acc flat loads (0: none; 1: two grids per transform; 4: the four
   // grids of a tile row per transform)
   static_assert(FLI == 0 || FLI == 1 || FLI == 4, "flat-load mode");
   static_assert(FLI == 0 || PF, "flat loads are a form of the prefetching accumulation");
   static constexpr bool FLB = FLI != 0;
   static constexpr int NGI = FLI == 4 ? 4 : 2;
-  static constexpr size_t lds = (size_t)N * (N + 1) * sizeof(cpx<T>);
+  static constexpr size_t lds =
+      PM == 2 ? (size_t)((N / 2) * (N + 1) > N * (N / 2 + 1) ? (N / 2) * (N + 1) : N * (N / 2 + 1)) *
+                    sizeof(cpx<T>)
+              : (size_t)N * (N + 1) * sizeof(cpx<T>);
   // band of the plane kernel's column-pruned instantiation (float32 cubic
   // grids from 64 up to 120, plain layouts): |kx| <= N / 4, the band of
   // orbitals at half the grid's plane-wave reach (a twofold oversampled grid)
@@ -1114,16 +1268,21 @@ struct FusedPipeline {
     fwd_launch<false>(g, nb, s);
   }
   static void plane(const PassGroup& g, int nb, hipStream_t s) {
+    if constexpr (PM == 2) {
+      hipLaunchKernelGGL((k_plane_h2<T, N, NTQ, SXF, SXI, SYF, SYI, NZ>), dim3(nb), dim3(NTQ), lds,
+                         s, g);
+      return;
+    }
     if constexpr (QB > 0) {
       bool band = true;
       for (int i = 0; i < g.count; ++i) band = band && g.a[i].kx_max <= QB;
       if (band) {
-        hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB>),
+        hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB, GMP>),
                            dim3(plane_grid(nb)), dim3(NTQ), lds, s, g);
         return;
       }
     }
-    hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ>),
+    hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, 0, GMP>),
                        dim3(plane_grid(nb)), dim3(NTQ), lds, s, g);
   }
   // screened (perm) and band-limited (kz_max < NZ / 2) plans take their own
@@ -1160,12 +1319,16 @@ struct FusedPipeline {
   static void inv_acc(const PassGroup& g, int nb, hipStream_t s) { inv_pass<true>(g, nb, s); }
   static void inv_energy(const PassGroup& g, int nb, hipStream_t s) { inv_pass<false>(g, nb, s); }
   static hipError_t prepare() {
+    if constexpr (PM == 2)
+      return hipFuncSetAttribute(
+          reinterpret_cast<const void*>(&k_plane_h2<T, N, NTQ, SXF, SXI, SYF, SYI, NZ>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ>),
+        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, 0, GMP>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess || QB == 0) return e;
     return hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB>),
+        reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB, GMP>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
   static Variant describe(const char* name) {
