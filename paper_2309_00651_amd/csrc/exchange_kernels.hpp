@@ -174,8 +174,10 @@ template <> struct HalfZ<64> { using type = Sched<8, 8>; };
 // sum over even points is half the full-length sum at every kept frequency;
 // the products are doubled (exact) and half-length frequency k maps to grid
 // plane k (k <= kz_max) or k + NZ / 2 (k >= NZ / 2 - kz_max).
+// HY (plans whose plane pass takes half-height input): bricks run at the even
+// rows y = 2y' only and store row y' of their planes, with doubled products.
 template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL, bool SCR, int NZ = N,
-          bool HZ = false, class SZH = typename HalfZ<NZ / 2>::type>
+          bool HZ = false, class SZH = typename HalfZ<NZ / 2>::type, bool HY = false>
 __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   int sys_ = 0;
   const int lg_ = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
@@ -189,12 +191,13 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   using E = FFT<G, false, SZ>;
   constexpr int RL = SchedInfo<SZ>::last;
   constexpr int NXB = (N + W - 1) / W;
-  constexpr int BR = N * NXB;
+  constexpr int BR = (HY ? N / 2 : N) * NXB;  // bricks per tile pair
   constexpr int P = ZL * W;
   constexpr int PT = (P + NT - 1) / NT;
   constexpr long long NR = (long long)NZ * N * N;
   constexpr int ZSL = (ZL / RL) * N * N;  // offset between legs of a last-stage butterfly
   constexpr int ZS = HZ ? 2 : 1;         // z stride of the product points
+  constexpr int YS = HY ? 2 : 1;         // y stride of the brick rows
   __shared__ cpx<T> lds[ZL * W2];
   __shared__ TwEntry<T> twl[tw_slots<T, SZ>()];
   __shared__ T mul[kMaxRows * TT];  // pair-density means of the tile, [a][b]
@@ -202,7 +205,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   const int tid = threadIdx.x;
   const int lg = lg_;
   const int t = lg / BR, br = lg - t * BR;
-  const int y = br / NXB, x0 = (br - y * NXB) * W;
+  const int y = br / NXB, x0 = (br - y * NXB) * W;  // y: the stored row (read at YS y)
   const TileDesc td = a.tiles[t];
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
   stage_twiddles<T, SZ, NT>(twl, HZ ? a.tw_zh : a.tw_zf, tid);
@@ -217,7 +220,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
     const int p = tid + k * NT;
     const int z = p / W, m = p - (p / W) * W;
     vA[k] = p < P && (x0 + m) < N;
-    offA[k] = vA[k] ? (ZS * z * N + y) * N + x0 + m : 0;
+    offA[k] = vA[k] ? (ZS * z * N + YS * y) * N + x0 + m : 0;
     ldsA[k] = z * W2 + m;
   }
   int offL[L::PER], gL[L::PER];
@@ -305,7 +308,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
         // pairs not evaluated (screened, or below the diagonal) transform as
         // zeros, so they add no rounding to the pair sharing their grid; the
         // half-length transform takes doubled products
-        on[q] = pair_live<TT, SCR>(td, ia, b0 + q) ? T(ZS) : T(0);
+        on[q] = pair_live<TT, SCR>(td, ia, b0 + q) ? T(ZS * YS) : T(0);
       }
 #pragma unroll
       for (int k = 0; k < PT; ++k)
@@ -759,8 +762,16 @@ constexpr int plane_waves_per_eu() {
 // L / kp (kp kept planes per grid), so workgroups running together stream
 // neighbouring planes of one grid; kz-major order (GM false) has them read the
 // same plane of many grids, whose addresses coincide modulo the grid size.
+// HY (band-limited along y too, 2 ky_max + 1 <= N / 2; with QB): pass 1 has
+// stored only the even rows y = 2y' (row y' of the plane, products doubled),
+// which sample the plane's y band exactly.  The forward x transforms run on
+// those N / 2 rows, the forward y transforms at length N / 2 (schedule SYH),
+// and the multiplied spectrum is written to its full-length rows (half-length
+// frequency k: row k below N / 4, else k + N / 2; the rows between, zeros)
+// before the inverse y transforms of length N, which restore every row.
 template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, bool SW = false,
-          bool PP = false, int NZ = N, int QB = 0, bool GM = false>
+          bool PP = false, int NZ = N, int QB = 0, bool GM = false, bool HY = false,
+          class SYH = SYF>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<T, N, NT>())))
 k_plane_conv(PassGroup grp) {
   int sys_ = 0;
@@ -768,22 +779,28 @@ k_plane_conv(PassGroup grp) {
   const PassArgs& a = grp.a[sys_];
   static_assert(!SW || N % 8 == 0, "swizzle needs whole blocks of 8");
   static_assert(QB == 0 || (!SW && 2 * QB + 1 < N), "band columns: no swizzle, inside the row");
+  static_assert(!HY || (QB > 0 && N % 4 == 0), "half-height planes come with band columns");
   constexpr int P = N + 1;
+  constexpr int NI = HY ? N / 2 : N;  // rows of the plane's input
+  constexpr int MB = QB ? 2 * QB + 1 : N;
   using GX = Geom<T, N, N, NT, false, 1, P, SW ? 1 : 0>;  // rows: sequence m = y, element n = x
+  using GXF = Geom<T, N, NI, NT, false, 1, P, SW ? 1 : 0>;  // the input rows
   // columns: sequence m = x (or the m-th column of the band), element n = y
-  using GY = Geom<T, N, QB ? 2 * QB + 1 : N, NT, true, P, 1, SW ? 2 : (QB ? 3 : 0)>;
-  using EXF = FFT<GX, false, SXF>;
+  using GY = Geom<T, N, MB, NT, true, P, 1, SW ? 2 : (QB ? 3 : 0)>;
+  using GYF = Geom<T, NI, MB, NT, true, P, 1, SW ? 2 : (QB ? 3 : 0), N>;  // forward y
+  using SYFX = std::conditional_t<HY, SYH, SYF>;
+  using EXF = FFT<GXF, false, SXF>;
   using EXI = FFT<GX, true, SXI>;
-  using EYF = FFT<GY, false, SYF>;
+  using EYF = FFT<GYF, false, SYFX>;
   using EYI = FFT<GY, true, SYI>;
-  using FX = FirstStage<GX, SXF>;
-  using LXF = LastStage<GX, SXF>;
-  using LY = LastStage<GY, SYF>;
+  using FX = FirstStage<GXF, SXF>;
+  using LXF = LastStage<GXF, SXF>;
+  using LY = LastStage<GYF, SYFX>;
   using FYI = FirstStage<GY, SYI>;
   using LYI = LastStage<GY, SYI>;
   using LXI = LastStage<GX, SXI>;
-  static_assert(SchedInfo<SYI>::first == SchedInfo<SYF>::last, "fused y schedules");
-  static_assert(FYI::VALS == LY::VALS, "fused y register maps");
+  static_assert(HY || SchedInfo<SYI>::first == SchedInfo<SYF>::last, "fused y schedules");
+  static_assert(HY || FYI::VALS == LY::VALS, "fused y register maps");
   constexpr long long NR = (long long)NZ * N * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* plane = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -793,10 +810,11 @@ k_plane_conv(PassGroup grp) {
   cpx<T>* __restrict__ gbase = static_cast<cpx<T>*>(a.grids);
 
   if (lg >= total) return;
-  __shared__ TwEntry<T> twxf[tw_slots<T, SXF>()], twyf[tw_slots<T, SYF>()],
+  __shared__ TwEntry<T> twxf[tw_slots<T, SXF>()], twyf[tw_slots<T, SYFX>()],
       twyi[tw_slots<T, SYI>()], twxi[tw_slots<T, SXI>()];
   stage_twiddles<T, SXF, NT>(twxf, a.tw_xf, tid);  // visible after the first barrier
-  stage_twiddles<T, SYF, NT>(twyf, a.tw_yf, tid);
+  // half-height: the half-length schedule is the plan's half-length z one
+  stage_twiddles<T, SYFX, NT>(twyf, HY ? a.tw_zh : a.tw_yf, tid);
   stage_twiddles<T, SYI, NT>(twyi, a.tw_yi, tid);
   stage_twiddles<T, SXI, NT>(twxi, a.tw_xi, tid);
   const int kp_ = kz_planes(NZ, a.kz_max);
@@ -829,8 +847,11 @@ k_plane_conv(PassGroup grp) {
       LY::mj(t, i, m, j);
       const bool ok = LY::valid(t, i);
 #pragma unroll
-      for (int r = 0; r < SchedInfo<SYF>::last; ++r)
-        f[i * SchedInfo<SYF>::last + r] = vt[ok ? LY::in_pos(j, r) * N + (QB ? GY::band_col(m) : m) : 0];
+      for (int r = 0; r < SchedInfo<SYFX>::last; ++r) {
+        const int k = LY::in_pos(j, r);
+        const int ky = HY ? (2 * k < NI ? k : k + N - NI) : k;  // full-length row
+        f[i * SchedInfo<SYFX>::last + r] = vt[ok ? ky * N + (QB ? GYF::band_col(m) : m) : 0];
+      }
     }
   };
   cpx<T> v[FX::VALS];
@@ -865,6 +886,8 @@ k_plane_conv(PassGroup grp) {
             const int x = LXF::out_pos(j, r);
             const bool in = x <= QB || x >= N - QB;
             plane[GX::idx(m, x)] = in ? o[i * SchedInfo<SXF>::last + r] : cpx<T>{T(0), T(0)};
+            // half-height: the lower rows' columns beyond the band are zero too
+            if (HY && !in) plane[GX::idx(m + NI, x)] = cpx<T>{T(0), T(0)};
           }
         }
       }
@@ -872,18 +895,46 @@ k_plane_conv(PassGroup grp) {
     __syncthreads();
     // y forward, multiply by v(G)/N_r, y inverse (hand-over in registers)
     cpx<T> oy[LY::VALS];
-    EYF::lds2reg(plane, twyf, t, oy);
+    EYF::lds2reg(plane, twyf, t, oy);  // ends with a barrier after its last LDS read
+    if constexpr (!HY) {
 #pragma unroll
-    for (int i = 0; i < LY::PER; ++i) {
-      if (!LY::valid(t, i)) continue;
+      for (int i = 0; i < LY::PER; ++i) {
+        if (!LY::valid(t, i)) continue;
 #pragma unroll
-      for (int r = 0; r < SchedInfo<SYF>::last; ++r)
-        oy[i * SchedInfo<SYF>::last + r] =
-            cscale(oy[i * SchedInfo<SYF>::last + r], vf[i * SchedInfo<SYF>::last + r]);
-    }
-    {
+        for (int r = 0; r < SchedInfo<SYF>::last; ++r)
+          oy[i * SchedInfo<SYF>::last + r] =
+              cscale(oy[i * SchedInfo<SYF>::last + r], vf[i * SchedInfo<SYF>::last + r]);
+      }
       cpx<T> o[LYI::VALS];
       EYI::reg2reg(oy, plane, twyi, t, o);
+      EYI::store_last(o, plane, t);
+    } else {
+      // the multiplied half-length spectrum goes to its full-length rows;
+      // frequencies beyond the y band hold rounding noise only: zeros
+#pragma unroll
+      for (int i = 0; i < LY::PER; ++i) {
+        if (!LY::valid(t, i)) continue;
+        int m, j;
+        LY::mj(t, i, m, j);
+#pragma unroll
+        for (int r = 0; r < SchedInfo<SYFX>::last; ++r) {
+          const int k = LY::in_pos(j, r);
+          const bool lo = 2 * k < NI;
+          const int row = lo ? k : k + N - NI;
+          const bool in = (lo ? k : NI - k) <= a.ky_max;
+          plane[row * P + GYF::band_col(m)] =
+              in ? cscale(oy[i * SchedInfo<SYFX>::last + r], vf[i * SchedInfo<SYFX>::last + r])
+                 : cpx<T>{T(0), T(0)};
+        }
+      }
+      // rows NI/2 .. N - NI/2 - 1 of the band columns: no half-length frequency
+      for (int e = t; e < (N - NI) * MB; e += NT) {
+        const int row = NI / 2 + e / MB, m = e - (e / MB) * MB;
+        plane[row * P + GYF::band_col(m)] = cpx<T>{T(0), T(0)};
+      }
+      __syncthreads();
+      cpx<T> o[LYI::VALS];
+      EYI::lds2reg(plane, twyi, t, o);
       EYI::store_last(o, plane, t);
     }
     __syncthreads();
@@ -1247,13 +1298,28 @@ struct FusedPipeline {
   }
   // half-length forward z for band-limited plans (float32)
   static constexpr bool HZOK = sizeof(T) == 4 && NZ % 2 == 0 && !std::is_void_v<SZH>;
-  template <bool HZ>
+  // half-height plane input (band columns, cubic grids; the half-length y
+  // transforms take the half-length z schedule and its twiddles)
+  static constexpr bool HYOK = QB > 0 && HZOK && NZ == N && N % 4 == 0 && PM == 1;
+  // the same test as the host's (run_exchange): every system of the group has
+  // its x band within the band columns and its y band within N / 4
+  static bool use_hy(const PassGroup& g) {
+    if constexpr (!HYOK) {
+      return false;
+    } else {
+      bool hy = true;
+      for (int i = 0; i < g.count; ++i)
+        hy = hy && g.a[i].kx_max <= QB && g.a[i].ky_max <= (N / 2 - 1) / 2;
+      return hy;
+    }
+  }
+  template <bool HZ, bool HY>
   static void fwd_launch(const PassGroup& g, int nb, hipStream_t s) {
     if (g.a[0].perm)
-      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true, NZ, HZ, SZH>), dim3(nb),
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true, NZ, HZ, SZH, HY>), dim3(nb),
                          dim3(NTF), 0, s, g);
     else
-      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false, NZ, HZ, SZH>), dim3(nb),
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false, NZ, HZ, SZH, HY>), dim3(nb),
                          dim3(NTF), 0, s, g);
   }
   static void pair_fwd(const PassGroup& g, int nb, hipStream_t s) {
@@ -1261,11 +1327,17 @@ struct FusedPipeline {
       bool half = true;
       for (int i = 0; i < g.count; ++i) half = half && g.a[i].kz_max <= (NZ / 2 - 1) / 2;
       if (half) {
-        fwd_launch<true>(g, nb, s);
+        if (use_hy(g))
+          fwd_launch<true, true>(g, nb, s);
+        else
+          fwd_launch<true, false>(g, nb, s);
         return;
       }
     }
-    fwd_launch<false>(g, nb, s);
+    if (use_hy(g))
+      fwd_launch<false, true>(g, nb, s);
+    else
+      fwd_launch<false, false>(g, nb, s);
   }
   static void plane(const PassGroup& g, int nb, hipStream_t s) {
     if constexpr (PM == 2) {
@@ -1277,6 +1349,14 @@ struct FusedPipeline {
       bool band = true;
       for (int i = 0; i < g.count; ++i) band = band && g.a[i].kx_max <= QB;
       if (band) {
+        if constexpr (HYOK) {
+          if (use_hy(g)) {
+            hipLaunchKernelGGL(
+                (k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB, GMP, true, SZH>),
+                dim3(plane_grid(nb)), dim3(NTQ), lds, s, g);
+            return;
+          }
+        }
         hipLaunchKernelGGL((k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB, GMP>),
                            dim3(plane_grid(nb)), dim3(NTQ), lds, s, g);
         return;
@@ -1327,9 +1407,17 @@ struct FusedPipeline {
         reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, 0, GMP>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess || QB == 0) return e;
-    return hipFuncSetAttribute(
+    e = hipFuncSetAttribute(
         reinterpret_cast<const void*>(&k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB, GMP>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if constexpr (HYOK) {
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(
+                &k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB, GMP, true, SZH>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    return e;
   }
   static Variant describe(const char* name) {
     Variant v{};
@@ -1355,6 +1443,8 @@ struct FusedPipeline {
     fill_radices(v.yi, v.nyi, SYI{});
     v.nzh = 0;
     if constexpr (HZOK) fill_radices(v.zh, v.nzh, SZH{});
+    v.qb = QB;
+    v.hy = HYOK;
     v.plane_lds = lds;
     v.pair_fwd = &pair_fwd;
     v.plane = &plane;

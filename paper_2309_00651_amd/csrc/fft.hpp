@@ -270,10 +270,12 @@ template <bool INV, typename T> struct DFT<16, INV, T> : DFTPQ<4, 4, INV, T> {};
 //     y*P + (x ^ ((x >> 3) & 7)), an XOR inside each block of 8 along x that
 //     spreads the stride-8 first-stage writes of the row transforms over the
 //     banks without extra LDS (needs N % 8 == 0).
-//   3 a band of columns of an N x N plane: M = 2Q + 1 sequences m are the
-//     columns x = 0..Q and N-Q..N-1 (m > Q maps to x = m + N - M); element n
-//     of column m at n*ES + x (TS = 1).
-template <typename T_, int N_, int M_, int NT_, bool MFAST_, int ES_, int TS_, int SWZ_ = 0>
+//   3 a band of columns of a plane BW points wide (BW = N unless the columns
+//     are transformed at another length): M = 2Q + 1 sequences m are the
+//     columns x = 0..Q and BW-Q..BW-1 (m > Q maps to x = m + BW - M); element
+//     n of column m at n*ES + x (TS = 1).
+template <typename T_, int N_, int M_, int NT_, bool MFAST_, int ES_, int TS_, int SWZ_ = 0,
+          int BW_ = N_>
 struct Geom {
   using T = T_;
   static constexpr int N = N_;     // transform length
@@ -283,8 +285,9 @@ struct Geom {
   static constexpr int ES = ES_;   // LDS stride between elements of a sequence
   static constexpr int TS = TS_;   // LDS stride between sequences
   static constexpr int SWZ = SWZ_;
+  static constexpr int BW = BW_;
   // column of sequence m in a band geometry (SWZ == 3)
-  HFX_HD static int band_col(int m) { return m <= (M - 1) / 2 ? m : m + N - M; }
+  HFX_HD static int band_col(int m) { return m <= (M - 1) / 2 ? m : m + BW - M; }
   HFX_HD static int idx(int m, int n) {
     if constexpr (SWZ == 1) {
       return m * TS + (n ^ ((n >> 3) & 7));

@@ -78,6 +78,7 @@ struct SystemPlan {
   // no plane is skipped)
   int kz_max = 1 << 30;
   int kx_max = 1 << 30;  // the same along x (from L_x)
+  int ky_max = 1 << 30;  // and along y (from L_y)
   int tiles_per_batch = 1;
   int slots_per_batch = 0;
   std::vector<TileDesc> tiles;
@@ -283,6 +284,14 @@ int bricks_per_tile(const Variant* v) {
 // 2 kz_max + 1 <= nz / 2 (the same test as the kernels' launchers).
 bool half_z(const Variant* v, int kz_max) {
   return v->nzh > 0 && v->nz % 2 == 0 && kz_max <= (v->nz / 2 - 1) / 2;
+}
+
+// Whether a system's plane pass takes half-height input (pass 1 on the even
+// rows only): x band within the plane kernel's band columns and y band within
+// a quarter of the grid (the same test as the kernels' launchers, over every
+// system of a launch).
+bool half_y(const Variant* v, int kx_max, int ky_max) {
+  return v->hy && kx_max <= v->qb && ky_max <= (v->n / 2 - 1) / 2;
 }
 
 ScheduleShape shape_of(const SystemPlan& sp) {
@@ -647,6 +656,7 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
     a.n_orb = sp.sys.n_orb;
     a.kz_max = sp.kz_max;
     a.kx_max = sp.kx_max;
+    a.ky_max = sp.ky_max;
     a.zero = sp.d_zero;
     max_batches = std::max(max_batches, sp.batches.size());
   }
@@ -678,6 +688,13 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
     double by_fwd = 0, fl_fwd = 0, by_pl = 0, fl_pl = 0, by_row = 0, fl_row = 0, by_col = 0,
            fl_col = 0, by_inv = 0, fl_inv = 0;
     std::vector<int> nb_fwd, nb_pl, nb_row, nb_col, nb_inv;
+    // half-height plane input: a decision for the whole launch, as the
+    // kernels' launchers take it
+    bool hy = v->hy;
+    for (int c = 0; c < nc; ++c)
+      if (k < calls[c].sp->batches.size())
+        hy = hy && half_y(v, calls[c].sp->kx_max, calls[c].sp->ky_max);
+    const double yf = hy ? 0.5 : 1.0;  // share of the rows pass 1 runs on
     for (int c = 0; c < nc; ++c) {
       SystemPlan& sp = *calls[c].sp;
       if (k >= sp.batches.size()) continue;
@@ -718,12 +735,14 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
       }
       const double grids = (double)b.n_active;
       const int kp = kz_planes(nz, sp.kz_max);
-      nb_fwd.push_back(b.n_tiles * br);
-      // a half-length forward z transform reads the orbitals on even z only
-      by_fwd += orbs * nr * elem * (half_z(v, sp.kz_max) ? 0.5 : 1.0) + grids * nr * ce * kzf;
-      fl_fwd += grids * fft_z;
+      nb_fwd.push_back(b.n_tiles * (hy ? (n / 2) * nxb : br));
+      // a half-length forward z transform reads the orbitals on even z only,
+      // half-height input on even y only (and stores half the rows)
+      by_fwd += orbs * nr * elem * (half_z(v, sp.kz_max) ? 0.5 : 1.0) * yf +
+                grids * nr * ce * kzf * yf;
+      fl_fwd += grids * fft_z * yf;
       nb_pl.push_back(b.n_active * kp);
-      by_pl += grids * nr * ce * 2.0 * kzf;
+      by_pl += grids * nr * ce * (1.0 + yf) * kzf;
       fl_pl += grids * fft_axis * 4.0 * kzf;
       nb_row.push_back(b.n_active * ((kp * n + v->rows_per_wg - 1) / std::max(v->rows_per_wg, 1)));
       by_row += grids * nr * ce * 2.0 * kzf;
@@ -1269,6 +1288,7 @@ hfx_status hfx_plan_create(hfx_plan* out, const hfx_system* sys, int n_sys, int 
     schedule_all_pairs(sp, sp.tiles_cap);
     sp.kz_max = kz_max_for(ecut, sys[i].L[2]);
     sp.kx_max = kz_max_for(ecut, sys[i].L[0]);
+    sp.ky_max = kz_max_for(ecut, sys[i].L[1]);
     sp.psi_off = psi_off;
     sp.m_off = m_off;
     sp.orb_off = orb_off;
@@ -1686,6 +1706,7 @@ const char* hfx_plan_describe(hfx_plan plan, int system) {
                                           : std::string()) +
                   (half_z(v, sp.kz_max) ? " z_fwd=half(" + sched(v->zh, v->nzh) + ")"
                                         : std::string()) +
+                  (half_y(v, sp.kx_max, sp.ky_max) ? " y_rows=half" : std::string()) +
                   " tiles_per_batch=" + std::to_string(sp.tiles_per_batch) +
                   " batches=" + std::to_string(sp.batches.size()) +
                   " streams=" + std::to_string(sp.nstreams) +

@@ -76,6 +76,7 @@ struct PassArgs {
   // the plane pass may skip the y transforms of those columns (kx_max >=
   // N / 2: every column is kept).
   int kx_max;
+  int ky_max;  // the same along y
 };
 
 // Zero block of band-limited plans: one 16-byte element per thread of a
@@ -139,6 +140,8 @@ struct Variant {
   bool persistent; // plane kernel loops over planes (grid of resident workgroups only)
   int zf[4], nzf, zi[4], nzi;  // z radix schedules (forward, inverse)
   int zh[4], nzh;              // forward z at half length (nzh = 0: not compiled)
+  int qb;                      // band columns of the plane kernel (|kx| <= qb), 0: none
+  bool hy;                     // half-height plane input compiled (band-limited y)
   int xf[4], nxf, xi[4], nxi;  // x
   int yf[4], nyf, yi[4], nyi;  // y
   size_t plane_lds;            // dynamic LDS bytes of the plane/row kernels

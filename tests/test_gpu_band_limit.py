@@ -61,6 +61,10 @@ def test_band_limited_planes_skipped(prec, n, nz, box, n_orb):
     plan = hfx.Plan(hfx.SystemSpec((n, n, nz), box, n_orb), prec, options=f"ecut={ecut}",
                     device=dev)
     assert f"kz_max={kzm}" in plan.describe()
+    # float32 plans whose pair band fits in half the z frequencies run the
+    # forward z transform at half length on the even z points
+    half = prec == hfx.FP32 and 2 * kzm + 1 <= nz // 2
+    assert ("z_fwd=half" in plan.describe()) == half
     pt = torch.from_numpy(psi).to(dev)
     kpsi, ex = plan.apply_exchange(pt)
     e_only = plan.exchange_energy(pt)
@@ -164,6 +168,7 @@ def test_band_limited_every_large_variant(n, L, ecut):
         plan = hfx.Plan(hfx.SystemSpec(n, box, n_orb), hfx.FP32, options=f"ecut={ecut};variant={v}",
                         device=dev)
         assert "kz_max" in plan.describe()
+        assert ("z_fwd=half" in plan.describe()) == (ecut == 5.0)
         kpsi, ex = plan.apply_exchange(pt)
         torch.cuda.synchronize()
         rel = abs(float(ex[0]) - ref["ex"]) / abs(ref["ex"])
