@@ -109,15 +109,20 @@ typedef struct hfx_plan_t* hfx_plan;
  * ecut (true of plane-wave orbitals of that cutoff, and kept by linear
  * combinations such as orthonormalisation): pair densities then vanish on the
  * kz planes with |kz| > 2 floor(sqrt(2 ecut) L_z / 2 pi), which the passes
- * skip (results agree with the full transform to rounding; orbitals outside
- * the sphere give wrong results, which check=1 detects); check=1 (or the
+ * skip, and, in float32 plans, where the band fits in half the grid along z
+ * (and along x and y on cubic grids), the first pass transforms only the
+ * even z points and rows and the plane pass only the band's columns
+ * (results agree with the full transform to rounding; orbitals outside the
+ * sphere give wrong results, which check=1 detects); check=1 (or the
  * environment variable HFX_CHECK_INPUTS=1) makes the energy, K psi, matrix
  * and gradient calls check psi first and return HFX_EINVAL, launching
  * nothing else, when an orbital holds a non-finite value or, in a plan with
- * ecut=, has more than 1e-12 of its power beyond the z band |m_z| <=
- * floor(sqrt(2 ecut) L_z / 2 pi) that the skipped planes rely on (a direct
- * z transform of every orbital column in float64; the call then waits for
- * its stream; skipped under graph capture); mix=<a>,
+ * ecut=, has more than 1e-12 of its power beyond the band |m| <=
+ * floor(sqrt(2 ecut) L / 2 pi) along z, y or x, which the skipped planes,
+ * the half-length z transform, the plane pass's band columns and its
+ * half-height input rely on (direct transforms of every orbital line along
+ * each axis in float64; the call then waits for its stream; skipped under
+ * graph capture); mix=<a>,
  * 0 < a <= 1,
  * is a hybrid functional's exact-exchange fraction: the kernel is scaled by a,
  * so E_x, K psi, M, the gradient and the ACE operator are a times the full

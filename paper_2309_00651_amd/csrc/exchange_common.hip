@@ -89,50 +89,58 @@ __global__ void __launch_bounds__(256) k_mask(double* __restrict__ m,
   if (i < n && !keep[i]) m[i] = 0.0;
 }
 
-// Input check of one x-chunk of one (orbital, y) row: the number of
-// non-finite values, sum psi^2, and, when m_max >= 0, the power of the z
-// spectrum beyond |m_z| <= m_max, sum over those k of |sum_z psi(z)
-// e^(-2 pi i k z / nz)|^2 (nz times its share of sum psi^2, by Parseval).
-// Direct DFT of the pruned frequencies from a column block in LDS: a check,
-// not a hot path.  One 64-thread workgroup: 32 x columns, two halves
-// splitting z rows and frequencies; a fixed-order wavefront sum.
+// Input check of 32 lines of psi along one axis: the number of non-finite
+// values, sum psi^2, and, when m_max >= 0, the power of the spectrum beyond
+// |m| <= m_max, sum over those k of |sum_z psi(z) e^(-2 pi i k z / len)|^2
+// (len times its share of sum psi^2, by Parseval).  Direct DFT of the pruned
+// frequencies from a line block in LDS: a check, not a hot path.  One
+// 64-thread workgroup: 32 lines, two halves splitting points and
+// frequencies; a fixed-order wavefront sum.
 constexpr int kCheckXC = 32, kCheckNZ = 128;
-__global__ void __launch_bounds__(64) k_check_orbitals(const double* __restrict__ psi, int nx,
-                                                      int ny, int nz, int m_max,
-                                                      double* __restrict__ part) {
+// Lines of psi along one axis, 32 per workgroup (two halves of 32 threads
+// share the points of a line): line l of orbital o starts at
+// o * ostride + u * so + l * sl (u < no: the third axis) and has len points
+// at stride sa.  Each thread sums its line's squares, counts non-finite
+// values, and forms the direct DFT of the line at the frequencies |m| > m_max
+// (m_max < 0: none), summing their power.
+__global__ void __launch_bounds__(64) k_check_orbitals(const double* __restrict__ psi,
+                                                      long long ostride, int len, long long sa,
+                                                      int nl, long long sl, int no, long long so,
+                                                      int m_max, double* __restrict__ part) {
   __shared__ double col[kCheckNZ][kCheckXC + 1];
   __shared__ double twc[kCheckNZ], tws[kCheckNZ];
-  const int xcs = (nx + kCheckXC - 1) / kCheckXC;
+  const int lcs = (nl + kCheckXC - 1) / kCheckXC;
   const long long b = blockIdx.x;
-  const int xc = (int)(b % xcs);
-  const int y = (int)((b / xcs) % ny);
-  const long long o = b / ((long long)xcs * ny);
+  const int lc = (int)(b % lcs);
+  const int u = (int)((b / lcs) % no);
+  const long long o = b / ((long long)lcs * no);
   const int t = threadIdx.x, c = t & (kCheckXC - 1), h = t >> 5;
-  const int x = xc * kCheckXC + c;
-  const bool valid = x < nx;
+  const int l = lc * kCheckXC + c;
+  const bool valid = l < nl;
+  const long long base = o * ostride + u * so + (valid ? l : 0) * sl;
   double tot = 0.0, bad = 0.0, oob = 0.0;
-  for (int z = h; z < nz; z += 2) {
-    const double v = valid ? psi[((o * nz + z) * ny + y) * (long long)nx + x] : 0.0;
+  for (int z = h; z < len; z += 2) {
+    const double v = valid ? psi[base + z * sa] : 0.0;
     col[z][c] = v;
     tot += v * v;
     bad += isfinite(v) ? 0.0 : 1.0;
   }
-  for (int k = t; k < nz; k += 64) {
+  for (int k = t; k < len; k += 64) {
     double sn, cs;
-    sincospi(-2.0 * k / nz, &sn, &cs);
+    sincospi(-2.0 * k / len, &sn, &cs);
     twc[k] = cs;
     tws[k] = sn;
   }
   __syncthreads();
   if (m_max >= 0 && valid) {
-    for (int k = m_max + 1 + h; k <= nz - 1 - m_max; k += 2) {
+    for (int k = m_max + 1 + h; k <= len - 1 - m_max; k += 2) {
       double re = 0.0, im = 0.0;
-      int idx = 0;  // k z mod nz
-      for (int z = 0; z < nz; ++z) {
+      int idx = 0;  // k z mod len
+      for (int z = 0; z < len; ++z) {
         re += col[z][c] * twc[idx];
         im += col[z][c] * tws[idx];
         idx += k;
-        if (idx >= nz) idx -= nz;
+        if (idx >= len) idx -= len;
       }
       oob += re * re + im * im;
     }
@@ -149,15 +157,31 @@ __global__ void __launch_bounds__(64) k_check_orbitals(const double* __restrict_
   }
 }
 
-long long check_partials(int n_orb, int nx, int ny) {
-  return (long long)n_orb * ny * ((nx + kCheckXC - 1) / kCheckXC);
+// Geometry of the lines along axis a (0 x, 1 y, 2 z) of a [z][y][x] orbital:
+// the lanes of a workgroup take neighbouring x (axes y and z) or y (axis x).
+struct CheckAxis {
+  int len, nl, no;
+  long long sa, sl, so;
+};
+static CheckAxis check_axis(int a, int nx, int ny, int nz) {
+  const long long nxy = (long long)nx * ny;
+  if (a == 2) return {nz, nx, ny, nxy, 1, nx};
+  if (a == 1) return {ny, nx, nz, nx, 1, nxy};
+  return {nx, ny, nz, 1, nx, nxy};
 }
 
-bool launch_check_orbitals(const double* psi, int n_orb, int nx, int ny, int nz, int m_max,
-                           double* part, hipStream_t s) {
-  if (nz > kCheckNZ) return false;
-  hipLaunchKernelGGL(k_check_orbitals, dim3((unsigned)check_partials(n_orb, nx, ny)), dim3(64),
-                     0, s, psi, nx, ny, nz, m_max, part);
+long long check_partials(int n_orb, int nx, int ny, int nz, int axis) {
+  const CheckAxis g = check_axis(axis, nx, ny, nz);
+  return (long long)n_orb * g.no * ((g.nl + kCheckXC - 1) / kCheckXC);
+}
+
+bool launch_check_orbitals(const double* psi, int n_orb, int nx, int ny, int nz, int axis,
+                           int m_max, double* part, hipStream_t s) {
+  const CheckAxis g = check_axis(axis, nx, ny, nz);
+  if (g.len > kCheckNZ) return false;
+  hipLaunchKernelGGL(k_check_orbitals, dim3((unsigned)check_partials(n_orb, nx, ny, nz, axis)),
+                     dim3(64), 0, s, psi, (long long)nx * ny * nz, g.len, g.sa, g.nl, g.sl, g.no,
+                     g.so, m_max, part);
   return true;
 }
 

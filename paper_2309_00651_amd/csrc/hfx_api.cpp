@@ -478,43 +478,54 @@ hfx_status check_call(hfx_plan plan, const void* psi, void* ws, size_t ws_bytes)
 constexpr double kBandTolerance = 1e-12;
 
 // Input check (option check=1): every orbital finite, and, for band-limited
-// plans, inside the z band |m_z| <= kz_max / 2 that the skipped kz planes
-// rely on.  Host-synchronous (waits for `st`); skipped under graph capture.
+// plans, inside the bands the passes rely on: |m| <= k_max / 2 along z (the
+// skipped kz planes and the half-length z transform), x (the plane pass's band
+// columns) and y (its half-height input).  Host-synchronous (waits for `st`);
+// skipped under graph capture.
 hfx_status check_inputs(hfx_plan plan, const double* psi, char* ws, hipStream_t st) {
   if (!plan->check || plan->capturing) return HFX_OK;
   for (size_t i = 0; i < plan->sys.size(); ++i) {
     const SystemPlan& sp = plan->sys[i];
     const int nx = sp.sys.n[0], ny = sp.sys.n[1], nz = sp.sys.n[2];
-    const int m_max = sp.kz_max < nz / 2 ? sp.kz_max / 2 : -1;
+    const int len[3] = {nx, ny, nz};
+    const int kmax[3] = {sp.kx_max, sp.ky_max, sp.kz_max};
+    const char* name[3] = {"x", "y", "z"};
     double* part = reinterpret_cast<double*>(ws + sp.off_ortho);
-    const long long np = check_partials(sp.sys.n_orb, nx, ny);
-    if (!launch_check_orbitals(psi + sp.psi_off, sp.sys.n_orb, nx, ny, nz, m_max, part, st))
-      return fail(HFX_EUNSUPPORTED, "input check supports z lengths up to 128");
-    HIP_TRY(hipGetLastError());
-    std::vector<double> h((size_t)np * 3);
-    HIP_TRY(hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    const long long per_orb = np / sp.sys.n_orb;
-    for (int o = 0; o < sp.sys.n_orb; ++o) {
-      double bad = 0.0, tot = 0.0, oob = 0.0;
-      for (long long k = 0; k < per_orb; ++k) {
-        const double* q = &h[(size_t)(o * per_orb + k) * 3];
-        bad += q[0];
-        tot += q[1];
-        oob += q[2];
-      }
-      const std::string at = "system " + std::to_string(i) + ", orbital " + std::to_string(o);
-      if (bad > 0.0 || !std::isfinite(tot))
-        return fail(HFX_EINVAL, "input check: " + at + " holds " +
-                                    std::to_string((long long)bad) + " non-finite values");
-      // Parseval: sum_k |psi~_k|^2 = nz sum_z psi(z)^2
-      const double frac = tot > 0.0 ? oob / (nz * tot) : 0.0;
-      if (m_max >= 0 && !(frac <= kBandTolerance)) {
-        char buf[64];
-        std::snprintf(buf, sizeof buf, "%.3e", frac);
-        return fail(HFX_EINVAL, "input check: " + at + " has " + buf +
-                                    " of its power beyond |m_z| <= " + std::to_string(m_max) +
-                                    ": the plan's ecut does not hold for these orbitals");
+    // z first: it also counts the non-finite values
+    for (int axis = 2; axis >= 0; --axis) {
+      const int m_max = kmax[axis] < len[axis] / 2 ? kmax[axis] / 2 : -1;
+      if (axis != 2 && m_max < 0) continue;
+      const long long np = check_partials(sp.sys.n_orb, nx, ny, nz, axis);
+      if (!launch_check_orbitals(psi + sp.psi_off, sp.sys.n_orb, nx, ny, nz, axis, m_max, part,
+                                 st))
+        return fail(HFX_EUNSUPPORTED, "input check supports axes of up to 128 points");
+      HIP_TRY(hipGetLastError());
+      std::vector<double> h((size_t)np * 3);
+      HIP_TRY(hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      const long long per_orb = np / sp.sys.n_orb;
+      for (int o = 0; o < sp.sys.n_orb; ++o) {
+        double bad = 0.0, tot = 0.0, oob = 0.0;
+        for (long long k = 0; k < per_orb; ++k) {
+          const double* q = &h[(size_t)(o * per_orb + k) * 3];
+          bad += q[0];
+          tot += q[1];
+          oob += q[2];
+        }
+        const std::string at = "system " + std::to_string(i) + ", orbital " + std::to_string(o);
+        if (bad > 0.0 || !std::isfinite(tot))
+          return fail(HFX_EINVAL, "input check: " + at + " holds " +
+                                      std::to_string((long long)bad) + " non-finite values");
+        // Parseval: sum_k |psi~_k|^2 = len sum psi^2 along every line
+        const double frac = tot > 0.0 ? oob / (len[axis] * tot) : 0.0;
+        if (m_max >= 0 && !(frac <= kBandTolerance)) {
+          char buf[64];
+          std::snprintf(buf, sizeof buf, "%.3e", frac);
+          return fail(HFX_EINVAL, "input check: " + at + " has " + buf +
+                                      " of its power beyond |m_" + name[axis] +
+                                      "| <= " + std::to_string(m_max) +
+                                      ": the plan's ecut does not hold for these orbitals");
+        }
       }
     }
   }

@@ -177,13 +177,14 @@ void launch_cast_group(const double* const* in, float* const* out, const size_t*
                        hipStream_t s);
 void launch_zero_group(void* const* p, const size_t* bytes, int count, hipStream_t s);
 
-// Input check (exchange_common.hip): per (orbital, y row, 32-column chunk)
-// three doubles: non-finite count, sum psi^2, power of the z spectrum beyond
-// |m_z| <= m_max (m_max < 0: not computed).  check_partials() triples of
-// output; false (nothing launched) for nz above 128.
-long long check_partials(int n_orb, int nx, int ny);
-bool launch_check_orbitals(const double* psi, int n_orb, int nx, int ny, int nz, int m_max,
-                           double* part, hipStream_t s);
+// Input check (exchange_common.hip) along axis 0 (x), 1 (y) or 2 (z): per
+// (orbital, index along a third axis, chunk of 32 lines) three doubles:
+// non-finite count, sum psi^2, power of the spectrum along the axis beyond
+// |m| <= m_max (m_max < 0: not computed).  check_partials() triples of
+// output; false (nothing launched) for an axis longer than 128.
+long long check_partials(int n_orb, int nx, int ny, int nz, int axis);
+bool launch_check_orbitals(const double* psi, int n_orb, int nx, int ny, int nz, int axis,
+                           int m_max, double* part, hipStream_t s);
 
 // Dense products (gemm.hip); `partial` holds gemm_partial_bytes(n_orb, nr).
 // C[k][l] = alpha * sum_r A[k][r] B[l][r], A float64 split into hi + lo

@@ -82,3 +82,23 @@ def test_non_finite_orbitals_rejected():
     psi[3, 5, 6, 7] = np.inf
     with pytest.raises(hfx.HfxError):
         plan.exchange_gradient(torch.from_numpy(psi).to(dev))
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_orbitals_beyond_the_band_along_x_or_y_rejected(axis):
+    """The band columns (x) and half-height planes (y) of the plane pass rely on
+    the x and y bands as the skipped planes rely on the z band: an orbital
+    whose z spectrum is fine but which holds a plane wave of |m| = 30 (beyond
+    the 20 Ha band, |m| <= 12 on this machine) along x or y is rejected too."""
+    dev = _dev()
+    plan = hfx.Plan(SPEC, hfx.FP32, options="ecut=20;check=1", device=dev)
+    psi = _gauss()
+    wave = np.cos(2 * np.pi * 30 * np.arange(N) / N)
+    if axis == "x":
+        psi[2] += 1e-3 * wave[None, None, :]
+    else:
+        psi[2] += 1e-3 * wave[None, :, None]
+    with pytest.raises(hfx.HfxError) as e:
+        plan.apply_exchange(torch.from_numpy(psi).to(dev))
+    assert e.value.status == 1 and f"|m_{axis}|" in str(e.value) and "orbital 2" in str(e.value)
+    print(f"  {e.value}", flush=True)
