@@ -176,8 +176,12 @@ template <> struct HalfZ<64> { using type = Sched<8, 8>; };
 // plane k (k <= kz_max) or k + NZ / 2 (k >= NZ / 2 - kz_max).
 // HY (plans whose plane pass takes half-height input): bricks run at the even
 // rows y = 2y' only and store row y' of their planes, with doubled products.
+// XD (with HY, half-width input too): the W columns of a brick are the even
+// x = 2x' (ψ read over 2W columns), stored as column x' of rows of N / 2
+// points (a quarter plane, N / 2 x N / 2 at the plane's start).
 template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL, bool SCR, int NZ = N,
-          bool HZ = false, class SZH = typename HalfZ<NZ / 2>::type, bool HY = false>
+          bool HZ = false, class SZH = typename HalfZ<NZ / 2>::type, bool HY = false,
+          bool XD = false>
 __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   int sys_ = 0;
   const int lg_ = grp.locate(xcd_remap(blockIdx.x, gridDim.x), sys_);
@@ -190,7 +194,9 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   using L = LastStage<G, SZ>;
   using E = FFT<G, false, SZ>;
   constexpr int RL = SchedInfo<SZ>::last;
-  constexpr int NXB = (N + W - 1) / W;
+  static_assert(!XD || HY, "half-width input comes with half-height input");
+  constexpr int NXI = XD ? N / 2 : N;          // x points (columns) stored per row
+  constexpr int NXB = (NXI + W - 1) / W;
   constexpr int BR = (HY ? N / 2 : N) * NXB;  // bricks per tile pair
   constexpr int P = ZL * W;
   constexpr int PT = (P + NT - 1) / NT;
@@ -198,6 +204,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   constexpr int ZSL = (ZL / RL) * N * N;  // offset between legs of a last-stage butterfly
   constexpr int ZS = HZ ? 2 : 1;         // z stride of the product points
   constexpr int YS = HY ? 2 : 1;         // y stride of the brick rows
+  constexpr int XS = XD ? 2 : 1;         // x stride of the brick columns
   __shared__ cpx<T> lds[ZL * W2];
   __shared__ TwEntry<T> twl[tw_slots<T, SZ>()];
   __shared__ T mul[kMaxRows * TT];  // pair-density means of the tile, [a][b]
@@ -219,8 +226,8 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   for (int k = 0; k < PT; ++k) {
     const int p = tid + k * NT;
     const int z = p / W, m = p - (p / W) * W;
-    vA[k] = p < P && (x0 + m) < N;
-    offA[k] = vA[k] ? (ZS * z * N + YS * y) * N + x0 + m : 0;
+    vA[k] = p < P && (x0 + m) < NXI;
+    offA[k] = vA[k] ? (ZS * z * N + YS * y) * N + XS * (x0 + m) : 0;
     ldsA[k] = z * W2 + m;
   }
   int offL[L::PER], gL[L::PER];
@@ -233,8 +240,8 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
     L::mj(tid, i, m, j);
     gL[i] = m / W;
     const int mx = m - gL[i] * W;
-    vL[i] = L::valid(tid, i) && (x0 + mx) < N;
-    offL[i] = vL[i] ? (j * N + y) * N + x0 + mx : 0;
+    vL[i] = L::valid(tid, i) && (x0 + mx) < NXI;
+    offL[i] = vL[i] ? j * N * N + y * NXI + x0 + mx : 0;
     kzL[i] = 0;
     hiL[i] = 0;
 #pragma unroll
@@ -308,7 +315,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
         // pairs not evaluated (screened, or below the diagonal) transform as
         // zeros, so they add no rounding to the pair sharing their grid; the
         // half-length transform takes doubled products
-        on[q] = pair_live<TT, SCR>(td, ia, b0 + q) ? T(ZS * YS) : T(0);
+        on[q] = pair_live<TT, SCR>(td, ia, b0 + q) ? T(ZS * YS * XS) : T(0);
       }
 #pragma unroll
       for (int k = 0; k < PT; ++k)
@@ -769,9 +776,14 @@ constexpr int plane_waves_per_eu() {
 // and the multiplied spectrum is written to its full-length rows (half-length
 // frequency k: row k below N / 4, else k + N / 2; the rows between, zeros)
 // before the inverse y transforms of length N, which restore every row.
+// XD (with HY, band-limited along x too): the input rows hold the even
+// x = 2x' only (N / 2 points each, a quarter plane); the forward x transforms
+// run at length N / 2 (the same half-length schedule) and place half-length
+// frequency k in column k below N / 4, else k + N / 2; the inverse x
+// transforms read the band's columns and take zeros elsewhere.
 template <typename T, int N, int NT, class SXF, class SXI, class SYF, class SYI, bool SW = false,
           bool PP = false, int NZ = N, int QB = 0, bool GM = false, bool HY = false,
-          class SYH = SYF>
+          class SYH = SYF, bool XD = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<T, N, NT>())))
 k_plane_conv(PassGroup grp) {
   int sys_ = 0;
@@ -780,21 +792,25 @@ k_plane_conv(PassGroup grp) {
   static_assert(!SW || N % 8 == 0, "swizzle needs whole blocks of 8");
   static_assert(QB == 0 || (!SW && 2 * QB + 1 < N), "band columns: no swizzle, inside the row");
   static_assert(!HY || (QB > 0 && N % 4 == 0), "half-height planes come with band columns");
+  static_assert(!XD || (HY && QB == N / 4), "half-width input comes with half-height input");
   constexpr int P = N + 1;
   constexpr int NI = HY ? N / 2 : N;  // rows of the plane's input
+  constexpr int NXI = XD ? N / 2 : N;  // points per input row
   constexpr int MB = QB ? 2 * QB + 1 : N;
   using GX = Geom<T, N, N, NT, false, 1, P, SW ? 1 : 0>;  // rows: sequence m = y, element n = x
-  using GXF = Geom<T, N, NI, NT, false, 1, P, SW ? 1 : 0>;  // the input rows
+  using GXF = Geom<T, NXI, NI, NT, false, 1, P, SW ? 1 : 0>;  // the input rows
+  using SXFX = std::conditional_t<XD, SYH, SXF>;
   // columns: sequence m = x (or the m-th column of the band), element n = y
   using GY = Geom<T, N, MB, NT, true, P, 1, SW ? 2 : (QB ? 3 : 0)>;
   using GYF = Geom<T, NI, MB, NT, true, P, 1, SW ? 2 : (QB ? 3 : 0), N>;  // forward y
   using SYFX = std::conditional_t<HY, SYH, SYF>;
-  using EXF = FFT<GXF, false, SXF>;
+  using EXF = FFT<GXF, false, SXFX>;
   using EXI = FFT<GX, true, SXI>;
   using EYF = FFT<GYF, false, SYFX>;
   using EYI = FFT<GY, true, SYI>;
-  using FX = FirstStage<GXF, SXF>;
-  using LXF = LastStage<GXF, SXF>;
+  using FX = FirstStage<GXF, SXFX>;
+  using LXF = LastStage<GXF, SXFX>;
+  using FXI = FirstStage<GX, SXI>;
   using LY = LastStage<GYF, SYFX>;
   using FYI = FirstStage<GY, SYI>;
   using LYI = LastStage<GY, SYI>;
@@ -810,9 +826,9 @@ k_plane_conv(PassGroup grp) {
   cpx<T>* __restrict__ gbase = static_cast<cpx<T>*>(a.grids);
 
   if (lg >= total) return;
-  __shared__ TwEntry<T> twxf[tw_slots<T, SXF>()], twyf[tw_slots<T, SYFX>()],
+  __shared__ TwEntry<T> twxf[tw_slots<T, SXFX>()], twyf[tw_slots<T, SYFX>()],
       twyi[tw_slots<T, SYI>()], twxi[tw_slots<T, SXI>()];
-  stage_twiddles<T, SXF, NT>(twxf, a.tw_xf, tid);  // visible after the first barrier
+  stage_twiddles<T, SXFX, NT>(twxf, XD ? a.tw_zh : a.tw_xf, tid);  // visible after the first barrier
   // half-height: the half-length schedule is the plan's half-length z one
   stage_twiddles<T, SYFX, NT>(twyf, HY ? a.tw_zh : a.tw_yf, tid);
   stage_twiddles<T, SYI, NT>(twyi, a.tw_yi, tid);
@@ -833,8 +849,8 @@ k_plane_conv(PassGroup grp) {
       int m, j;
       FX::mj(t, i, m, j);
 #pragma unroll
-      for (int r = 0; r < SchedInfo<SXF>::first; ++r)
-        v[i * SchedInfo<SXF>::first + r] = base[m * N + FX::in_pos(j, r)];
+      for (int r = 0; r < SchedInfo<SXFX>::first; ++r)
+        v[i * SchedInfo<SXFX>::first + r] = base[m * NXI + FX::in_pos(j, r)];
     }
   };
   // v(G) / N_r at the thread's multiply points of plane L
@@ -882,12 +898,26 @@ k_plane_conv(PassGroup grp) {
           int m, j;
           LXF::mj(t, i, m, j);
 #pragma unroll
-          for (int r = 0; r < SchedInfo<SXF>::last; ++r) {
-            const int x = LXF::out_pos(j, r);
-            const bool in = x <= QB || x >= N - QB;
-            plane[GX::idx(m, x)] = in ? o[i * SchedInfo<SXF>::last + r] : cpx<T>{T(0), T(0)};
-            // half-height: the lower rows' columns beyond the band are zero too
-            if (HY && !in) plane[GX::idx(m + NI, x)] = cpx<T>{T(0), T(0)};
+          for (int r = 0; r < SchedInfo<SXFX>::last; ++r) {
+            if constexpr (XD) {
+              // half-length frequency k: column k below N / 4, k + N / 2 above
+              // (negative); k = N / 4 (|kx| = N / 4, beyond the band, rounding
+              // noise only) clears the band's edge columns N / 4 and 3 N / 4;
+              // columns outside the band are never read (see the inverse x)
+              const int k = LXF::out_pos(j, r);
+              if (2 * k == NXI) {
+                plane[GX::idx(m, QB)] = cpx<T>{T(0), T(0)};
+                plane[GX::idx(m, N - QB)] = cpx<T>{T(0), T(0)};
+              } else {
+                plane[GX::idx(m, 2 * k < NXI ? k : k + N - NXI)] = o[i * SchedInfo<SXFX>::last + r];
+              }
+            } else {
+              const int x = LXF::out_pos(j, r);
+              const bool in = x <= QB || x >= N - QB;
+              plane[GX::idx(m, x)] = in ? o[i * SchedInfo<SXF>::last + r] : cpx<T>{T(0), T(0)};
+              // half-height: the lower rows' columns beyond the band are zero too
+              if (HY && !in) plane[GX::idx(m + NI, x)] = cpx<T>{T(0), T(0)};
+            }
           }
         }
       }
@@ -940,7 +970,26 @@ k_plane_conv(PassGroup grp) {
     __syncthreads();
     // x inverse, results straight to HBM
     cpx<T> ox[LXI::VALS];
-    EXI::lds2reg(plane, twxi, t, ox);
+    if constexpr (XD) {
+      // the band's columns from LDS, zeros elsewhere (never written)
+      cpx<T> xi[FXI::VALS];
+#pragma unroll
+      for (int i = 0; i < FXI::PER; ++i) {
+        if (!FXI::valid(t, i)) continue;
+        int m, j;
+        FXI::mj(t, i, m, j);
+#pragma unroll
+        for (int r = 0; r < SchedInfo<SXI>::first; ++r) {
+          const int x = FXI::in_pos(j, r);
+          xi[i * SchedInfo<SXI>::first + r] =
+              (x <= QB || x >= N - QB) ? plane[GX::idx(m, x)] : cpx<T>{T(0), T(0)};
+        }
+      }
+      __syncthreads();
+      EXI::reg2reg(xi, plane, twxi, t, ox);
+    } else {
+      EXI::lds2reg(plane, twxi, t, ox);
+    }
 #pragma unroll
     for (int i = 0; i < LXI::PER; ++i) {
       if (!LXI::valid(t, i)) continue;
@@ -1313,31 +1362,49 @@ struct FusedPipeline {
       return hy;
     }
   }
-  template <bool HZ, bool HY>
+  // half-width plane input as well (the host's half_x): every x band within
+  // N / 4 - 1, so that the even x points sample it exactly
+  static bool use_xd(const PassGroup& g) {
+    if constexpr (!HYOK) {
+      return false;
+    } else {
+      bool xd = use_hy(g);
+      for (int i = 0; i < g.count; ++i) xd = xd && g.a[i].kx_max <= (N / 2 - 1) / 2;
+      return xd;
+    }
+  }
+  template <bool HZ, bool HY, bool XD>
   static void fwd_launch(const PassGroup& g, int nb, hipStream_t s) {
     if (g.a[0].perm)
-      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true, NZ, HZ, SZH, HY>), dim3(nb),
-                         dim3(NTF), 0, s, g);
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, true, NZ, HZ, SZH, HY, XD>),
+                         dim3(nb), dim3(NTF), 0, s, g);
     else
-      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false, NZ, HZ, SZH, HY>), dim3(nb),
-                         dim3(NTF), 0, s, g);
+      hipLaunchKernelGGL((k_pair_fwd<T, N, W, NTF, TT, SZF, PIL, false, NZ, HZ, SZH, HY, XD>),
+                         dim3(nb), dim3(NTF), 0, s, g);
+  }
+  template <bool HZ>
+  static void fwd_rows(const PassGroup& g, int nb, hipStream_t s) {
+    if constexpr (HYOK) {
+      if (use_xd(g))
+        fwd_launch<HZ, true, true>(g, nb, s);
+      else if (use_hy(g))
+        fwd_launch<HZ, true, false>(g, nb, s);
+      else
+        fwd_launch<HZ, false, false>(g, nb, s);
+    } else {
+      fwd_launch<HZ, false, false>(g, nb, s);
+    }
   }
   static void pair_fwd(const PassGroup& g, int nb, hipStream_t s) {
     if constexpr (HZOK) {
       bool half = true;
       for (int i = 0; i < g.count; ++i) half = half && g.a[i].kz_max <= (NZ / 2 - 1) / 2;
       if (half) {
-        if (use_hy(g))
-          fwd_launch<true, true>(g, nb, s);
-        else
-          fwd_launch<true, false>(g, nb, s);
+        fwd_rows<true>(g, nb, s);
         return;
       }
     }
-    if (use_hy(g))
-      fwd_launch<false, true>(g, nb, s);
-    else
-      fwd_launch<false, false>(g, nb, s);
+    fwd_rows<false>(g, nb, s);
   }
   static void plane(const PassGroup& g, int nb, hipStream_t s) {
     if constexpr (PM == 2) {
@@ -1350,6 +1417,12 @@ struct FusedPipeline {
       for (int i = 0; i < g.count; ++i) band = band && g.a[i].kx_max <= QB;
       if (band) {
         if constexpr (HYOK) {
+          if (use_xd(g)) {
+            hipLaunchKernelGGL(
+                (k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB, GMP, true, SZH, true>),
+                dim3(plane_grid(nb)), dim3(NTQ), lds, s, g);
+            return;
+          }
           if (use_hy(g)) {
             hipLaunchKernelGGL(
                 (k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB, GMP, true, SZH>),
@@ -1416,6 +1489,11 @@ struct FusedPipeline {
             reinterpret_cast<const void*>(
                 &k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB, GMP, true, SZH>),
             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(
+                &k_plane_conv<T, N, NTQ, SXF, SXI, SYF, SYI, SW, PP, NZ, QB, GMP, true, SZH, true>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     }
     return e;
   }
@@ -1445,6 +1523,7 @@ struct FusedPipeline {
     if constexpr (HZOK) fill_radices(v.zh, v.nzh, SZH{});
     v.qb = QB;
     v.hy = HYOK;
+    v.xd = HYOK;
     v.plane_lds = lds;
     v.pair_fwd = &pair_fwd;
     v.plane = &plane;

@@ -294,6 +294,13 @@ bool half_y(const Variant* v, int kx_max, int ky_max) {
   return v->hy && kx_max <= v->qb && ky_max <= (v->n / 2 - 1) / 2;
 }
 
+// Whether the half-height input is half-width too (pass 1 on the even x
+// columns of the even rows, quarter planes): x band within a quarter of the
+// grid as well.
+bool half_x(const Variant* v, int kx_max, int ky_max) {
+  return v->xd && half_y(v, kx_max, ky_max) && kx_max <= (v->n / 2 - 1) / 2;
+}
+
 ScheduleShape shape_of(const SystemPlan& sp) {
   ScheduleShape sh;
   sh.n_orb = sp.sys.n_orb;
@@ -701,11 +708,15 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
     std::vector<int> nb_fwd, nb_pl, nb_row, nb_col, nb_inv;
     // half-height plane input: a decision for the whole launch, as the
     // kernels' launchers take it
-    bool hy = v->hy;
+    bool hy = v->hy, xd = v->xd;
     for (int c = 0; c < nc; ++c)
-      if (k < calls[c].sp->batches.size())
+      if (k < calls[c].sp->batches.size()) {
         hy = hy && half_y(v, calls[c].sp->kx_max, calls[c].sp->ky_max);
+        xd = xd && half_x(v, calls[c].sp->kx_max, calls[c].sp->ky_max);
+      }
     const double yf = hy ? 0.5 : 1.0;  // share of the rows pass 1 runs on
+    const double xf = xd ? 0.5 : 1.0;  // share of the columns it stores
+    const int nxbh = (n / 2 + v->brick - 1) / v->brick;  // bricks per half-width row
     for (int c = 0; c < nc; ++c) {
       SystemPlan& sp = *calls[c].sp;
       if (k >= sp.batches.size()) continue;
@@ -746,14 +757,16 @@ hfx_status run_exchange(hfx_plan plan, const std::vector<SysCall>& calls, char* 
       }
       const double grids = (double)b.n_active;
       const int kp = kz_planes(nz, sp.kz_max);
-      nb_fwd.push_back(b.n_tiles * (hy ? (n / 2) * nxb : br));
+      nb_fwd.push_back(b.n_tiles * (xd ? (n / 2) * nxbh : hy ? (n / 2) * nxb : br));
       // a half-length forward z transform reads the orbitals on even z only,
-      // half-height input on even y only (and stores half the rows)
+      // half-height input on even y only (and stores half the rows);
+      // half-width input stores half the columns (its orbital reads, every
+      // other point of a row, still move whole rows)
       by_fwd += orbs * nr * elem * (half_z(v, sp.kz_max) ? 0.5 : 1.0) * yf +
-                grids * nr * ce * kzf * yf;
-      fl_fwd += grids * fft_z * yf;
+                grids * nr * ce * kzf * yf * xf;
+      fl_fwd += grids * fft_z * yf * xf;
       nb_pl.push_back(b.n_active * kp);
-      by_pl += grids * nr * ce * (1.0 + yf) * kzf;
+      by_pl += grids * nr * ce * (1.0 + yf * xf) * kzf;
       fl_pl += grids * fft_axis * 4.0 * kzf;
       nb_row.push_back(b.n_active * ((kp * n + v->rows_per_wg - 1) / std::max(v->rows_per_wg, 1)));
       by_row += grids * nr * ce * 2.0 * kzf;
@@ -1718,6 +1731,7 @@ const char* hfx_plan_describe(hfx_plan plan, int system) {
                   (half_z(v, sp.kz_max) ? " z_fwd=half(" + sched(v->zh, v->nzh) + ")"
                                         : std::string()) +
                   (half_y(v, sp.kx_max, sp.ky_max) ? " y_rows=half" : std::string()) +
+                  (half_x(v, sp.kx_max, sp.ky_max) ? " x_cols=half" : std::string()) +
                   " tiles_per_batch=" + std::to_string(sp.tiles_per_batch) +
                   " batches=" + std::to_string(sp.batches.size()) +
                   " streams=" + std::to_string(sp.nstreams) +

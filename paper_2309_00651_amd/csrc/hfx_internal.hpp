@@ -142,6 +142,7 @@ struct Variant {
   int zh[4], nzh;              // forward z at half length (nzh = 0: not compiled)
   int qb;                      // band columns of the plane kernel (|kx| <= qb), 0: none
   bool hy;                     // half-height plane input compiled (band-limited y)
+  bool xd;                     // half-width plane input compiled too (band-limited x)
   int xf[4], nxf, xi[4], nxi;  // x
   int yf[4], nyf, yi[4], nyi;  // y
   size_t plane_lds;            // dynamic LDS bytes of the plane/row kernels

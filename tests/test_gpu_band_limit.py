@@ -65,6 +65,10 @@ def test_band_limited_planes_skipped(prec, n, nz, box, n_orb):
     # forward z transform at half length on the even z points
     half = prec == hfx.FP32 and 2 * kzm + 1 <= nz // 2
     assert ("z_fwd=half" in plan.describe()) == half
+    # at 64^3 the plane pass takes quarter planes: pass 1 on the even rows
+    # and columns (the x and y bands fit in a quarter of the grid too)
+    if prec == hfx.FP32 and n == 64:
+        assert "y_rows=half" in plan.describe() and "x_cols=half" in plan.describe()
     pt = torch.from_numpy(psi).to(dev)
     kpsi, ex = plan.apply_exchange(pt)
     e_only = plan.exchange_energy(pt)
@@ -168,7 +172,12 @@ def test_band_limited_every_large_variant(n, L, ecut):
         plan = hfx.Plan(hfx.SystemSpec(n, box, n_orb), hfx.FP32, options=f"ecut={ecut};variant={v}",
                         device=dev)
         assert "kz_max" in plan.describe()
-        assert ("z_fwd=half" in plan.describe()) == (ecut == 5.0)
+        d = plan.describe()
+        assert ("z_fwd=half" in d) == (ecut == 5.0)
+        # cubic boxes: the x band fits a quarter of the grid exactly when the
+        # y band does, so half-height input is half-width too
+        assert ("x_cols=half" in d) == ("y_rows=half" in d)
+        assert ecut == 5.0 or "y_rows=half" not in d
         kpsi, ex = plan.apply_exchange(pt)
         torch.cuda.synchronize()
         rel = abs(float(ex[0]) - ref["ex"]) / abs(ref["ex"])
