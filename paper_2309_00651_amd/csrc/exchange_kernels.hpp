@@ -531,11 +531,14 @@ __global__ void __launch_bounds__(NT)
       const cpx<T>* dummy = grids + (long long)td.slot0 * NR;
       const cpx<T>* g = ok ? grids + (long long)(slot0 + gF[i]) * NR + offF[i] : dummy;
       if constexpr (KZ == 1) {
-        // a leg on a pruned plane loads from the plan's zero block (this
-        // thread's own element): every load is issued and its value used as
-        // loaded (no branch, no select)
-        static_assert(NT * sizeof(cpx<T>) <= kZeroBytes, "zero block per thread");
-        const cpx<T>* zero = static_cast<const cpx<T>*>(a.zero) + tid;
+        // a leg on a pruned plane loads from the plan's zero block: every
+        // load is issued and its value used as loaded (no branch, no select).
+        // All lanes read the block's first element (one request per wave),
+        // so no per-lane pointer stays live across the loop: at 96^3 a
+        // per-lane one cost three spilled registers in the loop, whose
+        // scratch lines were evicted by the grid stream and written back
+        // (about 10 % extra HBM traffic)
+        const cpx<T>* zero = static_cast<const cpx<T>*>(a.zero);
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
           const bool kept = (kzF[i] >> r) & 1u;
@@ -565,7 +568,7 @@ __global__ void __launch_bounds__(NT)
       const bool ok = vFL[k] && ((um >> gFL[k]) & 1u);
       const cpx<T>* g = ok ? grids + (long long)(slot0 + gFL[k]) * NR + offFL[k] : dummy;
       if constexpr (KZ == 1) {
-        const cpx<T>* zero = static_cast<const cpx<T>*>(a.zero) + tid;
+        const cpx<T>* zero = static_cast<const cpx<T>*>(a.zero);
         v[k] = *(kzFL[k] ? g : zero);
       } else if constexpr (KZ == 2) {
         const cpx<T> val = *(ok && kzFL[k] ? g : dummy);

@@ -79,8 +79,8 @@ struct PassArgs {
   int ky_max;  // the same along y
 };
 
-// Zero block of band-limited plans: one 16-byte element per thread of a
-// workgroup, so that pruned loads spread over many cache lines.
+// Zero block of band-limited plans (the pruned planes' loads read its first
+// element).
 constexpr int kZeroBytes = 1024 * 16;
 
 // Whether z frequency index k (0 <= k < nz) lies on a kept plane.
