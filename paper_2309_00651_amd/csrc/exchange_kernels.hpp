@@ -144,6 +144,17 @@ __device__ __forceinline__ void stage_means(T* dst, const PassArgs& a, const Til
 // keeps every thread of a 256-thread workgroup busy in both stages (4 x 15
 // leaves half of them idle in the radix-15 stage: 103.6 against 93.5 ms per
 // K psi pass at 120^3 / 384 orbitals; 5 x 12 97.7, 6 x 10 95.9).
+// Row stride (elements) of the reduced plane input that pass 1 hands to the
+// plane pass: half-height planes (HY) hold N / 2 rows of N points, with
+// half-width (XD) rows of N / 2 points; the stride is rounded up to 16
+// elements, so every 16-column brick row of pass 1 is one whole 128-byte line
+// (at 108 or 120 points a row of 54, 60 or 108 elements would leave most
+// brick rows straddling two lines).  Full planes keep stride N.
+template <int N, bool HY, bool XD>
+constexpr int reduced_row_stride() {
+  return HY ? ((XD ? N / 2 : N) + 15) / 16 * 16 : N;
+}
+
 template <int L> struct HalfZ { using type = void; };
 template <> struct HalfZ<24> { using type = Sched<4, 6>; };
 template <> struct HalfZ<32> { using type = Sched<4, 8>; };
@@ -175,10 +186,11 @@ template <> struct HalfZ<64> { using type = Sched<8, 8>; };
 // the products are doubled (exact) and half-length frequency k maps to grid
 // plane k (k <= kz_max) or k + NZ / 2 (k >= NZ / 2 - kz_max).
 // HY (plans whose plane pass takes half-height input): bricks run at the even
-// rows y = 2y' only and store row y' of their planes, with doubled products.
+// rows y = 2y' only and store row y' of their planes, with doubled products
+// (rows of reduced_row_stride elements at the plane's start).
 // XD (with HY, half-width input too): the W columns of a brick are the even
-// x = 2x' (ψ read over 2W columns), stored as column x' of rows of N / 2
-// points (a quarter plane, N / 2 x N / 2 at the plane's start).
+// x = 2x' (psi read over 2W columns), stored as column x' of rows of N / 2
+// points (a quarter plane).
 template <typename T, int N, int W, int NT, int TT, class SZF, bool PIL, bool SCR, int NZ = N,
           bool HZ = false, class SZH = typename HalfZ<NZ / 2>::type, bool HY = false,
           bool XD = false>
@@ -196,6 +208,8 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   constexpr int RL = SchedInfo<SZ>::last;
   static_assert(!XD || HY, "half-width input comes with half-height input");
   constexpr int NXI = XD ? N / 2 : N;          // x points (columns) stored per row
+  constexpr int XST = reduced_row_stride<N, HY, XD>();  // stored row stride
+  static_assert(!HY || (N / 2) * XST <= N * N, "reduced planes fit the plane's slot");
   constexpr int NXB = (NXI + W - 1) / W;
   constexpr int BR = (HY ? N / 2 : N) * NXB;  // bricks per tile pair
   constexpr int P = ZL * W;
@@ -241,7 +255,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
     gL[i] = m / W;
     const int mx = m - gL[i] * W;
     vL[i] = L::valid(tid, i) && (x0 + mx) < NXI;
-    offL[i] = vL[i] ? j * N * N + y * NXI + x0 + mx : 0;
+    offL[i] = vL[i] ? j * N * N + y * XST + x0 + mx : 0;
     kzL[i] = 0;
     hiL[i] = 0;
 #pragma unroll
@@ -779,6 +793,7 @@ constexpr int plane_waves_per_eu() {
 // and the multiplied spectrum is written to its full-length rows (half-length
 // frequency k: row k below N / 4, else k + N / 2; the rows between, zeros)
 // before the inverse y transforms of length N, which restore every row.
+// In both modes the input rows lie reduced_row_stride elements apart.
 // XD (with HY, band-limited along x too): the input rows hold the even
 // x = 2x' only (N / 2 points each, a quarter plane); the forward x transforms
 // run at length N / 2 (the same half-length schedule) and place half-length
@@ -799,6 +814,7 @@ k_plane_conv(PassGroup grp) {
   constexpr int P = N + 1;
   constexpr int NI = HY ? N / 2 : N;  // rows of the plane's input
   constexpr int NXI = XD ? N / 2 : N;  // points per input row
+  constexpr int XST = reduced_row_stride<N, HY, XD>();  // input row stride
   constexpr int MB = QB ? 2 * QB + 1 : N;
   using GX = Geom<T, N, N, NT, false, 1, P, SW ? 1 : 0>;  // rows: sequence m = y, element n = x
   using GXF = Geom<T, NXI, NI, NT, false, 1, P, SW ? 1 : 0>;  // the input rows
@@ -853,7 +869,7 @@ k_plane_conv(PassGroup grp) {
       FX::mj(t, i, m, j);
 #pragma unroll
       for (int r = 0; r < SchedInfo<SXFX>::first; ++r)
-        v[i * SchedInfo<SXFX>::first + r] = base[m * NXI + FX::in_pos(j, r)];
+        v[i * SchedInfo<SXFX>::first + r] = base[m * XST + FX::in_pos(j, r)];
     }
   };
   // v(G) / N_r at the thread's multiply points of plane L
