@@ -167,6 +167,10 @@ template <> struct HalfZ<64> { using type = Sched<8, 8>; };
 
 // ---------------------------------------------------------------------------
 // Pass 1: pair product + forward z FFT on bricks.
+// On full planes a brick is W consecutive points of the xy plane in storage
+// order (W x values of one row where N is a multiple of W; at other N a brick
+// may run on into the next row), so every brick row of psi and of the grids
+// is whole 64- or 128-byte segments, and no brick is partly off the grid.
 // Two pair grids are transformed together: LDS holds [z][2W] with the brick
 // of grid g in columns [gW, gW + W).  Thread tid forms the products at brick
 // points p = tid + k NT (k < PT, contiguous x for coalesced psi reads) for both
@@ -211,7 +215,12 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   constexpr int XST = reduced_row_stride<N, HY, XD>();  // stored row stride
   static_assert(!HY || (N / 2) * XST <= N * N, "reduced planes fit the plane's slot");
   constexpr int NXB = (NXI + W - 1) / W;
-  constexpr int BR = (HY ? N / 2 : N) * NXB;  // bricks per tile pair
+  // full planes: a brick is W consecutive points of the xy plane in storage
+  // order (flat bricks, whole cache lines at any N); reduced planes: W
+  // columns of one stored row
+  static_assert(HY || (N * N) % W == 0, "flat bricks tile the plane");
+  constexpr int BR = HY ? (N / 2) * NXB : N * N / W;  // bricks per tile pair
+  constexpr int LIM = HY ? NXI : N * N;  // bound of x0 + m
   constexpr int P = ZL * W;
   constexpr int PT = (P + NT - 1) / NT;
   constexpr long long NR = (long long)NZ * N * N;
@@ -226,7 +235,8 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   const int tid = threadIdx.x;
   const int lg = lg_;
   const int t = lg / BR, br = lg - t * BR;
-  const int y = br / NXB, x0 = (br - y * NXB) * W;  // y: the stored row (read at YS y)
+  // y: the stored row (read at YS y); flat bricks: y = 0, x0 = flat offset
+  const int y = HY ? br / NXB : 0, x0 = HY ? (br - y * NXB) * W : br * W;
   const TileDesc td = a.tiles[t];
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
   stage_twiddles<T, SZ, NT>(twl, HZ ? a.tw_zh : a.tw_zf, tid);
@@ -240,7 +250,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
   for (int k = 0; k < PT; ++k) {
     const int p = tid + k * NT;
     const int z = p / W, m = p - (p / W) * W;
-    vA[k] = p < P && (x0 + m) < NXI;
+    vA[k] = p < P && (x0 + m) < LIM;
     offA[k] = vA[k] ? (ZS * z * N + YS * y) * N + XS * (x0 + m) : 0;
     ldsA[k] = z * W2 + m;
   }
@@ -254,7 +264,7 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
     L::mj(tid, i, m, j);
     gL[i] = m / W;
     const int mx = m - gL[i] * W;
-    vL[i] = L::valid(tid, i) && (x0 + mx) < NXI;
+    vL[i] = L::valid(tid, i) && (x0 + mx) < LIM;
     offL[i] = vL[i] ? j * N * N + y * XST + x0 + mx : 0;
     kzL[i] = 0;
     hiL[i] = 0;
@@ -361,7 +371,8 @@ __global__ void __launch_bounds__(NT) k_pair_fwd(PassGroup grp) {
 }
 
 // ---------------------------------------------------------------------------
-// Pass 3: inverse z FFT + pair energies + K psi accumulation on bricks.
+// Pass 3: inverse z FFT + pair energies + K psi accumulation on bricks (flat
+// bricks, as in pass 1).
 // Two pair grids are transformed together ([z][2W] in LDS, as in pass 1).
 // The inverse transform leaves the potentials in LDS in natural order; the
 // accumulation then uses its own point map: thread tid owns brick points
@@ -405,8 +416,9 @@ __global__ void __launch_bounds__(NT)
   using F = FirstStage<G, SZI>;
   using E = FFT<G, true, SZI>;
   constexpr int RF = SchedInfo<SZI>::first;
-  constexpr int NXB = (N + W - 1) / W;
-  constexpr int BR = N * NXB;
+  // flat bricks: W consecutive points of the xy plane in storage order
+  static_assert((N * N) % W == 0, "flat bricks tile the plane");
+  constexpr int BR = N * N / W;
   constexpr int P = NZ * W;                // brick points
   constexpr int PT = (P + NT - 1) / NT;    // accumulation points per thread
   constexpr long long NR = (long long)NZ * N * N;
@@ -419,7 +431,8 @@ __global__ void __launch_bounds__(NT)
   const int tid = threadIdx.x;
   const int lg = lg_;
   const int t = lg / BR, br = lg - t * BR;
-  const int y = br / NXB, x0 = (br - y * NXB) * W;
+  const int x0 = br * W;  // flat offset of the brick in the xy plane
+  constexpr int LIM = N * N;
   const TileDesc td = a.tiles[t];
   const T* __restrict__ psi = static_cast<const T*>(a.psi);
   T* __restrict__ kpsi = static_cast<T*>(a.kpsi);
@@ -438,8 +451,8 @@ __global__ void __launch_bounds__(NT)
     F::mj(tid, i, m, j);
     gF[i] = m / W;
     const int mx = m - gF[i] * W;
-    vF[i] = F::valid(tid, i) && (x0 + mx) < N;
-    offF[i] = vF[i] ? (j * N + y) * N + x0 + mx : 0;
+    vF[i] = F::valid(tid, i) && (x0 + mx) < LIM;
+    offF[i] = vF[i] ? j * N * N + x0 + mx : 0;
     kzF[i] = ~0u;
     if constexpr (KZ != 0) {
       kzF[i] = 0;
@@ -453,13 +466,13 @@ __global__ void __launch_bounds__(NT)
   for (int k = 0; k < PT; ++k) {
     const int p = tid + k * NT;
     const int z = p / W, m = p - (p / W) * W;
-    vA[k] = p < P && (x0 + m) < N;
-    offA[k] = vA[k] ? (z * N + y) * N + x0 + m : 0;
+    vA[k] = p < P && (x0 + m) < LIM;
+    offA[k] = vA[k] ? z * N * N + x0 + m : 0;
     ldsA[k] = z * W2 + m;
   }
 
   // FL: element e = tid + k NT of the brick, e = z NG W + c (c: column of
-  // the transform, grid c / W, x = x0 + c mod W) -- the LDS index of the engine
+  // the transform, grid c / W, flat point x0 + c mod W) -- the LDS index of the engine
   constexpr int FE = NZ * W2;
   constexpr int FLV = FL ? (FE + NT - 1) / NT : 1;
   int offFL[FLV], gFL[FLV];
@@ -469,9 +482,9 @@ __global__ void __launch_bounds__(NT)
     const int e = tid + k * NT;
     const int z = e / W2, c = e - (e / W2) * W2;
     const int g = c / W, m = c - (c / W) * W;
-    vFL[k] = FL && e < FE && x0 + m < N;
+    vFL[k] = FL && e < FE && x0 + m < LIM;
     gFL[k] = g;
-    offFL[k] = vFL[k] ? (z * N + y) * N + x0 + m : 0;
+    offFL[k] = vFL[k] ? z * N * N + x0 + m : 0;
     kzFL[k] = KZ == 0 || kz_kept(z < NZ ? z : 0, NZ, a.kz_max);
   }
 

@@ -275,8 +275,11 @@ bool parse_count(const std::string& v, long long* out) {
   return true;
 }
 
+// Workgroups of pass 3 (and of pass 1 on full planes) per tile pair: flat
+// bricks of `brick` consecutive points of the n x n plane (the kernels assert
+// that they tile it).
 int bricks_per_tile(const Variant* v) {
-  return v->n * ((v->n + v->brick - 1) / v->brick);
+  return v->n * v->n / v->brick;
 }
 
 // Whether the forward z transform of pair_fwd runs at half length: pair
