@@ -8,9 +8,10 @@ beyond are empty (the skipped planes), and when 2 k_max + 1 <= n / 2 the even
 grid points sample the pair density exactly: the length-n/2 DFT of the even
 samples, doubled, equals the length-n DFT at every frequency |k| <= k_max
 (frequency k lands on index k mod n/2).  The half-length forward z transform
-of pass 1 and the half-height plane input of pass 2 rest on this; when the
-band does not fit, the identity fails (aliasing), which the negative case
-shows.
+of pass 1 and the half-height and half-width plane input of pass 2 rest on
+this (along z, y and x; for a kz plane the even rows and columns together,
+four times the quarter plane's 2D DFT); when the band does not fit, the
+identity fails (aliasing), which the negative case shows.
 """
 import math
 
@@ -36,7 +37,8 @@ def test_pair_band_and_half_length_sampling(n, L):
     km = k_max(ecut, L)
     assert 2 * km + 1 <= n // 2
     freqs = np.fft.fftfreq(n, 1.0 / n).astype(int)
-    for axis in (0, 1):  # z (half-length forward z) and y (half-height planes)
+    # z (half-length forward z), y (half-height planes), x (half-width planes)
+    for axis in (0, 1, 2):
         full = np.fft.fft(rho, axis=axis)
         scale = np.max(np.abs(full))
         out = np.abs(freqs) > km
@@ -66,3 +68,33 @@ def test_half_length_sampling_fails_beyond_the_band():
     half = 2.0 * np.fft.fft(rho[0:n:2], axis=0)
     worst = max(np.max(np.abs(full[k % n] - half[k % (n // 2)])) for k in range(-15, 16))
     assert worst > 1e-3 * np.max(np.abs(full))
+
+
+@pytest.mark.parametrize("n,L", [(72, 17.6), (108, 26.4)])
+def test_quarter_plane_sampling(n, L):
+    """The plane pass's quarter-plane input: a kz plane of a pair density
+    (after the z transform) sampled at even y and even x; four times the
+    (n/2 x n/2) DFT of those samples equals the plane's (n x n) DFT at every
+    (ky, kx) in the band, half-length index k mapping to frequency k below n/4
+    and to k - n/2 above it (the bin n/4 itself is beyond the band)."""
+    ecut = 5.0
+    rho = _pair(n, (L,) * 3, ecut, seed=8300 + n)
+    km = k_max(ecut, L)
+    assert 2 * km + 1 <= n // 2
+    planes = np.fft.fft(rho, axis=0)
+    h = n // 2
+    for kz in (0, 1, km):
+        plane = planes[kz]
+        full = np.fft.fft2(plane)
+        quarter = 4.0 * np.fft.fft2(plane[0::2, 0::2])
+        scale = np.max(np.abs(full))
+        assert np.max(np.abs(quarter[h // 2, :])) <= 1e-11 * scale
+        assert np.max(np.abs(quarter[:, h // 2])) <= 1e-11 * scale
+        for ky in range(h):
+            for kx in range(h):
+                if ky == h // 2 or kx == h // 2:
+                    continue
+                fy = ky if 2 * ky < h else ky - h
+                fx = kx if 2 * kx < h else kx - h
+                # in the band the two agree; beyond it (|f| > k_max) both vanish
+                assert abs(full[fy % n, fx % n] - quarter[ky, kx]) <= 1e-11 * scale
