@@ -185,3 +185,34 @@ def test_band_limited_every_large_variant(n, L, ecut):
         print(f"  rel dE {rel:.2e} max dK {dk:.2e}", flush=True)
         assert rel <= e_bar and dk <= k_bar
         del plan
+
+
+@pytest.mark.parametrize("box,rows,cols", [
+    ((16.0, 12.0, 14.0), True, False),   # x band 16 = n/4: band columns and half rows, full width
+    ((12.0, 16.0, 14.0), False, False),  # y band 16 > 15: full planes
+    ((12.0, 13.0, 14.0), True, True),    # both within 15: quarter planes
+], ids=["half-rows", "full", "quarter"])
+def test_band_limited_orthorhombic_decisions(box, rows, cols):
+    """Orthorhombic boxes at 5 Ha on 64^3 (float32): the x and y bands differ,
+    so the half-height and half-width decisions part (kx_max from L_x, ky_max
+    from L_y; the half-length z transform from L_z); each combination
+    against the oracle's full transform."""
+    n, n_orb, ecut = 64, 9, 5.0
+    shape = (n, n, n)
+    psi = generate.random_pw(shape, box, n_orb, ecut, seed=7400)
+    kx, ky = kz_max(ecut, box[0]), kz_max(ecut, box[1])
+    print(f"case box={box} kx_max={kx} ky_max={ky}", flush=True)
+    ref = oracle.exchange(psi, box, oracle.coulomb_kernel(shape, box, hfx.TRUNCATED, 0.0),
+                          workers=4)
+    dev = _dev()
+    plan = hfx.Plan(hfx.SystemSpec(n, box, n_orb), hfx.FP32, options=f"ecut={ecut}", device=dev)
+    d = plan.describe()
+    assert ("y_rows=half" in d) == rows and ("x_cols=half" in d) == cols
+    assert "z_fwd=half" in d
+    kpsi, ex = plan.apply_exchange(torch.from_numpy(psi).to(dev))
+    torch.cuda.synchronize()
+    e_bar, k_bar = bars(hfx.FP32, ref["kpsi"])
+    rel = abs(float(ex[0]) - ref["ex"]) / abs(ref["ex"])
+    dk = np.max(np.abs(kpsi.double().cpu().numpy() - ref["kpsi"]))
+    print(f"  rel dE {rel:.2e} max dK {dk:.2e}", flush=True)
+    assert rel <= e_bar and dk <= k_bar
