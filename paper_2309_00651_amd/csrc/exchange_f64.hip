@@ -27,6 +27,12 @@ using P96q384 = FusedPipeline<double, 96, 16, 8, Sched<8, 12>, Sched<12, 8>, 384
                               Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
 using P96z8 = FusedPipeline<double, 96, 16, 8, Sched<8, 12>, Sched<8, 12>, 768, Sched<8, 12>,
                             Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
+// three-stage inverse z: the accumulation kernel stays below 160 registers
+// (12 x 8 and 10 x 8 spill 14 without a cutoff)
+using P96s3 = FusedPipeline<double, 96, 16, 8, Sched<8, 12>, Sched<8, 4, 3>, 768, Sched<8, 12>,
+                            Sched<12, 8>, Sched<8, 12>, Sched<12, 8>>;
+using P80s3 = FusedPipeline<double, 80, 16, 8, Sched<8, 10>, Sched<5, 4, 4>, 640, Sched<8, 10>,
+                            Sched<10, 8>, Sched<8, 10>, Sched<10, 8>>;
 // slab cells (n x n x nz); the 128-point inverse z takes 8 x 4 x 4, with
 // which its accumulation kernel does not spill (see below)
 using P24x48 = FusedPipeline<double, 24, 16, 8, Sched<4, 12>, Sched<12, 4>, 144, Sched<4, 6>,
@@ -70,6 +76,8 @@ const Variant* variants_f64(int* count) {
       P96::describe("f64-n96"),
       P96q384::describe("f64-n96-q384"),
       P96z8::describe("f64-n96-z8"),
+      P96s3::describe("f64-n96-s3"),
+      P80s3::describe("f64-n80-s3"),
       P108::describe("f64-n108"),
       P108z::describe("f64-n108-z"),
       P120::describe("f64-n120"),
