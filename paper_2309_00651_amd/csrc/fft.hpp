@@ -89,6 +89,65 @@ HFX_HD T mulk(T x, double c) {
   }
 }
 
+// Low part of a float32 constant split hi + lo.  A remainder below 2^-46 |c|
+// is the float64 evaluation's own error of a constant that float32 holds
+// exactly (0.5 = sin(pi/6) comes out one float64 ulp low): taken as zero, so
+// the product needs no correction term.
+HFX_HD float lo_part(double c, float hi) {
+  const double lo = c - (double)hi;
+  const double ac = c < 0 ? -c : c;
+  return (lo < 0 ? -lo : lo) <= ac * 0x1p-46 ? 0.0f : (float)lo;
+}
+
+// A float32 power of two: its products are exact, with no bits below the
+// last place.
+HFX_HD bool pow2f(float h) { return (__builtin_bit_cast(unsigned, h) & 0x7fffffu) == 0u; }
+
+// x c + y d (+ z) for compile-time constants c, d.  In float32 both
+// constants are split hi + lo as in mulk, and the sum is one chain of fused
+// multiply-adds: the low terms enter the fma of a product x c_hi or y d_hi
+// that is not exact (c_hi not a power of two), whose bits below the last
+// place make its rounding unbiased.  Added to an exact value (z, or a
+// product by 0.5) they would fall below half a unit in the last place and be
+// dropped, always in the same direction: the one-sided error the split is
+// there to remove.  3-4 instructions where two mulk products and their sum
+// take 5; two roundings of significant size instead of three.  z is added
+// last.
+template <typename T>
+HFX_HD T dotk(T x, double c, T y, double d) {
+  if constexpr (sizeof(T) == 8) {
+    return x * c + y * d;
+  } else {
+    float ch = (float)c, dh = (float)d;
+    if (pow2f(dh) && !pow2f(ch)) {
+      const T tx = x;
+      x = y;
+      y = tx;
+      const double tc = c;
+      c = d;
+      d = tc;
+      const float th = ch;
+      ch = dh;
+      dh = th;
+    }
+    const float cl = lo_part(c, ch), dl = lo_part(d, dh);
+    if (dl != 0.0f) {
+      const float s = cl != 0.0f ? __builtin_fmaf(x, cl, y * dl) : y * dl;
+      return __builtin_fmaf(x, ch, __builtin_fmaf(y, dh, s));
+    }
+    if (cl != 0.0f) return __builtin_fmaf(y, dh, __builtin_fmaf(x, ch, x * cl));
+    return __builtin_fmaf(x, ch, y * dh);
+  }
+}
+template <typename T>
+HFX_HD T dotk(T x, double c, T y, double d, T z) {
+  if constexpr (sizeof(T) == 8) {
+    return z + x * c + y * d;
+  } else {
+    return z + dotk(x, c, y, d);
+  }
+}
+
 // Stage twiddle table entry.  float32 tables hold norm-optimised values
 // (unit_f32 in twiddle.hpp), so a plain complex product keeps the transform
 // gain unbiased.
@@ -137,7 +196,7 @@ HFX_HD cpx<T> rot(cpx<T> a) {
     constexpr SinCos sc = sincos_2pi(k, N);
     constexpr double c = sc.c;
     constexpr double s = INV ? sc.s : -sc.s;
-    return {mulk(a.re, c) - mulk(a.im, s), mulk(a.re, s) + mulk(a.im, c)};
+    return {dotk(a.re, c, a.im, -s), dotk(a.re, s, a.im, c)};
   }
 }
 
@@ -208,12 +267,10 @@ struct DFT<5, INV, T> {
     const cpx<T> a1 = v[1] + v[4], b1 = v[1] - v[4];
     const cpx<T> a2 = v[2] + v[3], b2 = v[2] - v[3];
     const cpx<T> x0 = v[0];
-    const cpx<T> p1 = {x0.re + mulk(a1.re, c1) + mulk(a2.re, c2),
-                       x0.im + mulk(a1.im, c1) + mulk(a2.im, c2)};
-    const cpx<T> p2 = {x0.re + mulk(a1.re, c2) + mulk(a2.re, c1),
-                       x0.im + mulk(a1.im, c2) + mulk(a2.im, c1)};
-    const cpx<T> q1 = {mulk(b1.re, s1) + mulk(b2.re, s2), mulk(b1.im, s1) + mulk(b2.im, s2)};
-    const cpx<T> q2 = {mulk(b1.re, s2) - mulk(b2.re, s1), mulk(b1.im, s2) - mulk(b2.im, s1)};
+    const cpx<T> p1 = {dotk(a1.re, c1, a2.re, c2, x0.re), dotk(a1.im, c1, a2.im, c2, x0.im)};
+    const cpx<T> p2 = {dotk(a1.re, c2, a2.re, c1, x0.re), dotk(a1.im, c2, a2.im, c1, x0.im)};
+    const cpx<T> q1 = {dotk(b1.re, s1, b2.re, s2), dotk(b1.im, s1, b2.im, s2)};
+    const cpx<T> q2 = {dotk(b1.re, s2, b2.re, -s1), dotk(b1.im, s2, b2.im, -s1)};
     const cpx<T> iq1 = mul_pi(q1), iq2 = mul_pi(q2);
     v[0] = x0 + a1 + a2;
     if constexpr (INV) {
