@@ -248,6 +248,34 @@ void check(const char* name, double tol) {
   std::printf("%-34s fwd rel %.2e  conv rel %.2e  %s\n", name, rel, rel2, ok ? "ok" : "FAIL");
 }
 
+// Gain bias of one float32 codelet: sum |DFT_R v|^2 / (R sum |v|^2) - 1 over
+// random inputs.  Parseval makes it zero in exact arithmetic, and unbiased
+// rounding keeps it at the 1e-10 level over 10^6 butterflies (fixed seeds:
+// the values are reproducible).  A constant applied with a one-sided error
+// (its low part rounded away, e.g. added to an exact value before the
+// inexact product) shifts it to 1e-9 - 4e-9 for radices 5, 6, 10, 12 and 15,
+// which the 5e-10 bar catches; the convolution check above would not.
+template <int R, bool INV>
+double codelet_gain_bias(int trials) {
+  std::mt19937_64 rng(5 + R);
+  std::normal_distribution<double> nd;
+  double in = 0, out = 0;
+  for (int t = 0; t < trials; ++t) {
+    cpx<float> v[R];
+    double e = 0;
+    for (int k = 0; k < R; ++k) {
+      v[k] = {(float)nd(rng), (float)nd(rng)};
+      e += (double)v[k].re * v[k].re + (double)v[k].im * v[k].im;
+    }
+    DFT<R, INV, float>::run(v);
+    double o = 0;
+    for (int k = 0; k < R; ++k) o += (double)v[k].re * v[k].re + (double)v[k].im * v[k].im;
+    in += R * e;
+    out += o;
+  }
+  return out / in - 1.0;
+}
+
 int main() {
   // float64: rounding-level agreement
   check<double, 24, 16, 64, true, Sched<4, 6>, Sched<6, 4>>("f64 N24 pencil (4,6)", 1e-13);
@@ -277,6 +305,25 @@ int main() {
     const double b80 = energy_bias<float, 80, 16, 64, Sched<4, 4, 5>, Sched<5, 4, 4>>(400);
     std::printf("f32 convolution energy bias: N96 %.2e  N120 %.2e  N80 %.2e\n", b96, b120, b80);
     if (std::fabs(b96) > 1e-8 || std::fabs(b120) > 1e-8 || std::fabs(b80) > 1e-8) g_fail++;
+  }
+  {
+    // every codelet with compile-time constants, both directions
+    const double g[] = {codelet_gain_bias<3, false>(1000000),  codelet_gain_bias<5, false>(1000000),
+                        codelet_gain_bias<5, true>(1000000),   codelet_gain_bias<8, false>(1000000),
+                        codelet_gain_bias<8, true>(1000000),   codelet_gain_bias<9, false>(1000000),
+                        codelet_gain_bias<10, false>(1000000), codelet_gain_bias<12, false>(1000000),
+                        codelet_gain_bias<12, true>(1000000),  codelet_gain_bias<15, false>(1000000),
+                        codelet_gain_bias<15, true>(1000000),  codelet_gain_bias<16, false>(1000000),
+                        codelet_gain_bias<16, true>(1000000),  codelet_gain_bias<6, false>(1000000)};
+    const char* nm[] = {"3", "5", "5i", "8", "8i", "9", "10", "12", "12i", "15", "15i", "16", "16i", "6"};
+    double worst = 0;
+    std::printf("f32 codelet gain bias:");
+    for (int i = 0; i < 14; ++i) {
+      std::printf(" R%s %.1e", nm[i], g[i]);
+      worst = std::fmax(worst, std::fabs(g[i]));
+    }
+    std::printf("\n");
+    if (worst > 5e-10) g_fail++;
   }
   std::printf("%s\n", g_fail ? "FAILED" : "ALL OK");
   return g_fail ? 1 : 0;
