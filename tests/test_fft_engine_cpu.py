@@ -1,7 +1,8 @@
 """Host emulation of the workgroup FFT engine (tests/native/fft_engine_check.hip):
 every stage of the device transforms run thread by thread on the CPU and
 compared with a float64 O(N^2) DFT, plus the float32 convolution-energy bias
-of the codelet constants.  Compiled with hipcc as host code (no GPU)."""
+of the codelet constants and the gain bias of every float32 codelet (Parseval
+over 10^6 random butterflies).  Compiled with hipcc as host code (no GPU)."""
 import os
 import shutil
 import subprocess
